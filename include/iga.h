@@ -1,0 +1,223 @@
+/*
+ * iga.h -- C ABI of the MI355X (gfx950) library for the low-rank tensor-train
+ * method for isogeometric PDE-constrained optimisation (Buenger, Dolgov,
+ * Stoll): TT assembly of the Galerkin mass and stiffness operators from a
+ * B-spline geometry (Section 3), the KKT operator of the Poisson control
+ * problem (Section 4, stationary reading) and its block-AMEn solver
+ * (Section 5).
+ *
+ * Conventions
+ * -----------
+ * Status: every int-returning call returns IGA_OK (0) or a negative IGA_E*
+ *   code; iga_last_error() then returns a thread-local message. A failed call
+ *   leaves every handle it was given valid and allocates nothing the caller
+ *   must free (out-handles stay NULL).
+ * Ownership: every handle returned through an out-pointer is owned by the
+ *   caller and released by its *_destroy; destroy(NULL) is a no-op. Inputs
+ *   are never modified. Host arrays are copied before the call returns.
+ * Memory: "dev" pointers are device memory of the context's GPU; "host"
+ *   pointers are ordinary host memory.
+ * Streams: all work is enqueued on the stream given to iga_ctx_create;
+ *   calls that return host-visible results (ranks, norms, statistics)
+ *   synchronise that stream.
+ * Index order: C order (last index fastest). Three spatial directions.
+ *   The solution space per direction d has degree p, N_d = n_d + 2
+ *   B-splines on E_d = N_d - p uniform elements; n_d counts the free
+ *   unknowns left after the Dirichlet boundary functions are omitted
+ *   (Section 4). Full coefficient tensors are [n1][n2][n3].
+ * Layouts:
+ *   TT core          [r_{d-1}][n_d][r_d], r_0 = r_3 = 1        (eq. tt)
+ *   block-TT core    [3][r_{d-1}][n_d][r_d] at the core holding the
+ *                    component index l = (y, u, lambda), plain TT cores
+ *                    elsewhere                                (eq. btt)
+ *   TT-matrix core   banded [R_{d-1}][n_d][2p+1][R_d]: entry (i, o) is
+ *                    column j = i + o - p of row i; entries with j outside
+ *                    0..n_d-1 are zero.                 (eqs. M_kron, K_kron)
+ */
+#ifndef IGA_H
+#define IGA_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define IGA_OK 0
+#define IGA_EINVAL (-1)  /* bad argument: sizes, degrees, tolerances, NULL */
+#define IGA_ENOMEM (-2)  /* device allocation failed */
+#define IGA_EHIP (-3)    /* a HIP runtime call failed */
+#define IGA_EGEOM (-4)   /* det grad G <= 0 at an interpolation point: the map folds */
+#define IGA_ENOCONV (-5) /* block AMEn stopped at nswp sweeps above tolerance */
+#define IGA_ERANK (-6)   /* a rank cap was reached (weight_rmax or r_max) */
+
+#define IGA_FP64 0
+#define IGA_FP32 1
+
+typedef struct iga_ctx iga_ctx;
+typedef struct iga_tt iga_tt;     /* TT vector, 3 cores on the device        */
+typedef struct iga_ttop iga_ttop; /* TT-matrix with banded cores             */
+typedef struct iga_btt iga_btt;   /* block-TT holding (y, u, lambda)         */
+typedef struct iga_kkt iga_kkt;   /* KKT operator built from M, K and beta   */
+
+/* B-spline geometry map G = C : B (Section 2, eq. geometryMapping).
+ * degree: geometry degree; ncp[d]: control points per direction;
+ * knots[d]: host, open knot vector of length ncp[d] + degree + 1 on [0, 1];
+ * ctrl: host, [3][ncp0][ncp1][ncp2], physical coordinates of the control points. */
+typedef struct {
+  int degree;
+  int ncp[3];
+  const double* knots[3];
+  const double* ctrl;
+} iga_geometry;
+
+/* Options of the TT assembly (Section 3 and Section 6.1).
+ * p_interp: degree of the weight-interpolation space (<= 0: 2p+1);
+ * nquad: Gauss-Legendre points per element and direction (<= 0: 5);
+ * weight_tol: relative Frobenius tolerance of the TT-SVD of each weight tensor
+ *   (split as weight_tol / sqrt(2) per unfolding); 0 keeps all nonzero
+ *   singular values (up to rounding);
+ * weight_rmax: cap on each weight TT rank (<= 0: none). */
+typedef struct {
+  int p_interp;
+  int nquad;
+  double weight_tol;
+  int weight_rmax;
+} iga_assembly_opts;
+
+/* Options of the block-AMEn solve (Section 5). Zero or negative fields take
+ * the documented defaults.
+ * nswp: maximum half-sweeps (default 20); r_max: cap on solution ranks
+ * (default 256); kick_rank: residual-enrichment rank rho (default 4, -1 to
+ * disable); local_tol: relative tolerance of each local solve (default tol/10);
+ * local_maxit: maximum preconditioned GMRES iterations per local solve
+ * (default 400); local_restart: GMRES restart length (default 40);
+ * precision: IGA_FP64, or IGA_FP32 for the mixed form (local contractions in
+ * FP32 inside an FP64 iterative refinement); init_rank: rank of the random
+ * initial guess when x0 is NULL (default 2); seed: its seed; verbose: print
+ * one line per half-sweep to stderr. */
+typedef struct {
+  int nswp;
+  int r_max;
+  int kick_rank;
+  double local_tol;
+  int local_maxit;
+  int local_restart;
+  int precision;
+  int init_rank;
+  unsigned long long seed;
+  int verbose;
+} iga_amen_opts;
+
+/* Statistics of a solve; times in seconds from HIP events on the context stream. */
+typedef struct {
+  int half_sweeps;
+  int converged;
+  double max_local_residual;   /* of the last half-sweep, before its local solves */
+  double residual;             /* ||A f - b|| / ||b|| of the returned solution (FP64, exact) */
+  int ranks[2];                /* r_1, r_2 of the solution */
+  long long local_solves;
+  long long local_iterations;  /* preconditioned Krylov iterations, all local solves */
+  long long local_matvecs;     /* projected local matvecs (each = 3 M + 2 K applications) */
+  double local_matvec_flops;   /* algorithmic flops of those matvecs */
+  double t_total;
+  double t_local_matvec;       /* time inside the projected local matvec kernels */
+  double t_precond;
+  double t_krylov_other;
+  double t_interfaces;
+  double t_svd;
+  double t_residual;
+} iga_amen_stats;
+
+/* Context on GPU `device`; hip_stream is a hipStream_t (NULL: the default stream). */
+int iga_ctx_create(int device, void* hip_stream, iga_ctx** out);
+void iga_ctx_destroy(iga_ctx* ctx);
+
+/* Low-rank assembly of the mass and stiffness operators (Section 3):
+ * evaluates omega = |det grad G| and Q = (grad G^T grad G)^{-1} omega on the
+ * Greville grid of the interpolation space, compresses each of the seven
+ * weight tensors (omega, q11, q12, q13, q22, q23, q33) by TT-SVD, solves the
+ * collocation systems core by core (eq. weightEquationSolve), and integrates
+ * the univariate factors M^(d)(w . beta~) and K_kl^(d)(v . beta~) by Gauss
+ * quadrature (eqs. massMatrix1D, stiffnessFinal). M is returned as one
+ * TT-matrix; K as the rank concatenation of its nine (k, l) terms (terms whose
+ * weight vanishes are dropped). Boundary functions are omitted.
+ * degree >= 1; n[d] >= 1; the geometry must be one-to-one (else IGA_EGEOM).
+ * weight_ranks_out (nullable, host): [7][2] TT ranks (R1, R2) of the weights
+ * in the order above; 0 for a weight that vanishes. */
+int iga_assemble_factors(iga_ctx* ctx, const iga_geometry* geo, int degree, const int n[3],
+                         const iga_assembly_opts* opts, iga_ttop** M, iga_ttop** K,
+                         int* weight_ranks_out);
+
+/* TT-matrix from host banded cores (layout above); R[0] = R[3] = 1. */
+int iga_ttop_create(iga_ctx* ctx, int degree, const int n[3], const int R[4],
+                    const double* const host_cores[3], iga_ttop** out);
+/* Sizes: n[3], R[4], degree (any may be NULL). */
+int iga_ttop_info(const iga_ttop* op, int* n, int* R, int* degree);
+/* Copies banded core d to host [R_{d-1}][n_d][2p+1][R_d]. */
+int iga_ttop_get_core(iga_ctx* ctx, const iga_ttop* op, int d, double* host_out);
+void iga_ttop_destroy(iga_ttop* op);
+
+/* TT vectors. iga_tt_create copies host cores; iga_tt_wrap wraps caller-owned
+ * device cores without copying (they must outlive the handle). r[0]=r[3]=1. */
+int iga_tt_create(iga_ctx* ctx, const int n[3], const int r[4], const double* const host_cores[3],
+                  iga_tt** out);
+int iga_tt_wrap(iga_ctx* ctx, const int n[3], const int r[4], double* const dev_cores[3],
+                iga_tt** out);
+void iga_tt_destroy(iga_tt* t);
+
+/* Block-TT from host cores (layout above), component index at core ell_core. */
+int iga_btt_create(iga_ctx* ctx, const int n[3], const int r[4], int ell_core,
+                   const double* const host_cores[3], iga_btt** out);
+int iga_btt_info(const iga_btt* x, int* n, int* r, int* ell_core);
+int iga_btt_get_core(iga_ctx* ctx, const iga_btt* x, int d, double* host_out);
+/* Expands the three components into dev_out [3][n1][n2][n3] (tests, residuals). */
+int iga_btt_to_full(iga_ctx* ctx, const iga_btt* x, double* dev_out);
+void iga_btt_destroy(iga_btt* x);
+
+/* KKT operator [[M,0,K],[0,beta M,-M],[K,-M,0]] of the stationary control
+ * problem (eq. KKTSystem with one time step, tau = 1). beta > 0. M and K
+ * must share n and degree and outlive the handle. */
+int iga_kkt_create(iga_ctx* ctx, const iga_ttop* M, const iga_ttop* K, double beta, iga_kkt** out);
+void iga_kkt_destroy(iga_kkt* kkt);
+
+/* y = A x exactly, without rounding: y has ranks (R^M_d + R^K_d) r_d and its
+ * component index at the core of x (eqs. M_kron, K_kron, KKTSystem). */
+int iga_kkt_apply(iga_ctx* ctx, const iga_kkt* kkt, const iga_btt* x, iga_btt** y);
+
+/* ||A f - b|| / ||b|| with b = [M yhat; 0; 0], in FP64 on expanded vectors. */
+int iga_kkt_residual(iga_ctx* ctx, const iga_kkt* kkt, const iga_tt* yhat, const iga_btt* f,
+                     double* rel_residual);
+
+/* Block-AMEn solve of A f = [M yhat; 0; 0] (Section 5): alternating sweeps
+ * over the cores, each projecting the three block rows onto the frame of the
+ * current solution (eq. KKT_red), solving the projected system by
+ * preconditioned GMRES, enriching with a residual direction and moving the
+ * component index by a truncated SVD (eqs. svd1, svd2). Stops when every local
+ * residual of a half-sweep is <= tol (relative) or after nswp half-sweeps
+ * (IGA_ENOCONV; *sol is still returned). x0 (nullable) is the initial guess.
+ * stats (nullable) receives the statistics above. */
+int iga_amen_solve(iga_ctx* ctx, const iga_kkt* kkt, const iga_tt* yhat, double tol,
+                   const iga_amen_opts* opts, const iga_btt* x0, iga_btt** sol,
+                   iga_amen_stats* stats);
+
+/* The projected local TT-matvec of one block-AMEn step (eq. KKT_red), on raw
+ * device buffers: for l = 0..2 and A in {M, K}
+ *   (A x_l)[a',i,b'] = sum PhiL_A[al][a'][a] A[al][i][i+o-p][be] x_l[a][i+o-p][b] PhiR_A[be][b'][b]
+ * combined into y = [M x0 + K x2; beta M x1 - M x2; K x0 - M x1].
+ * x, y: dev [3][r0][n][r1]; PhiL_*: dev [R_{d-1}][r0][r0]; PhiR_*: dev [R_d][r1][r1];
+ * Mcore, Kcore: dev banded [R_{d-1}][n][2p+1][R_d] (dense in the rank indices).
+ * precision: IGA_FP64 or IGA_FP32 (inputs are FP64; FP32 converts them first).
+ * Enqueued on the context stream; returns immediately. */
+int iga_local_matvec(iga_ctx* ctx, int r0, int n, int r1, int degree, int RM0, int RM1, int RK0,
+                     int RK1, const double* PhiL_M, const double* PhiR_M, const double* PhiL_K,
+                     const double* PhiR_K, const double* Mcore, const double* Kcore, double beta,
+                     const double* x, double* y, int precision);
+
+/* Algorithmic flops of one iga_local_matvec call with these sizes. */
+double iga_local_matvec_flops(int r0, int n, int r1, int degree, int RM0, int RM1, int RK0, int RK1);
+
+const char* iga_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IGA_H */

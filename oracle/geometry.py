@@ -23,12 +23,12 @@ def evaluate(geo, x1, x2, x3):
     C = np.asarray(geo.ctrl, dtype=np.float64)
     B = [basis(geo.knots[d], p, x) for d, x in enumerate((x1, x2, x3))]
     dB = [basis(geo.knots[d], p, x, deriv=1) for d, x in enumerate((x1, x2, x3))]
-    G = np.einsum("aijk,pi,qj,rk->apqr", C, B[0], B[1], B[2])
+    G = np.einsum("aijk,pi,qj,rk->apqr", C, B[0], B[1], B[2], optimize=True)
     J = np.empty(G.shape[1:] + (3, 3))
     for a in range(3):
-        J[..., a, 0] = np.einsum("ijk,pi,qj,rk->pqr", C[a], dB[0], B[1], B[2])
-        J[..., a, 1] = np.einsum("ijk,pi,qj,rk->pqr", C[a], B[0], dB[1], B[2])
-        J[..., a, 2] = np.einsum("ijk,pi,qj,rk->pqr", C[a], B[0], B[1], dB[2])
+        J[..., a, 0] = np.einsum("ijk,pi,qj,rk->pqr", C[a], dB[0], B[1], B[2], optimize=True)
+        J[..., a, 1] = np.einsum("ijk,pi,qj,rk->pqr", C[a], B[0], dB[1], B[2], optimize=True)
+        J[..., a, 2] = np.einsum("ijk,pi,qj,rk->pqr", C[a], B[0], B[1], dB[2], optimize=True)
     return G, J
 
 

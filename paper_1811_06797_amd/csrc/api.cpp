@@ -1,0 +1,500 @@
+// C ABI entry points (include/iga.h): argument checks, handle management and
+// dispatch to the drivers. Every entry point converts exceptions to status codes.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "kernels.hpp"
+#include "ttops.hpp"
+
+namespace iga {
+
+thread_local std::string g_last_error;
+
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+[[noreturn]] void fail(int code, const std::string& msg) { throw Error(code, msg); }
+
+Pool::~Pool() {
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(device_);
+  for (auto& kv : free_) (void)hipFree(kv.second);
+  for (auto& kv : live_) (void)hipFree(kv.first);
+  (void)hipSetDevice(cur);
+}
+
+void* Pool::alloc(size_t bytes) {
+  bytes = (bytes + 255) & ~size_t(255);
+  auto it = free_.find(bytes);
+  void* p = nullptr;
+  if (it != free_.end()) {
+    p = it->second;
+    free_.erase(it);
+  } else {
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      // release cached blocks and retry once
+      for (auto& kv : free_) (void)hipFree(kv.second);
+      free_.clear();
+      (void)hipGetLastError();
+      e = hipMalloc(&p, bytes);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(IGA_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+      }
+    }
+  }
+  live_[p] = bytes;
+  in_use_ += bytes;
+  return p;
+}
+
+void Pool::release(void* p) {
+  auto it = live_.find(p);
+  if (it == live_.end()) return;
+  in_use_ -= it->second;
+  free_.emplace(it->second, p);
+  live_.erase(it);
+}
+
+void release_scratch(iga_ctx* ctx);
+void release_raw_cache(iga_ctx* ctx);
+int assemble_impl(iga_ctx* ctx, const iga_geometry* geo, int p, const int n[3],
+                  const iga_assembly_opts* opts, iga_ttop** M, iga_ttop** K, int* ranks_out);
+int amen_impl(iga_ctx* ctx, const iga_kkt* kkt, const iga_tt* yhat, double tol,
+              const iga_amen_opts* opts, const iga_btt* x0, iga_btt** sol, iga_amen_stats* stats);
+void local_matvec_impl(iga_ctx* ctx, int r0, int n, int r1, int p, int RM0, int RM1, int RK0, int RK1,
+                       const double* PhiL_M, const double* PhiR_M, const double* PhiL_K,
+                       const double* PhiR_K, const double* Mcore, const double* Kcore, double beta,
+                       const double* x, double* y, int precision);
+double local_matvec_flops(int r0, int n, int r1, int p, int RM0, int RM1, int RK0, int RK1);
+
+template <class F>
+int guarded(F&& f) {
+  try {
+    return f();
+  } catch (const Error& e) {
+    set_last_error(e.what());
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_last_error("host allocation failed");
+    return IGA_ENOMEM;
+  } catch (const std::exception& e) {
+    set_last_error(e.what());
+    return IGA_EINVAL;
+  }
+}
+
+static void use_device(iga_ctx* ctx) { IGA_HIP(hipSetDevice(ctx->device)); }
+
+static void upload(iga_ctx* ctx, double* dst, const double* src, size_t n) {
+  IGA_HIP(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+}
+
+}  // namespace iga
+
+using namespace iga;
+
+iga_kkt::~iga_kkt() { delete Kref; }
+
+extern "C" {
+
+const char* iga_last_error(void) { return g_last_error.c_str(); }
+
+int iga_ctx_create(int device, void* hip_stream, iga_ctx** out) {
+  return guarded([&] {
+    require(out != nullptr, IGA_EINVAL, "ctx_create: NULL out");
+    *out = nullptr;
+    int ndev = 0;
+    IGA_HIP(hipGetDeviceCount(&ndev));
+    require(device >= 0 && device < ndev, IGA_EINVAL, "ctx_create: no such device");
+    IGA_HIP(hipSetDevice(device));
+    std::unique_ptr<iga_ctx> c(new iga_ctx());
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->pool.reset(new Pool(device));
+    *out = c.release();
+    return IGA_OK;
+  });
+}
+
+void iga_ctx_destroy(iga_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  release_scratch(ctx);
+  release_raw_cache(ctx);
+  delete ctx;
+}
+
+int iga_assemble_factors(iga_ctx* ctx, const iga_geometry* geo, int degree, const int n[3],
+                         const iga_assembly_opts* opts, iga_ttop** M, iga_ttop** K,
+                         int* weight_ranks_out) {
+  return guarded([&] {
+    require(ctx && M && K, IGA_EINVAL, "assemble_factors: NULL argument");
+    *M = nullptr;
+    *K = nullptr;
+    use_device(ctx);
+    return assemble_impl(ctx, geo, degree, n, opts, M, K, weight_ranks_out);
+  });
+}
+
+int iga_ttop_create(iga_ctx* ctx, int degree, const int n[3], const int R[4],
+                    const double* const host_cores[3], iga_ttop** out) {
+  return guarded([&] {
+    require(ctx && n && R && host_cores && out, IGA_EINVAL, "ttop_create: NULL argument");
+    *out = nullptr;
+    require(degree >= 0 && degree <= 15, IGA_EINVAL, "ttop_create: bad degree");
+    require(R[0] == 1 && R[3] == 1 && R[1] >= 1 && R[2] >= 1, IGA_EINVAL, "ttop_create: bad ranks");
+    use_device(ctx);
+    std::unique_ptr<iga_ttop> op(new iga_ttop());
+    op->ctx = ctx;
+    op->p = degree;
+    const int b = 2 * degree + 1;
+    for (int d = 0; d < 4; ++d) op->R[d] = R[d];
+    for (int d = 0; d < 3; ++d) {
+      require(n[d] >= 1 && host_cores[d], IGA_EINVAL, "ttop_create: bad core");
+      op->n[d] = n[d];
+      OpCore& c = op->core[d];
+      c.R0 = R[d]; c.R1 = R[d + 1]; c.n = n[d];
+      const size_t sz = (size_t)c.R0 * n[d] * b * c.R1;
+      c.data.reset(ctx, sz);
+      upload(ctx, c.data.get(), host_cores[d], sz);
+      opcore_setup_blocks(ctx, c, {RankBlock{0, c.R0, 0, c.R1}});
+    }
+    IGA_HIP(hipStreamSynchronize(ctx->stream));
+    *out = op.release();
+    return IGA_OK;
+  });
+}
+
+int iga_ttop_info(const iga_ttop* op, int* n, int* R, int* degree) {
+  return guarded([&] {
+    require(op != nullptr, IGA_EINVAL, "ttop_info: NULL handle");
+    if (n) for (int d = 0; d < 3; ++d) n[d] = op->n[d];
+    if (R) for (int d = 0; d < 4; ++d) R[d] = op->R[d];
+    if (degree) *degree = op->p;
+    return IGA_OK;
+  });
+}
+
+int iga_ttop_get_core(iga_ctx* ctx, const iga_ttop* op, int d, double* host_out) {
+  return guarded([&] {
+    require(ctx && op && host_out && d >= 0 && d < 3, IGA_EINVAL, "ttop_get_core: bad argument");
+    use_device(ctx);
+    const OpCore& c = op->core[d];
+    const size_t sz = (size_t)c.R0 * c.n * (2 * op->p + 1) * c.R1;
+    IGA_HIP(hipMemcpyAsync(host_out, c.data.get(), sz * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    IGA_HIP(hipStreamSynchronize(ctx->stream));
+    return IGA_OK;
+  });
+}
+
+void iga_ttop_destroy(iga_ttop* op) {
+  if (!op) return;
+  (void)hipSetDevice(op->ctx->device);
+  (void)hipStreamSynchronize(op->ctx->stream);
+  delete op;
+}
+
+static void check_tt_shape(const int n[3], const int r[4]) {
+  require(n && r, IGA_EINVAL, "NULL sizes");
+  require(r[0] == 1 && r[3] == 1, IGA_EINVAL, "boundary ranks must be 1");
+  for (int d = 0; d < 3; ++d) {
+    require(n[d] >= 1, IGA_EINVAL, "mode sizes must be >= 1");
+    require(r[d + 1] >= 1, IGA_EINVAL, "ranks must be >= 1");
+  }
+}
+
+int iga_tt_create(iga_ctx* ctx, const int n[3], const int r[4], const double* const host_cores[3],
+                  iga_tt** out) {
+  return guarded([&] {
+    require(ctx && host_cores && out, IGA_EINVAL, "tt_create: NULL argument");
+    *out = nullptr;
+    check_tt_shape(n, r);
+    use_device(ctx);
+    std::unique_ptr<iga_tt> t(new iga_tt());
+    t->ctx = ctx;
+    for (int d = 0; d < 3; ++d) t->n[d] = n[d];
+    for (int d = 0; d < 4; ++d) t->r[d] = r[d];
+    for (int d = 0; d < 3; ++d) {
+      require(host_cores[d] != nullptr, IGA_EINVAL, "tt_create: NULL core");
+      const size_t sz = (size_t)r[d] * n[d] * r[d + 1];
+      t->own[d].reset(ctx, sz);
+      upload(ctx, t->own[d].get(), host_cores[d], sz);
+      t->core[d] = t->own[d].get();
+    }
+    IGA_HIP(hipStreamSynchronize(ctx->stream));
+    *out = t.release();
+    return IGA_OK;
+  });
+}
+
+int iga_tt_wrap(iga_ctx* ctx, const int n[3], const int r[4], double* const dev_cores[3], iga_tt** out) {
+  return guarded([&] {
+    require(ctx && dev_cores && out, IGA_EINVAL, "tt_wrap: NULL argument");
+    *out = nullptr;
+    check_tt_shape(n, r);
+    std::unique_ptr<iga_tt> t(new iga_tt());
+    t->ctx = ctx;
+    for (int d = 0; d < 3; ++d) t->n[d] = n[d];
+    for (int d = 0; d < 4; ++d) t->r[d] = r[d];
+    for (int d = 0; d < 3; ++d) {
+      require(dev_cores[d] != nullptr, IGA_EINVAL, "tt_wrap: NULL core");
+      t->core[d] = dev_cores[d];
+    }
+    *out = t.release();
+    return IGA_OK;
+  });
+}
+
+void iga_tt_destroy(iga_tt* t) {
+  if (!t) return;
+  (void)hipSetDevice(t->ctx->device);
+  (void)hipStreamSynchronize(t->ctx->stream);
+  delete t;
+}
+
+int iga_btt_create(iga_ctx* ctx, const int n[3], const int r[4], int ell_core,
+                   const double* const host_cores[3], iga_btt** out) {
+  return guarded([&] {
+    require(ctx && host_cores && out, IGA_EINVAL, "btt_create: NULL argument");
+    *out = nullptr;
+    check_tt_shape(n, r);
+    require(ell_core >= 0 && ell_core < 3, IGA_EINVAL, "btt_create: ell_core must be 0..2");
+    use_device(ctx);
+    std::unique_ptr<iga_btt> x(new iga_btt());
+    x->ctx = ctx;
+    x->ell = ell_core;
+    for (int d = 0; d < 3; ++d) x->n[d] = n[d];
+    for (int d = 0; d < 4; ++d) x->r[d] = r[d];
+    for (int d = 0; d < 3; ++d) {
+      require(host_cores[d] != nullptr, IGA_EINVAL, "btt_create: NULL core");
+      const size_t sz = (size_t)(d == ell_core ? 3 : 1) * r[d] * n[d] * r[d + 1];
+      x->core[d].reset(ctx, sz);
+      upload(ctx, x->core[d].get(), host_cores[d], sz);
+    }
+    IGA_HIP(hipStreamSynchronize(ctx->stream));
+    *out = x.release();
+    return IGA_OK;
+  });
+}
+
+int iga_btt_info(const iga_btt* x, int* n, int* r, int* ell_core) {
+  return guarded([&] {
+    require(x != nullptr, IGA_EINVAL, "btt_info: NULL handle");
+    if (n) for (int d = 0; d < 3; ++d) n[d] = x->n[d];
+    if (r) for (int d = 0; d < 4; ++d) r[d] = x->r[d];
+    if (ell_core) *ell_core = x->ell;
+    return IGA_OK;
+  });
+}
+
+int iga_btt_get_core(iga_ctx* ctx, const iga_btt* x, int d, double* host_out) {
+  return guarded([&] {
+    require(ctx && x && host_out && d >= 0 && d < 3, IGA_EINVAL, "btt_get_core: bad argument");
+    use_device(ctx);
+    const size_t sz = (size_t)(d == x->ell ? 3 : 1) * x->r[d] * x->n[d] * x->r[d + 1];
+    IGA_HIP(hipMemcpyAsync(host_out, x->core[d].get(), sz * sizeof(double), hipMemcpyDeviceToHost,
+                           ctx->stream));
+    IGA_HIP(hipStreamSynchronize(ctx->stream));
+    return IGA_OK;
+  });
+}
+
+int iga_btt_to_full(iga_ctx* ctx, const iga_btt* x, double* dev_out) {
+  return guarded([&] {
+    require(ctx && x && dev_out, IGA_EINVAL, "btt_to_full: NULL argument");
+    use_device(ctx);
+    btt_expand(ctx, x, dev_out);
+    IGA_HIP(hipStreamSynchronize(ctx->stream));
+    return IGA_OK;
+  });
+}
+
+void iga_btt_destroy(iga_btt* x) {
+  if (!x) return;
+  (void)hipSetDevice(x->ctx->device);
+  (void)hipStreamSynchronize(x->ctx->stream);
+  delete x;
+}
+
+int iga_kkt_create(iga_ctx* ctx, const iga_ttop* M, const iga_ttop* K, double beta, iga_kkt** out) {
+  return guarded([&] {
+    require(ctx && M && K && out, IGA_EINVAL, "kkt_create: NULL argument");
+    *out = nullptr;
+    require(beta > 0.0 && std::isfinite(beta), IGA_EINVAL, "kkt_create: beta must be > 0");
+    require(M->p == K->p, IGA_EINVAL, "kkt_create: M and K differ in degree");
+    for (int d = 0; d < 3; ++d) require(M->n[d] == K->n[d], IGA_EINVAL, "kkt_create: M and K differ in n");
+    use_device(ctx);
+    std::unique_ptr<iga_kkt> k(new iga_kkt());
+    k->ctx = ctx;
+    k->M = M;
+    k->K = K;
+    k->beta = beta;
+    if (M->has_ref) {
+      // Laplace-form reference operator sum_d c_d (Mbar (x) .. Kbar_d .. (x) Mbar), ranks (1,2,2,1)
+      const int p = M->p, b = 2 * p + 1;
+      std::vector<double> m[3], kk[3];
+      for (int d = 0; d < 3; ++d) {
+        const int n = M->n[d];
+        m[d].resize((size_t)n * b);
+        kk[d].resize((size_t)n * b);
+        IGA_HIP(hipMemcpyAsync(m[d].data(), M->refM[d].get(), m[d].size() * 8, hipMemcpyDeviceToHost, ctx->stream));
+        IGA_HIP(hipMemcpyAsync(kk[d].data(), M->refK[d].get(), kk[d].size() * 8, hipMemcpyDeviceToHost, ctx->stream));
+      }
+      IGA_HIP(hipStreamSynchronize(ctx->stream));
+      const int R[4] = {1, 2, 2, 1};
+      std::vector<double> c[3];
+      for (int d = 0; d < 3; ++d) {
+        const int n = M->n[d];
+        c[d].assign((size_t)R[d] * n * b * R[d + 1], 0.0);
+        auto at = [&](int a, int i, int o, int be) -> double& {
+          return c[d][(((size_t)a * n + i) * b + o) * R[d + 1] + be];
+        };
+        for (int i = 0; i < n; ++i)
+          for (int o = 0; o < b; ++o) {
+            const double mv = m[d][(size_t)i * b + o], kv = M->ref_c[d] * kk[d][(size_t)i * b + o];
+            if (d == 0) { at(0, i, o, 0) = kv; at(0, i, o, 1) = mv; }
+            if (d == 1) { at(0, i, o, 0) = mv; at(1, i, o, 0) = kv; at(1, i, o, 1) = mv; }
+            if (d == 2) { at(0, i, o, 0) = mv; at(1, i, o, 0) = kv; }
+          }
+      }
+      const double* hc[3] = {c[0].data(), c[1].data(), c[2].data()};
+      iga_ttop* kr = nullptr;
+      int rc = iga_ttop_create(ctx, p, M->n, R, hc, &kr);
+      require(rc == IGA_OK, rc, g_last_error);
+      k->Kref = kr;
+      // univariate generalised eigen-decompositions (c_d Kbar_d, Mbar_d)
+      for (int d = 0; d < 3; ++d) {
+        const int n = M->n[d];
+        std::vector<double> Am((size_t)n * n, 0.0), Bm((size_t)n * n, 0.0);
+        for (int i = 0; i < n; ++i)
+          for (int o = 0; o < b; ++o) {
+            const int j = i + o - p;
+            if (j < 0 || j >= n) continue;
+            Am[(size_t)i * n + j] = M->ref_c[d] * kk[d][(size_t)i * b + o];
+            Bm[(size_t)i * n + j] = m[d][(size_t)i * b + o];
+          }
+        // symmetrise (the factors are symmetric up to rounding)
+        for (int i = 0; i < n; ++i)
+          for (int j = 0; j < i; ++j) {
+            double a = 0.5 * (Am[(size_t)i * n + j] + Am[(size_t)j * n + i]);
+            Am[(size_t)i * n + j] = Am[(size_t)j * n + i] = a;
+            double bb = 0.5 * (Bm[(size_t)i * n + j] + Bm[(size_t)j * n + i]);
+            Bm[(size_t)i * n + j] = Bm[(size_t)j * n + i] = bb;
+          }
+        DBuf dA(ctx, (size_t)n * n), dB(ctx, (size_t)n * n);
+        upload(ctx, dA.get(), Am.data(), Am.size());
+        upload(ctx, dB.get(), Bm.data(), Bm.size());
+        k->Vn[d].reset(ctx, (size_t)n * n);
+        k->lamn[d].reset(ctx, n);
+        gen_eig(ctx, n, dA.get(), dB.get(), k->Vn[d].get(), k->lamn[d].get());
+      }
+    }
+    *out = k.release();
+    return IGA_OK;
+  });
+}
+
+void iga_kkt_destroy(iga_kkt* kkt) {
+  if (!kkt) return;
+  (void)hipSetDevice(kkt->ctx->device);
+  (void)hipStreamSynchronize(kkt->ctx->stream);
+  delete kkt;
+}
+
+static void check_btt_matches(const iga_kkt* kkt, const iga_btt* x) {
+  for (int d = 0; d < 3; ++d)
+    require(x->n[d] == kkt->M->n[d], IGA_EINVAL, "block-TT mode sizes differ from the operator");
+}
+
+int iga_kkt_apply(iga_ctx* ctx, const iga_kkt* kkt, const iga_btt* x, iga_btt** y) {
+  return guarded([&] {
+    require(ctx && kkt && x && y, IGA_EINVAL, "kkt_apply: NULL argument");
+    *y = nullptr;
+    check_btt_matches(kkt, x);
+    use_device(ctx);
+    iga_btt* r = kkt_apply_impl(ctx, kkt, x);
+    IGA_HIP(hipStreamSynchronize(ctx->stream));
+    *y = r;
+    return IGA_OK;
+  });
+}
+
+namespace iga {
+// ||A f - b|| / ||b|| with b = [M yhat; 0; 0], all in expanded form.
+double kkt_residual_impl(iga_ctx* ctx, const iga_kkt* kkt, const iga_tt* yhat, const iga_btt* f) {
+  const long N = (long)f->n[0] * f->n[1] * f->n[2];
+  std::unique_ptr<iga_btt> Af(kkt_apply_impl(ctx, kkt, f));
+  DBuf full(ctx, 3 * N), bfull(ctx, N);
+  btt_expand(ctx, Af.get(), full.get());
+  // b1 = M yhat: core products of M with yhat's cores
+  int s[4] = {1, kkt->M->R[1] * yhat->r[1], kkt->M->R[2] * yhat->r[2], 1};
+  DBuf bc[3];
+  const double* cp[3];
+  for (int d = 0; d < 3; ++d) {
+    bc[d].reset(ctx, (size_t)s[d] * f->n[d] * s[d + 1]);
+    core_product(ctx, view_of(kkt->M, d), yhat->core[d], yhat->r[d], yhat->r[d + 1], bc[d].get(), 1.0, 0.0);
+    cp[d] = bc[d].get();
+  }
+  tt_expand(ctx, f->n, s, cp, bfull.get());
+  const double nb = norm2_host(ctx, N, bfull.get());
+  k::axpby(ctx->stream, N, -1.0, bfull.get(), 1.0, full.get());
+  const double nr = norm2_host(ctx, 3 * N, full.get());
+  return nb > 0 ? std::sqrt(nr / nb) : std::sqrt(nr);
+}
+}  // namespace iga
+
+int iga_kkt_residual(iga_ctx* ctx, const iga_kkt* kkt, const iga_tt* yhat, const iga_btt* f,
+                     double* rel_residual) {
+  return guarded([&] {
+    require(ctx && kkt && yhat && f && rel_residual, IGA_EINVAL, "kkt_residual: NULL argument");
+    check_btt_matches(kkt, f);
+    for (int d = 0; d < 3; ++d) require(yhat->n[d] == f->n[d], IGA_EINVAL, "kkt_residual: yhat size");
+    use_device(ctx);
+    *rel_residual = kkt_residual_impl(ctx, kkt, yhat, f);
+    return IGA_OK;
+  });
+}
+
+int iga_amen_solve(iga_ctx* ctx, const iga_kkt* kkt, const iga_tt* yhat, double tol,
+                   const iga_amen_opts* opts, const iga_btt* x0, iga_btt** sol,
+                   iga_amen_stats* stats) {
+  return guarded([&] {
+    require(ctx && kkt && yhat && sol, IGA_EINVAL, "amen_solve: NULL argument");
+    *sol = nullptr;
+    require(tol > 0.0 && tol < 1.0, IGA_EINVAL, "amen_solve: tol must be in (0, 1)");
+    for (int d = 0; d < 3; ++d) require(yhat->n[d] == kkt->M->n[d], IGA_EINVAL, "amen_solve: yhat size");
+    if (x0) check_btt_matches(kkt, x0);
+    use_device(ctx);
+    return amen_impl(ctx, kkt, yhat, tol, opts, x0, sol, stats);
+  });
+}
+
+int iga_local_matvec(iga_ctx* ctx, int r0, int n, int r1, int degree, int RM0, int RM1, int RK0,
+                     int RK1, const double* PhiL_M, const double* PhiR_M, const double* PhiL_K,
+                     const double* PhiR_K, const double* Mcore, const double* Kcore, double beta,
+                     const double* x, double* y, int precision) {
+  return guarded([&] {
+    require(ctx && PhiL_M && PhiR_M && PhiL_K && PhiR_K && Mcore && Kcore && x && y, IGA_EINVAL,
+            "local_matvec: NULL argument");
+    require(r0 >= 1 && r1 >= 1 && n >= 1 && degree >= 0 && RM0 >= 1 && RM1 >= 1 && RK0 >= 1 && RK1 >= 1,
+            IGA_EINVAL, "local_matvec: sizes must be positive");
+    require(precision == IGA_FP64 || precision == IGA_FP32, IGA_EINVAL, "local_matvec: bad precision");
+    use_device(ctx);
+    local_matvec_impl(ctx, r0, n, r1, degree, RM0, RM1, RK0, RK1, PhiL_M, PhiR_M, PhiL_K, PhiR_K, Mcore,
+                      Kcore, beta, x, y, precision);
+    return IGA_OK;
+  });
+}
+
+double iga_local_matvec_flops(int r0, int n, int r1, int degree, int RM0, int RM1, int RK0, int RK1) {
+  return local_matvec_flops(r0, n, r1, degree, RM0, RM1, RK0, RK1);
+}
+
+}  // extern "C"

@@ -1,0 +1,472 @@
+// Generic kernels: strided batched GEMM, banded rank contraction, elementwise
+// updates, permutations and deterministic reductions (FP64; GEMM/band also FP32).
+#include <algorithm>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace iga {
+namespace k {
+namespace {
+
+constexpr int TM = 64, TN = 64, TK = 16, NT = 256;
+
+template <typename T>
+struct GemmArgs {
+  int M, N, K, Kout;
+  const T* A;
+  long sAm, sAk, sAko;
+  const T* B;
+  long sBk, sBn, sBko;
+  T* C;
+  long sCm, sCn;
+  int nb2;
+  long sAb1, sAb2, sBb1, sBb2, sCb1, sCb2;
+  T alpha, beta;
+};
+
+// 64x64 output tile per 256-thread workgroup, 4x4 outputs per thread, K staged
+// through LDS in slabs of 16. Loads are coalesced along whichever of the two
+// tile axes has unit stride.
+template <typename T>
+__global__ __launch_bounds__(NT) void gemm_kernel(GemmArgs<T> g) {
+  __shared__ T As[TK][TM + 1];
+  __shared__ T Bs[TK][TN + 1];
+  const int b = blockIdx.z;
+  const int b1 = b / g.nb2, b2 = b % g.nb2;
+  const T* A = g.A + b1 * g.sAb1 + b2 * g.sAb2;
+  const T* B = g.B + b1 * g.sBb1 + b2 * g.sBb2;
+  T* C = g.C + b1 * g.sCb1 + b2 * g.sCb2;
+  const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  T acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = T(0);
+  const long Ktot = (long)g.K * g.Kout;
+  const bool a_kfast = (g.sAk == 1);
+  const bool b_nfast = (g.sBn == 1);
+  for (long k0 = 0; k0 < Ktot; k0 += TK) {
+    for (int e = threadIdx.x; e < TM * TK; e += NT) {
+      int mm, kk;
+      if (a_kfast) { kk = e % TK; mm = e / TK; } else { mm = e % TM; kk = e / TM; }
+      const long k = k0 + kk;
+      const int m = m0 + mm;
+      T v = T(0);
+      if (m < g.M && k < Ktot) {
+        const long ko = k / g.K, ki = k - ko * g.K;
+        v = A[m * g.sAm + ki * g.sAk + ko * g.sAko];
+      }
+      As[kk][mm] = v;
+    }
+    for (int e = threadIdx.x; e < TN * TK; e += NT) {
+      int nn, kk;
+      if (b_nfast) { nn = e % TN; kk = e / TN; } else { kk = e % TK; nn = e / TK; }
+      const long k = k0 + kk;
+      const int nidx = n0 + nn;
+      T v = T(0);
+      if (nidx < g.N && k < Ktot) {
+        const long ko = k / g.K, ki = k - ko * g.K;
+        v = B[ki * g.sBk + nidx * g.sBn + ko * g.sBko];
+      }
+      Bs[kk][nn] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < TK; ++kk) {
+      T a[4], bb[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bb[j] = Bs[kk][tx + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], bb[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int m = m0 + ty + 16 * i;
+    if (m >= g.M) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int nidx = n0 + tx + 16 * j;
+      if (nidx >= g.N) continue;
+      T* c = C + m * g.sCm + nidx * g.sCn;
+      T v = g.alpha * acc[i][j];
+      if (g.beta != T(0)) v += g.beta * *c;
+      *c = v;
+    }
+  }
+}
+
+template <typename T, typename G>
+void launch_gemm(hipStream_t s, const G& d) {
+  if (d.M <= 0 || d.N <= 0 || d.nb1 <= 0 || d.nb2 <= 0) return;
+  GemmArgs<T> a{d.M, d.N, d.K, d.Kout, d.A, d.sAm, d.sAk, d.sAko, d.B, d.sBk, d.sBn, d.sBko,
+                d.C, d.sCm, d.sCn, d.nb2, d.sAb1, d.sAb2, d.sBb1, d.sBb2, d.sCb1, d.sCb2,
+                d.alpha, d.beta};
+  if (d.K <= 0 || d.Kout <= 0) {
+    // empty contraction: C = beta * C
+    a.K = 0;
+  }
+  long nb = (long)d.nb1 * d.nb2;
+  require(nb <= 65535, IGA_EINVAL, "gemm: batch too large");
+  dim3 grid((d.N + TN - 1) / TN, (d.M + TM - 1) / TM, (unsigned)nb);
+  gemm_kernel<T><<<grid, NT, 0, s>>>(a);
+  IGA_HIP(hipGetLastError());
+}
+
+template <typename T>
+struct BandArgs {
+  int n, p, b, R0, R1, rev, m, c, G;
+  const T* A;
+  const int* lo;
+  const int* hi;
+  const T* in;
+  T* out;
+  T alpha, beta;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void band_kernel(BandArgs<T> a) {
+  const long total = (long)a.G * a.m * a.n * a.c;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long)gridDim.x * blockDim.x) {
+    long t = idx;
+    const int cc = t % a.c; t /= a.c;
+    const int i = t % a.n; t /= a.n;
+    const int mm = t % a.m;
+    const int g = t / a.m;
+    const int d0 = a.lo[g], d1 = a.hi[g];
+    T acc = T(0);
+    const int olo = max(0, a.p - i), ohi = min(a.b, a.n - i + a.p);
+    for (int d = d0; d < d1; ++d) {
+      const T* inrow = a.in + (((long)d * a.m + mm) * a.n) * a.c + cc;
+      for (int o = olo; o < ohi; ++o) {
+        const int j = i + o - a.p;
+        const T coef = a.rev ? a.A[(((long)g * a.n + i) * a.b + o) * a.R1 + d]
+                             : a.A[(((long)d * a.n + i) * a.b + o) * a.R1 + g];
+        acc = fma(coef, inrow[(long)j * a.c], acc);
+      }
+    }
+    T v = a.alpha * acc;
+    if (a.beta != T(0)) v += a.beta * a.out[idx];
+    a.out[idx] = v;
+  }
+}
+
+template <typename T, typename D>
+void launch_band(hipStream_t s, const D& d, T alpha, T beta) {
+  const int G = d.rev ? d.R0 : d.R1;
+  BandArgs<T> a{d.n, d.p, 2 * d.p + 1, d.R0, d.R1, d.rev ? 1 : 0, d.m, d.c, G,
+                d.A, d.lo, d.hi, d.in, d.out, alpha, beta};
+  const long total = (long)G * d.m * d.n * d.c;
+  if (total <= 0) return;
+  const long blocks = std::min<long>((total + 255) / 256, 1L << 20);
+  band_kernel<T><<<(unsigned)blocks, 256, 0, s>>>(a);
+  IGA_HIP(hipGetLastError());
+}
+
+__global__ void axpby_kernel(long n, double a, const double* x, double b, double* y) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    y[i] = (b == 0.0) ? a * x[i] : a * x[i] + b * y[i];
+}
+__global__ void fill_kernel(long n, double v, double* y) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    y[i] = v;
+}
+__global__ void scale_kernel(long n, double a, double* y) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    y[i] *= a;
+}
+__global__ void to_f32_kernel(long n, const double* x, float* y) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    y[i] = (float)x[i];
+}
+__global__ void to_f64_kernel(long n, const float* x, double* y) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    y[i] = (double)x[i];
+}
+
+unsigned grid_for(long n) { return (unsigned)std::max<long>(1, std::min<long>((n + 255) / 256, 4096)); }
+
+struct Perm4 {
+  int od[4];   // output dims
+  long is[4];  // input stride of output axis k
+};
+__global__ void permute4_kernel(const double* in, double* out, Perm4 P, long total) {
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long)gridDim.x * blockDim.x) {
+    long t = idx;
+    long off = 0;
+#pragma unroll
+    for (int k = 3; k >= 0; --k) {
+      const int ik = t % P.od[k];
+      t /= P.od[k];
+      off += ik * P.is[k];
+    }
+    out[idx] = in[off];
+  }
+}
+
+constexpr int RED_BLOCKS = 512;
+
+__device__ double block_sum(double v) {
+  __shared__ double sh[256];
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(256) void dot_partial(long n, const double* x, const double* y,
+                                                   double* partial) {
+  double acc = 0.0;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    acc = fma(x[i], y[i], acc);
+  const double s = block_sum(acc);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+__global__ __launch_bounds__(256) void sum_partials(int np, int nrow, const double* partial,
+                                                    double* out) {
+  // one block per output row, fixed order
+  const int row = blockIdx.x;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) acc += partial[(long)row * np + i];
+  const double s = block_sum(acc);
+  if (threadIdx.x == 0 && row < nrow) out[row] = s;
+}
+
+constexpr int MD_CHUNKS = 128;
+__global__ __launch_bounds__(256) void multidot_partial(long n, const double* V, long ldv,
+                                                        const double* w, double* partial) {
+  const int j = blockIdx.y;
+  const double* v = V + j * ldv;
+  double acc = 0.0;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    acc = fma(v[i], w[i], acc);
+  const double s = block_sum(acc);
+  if (threadIdx.x == 0) partial[(long)j * gridDim.x + blockIdx.x] = s;
+}
+__global__ __launch_bounds__(256) void multiaxpy_kernel(long n, int k, const double* V, long ldv,
+                                                        const double* coef, double sign, double* w) {
+  __shared__ double c[64];
+  if ((int)threadIdx.x < k) c[threadIdx.x] = sign * coef[threadIdx.x];
+  __syncthreads();
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    double acc = w[i];
+    for (int j = 0; j < k; ++j) acc = fma(c[j], V[j * ldv + i], acc);
+    w[i] = acc;
+  }
+}
+__global__ __launch_bounds__(256) void colnorm_kernel(int m, int k, const double* A, long lda,
+                                                      double* out) {
+  const int j = blockIdx.x;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    const double v = A[(long)i * lda + j];
+    acc = fma(v, v, acc);
+  }
+  const double s = block_sum(acc);
+  if (threadIdx.x == 0) out[j] = sqrt(s);
+}
+
+__global__ void kkt_combine_kernel(long e, double beta, const double* zM, const double* zK,
+                                   double* y) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < e; i += (long)gridDim.x * blockDim.x) {
+    const double m0 = zM[i], m1 = zM[e + i], m2 = zM[2 * e + i];
+    const double k0 = zK[i], k2 = zK[e + i];
+    y[i] = m0 + k2;
+    y[e + i] = beta * m1 - m2;
+    y[2 * e + i] = k0 - m1;
+  }
+}
+
+__global__ void kkt_combine_f32_kernel(long e, float beta, const float* zM, const float* zK, float* y) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < e; i += (long)gridDim.x * blockDim.x) {
+    const float m0 = zM[i], m1 = zM[e + i], m2 = zM[2 * e + i];
+    const float k0 = zK[i], k2 = zK[e + i];
+    y[i] = m0 + k2;
+    y[e + i] = beta * m1 - m2;
+    y[2 * e + i] = k0 - m1;
+  }
+}
+
+__global__ void core_product_kernel(int R0, int R1, int n, int p, const double* A, int r0, int r1,
+                                    const double* X, double* Y, double alpha, double beta) {
+  const int b = 2 * p + 1;
+  const long total = (long)R0 * r0 * n * R1 * r1;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long)gridDim.x * blockDim.x) {
+    long t = idx;
+    const int bb = t % r1; t /= r1;
+    const int be = t % R1; t /= R1;
+    const int i = t % n; t /= n;
+    const int a = t % r0;
+    const int al = t / r0;
+    double acc = 0.0;
+    const int olo = max(0, p - i), ohi = min(b, n - i + p);
+    for (int o = olo; o < ohi; ++o) {
+      const int j = i + o - p;
+      acc = fma(A[(((long)al * n + i) * b + o) * R1 + be], X[((long)a * n + j) * r1 + bb], acc);
+    }
+    double v = alpha * acc;
+    if (beta != 0.0) v += beta * Y[idx];
+    Y[idx] = v;
+  }
+}
+
+__global__ void copy2d_kernel(int m, int k, const double* in, long si, long sj, double* out, long ldo) {
+  const long total = (long)m * k;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const int i = e / k, j = e % k;
+    out[(long)i * ldo + j] = in[(long)i * si + (long)j * sj];
+  }
+}
+
+__global__ void diag_kernel(int k, const double* H, double* out, int mode) {
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < k; j += gridDim.x * blockDim.x) {
+    const double v = H[(long)j * k + j];
+    out[j] = mode ? (v > 0.0 ? 1.0 / sqrt(v) : 0.0) : v;
+  }
+}
+
+}  // namespace
+
+void kkt_combine(hipStream_t s, long e, double beta, const double* zM, const double* zK, double* y) {
+  if (e <= 0) return;
+  kkt_combine_kernel<<<grid_for(e), 256, 0, s>>>(e, beta, zM, zK, y);
+  IGA_HIP(hipGetLastError());
+}
+
+void kkt_combine_f32(hipStream_t s, long e, float beta, const float* zM, const float* zK, float* y) {
+  if (e <= 0) return;
+  kkt_combine_f32_kernel<<<grid_for(e), 256, 0, s>>>(e, beta, zM, zK, y);
+  IGA_HIP(hipGetLastError());
+}
+
+void core_product(hipStream_t s, int R0, int R1, int n, int p, const double* A, int r0, int r1,
+                  const double* X, double* Y, double alpha, double beta) {
+  const long total = (long)R0 * r0 * n * R1 * r1;
+  if (total <= 0) return;
+  core_product_kernel<<<grid_for(total), 256, 0, s>>>(R0, R1, n, p, A, r0, r1, X, Y, alpha, beta);
+  IGA_HIP(hipGetLastError());
+}
+
+void copy2d(hipStream_t s, int m, int k, const double* in, long si, long sj, double* out, long ldo) {
+  const long total = (long)m * k;
+  if (total <= 0) return;
+  copy2d_kernel<<<grid_for(total), 256, 0, s>>>(m, k, in, si, sj, out, ldo);
+  IGA_HIP(hipGetLastError());
+}
+
+void diag_invsqrt(hipStream_t s, int k, const double* H, double* out) {
+  diag_kernel<<<(k + 255) / 256, 256, 0, s>>>(k, H, out, 1);
+  IGA_HIP(hipGetLastError());
+}
+void diag_get(hipStream_t s, int k, const double* H, double* out) {
+  diag_kernel<<<(k + 255) / 256, 256, 0, s>>>(k, H, out, 0);
+  IGA_HIP(hipGetLastError());
+}
+
+void gemm(hipStream_t s, const Gemm& g) { launch_gemm<double>(s, g); }
+void gemm_f32(hipStream_t s, const GemmF& g) { launch_gemm<float>(s, g); }
+
+void gemm_rm(hipStream_t s, int M, int N, int K, const double* A, long lda, bool tA,
+             const double* B, long ldb, bool tB, double* C, long ldc, double alpha, double beta) {
+  Gemm g;
+  g.M = M; g.N = N; g.K = K;
+  g.A = A; g.sAm = tA ? 1 : lda; g.sAk = tA ? lda : 1;
+  g.B = B; g.sBk = tB ? 1 : ldb; g.sBn = tB ? ldb : 1;
+  g.C = C; g.sCm = ldc; g.sCn = 1;
+  g.alpha = alpha; g.beta = beta;
+  gemm(s, g);
+}
+
+void band(hipStream_t s, const Band& b) { launch_band<double>(s, b, b.alpha, b.beta); }
+void band_f32(hipStream_t s, const BandF& b) { launch_band<float>(s, b, 1.0f, 0.0f); }
+
+void axpby(hipStream_t s, long n, double a, const double* x, double b, double* y) {
+  if (n <= 0) return;
+  axpby_kernel<<<grid_for(n), 256, 0, s>>>(n, a, x, b, y);
+  IGA_HIP(hipGetLastError());
+}
+void fill(hipStream_t s, long n, double v, double* y) {
+  if (n <= 0) return;
+  fill_kernel<<<grid_for(n), 256, 0, s>>>(n, v, y);
+  IGA_HIP(hipGetLastError());
+}
+void scale(hipStream_t s, long n, double a, double* y) {
+  if (n <= 0) return;
+  scale_kernel<<<grid_for(n), 256, 0, s>>>(n, a, y);
+  IGA_HIP(hipGetLastError());
+}
+void to_f32(hipStream_t s, long n, const double* x, float* y) {
+  if (n <= 0) return;
+  to_f32_kernel<<<grid_for(n), 256, 0, s>>>(n, x, y);
+  IGA_HIP(hipGetLastError());
+}
+void to_f64(hipStream_t s, long n, const float* x, double* y) {
+  if (n <= 0) return;
+  to_f64_kernel<<<grid_for(n), 256, 0, s>>>(n, x, y);
+  IGA_HIP(hipGetLastError());
+}
+
+void permute4(hipStream_t s, const double* in, const int dims[4], const int perm[4], double* out) {
+  Perm4 P;
+  long stride[4];
+  stride[3] = 1;
+  for (int k = 2; k >= 0; --k) stride[k] = stride[k + 1] * dims[k + 1];
+  long total = 1;
+  for (int k = 0; k < 4; ++k) {
+    P.od[k] = dims[perm[k]];
+    P.is[k] = stride[perm[k]];
+    total *= dims[k];
+  }
+  if (total <= 0) return;
+  permute4_kernel<<<grid_for(total), 256, 0, s>>>(in, out, P, total);
+  IGA_HIP(hipGetLastError());
+}
+
+int reduce_partials() { return RED_BLOCKS; }
+
+void dot(hipStream_t s, long n, const double* x, const double* y, double* partial, double* out) {
+  dot_partial<<<RED_BLOCKS, 256, 0, s>>>(n, x, y, partial);
+  sum_partials<<<1, 256, 0, s>>>(RED_BLOCKS, 1, partial, out);
+  IGA_HIP(hipGetLastError());
+}
+
+void multidot(hipStream_t s, long n, int k, const double* V, long ldv, const double* w,
+              double* partial, double* h) {
+  if (k <= 0) return;
+  require(k <= 64, IGA_EINVAL, "multidot: k > 64");
+  multidot_partial<<<dim3(MD_CHUNKS, k), 256, 0, s>>>(n, V, ldv, w, partial);
+  sum_partials<<<k, 256, 0, s>>>(MD_CHUNKS, k, partial, h);
+  IGA_HIP(hipGetLastError());
+}
+
+void multiaxpy(hipStream_t s, long n, int k, const double* V, long ldv, const double* coef,
+               double sign, double* w) {
+  if (k <= 0) return;
+  require(k <= 64, IGA_EINVAL, "multiaxpy: k > 64");
+  multiaxpy_kernel<<<grid_for(n), 256, 0, s>>>(n, k, V, ldv, coef, sign, w);
+  IGA_HIP(hipGetLastError());
+}
+
+void colnorms(hipStream_t s, int m, int k, const double* A, long lda, double* out) {
+  if (k <= 0) return;
+  colnorm_kernel<<<k, 256, 0, s>>>(m, k, A, lda, out);
+  IGA_HIP(hipGetLastError());
+}
+
+}  // namespace k
+}  // namespace iga

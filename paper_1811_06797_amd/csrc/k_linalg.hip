@@ -1,0 +1,258 @@
+// Small dense linear algebra in one workgroup: cyclic Jacobi eigen-decomposition
+// of symmetric matrices, Gauss-Jordan inverse, column gathers and block copies.
+#include <algorithm>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace iga {
+namespace k {
+namespace {
+
+constexpr int JT = 512;        // threads per Jacobi workgroup
+constexpr int LDS_MAX_K = 120; // H kept in LDS up to this size ((k+1)*k*8 bytes)
+
+// Parallel cyclic Jacobi with round-robin pairing (circle method): in every
+// round the k/2 disjoint pairs (p, q) are rotated at once; H <- J^T H J by a
+// row pass then a column pass, and the eigenvectors are accumulated as rows of
+// WT (WT <- J^T WT, i.e. W <- W J). A rotation is skipped when
+// |h_pq| <= max(tol * sqrt(|h_pp h_qq|), floor_rel * trace).
+template <bool USE_LDS>
+__global__ __launch_bounds__(JT) void jacobi_kernel(int k, double* Hs, long sH, double* WTs,
+                                                    long sW, double tol, int max_sweeps,
+                                                    int* sweeps_out) {
+  extern __shared__ double lds[];
+  double* Hg = Hs + blockIdx.x * sH;
+  double* WT = WTs + blockIdx.x * sW;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int ld = USE_LDS ? k + 1 : k;
+  double* H = USE_LDS ? lds : Hg;
+  if (USE_LDS)
+    for (int e = tid; e < k * k; e += nt) H[(e / k) * ld + e % k] = Hg[e];
+  for (int e = tid; e < k * k; e += nt) WT[e] = (e / k == e % k) ? 1.0 : 0.0;
+  __shared__ double cs[JT / 2], sn[JT / 2];
+  __shared__ int pp[JT / 2], qq[JT / 2];
+  __shared__ int rotated;
+  __shared__ double trace;
+  __syncthreads();
+  if (tid == 0) {
+    double t = 0.0;
+    for (int i = 0; i < k; ++i) t += fabs(H[i * ld + i]);
+    trace = t;
+  }
+  __syncthreads();
+  const double floor_abs = 1e-30 * trace;
+  const int kk = k + (k & 1);
+  const int npair = kk / 2;
+  int sweeps = 0;
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    if (tid == 0) rotated = 0;
+    __syncthreads();
+    for (int round = 0; round < kk - 1; ++round) {
+      for (int t = tid; t < npair; t += nt) {
+        // circle method: position 0 fixed, positions 1..kk-1 rotate
+        auto player = [&](int pos) { return pos == 0 ? 0 : 1 + (pos - 1 + round) % (kk - 1); };
+        int p = player(t), q = player(kk - 1 - t);
+        if (p > q) { int tmp = p; p = q; q = tmp; }
+        double c = 1.0, s = 0.0;
+        if (q < k) {
+          const double app = H[p * ld + p], aqq = H[q * ld + q], apq = H[p * ld + q];
+          const double thr = fmax(tol * sqrt(fabs(app * aqq)), floor_abs);
+          if (fabs(apq) > thr) {
+            const double tau = (aqq - app) / (2.0 * apq);
+            const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + tt * tt);
+            s = tt * c;
+            rotated = 1;
+          }
+        }
+        pp[t] = p; qq[t] = q; cs[t] = c; sn[t] = s;
+      }
+      __syncthreads();
+      // rows p, q of H and WT
+      for (int e = tid; e < npair * k; e += nt) {
+        const int t = e / k, j = e - t * k;
+        const double s = sn[t];
+        if (s == 0.0) continue;
+        const double c = cs[t];
+        const int p = pp[t], q = qq[t];
+        const double hp = H[p * ld + j], hq = H[q * ld + j];
+        H[p * ld + j] = c * hp - s * hq;
+        H[q * ld + j] = s * hp + c * hq;
+        const double wp = WT[p * k + j], wq = WT[q * k + j];
+        WT[p * k + j] = c * wp - s * wq;
+        WT[q * k + j] = s * wp + c * wq;
+      }
+      __syncthreads();
+      // columns p, q of H
+      for (int e = tid; e < npair * k; e += nt) {
+        const int t = e / k, i = e - t * k;
+        const double s = sn[t];
+        if (s == 0.0) continue;
+        const double c = cs[t];
+        const int p = pp[t], q = qq[t];
+        const double hp = H[i * ld + p], hq = H[i * ld + q];
+        H[i * ld + p] = c * hp - s * hq;
+        H[i * ld + q] = s * hp + c * hq;
+      }
+      __syncthreads();
+    }
+    if (!rotated) break;
+    ++sweeps;
+    __syncthreads();
+  }
+  if (USE_LDS)
+    for (int e = tid; e < k * k; e += nt) Hg[e] = H[(e / k) * ld + e % k];
+  if (tid == 0 && sweeps_out) sweeps_out[blockIdx.x] = sweeps;
+}
+
+__global__ void transpose_sq(int k, const double* in, long sin, double* out, long sout) {
+  const double* a = in + blockIdx.y * sin;
+  double* b = out + blockIdx.y * sout;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < (long)k * k;
+       e += (long)gridDim.x * blockDim.x) {
+    const int i = e / k, j = e % k;
+    b[(long)j * k + i] = a[e];
+  }
+}
+
+__global__ __launch_bounds__(1024) void gauss_jordan(int k, const double* A, double* Ainv,
+                                                     double* work, int* singular) {
+  // work: [k][2k] augmented matrix
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int w = 2 * k;
+  for (int e = tid; e < k * w; e += nt) {
+    const int i = e / w, j = e % w;
+    work[e] = (j < k) ? A[i * k + j] : ((j - k == i) ? 1.0 : 0.0);
+  }
+  __shared__ double best[1024];
+  __shared__ int besti[1024];
+  __shared__ int piv;
+  if (tid == 0) *singular = 0;
+  __syncthreads();
+  for (int c = 0; c < k; ++c) {
+    double bv = -1.0;
+    int bi = c;
+    for (int r = c + tid; r < k; r += nt) {
+      const double v = fabs(work[r * w + c]);
+      if (v > bv) { bv = v; bi = r; }
+    }
+    best[tid] = bv; besti[tid] = bi;
+    __syncthreads();
+    for (int s = nt / 2; s > 0; s >>= 1) {
+      if (tid < s && (best[tid + s] > best[tid] ||
+                      (best[tid + s] == best[tid] && besti[tid + s] < besti[tid]))) {
+        best[tid] = best[tid + s]; besti[tid] = besti[tid + s];
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      piv = besti[0];
+      if (best[0] == 0.0) *singular = 1;
+    }
+    __syncthreads();
+    const int pr = piv;
+    if (pr != c)
+      for (int j = tid; j < w; j += nt) {
+        const double t = work[c * w + j];
+        work[c * w + j] = work[pr * w + j];
+        work[pr * w + j] = t;
+      }
+    __syncthreads();
+    const double d = work[c * w + c];
+    const double inv = d != 0.0 ? 1.0 / d : 0.0;
+    __syncthreads();
+    for (int j = tid; j < w; j += nt) work[c * w + j] *= inv;
+    __syncthreads();
+    for (int e = tid; e < k * w; e += nt) {
+      const int i = e / w, j = e % w;
+      if (i == c || j == c) continue;
+      work[e] -= work[i * w + c] * work[c * w + j];
+    }
+    __syncthreads();
+    for (int i = tid; i < k; i += nt)
+      if (i != c) work[i * w + c] = 0.0;
+    __syncthreads();
+  }
+  for (int e = tid; e < k * k; e += nt) Ainv[e] = work[(e / k) * w + k + e % k];
+}
+
+__global__ void gather_cols_kernel(int m, int kin, int kout, const double* in, long ldi,
+                                   const int* idx, const double* scale, double* out, long ldo) {
+  const long total = (long)m * kout;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x) {
+    const int i = e / kout, j = e % kout;
+    double v = in[(long)i * ldi + idx[j]];
+    if (scale) v *= scale[j];
+    out[(long)i * ldo + j] = v;
+  }
+}
+
+__global__ void place_block_kernel(int na, int nb, int inner, const double* src, double* dst,
+                                   int R1dst, int a0, int b0) {
+  // src [na][inner][nb] -> dst [..][inner][R1dst] at (a0 + a, ., b0 + b)
+  const long total = (long)na * inner * nb;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x) {
+    const int b = e % nb;
+    const long t = e / nb;
+    const int x = t % inner;
+    const int a = t / inner;
+    dst[((long)(a0 + a) * inner + x) * R1dst + b0 + b] = src[e];
+  }
+}
+
+}  // namespace
+
+void jacobi_eig(hipStream_t s, int nmat, int k, double* H, long strideH, double* W, long strideW,
+                double tol, int max_sweeps, int* sweeps_out) {
+  require(k >= 1 && k <= 1024, IGA_EINVAL, "jacobi_eig: k out of range");
+  if (k <= LDS_MAX_K) {
+    const size_t lds = (size_t)(k + 1) * k * sizeof(double);
+    static bool attr_set = false;
+    if (!attr_set) {
+      IGA_HIP(hipFuncSetAttribute((const void*)jacobi_kernel<true>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (LDS_MAX_K + 1) * LDS_MAX_K * (int)sizeof(double)));
+      attr_set = true;
+    }
+    jacobi_kernel<true><<<nmat, JT, lds, s>>>(k, H, strideH, W, strideW, tol, max_sweeps, sweeps_out);
+  } else {
+    jacobi_kernel<false><<<nmat, JT, 0, s>>>(k, H, strideH, W, strideW, tol, max_sweeps, sweeps_out);
+  }
+  IGA_HIP(hipGetLastError());
+}
+
+void transpose_square(hipStream_t s, int nmat, int k, const double* in, long sin, double* out,
+                      long sout) {
+  dim3 grid((unsigned)std::max<long>(1, std::min<long>(((long)k * k + 255) / 256, 1024)), nmat);
+  transpose_sq<<<grid, 256, 0, s>>>(k, in, sin, out, sout);
+  IGA_HIP(hipGetLastError());
+}
+
+void invert(hipStream_t s, int k, const double* A, double* Ainv, double* work, int* singular) {
+  gauss_jordan<<<1, 1024, 0, s>>>(k, A, Ainv, work, singular);
+  IGA_HIP(hipGetLastError());
+}
+
+void gather_cols(hipStream_t s, int m, int kin, int kout, const double* in, long ldi, const int* idx,
+                 const double* scale, double* out, long ldo) {
+  const long total = (long)m * kout;
+  if (total <= 0) return;
+  gather_cols_kernel<<<(unsigned)std::min<long>((total + 255) / 256, 4096), 256, 0, s>>>(
+      m, kin, kout, in, ldi, idx, scale, out, ldo);
+  IGA_HIP(hipGetLastError());
+}
+
+void place_block(hipStream_t s, int na, int nb, int inner, const double* src, double* dst, int R1dst,
+                 int a0, int b0) {
+  const long total = (long)na * inner * nb;
+  if (total <= 0) return;
+  place_block_kernel<<<(unsigned)std::min<long>((total + 255) / 256, 4096), 256, 0, s>>>(
+      na, nb, inner, src, dst, R1dst, a0, b0);
+  IGA_HIP(hipGetLastError());
+}
+
+}  // namespace k
+}  // namespace iga

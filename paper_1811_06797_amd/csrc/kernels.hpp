@@ -1,0 +1,146 @@
+// Launchers of the HIP kernels (gfx950). All are asynchronous on the given stream.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace iga {
+namespace k {
+
+// C[b][m][n] = alpha * sum_{ko<Kout, k<K} A[b][m][ko,k] B[b][ko,k][n] + beta * C[b][m][n]
+// with arbitrary element strides; batch index b = b1 * nb2 + b2.
+struct Gemm {
+  int M = 0, N = 0, K = 0, Kout = 1;
+  const double* A = nullptr;
+  long sAm = 0, sAk = 0, sAko = 0;
+  const double* B = nullptr;
+  long sBk = 0, sBn = 0, sBko = 0;
+  double* C = nullptr;
+  long sCm = 0, sCn = 0;
+  int nb1 = 1, nb2 = 1;
+  long sAb1 = 0, sAb2 = 0, sBb1 = 0, sBb2 = 0, sCb1 = 0, sCb2 = 0;
+  double alpha = 1.0, beta = 0.0;
+};
+void gemm(hipStream_t s, const Gemm& g);
+
+// Row-major convenience: C (MxN, ldc) = alpha op(A) op(B) + beta C, op = transpose if t*.
+void gemm_rm(hipStream_t s, int M, int N, int K, const double* A, long lda, bool tA,
+             const double* B, long ldb, bool tB, double* C, long ldc, double alpha = 1.0,
+             double beta = 0.0);
+
+// Banded rank contraction of a TT-matrix core with a 4-way tensor:
+//   out[g][m][i][c] = alpha * sum_{d in [lo[g],hi[g])} sum_o A(d,i,o,g) in[d][m][i+o-p][c] + beta*out
+// A banded [R0][n][2p+1][R1]; rev=false: d runs over R0 and g over R1; rev=true: the converse.
+struct Band {
+  int n = 0, p = 0, R0 = 0, R1 = 0;
+  bool rev = false;
+  int m = 0, c = 0;
+  const double* A = nullptr;
+  const int* lo = nullptr;
+  const int* hi = nullptr;
+  const double* in = nullptr;
+  double* out = nullptr;
+  double alpha = 1.0, beta = 0.0;
+};
+void band(hipStream_t s, const Band& b);
+
+// Same contraction in FP32 (mixed-precision form).
+struct BandF {
+  int n = 0, p = 0, R0 = 0, R1 = 0;
+  bool rev = false;
+  int m = 0, c = 0;
+  const float* A = nullptr;
+  const int* lo = nullptr;
+  const int* hi = nullptr;
+  const float* in = nullptr;
+  float* out = nullptr;
+};
+void band_f32(hipStream_t s, const BandF& b);
+
+struct GemmF {
+  int M = 0, N = 0, K = 0, Kout = 1;
+  const float* A = nullptr;
+  long sAm = 0, sAk = 0, sAko = 0;
+  const float* B = nullptr;
+  long sBk = 0, sBn = 0, sBko = 0;
+  float* C = nullptr;
+  long sCm = 0, sCn = 0;
+  int nb1 = 1, nb2 = 1;
+  long sAb1 = 0, sAb2 = 0, sBb1 = 0, sBb2 = 0, sCb1 = 0, sCb2 = 0;
+  float alpha = 1.0f, beta = 0.0f;
+};
+void gemm_f32(hipStream_t s, const GemmF& g);
+
+// y = a x + b y (n doubles)
+void axpby(hipStream_t s, long n, double a, const double* x, double b, double* y);
+void fill(hipStream_t s, long n, double v, double* y);
+void scale(hipStream_t s, long n, double a, double* y);
+void to_f32(hipStream_t s, long n, const double* x, float* y);
+void to_f64(hipStream_t s, long n, const float* x, double* y);
+// out[o0][o1][o2][o3] = in[...] with out dims = in dims permuted: out axis k is in axis perm[k]
+void permute4(hipStream_t s, const double* in, const int dims[4], const int perm[4], double* out);
+
+// Deterministic reductions into device scalars (two passes, fixed order).
+// partial must hold at least reduce_partials() doubles.
+int reduce_partials();
+void dot(hipStream_t s, long n, const double* x, const double* y, double* partial, double* out);
+// h[j] = sum_i V[j*ldv + i] w[i], j < k (k <= 64); partial holds reduce_partials()*64 doubles
+void multidot(hipStream_t s, long n, int k, const double* V, long ldv, const double* w,
+              double* partial, double* h);
+// w[i] += sum_j coef[j] V[j*ldv + i]   (coef on device, k <= 64)
+void multiaxpy(hipStream_t s, long n, int k, const double* V, long ldv, const double* coef,
+               double sign, double* w);
+// column norms of a row-major m x k matrix: out[j] = sqrt(sum_i A[i][j]^2)
+void colnorms(hipStream_t s, int m, int k, const double* A, long lda, double* out);
+
+// KKT block combination of the five operator applications of a local matvec:
+// y0 = zM0 + zK1, y1 = beta zM1 - zM2, y2 = zK0 - zM1 (zM [3][e], zK [2][e], y [3][e]).
+void kkt_combine(hipStream_t s, long e, double beta, const double* zM, const double* zK, double* y);
+void kkt_combine_f32(hipStream_t s, long e, float beta, const float* zM, const float* zK, float* y);
+// Y[(al a)][i][(be b)] = alpha sum_o A[al][i][o][be] X[a][i+o-p][b] + beta Y (banded A [R0][n][2p+1][R1])
+void core_product(hipStream_t s, int R0, int R1, int n, int p, const double* A, int r0, int r1,
+                  const double* X, double* Y, double alpha, double beta);
+// out[i][j] = in[i*si + j*sj], i < m, j < k (out row-major, ldo)
+void copy2d(hipStream_t s, int m, int k, const double* in, long si, long sj, double* out, long ldo);
+// out[j] = 1/sqrt(H[j][j]) (0 if H[j][j] <= 0)
+void diag_invsqrt(hipStream_t s, int k, const double* H, double* out);
+// out[j] = H[j][j]
+void diag_get(hipStream_t s, int k, const double* H, double* out);
+
+// Symmetric Jacobi eigen-decomposition, one workgroup per matrix, nmat matrices of size k
+// (k <= 1024): H (in: symmetric, out: diagonal holds the eigenvalues), WT (out: row i is
+// the i-th eigenvector, H_in = WT^T diag WT). Rotations are skipped when
+// |h_pq| <= max(tol * sqrt(|h_pp h_qq|), 1e-30 trace). sweeps_out[mat] (nullable) counts
+// the sweeps that rotated anything (0: H was already diagonal to that tolerance).
+void jacobi_eig(hipStream_t s, int nmat, int k, double* H, long strideH, double* WT, long strideW,
+                double tol, int max_sweeps, int* sweeps_out);
+void transpose_square(hipStream_t s, int nmat, int k, const double* in, long sin, double* out,
+                      long sout);
+// out[i][j] = in[i][idx[j]] * (scale ? scale[j] : 1), i < m, j < kout
+void gather_cols(hipStream_t s, int m, int kin, int kout, const double* in, long ldi, const int* idx,
+                 const double* scale, double* out, long ldo);
+// src [na][inner][nb] -> dst [R0dst][inner][R1dst] at rank offsets (a0, b0)
+void place_block(hipStream_t s, int na, int nb, int inner, const double* src, double* dst, int R1dst,
+                 int a0, int b0);
+
+// Inverse of a dense k x k matrix (row-major) by Gauss-Jordan with partial pivoting,
+// one workgroup; work holds 2*k*k doubles. Sets *singular if a pivot is exactly zero.
+void invert(hipStream_t s, int k, const double* A, double* Ainv, double* work, int* singular);
+
+// ---- assembly ----
+// Values (deriv=0) or first derivatives (deriv=1) of all B-splines of an open knot
+// vector at the given points: out[np][nknots-deg-1].
+void bspline_tabulate(hipStream_t s, const double* knots, int nknots, int deg, const double* pts,
+                      int np, int deriv, double* out);
+// omega, q11, q12, q13, q22, q23, q33 on a tensor grid from the geometry:
+// Bv_d/Bd_d: basis values/derivatives [np_d][ncp_d]; ctrl [3][ncp0][ncp1][ncp2];
+// out [7][np0][np1][np2]; *bad counts points with det <= 0.
+void geometry_weights(hipStream_t s, const int np[3], const int ncp[3], const double* const Bv[3],
+                      const double* const Bd[3], const double* ctrl, double* out, int* bad);
+// Univariate factor quadrature (eqs. massMatrix1D and the D^2 stiffness factors):
+//   out[s][i][o] = sum_q w[q] Bi(q, i+1) Bj(q, j+1) E[s][q], j = i + o - p, interior i, j only,
+// Bi/Bj: dense tables [Q][N] of values or derivatives, Q = nel*nq points (element-major).
+void factor_quadrature(hipStream_t s, int S, int n, int p, int nel, int nq, const double* Bi,
+                       const double* Bj, const double* w, const double* E, double* out);
+
+}  // namespace k
+}  // namespace iga

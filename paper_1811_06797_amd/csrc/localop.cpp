@@ -1,0 +1,177 @@
+// Projected local KKT operator (see localop.hpp) and the raw-buffer entry point.
+#include "localop.hpp"
+
+#include <algorithm>
+#include <memory>
+#include <unordered_map>
+#include <vector>
+
+#include "kernels.hpp"
+
+namespace iga {
+
+double band_nnz(int n, int p) {
+  double s = 0;
+  for (int i = 0; i < n; ++i) s += std::min(n - 1, i + p) - std::max(0, i - p) + 1;
+  return s;
+}
+
+static double op_flops(const OpView& A, int r0, int r1, int ncol, double nnz_band) {
+  // stage 1: 2 r0^2 R0 n r1; stage 2: 2 r0 r1 (nonzero R0 x R1) nnz_band; stage 3: 2 r0 n R1 r1^2
+  const double nz_blocks = A.flops_dense_factor * double(A.R0) * A.R1;
+  return ncol * (2.0 * r0 * r0 * A.R0 * A.n * r1 + 2.0 * r0 * r1 * nz_blocks * nnz_band +
+                 2.0 * r0 * A.n * A.R1 * (double)r1 * r1);
+}
+
+double local_flops(const LocalOp& L) {
+  const double nb = band_nnz(L.n, L.M.p);
+  return op_flops(L.M, L.r0, L.r1, 3, nb) + op_flops(L.K, L.r0, L.r1, 2, nb);
+}
+
+static void stage3_all(iga_ctx* ctx, const OpView& A, const double* t2, int ncol, const double* PhiR,
+                       int ra_out, int rb_out, int rb_in, double* y, long ycs) {
+  const long colsz = (long)ra_out * A.n * rb_in;
+  k::Gemm g;
+  g.M = ra_out * A.n; g.N = rb_out; g.K = rb_in; g.Kout = A.R1;
+  g.A = t2; g.sAm = rb_in; g.sAk = 1; g.sAko = ncol * colsz;
+  g.B = PhiR; g.sBk = 1; g.sBn = rb_in; g.sBko = (long)rb_out * rb_in;
+  g.C = y; g.sCm = rb_out; g.sCn = 1;
+  g.nb1 = ncol; g.sAb1 = colsz; g.sCb1 = ycs;
+  k::gemm(ctx->stream, g);
+}
+
+void local_matvec(iga_ctx* ctx, const LocalOp& L, const double* x, double* y, LocalWork& w) {
+  const long colsz = (long)L.r0 * L.n * L.r1;
+  w.tM.ensure(ctx, (size_t)L.M.R1 * 3 * colsz);
+  w.tK.ensure(ctx, (size_t)L.K.R1 * 2 * colsz);
+  w.z.ensure(ctx, (size_t)5 * colsz);
+  local_stage12(ctx, L.M, L.PhiL_M, L.r0, L.r0, L.r1, 3, x, colsz, w.tM.get());
+  stage3_all(ctx, L.M, w.tM.get(), 3, L.PhiR_M, L.r0, L.r1, L.r1, w.z.get(), colsz);
+  local_stage12(ctx, L.K, L.PhiL_K, L.r0, L.r0, L.r1, 2, x, 2 * colsz, w.tK.get());
+  stage3_all(ctx, L.K, w.tK.get(), 2, L.PhiR_K, L.r0, L.r1, L.r1, w.z.get() + 3 * colsz, colsz);
+  k::kkt_combine(ctx->stream, colsz, L.beta, w.z.get(), w.z.get() + 3 * colsz, y);
+}
+
+static void apply_f32(iga_ctx* ctx, const OpView& A, const float* PhiL, const float* PhiR, int r0, int r1,
+                      int ncol, const float* x, long xcs, float* t2, float* t1, float* out, long ocs) {
+  const int n = A.n;
+  const long colsz = (long)r0 * n * r1;
+  k::GemmF g;
+  g.M = r0; g.N = n * r1; g.K = r0;
+  g.A = PhiL; g.sAm = r0; g.sAk = 1;
+  g.B = x; g.sBk = (long)n * r1; g.sBn = 1;
+  g.C = t1; g.sCm = (long)n * r1; g.sCn = 1;
+  g.nb1 = A.R0; g.nb2 = ncol;
+  g.sAb1 = (long)r0 * r0; g.sBb2 = xcs;
+  g.sCb1 = ncol * colsz; g.sCb2 = colsz;
+  k::gemm_f32(ctx->stream, g);
+  k::BandF b;
+  b.n = n; b.p = A.p; b.R0 = A.R0; b.R1 = A.R1; b.rev = false;
+  b.m = ncol * r0; b.c = r1;
+  b.A = A.Af; b.lo = A.lo_R1; b.hi = A.hi_R1;
+  b.in = t1; b.out = t2;
+  k::band_f32(ctx->stream, b);
+  k::GemmF h;
+  h.M = r0 * n; h.N = r1; h.K = r1; h.Kout = A.R1;
+  h.A = t2; h.sAm = r1; h.sAk = 1; h.sAko = ncol * colsz;
+  h.B = PhiR; h.sBk = 1; h.sBn = r1; h.sBko = (long)r1 * r1;
+  h.C = out; h.sCm = r1; h.sCn = 1;
+  h.nb1 = ncol; h.sAb1 = colsz; h.sCb1 = ocs;
+  k::gemm_f32(ctx->stream, h);
+}
+
+void local_matvec_f32(iga_ctx* ctx, const LocalOp& L, const float* x, float* y, LocalWork& w) {
+  const long colsz = (long)L.r0 * L.n * L.r1;
+  w.ftM.ensure(ctx, (size_t)L.M.R1 * 3 * colsz);
+  w.ftK.ensure(ctx, (size_t)L.K.R1 * 2 * colsz);
+  w.ft1.ensure(ctx, (size_t)std::max(L.M.R0 * 3, L.K.R0 * 2) * colsz);
+  w.fz.ensure(ctx, (size_t)5 * colsz);
+  apply_f32(ctx, L.M, L.fPhiL_M, L.fPhiR_M, L.r0, L.r1, 3, x, colsz, w.ftM.get(), w.ft1.get(), w.fz.get(),
+            colsz);
+  apply_f32(ctx, L.K, L.fPhiL_K, L.fPhiR_K, L.r0, L.r1, 2, x, 2 * colsz, w.ftK.get(), w.ft1.get(),
+            w.fz.get() + 3 * colsz, colsz);
+  k::kkt_combine_f32(ctx->stream, colsz, (float)L.beta, w.fz.get(), w.fz.get() + 3 * colsz, y);
+}
+
+// ---- raw-buffer entry point (dense rank blocks) ----
+
+namespace {
+struct RawCache {
+  IBuf loM1, hiM1, loM0, hiM0, loK1, hiK1, loK0, hiK0;
+  int RM0 = -1, RM1 = -1, RK0 = -1, RK1 = -1;
+  LocalWork w;
+  FBuf fPhi[4], fM, fK, fx, fy;
+};
+std::unordered_map<iga_ctx*, std::unique_ptr<RawCache>> g_raw;
+RawCache& raw_cache(iga_ctx* ctx) {
+  auto& p = g_raw[ctx];
+  if (!p) p.reset(new RawCache());
+  return *p;
+}
+void dense_ranges(iga_ctx* ctx, int R0, int R1, IBuf& lo1, IBuf& hi1, IBuf& lo0, IBuf& hi0) {
+  std::vector<int> z1(R1, 0), h1(R1, R0), z0(R0, 0), h0(R0, R1);
+  lo1.reset(ctx, R1); hi1.reset(ctx, R1); lo0.reset(ctx, R0); hi0.reset(ctx, R0);
+  IGA_HIP(hipMemcpyAsync(lo1.get(), z1.data(), R1 * 4, hipMemcpyHostToDevice, ctx->stream));
+  IGA_HIP(hipMemcpyAsync(hi1.get(), h1.data(), R1 * 4, hipMemcpyHostToDevice, ctx->stream));
+  IGA_HIP(hipMemcpyAsync(lo0.get(), z0.data(), R0 * 4, hipMemcpyHostToDevice, ctx->stream));
+  IGA_HIP(hipMemcpyAsync(hi0.get(), h0.data(), R0 * 4, hipMemcpyHostToDevice, ctx->stream));
+  IGA_HIP(hipStreamSynchronize(ctx->stream));
+}
+}  // namespace
+
+void release_raw_cache(iga_ctx* ctx) { g_raw.erase(ctx); }
+
+double local_matvec_flops(int r0, int n, int r1, int p, int RM0, int RM1, int RK0, int RK1) {
+  LocalOp L;
+  L.r0 = r0; L.n = n; L.r1 = r1;
+  L.M.R0 = RM0; L.M.R1 = RM1; L.M.n = n; L.M.p = p;
+  L.K.R0 = RK0; L.K.R1 = RK1; L.K.n = n; L.K.p = p;
+  return local_flops(L);
+}
+
+void local_matvec_impl(iga_ctx* ctx, int r0, int n, int r1, int p, int RM0, int RM1, int RK0, int RK1,
+                       const double* PhiL_M, const double* PhiR_M, const double* PhiL_K,
+                       const double* PhiR_K, const double* Mcore, const double* Kcore, double beta,
+                       const double* x, double* y, int precision) {
+  RawCache& C = raw_cache(ctx);
+  if (C.RM0 != RM0 || C.RM1 != RM1) {
+    dense_ranges(ctx, RM0, RM1, C.loM1, C.hiM1, C.loM0, C.hiM0);
+    C.RM0 = RM0; C.RM1 = RM1;
+  }
+  if (C.RK0 != RK0 || C.RK1 != RK1) {
+    dense_ranges(ctx, RK0, RK1, C.loK1, C.hiK1, C.loK0, C.hiK0);
+    C.RK0 = RK0; C.RK1 = RK1;
+  }
+  LocalOp L;
+  L.r0 = r0; L.n = n; L.r1 = r1; L.beta = beta;
+  L.M.R0 = RM0; L.M.R1 = RM1; L.M.n = n; L.M.p = p; L.M.A = Mcore;
+  L.M.lo_R1 = C.loM1.get(); L.M.hi_R1 = C.hiM1.get(); L.M.lo_R0 = C.loM0.get(); L.M.hi_R0 = C.hiM0.get();
+  L.K.R0 = RK0; L.K.R1 = RK1; L.K.n = n; L.K.p = p; L.K.A = Kcore;
+  L.K.lo_R1 = C.loK1.get(); L.K.hi_R1 = C.hiK1.get(); L.K.lo_R0 = C.loK0.get(); L.K.hi_R0 = C.hiK0.get();
+  L.PhiL_M = PhiL_M; L.PhiR_M = PhiR_M; L.PhiL_K = PhiL_K; L.PhiR_K = PhiR_K;
+  if (precision == IGA_FP64) {
+    local_matvec(ctx, L, x, y, C.w);
+    return;
+  }
+  // FP32: convert every operand, contract in FP32, convert the result back
+  hipStream_t st = ctx->stream;
+  const int b = 2 * p + 1;
+  const long szs[4] = {(long)RM0 * r0 * r0, (long)RM1 * r1 * r1, (long)RK0 * r0 * r0, (long)RK1 * r1 * r1};
+  const double* src[4] = {PhiL_M, PhiR_M, PhiL_K, PhiR_K};
+  for (int i = 0; i < 4; ++i) {
+    C.fPhi[i].ensure(ctx, szs[i]);
+    k::to_f32(st, szs[i], src[i], C.fPhi[i].get());
+  }
+  const long mz = (long)RM0 * n * b * RM1, kz = (long)RK0 * n * b * RK1, xz = L.size();
+  C.fM.ensure(ctx, mz); C.fK.ensure(ctx, kz); C.fx.ensure(ctx, xz); C.fy.ensure(ctx, xz);
+  k::to_f32(st, mz, Mcore, C.fM.get());
+  k::to_f32(st, kz, Kcore, C.fK.get());
+  k::to_f32(st, xz, x, C.fx.get());
+  L.M.Af = C.fM.get(); L.K.Af = C.fK.get();
+  L.fPhiL_M = C.fPhi[0].get(); L.fPhiR_M = C.fPhi[1].get();
+  L.fPhiL_K = C.fPhi[2].get(); L.fPhiR_K = C.fPhi[3].get();
+  local_matvec_f32(ctx, L, C.fx.get(), C.fy.get(), C.w);
+  k::to_f64(st, xz, C.fy.get(), y);
+}
+
+}  // namespace iga

@@ -1,0 +1,41 @@
+// The projected local KKT operator of one block-AMEn step (eq. KKT_red, tau = 1):
+//   y = [M x0 + K x2 ; beta M x1 - M x2 ; K x0 - M x1]
+// with M, K the reduced operators PhiL (x) A_d (x) PhiR of the two TT-matrices.
+#pragma once
+
+#include "common.hpp"
+#include "ttops.hpp"
+
+namespace iga {
+
+struct LocalOp {
+  OpView M, K;
+  const double* PhiL_M = nullptr;  // [RM0][r0][r0]
+  const double* PhiR_M = nullptr;  // [RM1][r1][r1]
+  const double* PhiL_K = nullptr;
+  const double* PhiR_K = nullptr;
+  int r0 = 0, n = 0, r1 = 0;
+  double beta = 0.0;
+  // FP32 copies for the mixed-precision form (null when unused)
+  const float* fPhiL_M = nullptr;
+  const float* fPhiR_M = nullptr;
+  const float* fPhiL_K = nullptr;
+  const float* fPhiR_K = nullptr;
+  long size() const { return 3L * r0 * n * r1; }
+};
+
+struct LocalWork {
+  DBuf tM, tK, z;
+  FBuf ftM, ftK, fz, ft1, fx, fy;
+};
+
+// y = A_loc x (FP64); x, y: [3][r0][n][r1]
+void local_matvec(iga_ctx* ctx, const LocalOp& L, const double* x, double* y, LocalWork& w);
+// Same product with every contraction in FP32 (x, y FP32); needs the f* fields and Af views.
+void local_matvec_f32(iga_ctx* ctx, const LocalOp& L, const float* x, float* y, LocalWork& w);
+// Algorithmic flops of local_matvec: banded middle stage counted over the band's
+// nonzero entries and over the nonzero rank blocks only.
+double local_flops(const LocalOp& L);
+double band_nnz(int n, int p);
+
+}  // namespace iga

@@ -1,0 +1,61 @@
+"""GPU parity of the projected local TT-matvec (eq. KKT_red) against the oracle's einsum
+definition, which is itself pinned to F^T A F x on tiny cases (tests/test_oracle_tt.py)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import tt
+from tests.gpu_util import kkt_rows, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _reference(prob, p, beta):
+    Md = tt.banded_to_dense(prob["M"], p)
+    Kd = tt.banded_to_dense(prob["K"], p)
+    x = prob["x"]
+    Mf = [tt.local_apply(prob["PhiL_M"], Md, prob["PhiR_M"], x[l]) for l in range(3)]
+    Kf = [tt.local_apply(prob["PhiL_K"], Kd, prob["PhiR_K"], x[l]) for l in range(3)]
+    return np.stack(kkt_rows(Mf, Kf, beta))
+
+
+def _run(gpu_ctx, prob, r, n, p, RM, RK, beta, precision, rr=None):
+    import torch
+    from paper_1811_06797_amd import iga
+    rr = r if rr is None else rr
+    dev = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda() for k, v in prob.items()}
+    y = torch.empty_like(dev["x"])
+    iga.local_matvec(gpu_ctx, r, n, rr, p, RM, RM, RK, RK, dev["PhiL_M"], dev["PhiR_M"], dev["PhiL_K"],
+                     dev["PhiR_K"], dev["M"], dev["K"], beta, dev["x"], y, precision)
+    torch.cuda.synchronize()
+    return y.cpu().numpy()
+
+
+@pytest.mark.parametrize("r,RM,RK,n,p,rr", [(3, 1, 2, 5, 1, None), (5, 2, 3, 9, 2, None), (7, 3, 5, 13, 3, 4),
+                                             (1, 1, 3, 6, 2, 4), (17, 2, 9, 23, 3, None)])
+def test_local_matvec_matches_oracle(gpu_ctx, r, RM, RK, n, p, rr):
+    from paper_1811_06797_amd import iga
+    prob = synth.random_local_problem(r, RM, RK, n, p, seed=r + n, r_right=rr)
+    beta = 1e-3
+    y = _run(gpu_ctx, prob, r, n, p, RM, RK, beta, iga.FP64, rr)
+    assert rel_err(y, _reference(prob, p, beta)) < 1e-13
+
+
+def test_local_matvec_benchmark_shape(gpu_ctx):
+    """The n = 64 benchmark shape (r, R_M, R_K, n, b) = (32, 10, 60, 64, 7)."""
+    from paper_1811_06797_amd import iga
+    r, RM, RK, n, p = 32, 10, 60, 64, 3
+    prob = synth.random_local_problem(r, RM, RK, n, p, seed=1)
+    y = _run(gpu_ctx, prob, r, n, p, RM, RK, 1e-6, iga.FP64)
+    ref = _reference(prob, p, 1e-6)
+    assert rel_err(y, ref) < 1e-13
+    yf = _run(gpu_ctx, prob, r, n, p, RM, RK, 1e-6, iga.FP32)
+    assert rel_err(yf, ref) < 1e-5
+
+
+def test_local_matvec_flops_formula():
+    from paper_1811_06797_amd import iga
+    r, RM, RK, n, p = 32, 10, 60, 64, 3
+    nnz = sum(min(n - 1, i + p) - max(0, i - p) + 1 for i in range(n))
+    per = lambda R: 2 * r * r * R * n * r + 2 * r * r * R * R * nnz + 2 * r * n * R * r * r
+    assert abs(iga.local_matvec_flops(r, n, r, p, RM, RM, RK, RK) - (3 * per(RM) + 2 * per(RK))) < 1.0
