@@ -13,6 +13,7 @@
 namespace iga {
 
 thread_local std::string g_last_error;
+thread_local const char* g_phase = "";
 
 void set_last_error(const std::string& msg) { g_last_error = msg; }
 
@@ -27,8 +28,22 @@ Pool::~Pool() {
   (void)hipSetDevice(cur);
 }
 
+// Sizes are rounded up to classes 2^k, 1.25 2^k, 1.5 2^k, 1.75 2^k (at most 25% waste) and a
+// free block of the same class is reused.
+static size_t size_class(size_t bytes) {
+  if (bytes <= 4096) return 4096;
+  size_t p = 4096;
+  while (p * 2 <= bytes) p *= 2;
+  for (int q = 4; q <= 8; ++q) {
+    const size_t c = p / 4 * q;
+    if (c >= bytes) return c;
+  }
+  return p * 2;
+}
+
 void* Pool::alloc(size_t bytes) {
-  bytes = (bytes + 255) & ~size_t(255);
+  const size_t requested = bytes;
+  bytes = size_class(bytes);
   auto it = free_.find(bytes);
   void* p = nullptr;
   if (it != free_.end()) {
@@ -44,7 +59,8 @@ void* Pool::alloc(size_t bytes) {
       e = hipMalloc(&p, bytes);
       if (e != hipSuccess) {
         (void)hipGetLastError();
-        fail(IGA_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+        fail(IGA_ENOMEM, "device allocation of " + std::to_string(requested) + " bytes failed (in " +
+                             std::string(g_phase) + ")");
       }
     }
   }
@@ -95,6 +111,37 @@ static void upload(iga_ctx* ctx, double* dst, const double* src, size_t n) {
   IGA_HIP(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
 }
 
+}  // namespace iga
+
+namespace iga {
+// ||A f - b|| / ||b|| with b = [M yhat; 0; 0]: f and yhat are expanded and the TT-matrices
+// applied to the full tensors mode by mode, all in FP64.
+double kkt_residual_impl(iga_ctx* ctx, const iga_kkt* kkt, const iga_tt* yhat, const iga_btt* f) {
+  const long N = (long)f->n[0] * f->n[1] * f->n[2];
+  DBuf full(ctx, 3 * N), yh(ctx, N), r(ctx, 3 * N);
+  btt_expand(ctx, f, full.get());
+  tt_expand(ctx, yhat->n, yhat->r, yhat->core, yh.get());
+  const double* f0 = full.get();
+  const double* f1 = full.get() + N;
+  const double* f2 = full.get() + 2 * N;
+  double* r0 = r.get();
+  double* r1 = r.get() + N;
+  double* r2 = r.get() + 2 * N;
+  const iga_ttop* M = kkt->M;
+  const iga_ttop* K = kkt->K;
+  // r0 = M f0 + K f2 - M yhat;  r1 = beta M f1 - M f2;  r2 = K f0 - M f1
+  full_apply(ctx, M, yh.get(), r2, 1.0, 0.0);  // b (kept in r2 for its norm)
+  const double nb = norm2_host(ctx, N, r2);
+  full_apply(ctx, M, f0, r0, 1.0, 0.0);
+  k::axpby(ctx->stream, N, -1.0, r2, 1.0, r0);
+  full_apply(ctx, K, f2, r0, 1.0, 1.0);
+  full_apply(ctx, M, f1, r1, kkt->beta, 0.0);
+  full_apply(ctx, M, f2, r1, -1.0, 1.0);
+  full_apply(ctx, K, f0, r2, 1.0, 0.0);
+  full_apply(ctx, M, f1, r2, -1.0, 1.0);
+  const double nr = norm2_host(ctx, 3 * N, r.get());
+  return nb > 0 ? std::sqrt(nr / nb) : std::sqrt(nr);
+}
 }  // namespace iga
 
 using namespace iga;
@@ -426,29 +473,6 @@ int iga_kkt_apply(iga_ctx* ctx, const iga_kkt* kkt, const iga_btt* x, iga_btt** 
   });
 }
 
-namespace iga {
-// ||A f - b|| / ||b|| with b = [M yhat; 0; 0], all in expanded form.
-double kkt_residual_impl(iga_ctx* ctx, const iga_kkt* kkt, const iga_tt* yhat, const iga_btt* f) {
-  const long N = (long)f->n[0] * f->n[1] * f->n[2];
-  std::unique_ptr<iga_btt> Af(kkt_apply_impl(ctx, kkt, f));
-  DBuf full(ctx, 3 * N), bfull(ctx, N);
-  btt_expand(ctx, Af.get(), full.get());
-  // b1 = M yhat: core products of M with yhat's cores
-  int s[4] = {1, kkt->M->R[1] * yhat->r[1], kkt->M->R[2] * yhat->r[2], 1};
-  DBuf bc[3];
-  const double* cp[3];
-  for (int d = 0; d < 3; ++d) {
-    bc[d].reset(ctx, (size_t)s[d] * f->n[d] * s[d + 1]);
-    core_product(ctx, view_of(kkt->M, d), yhat->core[d], yhat->r[d], yhat->r[d + 1], bc[d].get(), 1.0, 0.0);
-    cp[d] = bc[d].get();
-  }
-  tt_expand(ctx, f->n, s, cp, bfull.get());
-  const double nb = norm2_host(ctx, N, bfull.get());
-  k::axpby(ctx->stream, N, -1.0, bfull.get(), 1.0, full.get());
-  const double nr = norm2_host(ctx, 3 * N, full.get());
-  return nb > 0 ? std::sqrt(nr / nb) : std::sqrt(nr);
-}
-}  // namespace iga
 
 int iga_kkt_residual(iga_ctx* ctx, const iga_kkt* kkt, const iga_tt* yhat, const iga_btt* f,
                      double* rel_residual) {

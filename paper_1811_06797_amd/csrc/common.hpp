@@ -26,6 +26,8 @@ inline void require(bool ok, int code, const std::string& msg) {
   if (!ok) fail(code, msg);
 }
 void set_last_error(const std::string& msg);
+// Name of the driver phase in progress (reported with allocation failures).
+extern thread_local const char* g_phase;
 
 #define IGA_HIP(call)                                                                      \
   do {                                                                                     \

@@ -280,24 +280,53 @@ __global__ __launch_bounds__(256) void colnorm_kernel(int m, int k, const double
   if (threadIdx.x == 0) out[j] = sqrt(s);
 }
 
-__global__ void kkt_combine_kernel(long e, double beta, const double* zM, const double* zK,
-                                   double* y) {
+template <typename T>
+__global__ void kkt_combine_kernel(long e, T k02, T m11, T m12, T k20, T m21, const T* zM, const T* zK,
+                                   T* y) {
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < e; i += (long)gridDim.x * blockDim.x) {
-    const double m0 = zM[i], m1 = zM[e + i], m2 = zM[2 * e + i];
-    const double k0 = zK[i], k2 = zK[e + i];
-    y[i] = m0 + k2;
-    y[e + i] = beta * m1 - m2;
-    y[2 * e + i] = k0 - m1;
+    const T a0 = zM[i], a1 = zM[e + i], a2 = zM[2 * e + i];
+    const T b0 = zK[i], b2 = zK[e + i];
+    y[i] = a0 + k02 * b2;
+    y[e + i] = m11 * a1 + m12 * a2;
+    y[2 * e + i] = k20 * b0 + m21 * a1;
   }
 }
 
-__global__ void kkt_combine_f32_kernel(long e, float beta, const float* zM, const float* zK, float* y) {
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < e; i += (long)gridDim.x * blockDim.x) {
-    const float m0 = zM[i], m1 = zM[e + i], m2 = zM[2 * e + i];
-    const float k0 = zK[i], k2 = zK[e + i];
-    y[i] = m0 + k2;
-    y[e + i] = beta * m1 - m2;
-    y[2 * e + i] = k0 - m1;
+__global__ void scale3_kernel(long e, double s0, double s1, double s2, double* y) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < 3 * e; i += (long)gridDim.x * blockDim.x) {
+    const int c = i / e;
+    y[i] *= (c == 0 ? s0 : (c == 1 ? s1 : s2));
+  }
+}
+
+__global__ void fd_solve_kernel(int r0, int n, int r1, const double* lamL, const double* lamN,
+                                const double* lamR, double c, double g, double* v) {
+  const long e = (long)r0 * n * r1;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < e;
+       idx += (long)gridDim.x * blockDim.x) {
+    const int b = idx % r1;
+    const int i = (idx / r1) % n;
+    const int a = idx / ((long)r1 * n);
+    const double k = g * (lamL[a] + lamN[i] + lamR[b]);
+    const double f1 = v[idx], f2 = v[e + idx], f3 = v[2 * e + idx];
+    // [[1,0,k],[0,c,-1],[k,-1,0]] [y;u;l] = [f1;f2;f3]:  u = k y - f3, l = c u - f2
+    const double y = (f1 + k * f2 + c * k * f3) / (1.0 + c * k * k);
+    const double u = k * y - f3;
+    v[idx] = y;
+    v[e + idx] = u;
+    v[2 * e + idx] = c * u - f2;
+  }
+}
+
+__global__ void symmetrize_kernel(int k, double* Hs, long stride) {
+  double* H = Hs + blockIdx.y * stride;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < (long)k * k;
+       e += (long)gridDim.x * blockDim.x) {
+    const int i = e / k, j = e % k;
+    if (j <= i) continue;
+    const double m = 0.5 * (H[(long)i * k + j] + H[(long)j * k + i]);
+    H[(long)i * k + j] = m;
+    H[(long)j * k + i] = m;
   }
 }
 
@@ -342,15 +371,37 @@ __global__ void diag_kernel(int k, const double* H, double* out, int mode) {
 
 }  // namespace
 
-void kkt_combine(hipStream_t s, long e, double beta, const double* zM, const double* zK, double* y) {
+void kkt_combine(hipStream_t s, long e, const KktCoef& c, const double* zM, const double* zK, double* y) {
   if (e <= 0) return;
-  kkt_combine_kernel<<<grid_for(e), 256, 0, s>>>(e, beta, zM, zK, y);
+  kkt_combine_kernel<double><<<grid_for(e), 256, 0, s>>>(e, c.k02, c.m11, c.m12, c.k20, c.m21, zM, zK, y);
   IGA_HIP(hipGetLastError());
 }
 
-void kkt_combine_f32(hipStream_t s, long e, float beta, const float* zM, const float* zK, float* y) {
+void scale3(hipStream_t s, long e, double s0, double s1, double s2, double* y) {
   if (e <= 0) return;
-  kkt_combine_f32_kernel<<<grid_for(e), 256, 0, s>>>(e, beta, zM, zK, y);
+  scale3_kernel<<<grid_for(3 * e), 256, 0, s>>>(e, s0, s1, s2, y);
+  IGA_HIP(hipGetLastError());
+}
+
+void fd_solve(hipStream_t s, int r0, int n, int r1, const double* lamL, const double* lamN,
+              const double* lamR, double c, double g, double* v) {
+  const long e = (long)r0 * n * r1;
+  if (e <= 0) return;
+  fd_solve_kernel<<<grid_for(e), 256, 0, s>>>(r0, n, r1, lamL, lamN, lamR, c, g, v);
+  IGA_HIP(hipGetLastError());
+}
+
+void symmetrize(hipStream_t s, int nmat, int k, double* H, long stride) {
+  if (k <= 1 || nmat <= 0) return;
+  dim3 grid((unsigned)std::max<long>(1, std::min<long>(((long)k * k + 255) / 256, 1024)), nmat);
+  symmetrize_kernel<<<grid, 256, 0, s>>>(k, H, stride);
+  IGA_HIP(hipGetLastError());
+}
+
+void kkt_combine_f32(hipStream_t s, long e, const KktCoef& c, const float* zM, const float* zK, float* y) {
+  if (e <= 0) return;
+  kkt_combine_kernel<float><<<grid_for(e), 256, 0, s>>>(e, (float)c.k02, (float)c.m11, (float)c.m12,
+                                                        (float)c.k20, (float)c.m21, zM, zK, y);
   IGA_HIP(hipGetLastError());
 }
 

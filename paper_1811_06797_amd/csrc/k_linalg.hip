@@ -16,7 +16,8 @@ constexpr int LDS_MAX_K = 120; // H kept in LDS up to this size ((k+1)*k*8 bytes
 // round the k/2 disjoint pairs (p, q) are rotated at once; H <- J^T H J by a
 // row pass then a column pass, and the eigenvectors are accumulated as rows of
 // WT (WT <- J^T WT, i.e. W <- W J). A rotation is skipped when
-// |h_pq| <= max(tol * sqrt(|h_pp h_qq|), floor_rel * trace).
+// |h_pq| <= max(tol * sqrt(|h_pp h_qq|), 1e-30 trace), or when both h_pp and h_qq are
+// below 1e-28 trace (directions at the rounding level of the largest one).
 template <bool USE_LDS>
 __global__ __launch_bounds__(JT) void jacobi_kernel(int k, double* Hs, long sH, double* WTs,
                                                     long sW, double tol, int max_sweeps,
@@ -42,6 +43,7 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(int k, double* Hs, long sH, 
   }
   __syncthreads();
   const double floor_abs = 1e-30 * trace;
+  const double floor_col = 1e-28 * trace;
   const int kk = k + (k & 1);
   const int npair = kk / 2;
   int sweeps = 0;
@@ -58,7 +60,9 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(int k, double* Hs, long sH, 
         if (q < k) {
           const double app = H[p * ld + p], aqq = H[q * ld + q], apq = H[p * ld + q];
           const double thr = fmax(tol * sqrt(fabs(app * aqq)), floor_abs);
-          if (fabs(apq) > thr) {
+          // columns at the rounding level of the largest are not rotated among themselves
+          const bool negligible = fabs(app) <= floor_col && fabs(aqq) <= floor_col;
+          if (!negligible && fabs(apq) > thr) {
             const double tau = (aqq - app) / (2.0 * apq);
             const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
             c = 1.0 / sqrt(1.0 + tt * tt);

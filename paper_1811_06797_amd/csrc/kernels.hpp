@@ -92,10 +92,22 @@ void multiaxpy(hipStream_t s, long n, int k, const double* V, long ldv, const do
 // column norms of a row-major m x k matrix: out[j] = sqrt(sum_i A[i][j]^2)
 void colnorms(hipStream_t s, int m, int k, const double* A, long lda, double* out);
 
-// KKT block combination of the five operator applications of a local matvec:
-// y0 = zM0 + zK1, y1 = beta zM1 - zM2, y2 = zK0 - zM1 (zM [3][e], zK [2][e], y [3][e]).
-void kkt_combine(hipStream_t s, long e, double beta, const double* zM, const double* zK, double* y);
-void kkt_combine_f32(hipStream_t s, long e, float beta, const float* zM, const float* zK, float* y);
+// KKT block combination of the five operator applications of a local matvec
+// (zM = M x0, M x1, M x2 and zK = K x0, K x2; each [e]):
+//   y0 = zM0 + k02 zK(x2), y1 = m11 zM1 + m12 zM2, y2 = k20 zK(x0) + m21 zM1.
+struct KktCoef {
+  double k02 = 1, m11 = 0, m12 = -1, k20 = 1, m21 = -1;
+};
+void kkt_combine(hipStream_t s, long e, const KktCoef& c, const double* zM, const double* zK, double* y);
+void kkt_combine_f32(hipStream_t s, long e, const KktCoef& c, const float* zM, const float* zK, float* y);
+// y[l][.] *= scale[l] for the three components of a [3][e] vector
+void scale3(hipStream_t s, long e, double s0, double s1, double s2, double* y);
+// Fast-diagonalisation solve of the per-mode 3x3 KKT blocks [[1,0,k],[0,c,-1],[k,-1,0]],
+// k = g (lamL[a] + lamN[i] + lamR[b]), in place on v [3][r0][n][r1].
+void fd_solve(hipStream_t s, int r0, int n, int r1, const double* lamL, const double* lamN,
+              const double* lamR, double c, double g, double* v);
+// H <- (H + H^T) / 2 for nmat k x k matrices stored stride apart
+void symmetrize(hipStream_t s, int nmat, int k, double* H, long stride);
 // Y[(al a)][i][(be b)] = alpha sum_o A[al][i][o][be] X[a][i+o-p][b] + beta Y (banded A [R0][n][2p+1][R1])
 void core_product(hipStream_t s, int R0, int R1, int n, int p, const double* A, int r0, int r1,
                   const double* X, double* Y, double alpha, double beta);

@@ -16,16 +16,17 @@ double band_nnz(int n, int p) {
   return s;
 }
 
-static double op_flops(const OpView& A, int r0, int r1, int ncol, double nnz_band) {
-  // stage 1: 2 r0^2 R0 n r1; stage 2: 2 r0 r1 (nonzero R0 x R1) nnz_band; stage 3: 2 r0 n R1 r1^2
+static double op_flops(const OpView& A, int r0o, int r0, int r1o, int r1, int ncol, double nnz_band) {
+  // stage 1: 2 r0o r0 R0 n r1; stage 2: 2 r0o r1 (nonzero R0 x R1) nnz_band; stage 3: 2 r0o n R1 r1 r1o
   const double nz_blocks = A.flops_dense_factor * double(A.R0) * A.R1;
-  return ncol * (2.0 * r0 * r0 * A.R0 * A.n * r1 + 2.0 * r0 * r1 * nz_blocks * nnz_band +
-                 2.0 * r0 * A.n * A.R1 * (double)r1 * r1);
+  return ncol * (2.0 * r0o * r0 * A.R0 * A.n * r1 + 2.0 * r0o * r1 * nz_blocks * nnz_band +
+                 2.0 * r0o * A.n * A.R1 * (double)r1 * r1o);
 }
 
 double local_flops(const LocalOp& L) {
   const double nb = band_nnz(L.n, L.M.p);
-  return op_flops(L.M, L.r0, L.r1, 3, nb) + op_flops(L.K, L.r0, L.r1, 2, nb);
+  return op_flops(L.M, L.out0(), L.r0, L.out1(), L.r1, 3, nb) +
+         op_flops(L.K, L.out0(), L.r0, L.out1(), L.r1, 2, nb);
 }
 
 static void stage3_all(iga_ctx* ctx, const OpView& A, const double* t2, int ncol, const double* PhiR,
@@ -42,14 +43,17 @@ static void stage3_all(iga_ctx* ctx, const OpView& A, const double* t2, int ncol
 
 void local_matvec(iga_ctx* ctx, const LocalOp& L, const double* x, double* y, LocalWork& w) {
   const long colsz = (long)L.r0 * L.n * L.r1;
-  w.tM.ensure(ctx, (size_t)L.M.R1 * 3 * colsz);
-  w.tK.ensure(ctx, (size_t)L.K.R1 * 2 * colsz);
-  w.z.ensure(ctx, (size_t)5 * colsz);
-  local_stage12(ctx, L.M, L.PhiL_M, L.r0, L.r0, L.r1, 3, x, colsz, w.tM.get());
-  stage3_all(ctx, L.M, w.tM.get(), 3, L.PhiR_M, L.r0, L.r1, L.r1, w.z.get(), colsz);
-  local_stage12(ctx, L.K, L.PhiL_K, L.r0, L.r0, L.r1, 2, x, 2 * colsz, w.tK.get());
-  stage3_all(ctx, L.K, w.tK.get(), 2, L.PhiR_K, L.r0, L.r1, L.r1, w.z.get() + 3 * colsz, colsz);
-  k::kkt_combine(ctx->stream, colsz, L.beta, w.z.get(), w.z.get() + 3 * colsz, y);
+  const int r0o = L.out0(), r1o = L.out1();
+  const long t2sz = (long)r0o * L.n * L.r1;       // one column of stage-2 output
+  const long osz = (long)r0o * L.n * r1o;         // one output column
+  w.tM.ensure(ctx, (size_t)L.M.R1 * 3 * t2sz);
+  w.tK.ensure(ctx, (size_t)L.K.R1 * 2 * t2sz);
+  w.z.ensure(ctx, (size_t)5 * osz);
+  local_stage12(ctx, L.M, L.PhiL_M, r0o, L.r0, L.r1, 3, x, colsz, w.tM.get());
+  stage3_all(ctx, L.M, w.tM.get(), 3, L.PhiR_M, r0o, r1o, L.r1, w.z.get(), osz);
+  local_stage12(ctx, L.K, L.PhiL_K, r0o, L.r0, L.r1, 2, x, 2 * colsz, w.tK.get());
+  stage3_all(ctx, L.K, w.tK.get(), 2, L.PhiR_K, r0o, r1o, L.r1, w.z.get() + 3 * osz, osz);
+  k::kkt_combine(ctx->stream, osz, L.coef, w.z.get(), w.z.get() + 3 * osz, y);
 }
 
 static void apply_f32(iga_ctx* ctx, const OpView& A, const float* PhiL, const float* PhiR, int r0, int r1,
@@ -90,7 +94,7 @@ void local_matvec_f32(iga_ctx* ctx, const LocalOp& L, const float* x, float* y, 
             colsz);
   apply_f32(ctx, L.K, L.fPhiL_K, L.fPhiR_K, L.r0, L.r1, 2, x, 2 * colsz, w.ftK.get(), w.ft1.get(),
             w.fz.get() + 3 * colsz, colsz);
-  k::kkt_combine_f32(ctx->stream, colsz, (float)L.beta, w.fz.get(), w.fz.get() + 3 * colsz, y);
+  k::kkt_combine_f32(ctx->stream, colsz, L.coef, w.fz.get(), w.fz.get() + 3 * colsz, y);
 }
 
 // ---- raw-buffer entry point (dense rank blocks) ----
@@ -143,7 +147,8 @@ void local_matvec_impl(iga_ctx* ctx, int r0, int n, int r1, int p, int RM0, int 
     C.RK0 = RK0; C.RK1 = RK1;
   }
   LocalOp L;
-  L.r0 = r0; L.n = n; L.r1 = r1; L.beta = beta;
+  L.r0 = r0; L.n = n; L.r1 = r1;
+  L.coef.m11 = beta;
   L.M.R0 = RM0; L.M.R1 = RM1; L.M.n = n; L.M.p = p; L.M.A = Mcore;
   L.M.lo_R1 = C.loM1.get(); L.M.hi_R1 = C.hiM1.get(); L.M.lo_R0 = C.loM0.get(); L.M.hi_R0 = C.hiM0.get();
   L.K.R0 = RK0; L.K.R1 = RK1; L.K.n = n; L.K.p = p; L.K.A = Kcore;

@@ -1,9 +1,12 @@
 // The projected local KKT operator of one block-AMEn step (eq. KKT_red, tau = 1):
 //   y = [M x0 + K x2 ; beta M x1 - M x2 ; K x0 - M x1]
-// with M, K the reduced operators PhiL (x) A_d (x) PhiR of the two TT-matrices.
+// with M, K the reduced operators PhiL (x) A_d (x) PhiR of the two TT-matrices,
+// optionally composed with a scaling of the unknowns (see KktCoef).
+// The interfaces may be rectangular (test ranks r0o, r1o; trial ranks r0, r1).
 #pragma once
 
 #include "common.hpp"
+#include "kernels.hpp"
 #include "ttops.hpp"
 
 namespace iga {
@@ -14,14 +17,18 @@ struct LocalOp {
   const double* PhiR_M = nullptr;  // [RM1][r1][r1]
   const double* PhiL_K = nullptr;
   const double* PhiR_K = nullptr;
-  int r0 = 0, n = 0, r1 = 0;
-  double beta = 0.0;
+  int r0 = 0, n = 0, r1 = 0;     // trial (input) ranks
+  int r0o = -1, r1o = -1;        // test (output) ranks; -1: same as the trial ranks
+  k::KktCoef coef;
   // FP32 copies for the mixed-precision form (null when unused)
   const float* fPhiL_M = nullptr;
   const float* fPhiR_M = nullptr;
   const float* fPhiL_K = nullptr;
   const float* fPhiR_K = nullptr;
+  int out0() const { return r0o < 0 ? r0 : r0o; }
+  int out1() const { return r1o < 0 ? r1 : r1o; }
   long size() const { return 3L * r0 * n * r1; }
+  long out_size() const { return 3L * out0() * n * out1(); }
 };
 
 struct LocalWork {
@@ -29,7 +36,7 @@ struct LocalWork {
   FBuf ftM, ftK, fz, ft1, fx, fy;
 };
 
-// y = A_loc x (FP64); x, y: [3][r0][n][r1]
+// y = A_loc x (FP64); x: [3][r0][n][r1], y: [3][r0o][n][r1o]
 void local_matvec(iga_ctx* ctx, const LocalOp& L, const double* x, double* y, LocalWork& w);
 // Same product with every contraction in FP32 (x, y FP32); needs the f* fields and Af views.
 void local_matvec_f32(iga_ctx* ctx, const LocalOp& L, const float* x, float* y, LocalWork& w);

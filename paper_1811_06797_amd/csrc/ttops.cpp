@@ -2,6 +2,7 @@
 #include "ttops.hpp"
 
 #include <algorithm>
+#include <cstdio>
 #include <cmath>
 #include <mutex>
 #include <numeric>
@@ -148,6 +149,7 @@ void core_product(iga_ctx* ctx, const OpView& A, const double* X, int r0, int r1
 
 void tt_expand(iga_ctx* ctx, const int n[3], const int r[4], const double* const core[3], double* out) {
   Scratch& S = scratch_of(ctx);
+  g_phase = "tt_expand";
   // T (n0 n1 x r2) = core0 (n0 x r1) . core1 (r1 x n1 r2)
   S.t3.ensure(ctx, (size_t)n[0] * n[1] * r[2]);
   k::gemm_rm(ctx->stream, n[0], n[1] * r[2], r[1], core[0], r[1], false, core[1], (long)n[1] * r[2],
@@ -168,7 +170,36 @@ void btt_expand(iga_ctx* ctx, const iga_btt* x, double* out) {
   }
 }
 
+void full_apply(iga_ctx* ctx, const iga_ttop* A, const double* x, double* y, double alpha, double beta) {
+  Scratch& S = scratch_of(ctx);
+  g_phase = "full_apply";
+  const int n0 = A->n[0], n1 = A->n[1], n2 = A->n[2];
+  const long N = (long)n0 * n1 * n2;
+  S.t1.ensure(ctx, (size_t)A->R[1] * N);
+  S.t2.ensure(ctx, (size_t)A->R[2] * N);
+  // T1[al][i1][j2 j3] = sum_j1 A0[0][i1][j1][al] x[j1][j2 j3]
+  OpView v0 = view_of(A, 0), v1 = view_of(A, 1), v2 = view_of(A, 2);
+  k::Band b;
+  b.n = n0; b.p = A->p; b.R0 = 1; b.R1 = A->R[1]; b.rev = false; b.m = 1; b.c = n1 * n2;
+  b.A = v0.A; b.lo = v0.lo_R1; b.hi = v0.hi_R1; b.in = x; b.out = S.t1.get();
+  k::band(ctx->stream, b);
+  // T2[be][i1][i2][j3] = sum_{al, j2} A1[al][i2][j2][be] T1[al][i1][j2][j3]
+  k::Band c;
+  c.n = n1; c.p = A->p; c.R0 = A->R[1]; c.R1 = A->R[2]; c.rev = false; c.m = n0; c.c = n2;
+  c.A = v1.A; c.lo = v1.lo_R1; c.hi = v1.hi_R1; c.in = S.t1.get(); c.out = S.t2.get();
+  k::band(ctx->stream, c);
+  // y[i1 i2][i3] = sum_{be, j3} A2[be][i3][j3][0] T2[be][i1 i2][j3]
+  k::Band e;
+  e.n = n2; e.p = A->p; e.R0 = A->R[2]; e.R1 = 1; e.rev = false; e.m = n0 * n1; e.c = 1;
+  e.A = v2.A; e.lo = v2.lo_R1; e.hi = v2.hi_R1; e.in = S.t2.get(); e.out = y;
+  e.alpha = alpha; e.beta = beta;
+  k::band(ctx->stream, e);
+}
+
 iga_btt* kkt_apply_impl(iga_ctx* ctx, const iga_kkt* kkt, const iga_btt* x) {
+  static thread_local char ph[160];
+  std::snprintf(ph, sizeof ph, "kkt_apply ranks %d %d ell %d", x->r[1], x->r[2], x->ell);
+  g_phase = ph;
   const iga_ttop* M = kkt->M;
   const iga_ttop* K = kkt->K;
   std::unique_ptr<iga_btt> y(new iga_btt());
@@ -240,9 +271,9 @@ void svd(iga_ctx* ctx, const double* A, int m, int k, long lda, bool trans, Svd&
     IGA_HIP(hipStreamSynchronize(st));
   }
   int passes = 0;
-  for (int pass = 0; pass < 8; ++pass) {
+  for (int pass = 0; pass < 6; ++pass) {
     k::gemm_rm(st, k, k, m, out.B.get(), k, true, out.B.get(), k, false, H.get(), k);
-    k::jacobi_eig(st, 1, k, H.get(), 0, WT.get(), 0, 1e-15, 60, sweeps.get());
+    k::jacobi_eig(st, 1, k, H.get(), 0, WT.get(), 0, 1e-15, 40, sweeps.get());
     int sw = 0;
     IGA_HIP(hipMemcpyAsync(&sw, sweeps.get(), sizeof(int), hipMemcpyDeviceToHost, st));
     IGA_HIP(hipStreamSynchronize(st));

@@ -58,6 +58,10 @@ void core_product(iga_ctx* ctx, const OpView& A, const double* X, int r0, int r1
 void tt_expand(iga_ctx* ctx, const int n[3], const int r[4], const double* const core[3], double* out);
 void btt_expand(iga_ctx* ctx, const iga_btt* x, double* out);
 
+// y = A x for a TT-matrix A and a full tensor x [n0][n1][n2], mode by mode (banded):
+// y = alpha A x + beta y.
+void full_apply(iga_ctx* ctx, const iga_ttop* A, const double* x, double* y, double alpha, double beta);
+
 // y = A x for the KKT operator (exact, ranks (RM+RK) r); y allocated here.
 iga_btt* kkt_apply_impl(iga_ctx* ctx, const iga_kkt* kkt, const iga_btt* x);
 

@@ -43,3 +43,11 @@ def test_error_path_without_device_context():
     from paper_1811_06797_amd import iga
     with pytest.raises(iga.IgaError):
         iga.ctx_create(device=10 ** 6)
+
+
+def test_no_unresolved_library_symbols():
+    import subprocess
+    out = subprocess.run(["nm", "-D", "--undefined-only", LIB], capture_output=True, text=True)
+    if out.returncode != 0:
+        pytest.skip("nm unavailable")
+    assert "iga" not in out.stdout
