@@ -220,10 +220,10 @@ void Amen::right_orth_plain(DBuf* cores, int* ranks, int d, bool prev_is_ell) {
   IGA_HIP(hipMemcpyAsync(didx.get(), idx.data(), k * sizeof(int), hipMemcpyHostToDevice, st_));
   IGA_HIP(hipMemcpyAsync(dinv.get(), inv.data(), k * sizeof(double), hipMemcpyHostToDevice, st_));
   IGA_HIP(hipMemcpyAsync(dsg.get(), sg.data(), k * sizeof(double), hipMemcpyHostToDevice, st_));
-  k::gather_cols(st_, m, r0, k, s.B.get(), r0, didx.get(), dinv.get(), T.get(), k);
+  k::gather_cols(st_, m, r0, k, s.B.get(), s.p, didx.get(), dinv.get(), T.get(), k);
   DBuf nc(ctx_, (size_t)k * m);
   k::copy2d(st_, k, m, T.get(), 1, k, nc.get(), m);
-  k::gather_cols(st_, r0, r0, k, s.V.get(), r0, didx.get(), dsg.get(), F.get(), k);
+  k::gather_cols(st_, r0, r0, k, s.V.get(), s.p, didx.get(), dsg.get(), F.get(), k);
   // previous core [.][n'][r0] times F (r0 x k)
   const int rp = ranks[d - 1], np = n_[d - 1];
   const int nl = prev_is_ell ? 3 : 1;
@@ -582,7 +582,7 @@ void Amen::orthonormal_columns(double* A, int m, int k, int kmax, DBuf& Q, int& 
   IGA_HIP(hipMemcpyAsync(didx.get(), idx.data(), q * sizeof(int), hipMemcpyHostToDevice, st_));
   IGA_HIP(hipMemcpyAsync(dinv.get(), inv.data(), q * sizeof(double), hipMemcpyHostToDevice, st_));
   Q.reset(ctx_, (size_t)m * q);
-  k::gather_cols(st_, m, k, q, s.B.get(), k, didx.get(), dinv.get(), Q.get(), q);
+  k::gather_cols(st_, m, k, q, s.B.get(), s.p, didx.get(), dinv.get(), Q.get(), q);
   IGA_HIP(hipStreamSynchronize(st_));
 }
 
@@ -652,7 +652,7 @@ void Amen::move_right(int d) {
     for (double v : s.sigma) nz += v > 1e-14 * s.sigma[0];
     DBuf Fk(ctx_, (size_t)m * K3);
     auto recon = [&](int kk, double* out) {
-      k::gemm_rm(st_, m, K3, kk, s.B.get(), K3, false, s.V.get(), K3, true, Fk.get(), K3);
+      k::gemm_rm(st_, m, K3, kk, s.B.get(), s.p, false, s.V.get(), s.p, true, Fk.get(), K3);
       const int dims[4] = {r0, n, 3, r1};
       const int perm[4] = {2, 0, 1, 3};
       k::permute4(st_, Fk.get(), dims, perm, out);
@@ -675,10 +675,10 @@ void Amen::move_right(int d) {
   IGA_HIP(hipMemcpyAsync(dinv.get(), inv.data(), rt * sizeof(double), hipMemcpyHostToDevice, st_));
   IGA_HIP(hipMemcpyAsync(dsg.get(), sg.data(), rt * sizeof(double), hipMemcpyHostToDevice, st_));
   DBuf U(ctx_, (size_t)m * rt);
-  k::gather_cols(st_, m, 3 * r1, rt, s.B.get(), 3 * r1, didx.get(), dinv.get(), U.get(), rt);
+  k::gather_cols(st_, m, 3 * r1, rt, s.B.get(), s.p, didx.get(), dinv.get(), U.get(), rt);
   // C = Sigma V^T: (rt x 3 r1)
   DBuf CT(ctx_, (size_t)3 * r1 * rt), C(ctx_, (size_t)rt * 3 * r1);
-  k::gather_cols(st_, 3 * r1, 3 * r1, rt, s.V.get(), 3 * r1, didx.get(), dsg.get(), CT.get(), rt);
+  k::gather_cols(st_, 3 * r1, 3 * r1, rt, s.V.get(), s.p, didx.get(), dsg.get(), CT.get(), rt);
   k::copy2d(st_, rt, 3 * r1, CT.get(), 1, rt, C.get(), 3 * r1);
   // enrichment directions orthogonal to U
   DBuf Qz;
@@ -760,7 +760,7 @@ void Amen::move_left(int d) {
     for (double v : s.sigma) nz += v > 1e-14 * s.sigma[0];
     auto recon = [&](int kk, double* out) {
       // F_k = V_k B_k^T: (3 r0) x (n r1) in the natural [l][a][j][b] layout
-      k::gemm_rm(st_, K3, m, kk, s.V.get(), K3, false, s.B.get(), K3, true, out, m);
+      k::gemm_rm(st_, K3, m, kk, s.V.get(), s.p, false, s.B.get(), s.p, true, out, m);
     };
     rt = residual_rank(d, 1, std::min(rmax, std::max(nz, 1)), recon);
   }
@@ -780,9 +780,9 @@ void Amen::move_left(int d) {
   IGA_HIP(hipMemcpyAsync(dinv.get(), inv.data(), rt * sizeof(double), hipMemcpyHostToDevice, st_));
   IGA_HIP(hipMemcpyAsync(dsg.get(), sg.data(), rt * sizeof(double), hipMemcpyHostToDevice, st_));
   DBuf U(ctx_, (size_t)m * rt);  // (n r1) x rt
-  k::gather_cols(st_, m, 3 * r0, rt, s.B.get(), 3 * r0, didx.get(), dinv.get(), U.get(), rt);
+  k::gather_cols(st_, m, 3 * r0, rt, s.B.get(), s.p, didx.get(), dinv.get(), U.get(), rt);
   DBuf C(ctx_, (size_t)3 * r0 * rt);  // (3 r0) x rt = V Sigma
-  k::gather_cols(st_, 3 * r0, 3 * r0, rt, s.V.get(), 3 * r0, didx.get(), dsg.get(), C.get(), rt);
+  k::gather_cols(st_, 3 * r0, 3 * r0, rt, s.V.get(), s.p, didx.get(), dsg.get(), C.get(), rt);
   DBuf Qz;
   int q = 0;
   if (kick_ > 0 && rt < m) {
@@ -870,8 +870,8 @@ void Amen::move_ell_to_first() {
     IGA_HIP(hipMemcpyAsync(didx.get(), idx.data(), rt * sizeof(int), hipMemcpyHostToDevice, st_));
     IGA_HIP(hipMemcpyAsync(dinv.get(), inv.data(), rt * sizeof(double), hipMemcpyHostToDevice, st_));
     IGA_HIP(hipMemcpyAsync(dsg.get(), sg.data(), rt * sizeof(double), hipMemcpyHostToDevice, st_));
-    k::gather_cols(st_, m, 3 * r0, rt, s.B.get(), 3 * r0, didx.get(), dinv.get(), U.get(), rt);
-    k::gather_cols(st_, 3 * r0, 3 * r0, rt, s.V.get(), 3 * r0, didx.get(), dsg.get(), C.get(), rt);
+    k::gather_cols(st_, m, 3 * r0, rt, s.B.get(), s.p, didx.get(), dinv.get(), U.get(), rt);
+    k::gather_cols(st_, 3 * r0, 3 * r0, rt, s.V.get(), s.p, didx.get(), dsg.get(), C.get(), rt);
     k::copy2d(st_, rt, m, U.get(), 1, rt, Xn.get(), m);
     const int rp = r_[d - 1], np = n_[d - 1];
     DBuf Xp(ctx_, (size_t)3 * rp * np * rt);

@@ -105,9 +105,9 @@ void tt_svd3(iga_ctx* ctx, const double* F, const int nt[3], double delta, int r
   const int R1 = trunc_rank(s1.sigma, delta, rmax);
   out.r[1] = R1;
   out.core[0].reset(ctx, (size_t)nt[0] * R1);
-  k::copy2d(st, nt[0], R1, s1.V.get(), nt[0], 1, out.core[0].get(), R1);
+  k::copy2d(st, nt[0], R1, s1.V.get(), s1.p, 1, out.core[0].get(), R1);
   DBuf Y(ctx, (size_t)R1 * m1);
-  k::copy2d(st, R1, m1, s1.B.get(), 1, nt[0], Y.get(), m1);
+  k::copy2d(st, R1, m1, s1.B.get(), 1, s1.p, Y.get(), m1);
   const int m2 = R1 * nt[1], k2 = nt[2];
   Svd s2;
   std::vector<int> id;
@@ -126,9 +126,9 @@ void tt_svd3(iga_ctx* ctx, const double* F, const int nt[3], double delta, int r
     DBuf dinv = upload(ctx, inv.data(), R2), dsg = upload(ctx, sg.data(), R2);
     IGA_HIP(hipMemcpyAsync(did.get(), id.data(), R2 * sizeof(int), hipMemcpyHostToDevice, st));
     out.core[1].reset(ctx, (size_t)m2 * R2);
-    k::gather_cols(st, m2, k2, R2, s2.B.get(), k2, did.get(), dinv.get(), out.core[1].get(), R2);
+    k::gather_cols(st, m2, k2, R2, s2.B.get(), s2.p, did.get(), dinv.get(), out.core[1].get(), R2);
     DBuf T(ctx, (size_t)k2 * R2);
-    k::gather_cols(st, k2, k2, R2, s2.V.get(), k2, did.get(), dsg.get(), T.get(), R2);
+    k::gather_cols(st, k2, k2, R2, s2.V.get(), s2.p, did.get(), dsg.get(), T.get(), R2);
     out.core[2].reset(ctx, (size_t)R2 * k2);
     k::copy2d(st, R2, k2, T.get(), 1, R2, out.core[2].get(), k2);
     IGA_HIP(hipStreamSynchronize(st));
@@ -137,9 +137,9 @@ void tt_svd3(iga_ctx* ctx, const double* F, const int nt[3], double delta, int r
     const int R2 = trunc_rank(s2.sigma, delta, rmax);
     out.r[2] = R2;
     out.core[1].reset(ctx, (size_t)m2 * R2);
-    k::copy2d(st, m2, R2, s2.V.get(), m2, 1, out.core[1].get(), R2);
+    k::copy2d(st, m2, R2, s2.V.get(), s2.p, 1, out.core[1].get(), R2);
     out.core[2].reset(ctx, (size_t)R2 * k2);
-    k::copy2d(st, R2, k2, s2.B.get(), 1, m2, out.core[2].get(), k2);
+    k::copy2d(st, R2, k2, s2.B.get(), 1, s2.p, out.core[2].get(), k2);
   }
 }
 
@@ -396,14 +396,26 @@ int assemble_impl(iga_ctx* ctx, const iga_geometry* geo, int p, const int n[3],
       sw[d + 1] = dot_host(ctx, G, fields.get() + diag_w[d] * G, ones.get());
       M->ref_c[d] = sw[0] != 0.0 ? sw[d + 1] / sw[0] : 1.0;
     }
+    DBuf wc[3];
     for (int d = 0; d < 3; ++d) {
-      DBuf wc(ctx, nt[d]);
+      wc[d].reset(ctx, nt[d]);
       k::gemm_rm(st, nt[d], 1, nt[d], dir[d].Binv.get(), nt[d], false, r1.core[d].get(), 1, false,
-                 wc.get(), 1);
+                 wc[d].get(), 1);
+    }
+    // the separable factors of omega > 0 may carry pairs of sign flips: make each positive
+    for (int d = 0; d < 2; ++d) {
+      DBuf one(ctx, nt[d]);
+      k::fill(st, nt[d], 1.0, one.get());
+      if (dot_host(ctx, nt[d], wc[d].get(), one.get()) < 0.0) {
+        k::scale(st, nt[d], -1.0, wc[d].get());
+        k::scale(st, nt[2], -1.0, wc[2].get());
+      }
+    }
+    for (int d = 0; d < 3; ++d) {
       M->refM[d].reset(ctx, (size_t)n[d] * b);
       M->refK[d].reset(ctx, (size_t)n[d] * b);
-      build_factor(ctx, dir[d], p, nq, wc.get(), 1, 1, false, false, M->refM[d].get());
-      build_factor(ctx, dir[d], p, nq, wc.get(), 1, 1, true, true, M->refK[d].get());
+      build_factor(ctx, dir[d], p, nq, wc[d].get(), 1, 1, false, false, M->refM[d].get());
+      build_factor(ctx, dir[d], p, nq, wc[d].get(), 1, 1, true, true, M->refK[d].get());
     }
     M->has_ref = true;
   }

@@ -207,7 +207,152 @@ __global__ void place_block_kernel(int na, int nb, int inner, const double* src,
   }
 }
 
+// ---- one-sided block Jacobi SVD ----
+
+constexpr int OSB = 16;        // columns per block
+constexpr int OSP = 2 * OSB;   // columns per block pair
+constexpr int OST = 256;       // threads per pair workgroup
+constexpr int OSR = 64;        // rows per LDS tile
+
+__device__ inline void circle_pair(int t, int round, int nplayers, int& a, int& b) {
+  auto player = [&](int pos) { return pos == 0 ? 0 : 1 + (pos - 1 + round) % (nplayers - 1); };
+  a = player(t);
+  b = player(nplayers - 1 - t);
+  if (a > b) { const int x = a; a = b; b = x; }
+}
+
+// One round of the one-sided block Jacobi method: workgroup t takes the block pair (I, J)
+// of the round-robin schedule, forms the 32 x 32 Gram matrix of those columns of B,
+// diagonalises it by cyclic Jacobi in LDS, and applies the accumulated rotation to the
+// 32 columns of B (m rows) and of V (kv rows). flags[t] = 1 if anything rotated.
+__global__ __launch_bounds__(OST) void osbj_round_kernel(double* B, int m, long ldb, double* V, int kv,
+                                                         long ldv, int nb, int round, double tol,
+                                                         double floor_col, int* flags) {
+  __shared__ double G[OSP][OSP + 1];
+  __shared__ double W[OSP][OSP + 1];
+  __shared__ double T[OSR][OSP + 1];
+  __shared__ double cs[OSP / 2], sn[OSP / 2];
+  __shared__ int pp[OSP / 2], qq[OSP / 2];
+  __shared__ int rot_any, rot_sweep;
+  const int tid = threadIdx.x;
+  int I, J;
+  circle_pair(blockIdx.x, round, nb, I, J);
+  auto col = [&](int c) { return c < OSB ? I * OSB + c : J * OSB + (c - OSB); };
+  // Gram of the pair's columns, 4 entries per thread
+  double acc[4] = {0, 0, 0, 0};
+  for (int r0 = 0; r0 < m; r0 += OSR) {
+    for (int e = tid; e < OSR * OSP; e += OST) {
+      const int rr = e / OSP, c = e % OSP, row = r0 + rr;
+      T[rr][c] = row < m ? B[(long)row * ldb + col(c)] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int e = tid + OST * s, i = e / OSP, j = e % OSP;
+      double a = acc[s];
+      for (int rr = 0; rr < OSR; ++rr) a = fma(T[rr][i], T[rr][j], a);
+      acc[s] = a;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int e = tid + OST * s, i = e / OSP, j = e % OSP;
+    G[i][j] = acc[s];
+    W[i][j] = (i == j) ? 1.0 : 0.0;
+  }
+  if (tid == 0) rot_any = 0;
+  __syncthreads();
+  // cyclic Jacobi on G (32 x 32), accumulating W <- W J
+  for (int sweep = 0; sweep < 20; ++sweep) {
+    if (tid == 0) rot_sweep = 0;
+    __syncthreads();
+    for (int r2 = 0; r2 < OSP - 1; ++r2) {
+      if (tid < OSP / 2) {
+        int p, q;
+        circle_pair(tid, r2, OSP, p, q);
+        double c = 1.0, sv = 0.0;
+        const double app = G[p][p], aqq = G[q][q], apq = G[p][q];
+        const bool negligible = app <= floor_col && aqq <= floor_col;
+        if (!negligible && fabs(apq) > tol * sqrt(fabs(app * aqq))) {
+          const double tau = (aqq - app) / (2.0 * apq);
+          const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          c = 1.0 / sqrt(1.0 + t * t);
+          sv = t * c;
+          rot_sweep = 1;
+        }
+        pp[tid] = p; qq[tid] = q; cs[tid] = c; sn[tid] = sv;
+      }
+      __syncthreads();
+      for (int e = tid; e < (OSP / 2) * OSP; e += OST) {
+        const int t = e / OSP, j = e % OSP;
+        const double sv = sn[t];
+        if (sv == 0.0) continue;
+        const double c = cs[t];
+        const int p = pp[t], q = qq[t];
+        const double gp = G[p][j], gq = G[q][j];
+        G[p][j] = c * gp - sv * gq;
+        G[q][j] = sv * gp + c * gq;
+      }
+      __syncthreads();
+      for (int e = tid; e < (OSP / 2) * OSP; e += OST) {
+        const int t = e / OSP, i = e % OSP;
+        const double sv = sn[t];
+        if (sv == 0.0) continue;
+        const double c = cs[t];
+        const int p = pp[t], q = qq[t];
+        const double gp = G[i][p], gq = G[i][q];
+        G[i][p] = c * gp - sv * gq;
+        G[i][q] = sv * gp + c * gq;
+        const double wp = W[i][p], wq = W[i][q];
+        W[i][p] = c * wp - sv * wq;
+        W[i][q] = sv * wp + c * wq;
+      }
+      __syncthreads();
+    }
+    const int any = rot_sweep;
+    if (sweep == 0 && tid == 0) rot_any = any;
+    __syncthreads();
+    if (!any) break;
+  }
+  if (!rot_any) {
+    if (tid == 0) flags[blockIdx.x] = 0;
+    return;
+  }
+  // [B_I B_J] <- [B_I B_J] W and [V_I V_J] <- [V_I V_J] W, tile by tile
+  for (int pass = 0; pass < 2; ++pass) {
+    double* X = pass == 0 ? B : V;
+    const int rows = pass == 0 ? m : kv;
+    const long ld = pass == 0 ? ldb : ldv;
+    for (int r0 = 0; r0 < rows; r0 += OSR) {
+      for (int e = tid; e < OSR * OSP; e += OST) {
+        const int rr = e / OSP, c = e % OSP, row = r0 + rr;
+        T[rr][c] = row < rows ? X[(long)row * ld + col(c)] : 0.0;
+      }
+      __syncthreads();
+      for (int e = tid; e < OSR * OSP; e += OST) {
+        const int rr = e / OSP, c = e % OSP, row = r0 + rr;
+        if (row >= rows) continue;
+        double a = 0.0;
+        for (int q = 0; q < OSP; ++q) a = fma(T[rr][q], W[q][c], a);
+        X[(long)row * ld + col(c)] = a;
+      }
+      __syncthreads();
+    }
+  }
+  if (tid == 0) flags[blockIdx.x] = 1;
+}
+
 }  // namespace
+
+void osbj_round(hipStream_t s, double* B, int m, long ldb, double* V, int kv, long ldv, int nb, int round,
+                double tol, double floor_col, int* flags) {
+  require(nb >= 2 && nb % 2 == 0, IGA_EINVAL, "osbj_round: block count must be even");
+  osbj_round_kernel<<<nb / 2, OST, 0, s>>>(B, m, ldb, V, kv, ldv, nb, round, tol, floor_col, flags);
+  IGA_HIP(hipGetLastError());
+}
+
+int osbj_block() { return OSB; }
 
 void jacobi_eig(hipStream_t s, int nmat, int k, double* H, long strideH, double* W, long strideW,
                 double tol, int max_sweeps, int* sweeps_out) {

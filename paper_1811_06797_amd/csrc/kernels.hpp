@@ -125,6 +125,11 @@ void diag_get(hipStream_t s, int k, const double* H, double* out);
 // the sweeps that rotated anything (0: H was already diagonal to that tolerance).
 void jacobi_eig(hipStream_t s, int nmat, int k, double* H, long strideH, double* WT, long strideW,
                 double tol, int max_sweeps, int* sweeps_out);
+// One round of the one-sided block Jacobi SVD on B (m x kp, kp = nb * osbj_block(), nb even)
+// with V (kv x kp) accumulated; flags[nb/2] receive 1 for pairs that rotated.
+void osbj_round(hipStream_t s, double* B, int m, long ldb, double* V, int kv, long ldv, int nb, int round,
+                double tol, double floor_col, int* flags);
+int osbj_block();
 void transpose_square(hipStream_t s, int nmat, int k, const double* in, long sin, double* out,
                       long sout);
 // out[i][j] = in[i][idx[j]] * (scale ? scale[j] : 1), i < m, j < kout

@@ -255,54 +255,83 @@ iga_btt* kkt_apply_impl(iga_ctx* ctx, const iga_kkt* kkt, const iga_btt* x) {
 void svd(iga_ctx* ctx, const double* A, int m, int k, long lda, bool trans, Svd& out) {
   require(m >= 1 && k >= 1, IGA_EINVAL, "svd: empty matrix");
   hipStream_t st = ctx->stream;
-  out.m = m; out.k = k;
-  out.B.reset(ctx, (size_t)m * k);
-  if (!trans) k::copy2d(st, m, k, A, lda, 1, out.B.get(), k);
-  else k::copy2d(st, m, k, A, 1, lda, out.B.get(), k);
-  DBuf V(ctx, (size_t)k * k), H(ctx, (size_t)k * k), WT(ctx, (size_t)k * k), T(ctx, (size_t)m * k),
-      V2(ctx, (size_t)k * k);
-  IBuf sweeps(ctx, 1);
-  // V = I
-  k::fill(st, (long)k * k, 0.0, V.get());
+  if (m < k) {
+    // work on the tall transpose: A^T = U' S V'^T  =>  A = V' S U'^T
+    Svd t;
+    svd(ctx, A, k, m, lda, !trans, t);
+    const int p = t.p;
+    std::vector<double> sg(t.sigma.begin(), t.sigma.begin() + p), inv(p);
+    for (int j = 0; j < p; ++j) inv[j] = sg[j] > 0 ? 1.0 / sg[j] : 0.0;
+    std::vector<int> id(p);
+    std::iota(id.begin(), id.end(), 0);
+    IBuf did(ctx, p);
+    DBuf dsg(ctx, p), dinv(ctx, p);
+    IGA_HIP(hipMemcpyAsync(did.get(), id.data(), p * sizeof(int), hipMemcpyHostToDevice, st));
+    IGA_HIP(hipMemcpyAsync(dsg.get(), sg.data(), p * sizeof(double), hipMemcpyHostToDevice, st));
+    IGA_HIP(hipMemcpyAsync(dinv.get(), inv.data(), p * sizeof(double), hipMemcpyHostToDevice, st));
+    out.m = m; out.k = k; out.p = p;
+    out.B.reset(ctx, (size_t)m * p);
+    out.V.reset(ctx, (size_t)k * p);
+    k::gather_cols(st, m, p, p, t.V.get(), p, did.get(), dsg.get(), out.B.get(), p);
+    k::gather_cols(st, k, p, p, t.B.get(), p, did.get(), dinv.get(), out.V.get(), p);
+    out.sigma = sg;
+    out.passes = t.passes;
+    IGA_HIP(hipStreamSynchronize(st));
+    return;
+  }
+  // one-sided block Jacobi on the m x kp zero-padded copy
+  const int bs = k::osbj_block();
+  const int kp = ((k + 2 * bs - 1) / (2 * bs)) * (2 * bs);
+  const int nb = kp / bs;
+  DBuf B(ctx, (size_t)m * kp), V(ctx, (size_t)kp * kp);
+  k::fill(st, (long)m * kp, 0.0, B.get());
+  if (!trans) k::copy2d(st, m, k, A, lda, 1, B.get(), kp);
+  else k::copy2d(st, m, k, A, 1, lda, B.get(), kp);
   {
-    std::vector<double> eye((size_t)k * k, 0.0);
-    for (int i = 0; i < k; ++i) eye[(size_t)i * k + i] = 1.0;
+    std::vector<double> eye((size_t)kp * kp, 0.0);
+    for (int i = 0; i < kp; ++i) eye[(size_t)i * kp + i] = 1.0;
     IGA_HIP(hipMemcpyAsync(V.get(), eye.data(), eye.size() * sizeof(double), hipMemcpyHostToDevice, st));
     IGA_HIP(hipStreamSynchronize(st));
   }
-  int passes = 0;
-  for (int pass = 0; pass < 6; ++pass) {
-    k::gemm_rm(st, k, k, m, out.B.get(), k, true, out.B.get(), k, false, H.get(), k);
-    k::jacobi_eig(st, 1, k, H.get(), 0, WT.get(), 0, 1e-15, 40, sweeps.get());
-    int sw = 0;
-    IGA_HIP(hipMemcpyAsync(&sw, sweeps.get(), sizeof(int), hipMemcpyDeviceToHost, st));
-    IGA_HIP(hipStreamSynchronize(st));
-    ++passes;
-    if (sw == 0) break;
-    // B <- B W, V <- V W  (W = WT^T)
-    k::gemm_rm(st, m, k, k, out.B.get(), k, false, WT.get(), k, true, T.get(), k);
-    std::swap(out.B, T);
-    k::gemm_rm(st, k, k, k, V.get(), k, false, WT.get(), k, true, V2.get(), k);
-    std::swap(V, V2);
+  const double fro2 = norm2_host(ctx, (long)m * kp, B.get());
+  const double floor_col = 1e-28 * fro2;
+  const double tol = 4e-16 * std::max(1.0, std::sqrt((double)m));
+  const int npair = nb / 2, nround = nb - 1;
+  IBuf flags(ctx, (size_t)npair * nround);
+  std::vector<int> hf((size_t)npair * nround);
+  int sweeps = 0;
+  if (fro2 > 0) {
+    for (int sweep = 0; sweep < 30; ++sweep) {
+      for (int rd = 0; rd < nround; ++rd)
+        k::osbj_round(st, B.get(), m, kp, V.get(), kp, kp, nb, rd, tol, floor_col, flags.get() + rd * npair);
+      IGA_HIP(hipMemcpyAsync(hf.data(), flags.get(), hf.size() * sizeof(int), hipMemcpyDeviceToHost, st));
+      IGA_HIP(hipStreamSynchronize(st));
+      ++sweeps;
+      bool any = false;
+      for (int f : hf) any = any || f;
+      if (!any) break;
+    }
   }
-  out.passes = passes;
-  DBuf nrm(ctx, k);
-  k::colnorms(st, m, k, out.B.get(), k, nrm.get());
-  std::vector<double> sig(k);
-  IGA_HIP(hipMemcpyAsync(sig.data(), nrm.get(), k * sizeof(double), hipMemcpyDeviceToHost, st));
+  out.passes = sweeps;
+  DBuf nrm(ctx, kp);
+  k::colnorms(st, m, kp, B.get(), kp, nrm.get());
+  std::vector<double> sig(kp);
+  IGA_HIP(hipMemcpyAsync(sig.data(), nrm.get(), kp * sizeof(double), hipMemcpyDeviceToHost, st));
   IGA_HIP(hipStreamSynchronize(st));
-  std::vector<int> idx(k);
+  std::vector<int> idx(kp);
   std::iota(idx.begin(), idx.end(), 0);
   std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return sig[a] > sig[b]; });
-  out.sigma.resize(k);
-  for (int j = 0; j < k; ++j) out.sigma[j] = sig[idx[j]];
-  IBuf didx(ctx, k);
-  IGA_HIP(hipMemcpyAsync(didx.get(), idx.data(), k * sizeof(int), hipMemcpyHostToDevice, st));
-  k::gather_cols(st, m, k, k, out.B.get(), k, didx.get(), nullptr, T.get(), k);
-  std::swap(out.B, T);
-  out.V.reset(ctx, (size_t)k * k);
-  k::gather_cols(st, k, k, k, V.get(), k, didx.get(), nullptr, out.V.get(), k);
-  IGA_HIP(hipStreamSynchronize(st));  // didx lives on the host stack scope
+  const int p = k;
+  out.m = m; out.k = k; out.p = p;
+  out.sigma.resize(p);
+  for (int j = 0; j < p; ++j) out.sigma[j] = sig[idx[j]];
+  IBuf didx(ctx, p);
+  IGA_HIP(hipMemcpyAsync(didx.get(), idx.data(), p * sizeof(int), hipMemcpyHostToDevice, st));
+  out.B.reset(ctx, (size_t)m * p);
+  out.V.reset(ctx, (size_t)k * p);
+  k::gather_cols(st, m, kp, p, B.get(), kp, didx.get(), nullptr, out.B.get(), p);
+  k::gather_cols(st, k, kp, p, V.get(), kp, didx.get(), nullptr, out.V.get(), p);
+  IGA_HIP(hipStreamSynchronize(st));
 }
 
 int trunc_rank(const std::vector<double>& sigma, double abs_tol, int rmax, int rmin) {

@@ -65,16 +65,17 @@ void full_apply(iga_ctx* ctx, const iga_ttop* A, const double* x, double* y, dou
 // y = A x for the KKT operator (exact, ranks (RM+RK) r); y allocated here.
 iga_btt* kkt_apply_impl(iga_ctx* ctx, const iga_kkt* kkt, const iga_btt* x);
 
-// SVD of an m x k matrix (row-major, leading dimension lda), or of the transpose of a
-// k x m row-major matrix when trans. Gram-Jacobi iteration: H = B^T B, B <- B W with W the
-// Jacobi eigenvectors of H, repeated until H is diagonal to working precision; then
-// sigma_j = ||b_j||, U = B diag(1/sigma), A = U diag(sigma) V^T.
+// Thin SVD of an m x k matrix (row-major, leading dimension lda), or of the transpose of a
+// k x m row-major matrix when trans, by the one-sided block Jacobi method on the taller
+// orientation: columns are rotated pairwise (in blocks) until mutually orthogonal to
+// working precision; then sigma_j = ||b_j||, U = B diag(1/sigma), A = U diag(sigma) V^T.
+// p = min(m, k) triplets are returned.
 struct Svd {
-  int m = 0, k = 0;
-  DBuf B;  // m x k, = A V, columns by decreasing sigma
-  DBuf V;  // k x k, right singular vectors in columns, same order
+  int m = 0, k = 0, p = 0;
+  DBuf B;  // m x p, = A V = U diag(sigma), columns by decreasing sigma
+  DBuf V;  // k x p, right singular vectors in columns, same order
   std::vector<double> sigma;
-  int passes = 0;
+  int passes = 0;  // Jacobi sweeps
 };
 void svd(iga_ctx* ctx, const double* A, int m, int k, long lda, bool trans, Svd& out);
 // Smallest r with ||sigma[r:]|| <= abs_tol, capped to [rmin, rmax] (rmax <= 0: no cap).
