@@ -315,6 +315,8 @@ LocalOp Amen::make_op(int d, Frame left, Frame right) const {
   LocalOp L;
   L.M = view(0, d);
   L.K = view(1, d);
+  L.Mblocks = ops_[0]->core[d].blocks;
+  L.Kblocks = ops_[1]->core[d].blocks;
   L.r0 = r_[d]; L.n = n_[d]; L.r1 = r_[d + 1];
   // A D: columns 1 and 2 carry the factors 1/g and g of the scaled unknowns
   L.coef.k02 = g_;

@@ -22,6 +22,24 @@ struct Gemm {
 };
 void gemm(hipStream_t s, const Gemm& g);
 
+// FP64 MFMA GEMM with two-level index maps (k_gemm.hip): every index x of m, n, k is split
+// as x = x1 * X2 + x2 (X2 = inner extent; the default 1 << 30 makes it single-level with
+// stride s*2) and addressed as x1 * s*1 + x2 * s*2 per operand; batch b = b1 * nb2 + b2.
+struct Gemm2 {
+  int M = 0, N = 0, K = 0;
+  int M2 = 1 << 30, N2 = 1 << 30, K2 = 1 << 30;
+  const double* A = nullptr;
+  long sAm1 = 0, sAm2 = 0, sAk1 = 0, sAk2 = 0;
+  const double* B = nullptr;
+  long sBk1 = 0, sBk2 = 0, sBn1 = 0, sBn2 = 0;
+  double* C = nullptr;
+  long sCm1 = 0, sCm2 = 0, sCn1 = 0, sCn2 = 0;
+  int nb1 = 1, nb2 = 1;
+  long sAb1 = 0, sAb2 = 0, sBb1 = 0, sBb2 = 0, sCb1 = 0, sCb2 = 0;
+  double alpha = 1.0, beta = 0.0;
+};
+void gemm2(hipStream_t s, const Gemm2& g);
+
 // Row-major convenience: C (MxN, ldc) = alpha op(A) op(B) + beta C, op = transpose if t*.
 void gemm_rm(hipStream_t s, int M, int N, int K, const double* A, long lda, bool tA,
              const double* B, long ldb, bool tB, double* C, long ldc, double alpha = 1.0,

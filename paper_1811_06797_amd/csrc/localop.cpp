@@ -29,7 +29,7 @@ double local_flops(const LocalOp& L) {
          op_flops(L.K, L.out0(), L.r0, L.out1(), L.r1, 2, nb);
 }
 
-static void stage3_all(iga_ctx* ctx, const OpView& A, const double* t2, int ncol, const double* PhiR,
+[[maybe_unused]] static void stage3_all(iga_ctx* ctx, const OpView& A, const double* t2, int ncol, const double* PhiR,
                        int ra_out, int rb_out, int rb_in, double* y, long ycs) {
   const long colsz = (long)ra_out * A.n * rb_in;
   k::Gemm g;
@@ -41,18 +41,64 @@ static void stage3_all(iga_ctx* ctx, const OpView& A, const double* t2, int ncol
   k::gemm(ctx->stream, g);
 }
 
+// One operator of the local matvec on matrix cores: for the ncol columns c of x
+//   z[c][a'][i][b'] = sum PhiL[d][a'][a] A[d][i][i+o-p][g] x[c][a][i+o-p][b] PhiR[g][b'][b].
+// Stage 1 writes t1[j + p][d][c][a'][b] (p zero slices on both ends of j), so that the
+// banded stage is, for every row i, one dense GEMM over (o, d) whose B operand is the
+// contiguous window of slices j = i-p .. i+p; one GEMM per nonzero rank block.
+static void op_apply_mfma(iga_ctx* ctx, const OpView& A, const std::vector<RankBlock>& blocks,
+                          const double* PhiL, const double* PhiR, int r0o, int r0, int r1, int r1o, int ncol,
+                          const double* x, long xcs, double* z, long zcs, DBuf& t1, DBuf& t2) {
+  hipStream_t st = ctx->stream;
+  const int n = A.n, p = A.p, b = 2 * p + 1, R0 = A.R0, R1 = A.R1;
+  const long S2 = (long)r0o * r1;         // one (c) slab of (a', b)
+  const long S1 = (long)ncol * S2;        // one (d) slab
+  const long SJ = (long)R0 * S1;          // one j slice of t1
+  t1.ensure(ctx, (size_t)(n + 2 * p) * SJ);
+  t2.ensure(ctx, (size_t)n * R1 * S1);
+  if (p > 0) {
+    k::fill(st, p * SJ, 0.0, t1.get());
+    k::fill(st, p * SJ, 0.0, t1.get() + (long)(n + p) * SJ);
+  }
+  // stage 1
+  k::Gemm2 g1;
+  g1.M = r0o; g1.N = n * r1; g1.N2 = r1; g1.K = r0;
+  g1.A = PhiL; g1.sAm2 = r0; g1.sAk2 = 1;
+  g1.B = x; g1.sBk2 = (long)n * r1; g1.sBn1 = r1; g1.sBn2 = 1;
+  g1.C = t1.get() + p * SJ; g1.sCm2 = r1; g1.sCn1 = SJ; g1.sCn2 = 1;
+  g1.nb1 = R0; g1.nb2 = ncol;
+  g1.sAb1 = (long)r0o * r0; g1.sBb2 = xcs; g1.sCb1 = S1; g1.sCb2 = S2;
+  k::gemm2(st, g1);
+  // stage 2: per rank block, batched over rows i
+  for (const RankBlock& rb : blocks) {
+    k::Gemm2 g2;
+    g2.M = rb.nb; g2.N = (int)S1; g2.K = rb.na * b; g2.K2 = rb.na;
+    g2.A = A.A + (long)rb.a0 * n * b * R1 + rb.b0;
+    g2.sAm2 = 1; g2.sAk1 = R1; g2.sAk2 = (long)n * b * R1;
+    g2.B = t1.get() + rb.a0 * S1; g2.sBk1 = SJ; g2.sBk2 = S1; g2.sBn2 = 1;
+    g2.C = t2.get() + rb.b0 * S1; g2.sCm2 = S1; g2.sCn2 = 1;
+    g2.nb1 = n; g2.sAb1 = (long)b * R1; g2.sBb1 = SJ; g2.sCb1 = (long)R1 * S1;
+    k::gemm2(st, g2);
+  }
+  // stage 3: z[c][(a' i)][b'] = sum_{(g, b)} t2[i][g][c][a'][b] PhiR[g][b'][b]
+  k::Gemm2 g3;
+  g3.M = r0o * n; g3.M2 = n; g3.N = r1o; g3.K = R1 * r1; g3.K2 = r1;
+  g3.A = t2.get(); g3.sAm1 = r1; g3.sAm2 = (long)R1 * S1; g3.sAk1 = S1; g3.sAk2 = 1;
+  g3.B = PhiR; g3.sBk1 = (long)r1o * r1; g3.sBk2 = 1; g3.sBn2 = r1;
+  g3.C = z; g3.sCm1 = (long)n * r1o; g3.sCm2 = r1o; g3.sCn2 = 1;
+  g3.nb1 = ncol; g3.sAb1 = S2; g3.sCb1 = zcs;
+  k::gemm2(st, g3);
+}
+
 void local_matvec(iga_ctx* ctx, const LocalOp& L, const double* x, double* y, LocalWork& w) {
   const long colsz = (long)L.r0 * L.n * L.r1;
   const int r0o = L.out0(), r1o = L.out1();
-  const long t2sz = (long)r0o * L.n * L.r1;       // one column of stage-2 output
-  const long osz = (long)r0o * L.n * r1o;         // one output column
-  w.tM.ensure(ctx, (size_t)L.M.R1 * 3 * t2sz);
-  w.tK.ensure(ctx, (size_t)L.K.R1 * 2 * t2sz);
+  const long osz = (long)r0o * L.n * r1o;  // one output column
   w.z.ensure(ctx, (size_t)5 * osz);
-  local_stage12(ctx, L.M, L.PhiL_M, r0o, L.r0, L.r1, 3, x, colsz, w.tM.get());
-  stage3_all(ctx, L.M, w.tM.get(), 3, L.PhiR_M, r0o, r1o, L.r1, w.z.get(), osz);
-  local_stage12(ctx, L.K, L.PhiL_K, r0o, L.r0, L.r1, 2, x, 2 * colsz, w.tK.get());
-  stage3_all(ctx, L.K, w.tK.get(), 2, L.PhiR_K, r0o, r1o, L.r1, w.z.get() + 3 * osz, osz);
+  op_apply_mfma(ctx, L.M, L.Mblocks, L.PhiL_M, L.PhiR_M, r0o, L.r0, L.r1, r1o, 3, x, colsz, w.z.get(), osz,
+                w.tM, w.tM2);
+  op_apply_mfma(ctx, L.K, L.Kblocks, L.PhiL_K, L.PhiR_K, r0o, L.r0, L.r1, r1o, 2, x, 2 * colsz,
+                w.z.get() + 3 * osz, osz, w.tK, w.tK2);
   k::kkt_combine(ctx->stream, osz, L.coef, w.z.get(), w.z.get() + 3 * osz, y);
 }
 
@@ -154,6 +200,8 @@ void local_matvec_impl(iga_ctx* ctx, int r0, int n, int r1, int p, int RM0, int 
   L.K.R0 = RK0; L.K.R1 = RK1; L.K.n = n; L.K.p = p; L.K.A = Kcore;
   L.K.lo_R1 = C.loK1.get(); L.K.hi_R1 = C.hiK1.get(); L.K.lo_R0 = C.loK0.get(); L.K.hi_R0 = C.hiK0.get();
   L.PhiL_M = PhiL_M; L.PhiR_M = PhiR_M; L.PhiL_K = PhiL_K; L.PhiR_K = PhiR_K;
+  L.Mblocks = {RankBlock{0, RM0, 0, RM1}};
+  L.Kblocks = {RankBlock{0, RK0, 0, RK1}};
   if (precision == IGA_FP64) {
     local_matvec(ctx, L, x, y, C.w);
     return;

@@ -5,6 +5,8 @@
 // The interfaces may be rectangular (test ranks r0o, r1o; trial ranks r0, r1).
 #pragma once
 
+#include <vector>
+
 #include "common.hpp"
 #include "kernels.hpp"
 #include "ttops.hpp"
@@ -13,6 +15,7 @@ namespace iga {
 
 struct LocalOp {
   OpView M, K;
+  std::vector<RankBlock> Mblocks, Kblocks;  // nonzero rank blocks of the two cores
   const double* PhiL_M = nullptr;  // [RM0][r0][r0]
   const double* PhiR_M = nullptr;  // [RM1][r1][r1]
   const double* PhiL_K = nullptr;
@@ -32,7 +35,7 @@ struct LocalOp {
 };
 
 struct LocalWork {
-  DBuf tM, tK, z;
+  DBuf tM, tK, tM2, tK2, z;
   FBuf ftM, ftK, fz, ft1, fx, fy;
 };
 
