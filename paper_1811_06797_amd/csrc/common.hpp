@@ -79,6 +79,7 @@ class DevBuf {
       free();
       ctx_ = o.ctx_; p_ = o.p_; n_ = o.n_;
       o.p_ = nullptr; o.n_ = 0;
+      ++gen_;
     }
     return *this;
   }
@@ -87,6 +88,7 @@ class DevBuf {
     ctx_ = ctx;
     n_ = count;
     p_ = count ? static_cast<T*>(ctx->pool->alloc(count * sizeof(T))) : nullptr;
+    ++gen_;
   }
   // grow-only reuse for scratch buffers
   void ensure(iga_ctx* ctx, size_t count) {
@@ -99,11 +101,14 @@ class DevBuf {
   }
   T* get() const { return p_; }
   size_t size() const { return n_; }
+  // changes whenever the buffer is (re)allocated, so owners can cache facts about its contents
+  unsigned gen() const { return gen_; }
 
  private:
   iga_ctx* ctx_ = nullptr;
   T* p_ = nullptr;
   size_t n_ = 0;
+  unsigned gen_ = 0;
 };
 using DBuf = DevBuf<double>;
 using FBuf = DevBuf<float>;

@@ -39,6 +39,9 @@ struct Gemm2 {
   double alpha = 1.0, beta = 0.0;
 };
 void gemm2(hipStream_t s, const Gemm2& g);
+// Same, with a workspace of work_len doubles that lets short-output, long-K products be split
+// along K (partials summed in a fixed order, so results are deterministic).
+void gemm2(hipStream_t s, const Gemm2& g, double* work, size_t work_len);
 
 // Row-major convenience: C (MxN, ldc) = alpha op(A) op(B) + beta C, op = transpose if t*.
 void gemm_rm(hipStream_t s, int M, int N, int K, const double* A, long lda, bool tA,

@@ -29,18 +29,6 @@ double local_flops(const LocalOp& L) {
          op_flops(L.K, L.out0(), L.r0, L.out1(), L.r1, 2, nb);
 }
 
-[[maybe_unused]] static void stage3_all(iga_ctx* ctx, const OpView& A, const double* t2, int ncol, const double* PhiR,
-                       int ra_out, int rb_out, int rb_in, double* y, long ycs) {
-  const long colsz = (long)ra_out * A.n * rb_in;
-  k::Gemm g;
-  g.M = ra_out * A.n; g.N = rb_out; g.K = rb_in; g.Kout = A.R1;
-  g.A = t2; g.sAm = rb_in; g.sAk = 1; g.sAko = ncol * colsz;
-  g.B = PhiR; g.sBk = 1; g.sBn = rb_in; g.sBko = (long)rb_out * rb_in;
-  g.C = y; g.sCm = rb_out; g.sCn = 1;
-  g.nb1 = ncol; g.sAb1 = colsz; g.sCb1 = ycs;
-  k::gemm(ctx->stream, g);
-}
-
 // One operator of the local matvec on matrix cores: for the ncol columns c of x
 //   z[c][a'][i][b'] = sum PhiL[d][a'][a] A[d][i][i+o-p][g] x[c][a][i+o-p][b] PhiR[g][b'][b].
 // Stage 1 writes t1[j + p][d][c][a'][b] (p zero slices on both ends of j), so that the
@@ -48,7 +36,8 @@ double local_flops(const LocalOp& L) {
 // contiguous window of slices j = i-p .. i+p; one GEMM per nonzero rank block.
 static void op_apply_mfma(iga_ctx* ctx, const OpView& A, const std::vector<RankBlock>& blocks,
                           const double* PhiL, const double* PhiR, int r0o, int r0, int r1, int r1o, int ncol,
-                          const double* x, long xcs, double* z, long zcs, DBuf& t1, DBuf& t2) {
+                          const double* x, long xcs, double* z, long zcs, DBuf& t1, DBuf& t2,
+                          DBuf& wk, LocalWork::PadKey& pad) {
   hipStream_t st = ctx->stream;
   const int n = A.n, p = A.p, b = 2 * p + 1, R0 = A.R0, R1 = A.R1;
   const long S2 = (long)r0o * r1;         // one (c) slab of (a', b)
@@ -56,18 +45,19 @@ static void op_apply_mfma(iga_ctx* ctx, const OpView& A, const std::vector<RankB
   const long SJ = (long)R0 * S1;          // one j slice of t1
   t1.ensure(ctx, (size_t)(n + 2 * p) * SJ);
   t2.ensure(ctx, (size_t)n * R1 * S1);
-  if (p > 0) {
+  // the p zero slices at both ends of j are never written by stage 1: fill them once per layout
+  if (p > 0 && (pad.gen != t1.gen() || pad.sj != SJ || pad.n != n || pad.p != p)) {
     k::fill(st, p * SJ, 0.0, t1.get());
     k::fill(st, p * SJ, 0.0, t1.get() + (long)(n + p) * SJ);
+    pad.gen = t1.gen(); pad.sj = SJ; pad.n = n; pad.p = p;
   }
-  // stage 1
+  // stage 1: one GEMM per column c with rows (d, a'): t1[j+p][d][c][a'][b] = sum_a PhiL[d][a'][a] x[c][a][j][b]
   k::Gemm2 g1;
-  g1.M = r0o; g1.N = n * r1; g1.N2 = r1; g1.K = r0;
-  g1.A = PhiL; g1.sAm2 = r0; g1.sAk2 = 1;
+  g1.M = R0 * r0o; g1.N = n * r1; g1.N2 = r1; g1.K = r0;
+  g1.A = PhiL; g1.sAm1 = (long)r0o * r0; g1.sAm2 = r0; g1.sAk2 = 1;
   g1.B = x; g1.sBk2 = (long)n * r1; g1.sBn1 = r1; g1.sBn2 = 1;
-  g1.C = t1.get() + p * SJ; g1.sCm2 = r1; g1.sCn1 = SJ; g1.sCn2 = 1;
-  g1.nb1 = R0; g1.nb2 = ncol;
-  g1.sAb1 = (long)r0o * r0; g1.sBb2 = xcs; g1.sCb1 = S1; g1.sCb2 = S2;
+  g1.C = t1.get() + p * SJ; g1.M2 = r0o; g1.sCm1 = S1; g1.sCm2 = r1; g1.sCn1 = SJ; g1.sCn2 = 1;
+  g1.nb1 = ncol; g1.sBb1 = xcs; g1.sCb1 = S2;
   k::gemm2(st, g1);
   // stage 2: per rank block, batched over rows i
   for (const RankBlock& rb : blocks) {
@@ -87,7 +77,9 @@ static void op_apply_mfma(iga_ctx* ctx, const OpView& A, const std::vector<RankB
   g3.B = PhiR; g3.sBk1 = (long)r1o * r1; g3.sBk2 = 1; g3.sBn2 = r1;
   g3.C = z; g3.sCm1 = (long)n * r1o; g3.sCm2 = r1o; g3.sCn2 = 1;
   g3.nb1 = ncol; g3.sAb1 = S2; g3.sCb1 = zcs;
-  k::gemm2(st, g3);
+  const size_t wlen = (size_t)16 * ncol * r0o * n * r1o;
+  wk.ensure(ctx, wlen);
+  k::gemm2(st, g3, wk.get(), wlen);
 }
 
 void local_matvec(iga_ctx* ctx, const LocalOp& L, const double* x, double* y, LocalWork& w) {
@@ -96,9 +88,9 @@ void local_matvec(iga_ctx* ctx, const LocalOp& L, const double* x, double* y, Lo
   const long osz = (long)r0o * L.n * r1o;  // one output column
   w.z.ensure(ctx, (size_t)5 * osz);
   op_apply_mfma(ctx, L.M, L.Mblocks, L.PhiL_M, L.PhiR_M, r0o, L.r0, L.r1, r1o, 3, x, colsz, w.z.get(), osz,
-                w.tM, w.tM2);
+                w.tM, w.tM2, w.split, w.padM);
   op_apply_mfma(ctx, L.K, L.Kblocks, L.PhiL_K, L.PhiR_K, r0o, L.r0, L.r1, r1o, 2, x, 2 * colsz,
-                w.z.get() + 3 * osz, osz, w.tK, w.tK2);
+                w.z.get() + 3 * osz, osz, w.tK, w.tK2, w.split, w.padK);
   k::kkt_combine(ctx->stream, osz, L.coef, w.z.get(), w.z.get() + 3 * osz, y);
 }
 

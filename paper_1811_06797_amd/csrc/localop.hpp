@@ -35,7 +35,9 @@ struct LocalOp {
 };
 
 struct LocalWork {
-  DBuf tM, tK, tM2, tK2, z;
+  DBuf tM, tK, tM2, tK2, z, split;  // split: split-K partials of the short-output stages
+  // layout (generation of tM / tK, slice size, n, p) whose zero end slices are in place
+  struct PadKey { unsigned gen = ~0u; long sj = -1; int n = -1, p = -1; } padM, padK;
   FBuf ftM, ftK, fz, ft1, fx, fy;
 };
 
