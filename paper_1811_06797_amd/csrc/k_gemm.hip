@@ -25,7 +25,7 @@ namespace iga {
 namespace k {
 namespace {
 
-constexpr int BK = 16, NTHR = 256;
+constexpr int NTHR = 256;
 
 struct G2Args {
   int M, N, K, M2, N2, K2;
@@ -38,7 +38,7 @@ struct G2Args {
   int nb2, nbatch;
   long sAb1, sAb2, sBb1, sBb2, sCb1, sCb2;
   double alpha, beta;
-  int ksplit, kchunk;   // split-K: chunk length (multiple of BK); ksplit == 1: direct store
+  int ksplit, kchunk;   // split-K: chunk length (multiple of the K tile); ksplit == 1: direct store
   double* work;         // [ksplit][nbatch][M][N] partial products when ksplit > 1
 };
 
@@ -47,54 +47,57 @@ __device__ __forceinline__ long off2(int idx, int inner, long s_outer, long s_in
   return (long)o * s_outer + (long)(idx - o * inner) * s_inner;
 }
 
-// Running (outer, inner) decomposition of a k index advanced in steps of BK.
-struct KIdx {
-  int k1, k2;
-  __device__ void init(int k, int K2) { k1 = k / K2; k2 = k - k1 * K2; }
-  __device__ void step(int q, int rem, int K2) {
-    k1 += q;
-    k2 += rem;
-    if (k2 >= K2) { k2 -= K2; ++k1; }
-  }
-  __device__ long off(long s1, long s2) const { return (long)k1 * s1 + (long)k2 * s2; }
-};
-
 // Row pitch of the LDS tiles: an odd multiple of 16 doubles, so that the two k rows a
 // half-wave reads for one MFMA operand fall into disjoint halves of the 64 banks.
 constexpr int lds_pad(int w) { return ((16 - w % 32) + 32) % 32; }
 
-template <int WM, int WN, int WAVES_M, int WAVES_N>
+template <int WM, int WN, int WAVES_M, int WAVES_N, int BK, int NBUF>
 __global__ __launch_bounds__(NTHR) void gemm2_kernel(G2Args g) {
   constexpr int BM = 4 * WM * WAVES_M, BN = 16 * WN * WAVES_N;
   constexpr int LA = BM * BK / NTHR, LB = BN * BK / NTHR;
   static_assert(WAVES_M * WAVES_N == 4, "four waves");
   static_assert(LA >= 1 && LB >= 1, "tile too small");
-  __shared__ double As[2][BK][BM + lds_pad(BM)];
-  __shared__ double Bs[2][BK][BN + lds_pad(BN)];
-  const int bz = blockIdx.z;
+  __shared__ double As[NBUF][BK][BM + lds_pad(BM)];
+  __shared__ double Bs[NBUF][BK][BN + lds_pad(BN)];
+  // Workgroups are dealt to the 8 XCDs round-robin by linear id; renumber them so that each
+  // XCD (own L2) works through one contiguous range of (batch, m-tile, n-tile), where
+  // neighbouring tiles share operand rows and columns.
+  const int gx = gridDim.x, gy = gridDim.y;
+  const int total = gx * gy * gridDim.z;
+  const int lin = (blockIdx.z * gy + blockIdx.y) * gx + blockIdx.x;
+  const int xcd = lin % 8, q = lin / 8, base = total / 8, rem = total % 8;
+  const int tile = (xcd < rem ? xcd * (base + 1) : rem * (base + 1) + (xcd - rem) * base) + q;
+  const int bx = tile % gx, by = (tile / gx) % gy, bz = tile / (gx * gy);
   const int split = bz / g.nbatch, bb = bz - split * g.nbatch;
   const int b1 = bb / g.nb2, b2 = bb - b1 * g.nb2;
   const double* A = g.A + b1 * g.sAb1 + b2 * g.sAb2;
   const double* B = g.B + b1 * g.sBb1 + b2 * g.sBb2;
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int m0 = by * BM, n0 = bx * BN;
   const int tid = threadIdx.x;
   const int kbeg = split * g.kchunk;
   const int kend = min(g.K, kbeg + g.kchunk);
 
   const bool a_kfast = (g.sAk2 == 1 && g.K2 > 1) || (g.K2 == 1 && g.sAk1 == 1);
   const bool b_nfast = (g.sBn2 == 1 && g.N2 > 1) || (g.N2 == 1 && g.sBn1 == 1);
-  int a_mm[LA], a_kk[LA], b_nn[LB], b_kk[LB];
-  long a_row[LA], b_col[LB];
+  // Each thread loads LA elements of the A tile and LB of the B tile per K step, at offsets
+  // advanced incrementally: k = k1 * K2 + k2 moves by BK = kq * K2 + krem, with one carry
+  // into k1 when k2 wraps. Out-of-range elements read the (valid) operand base and are
+  // replaced by zero, so the loads need no branches.
+  const int kq = BK / g.K2, krem = BK - kq * g.K2;
+  const int dA = kq * (int)g.sAk1 + krem * (int)g.sAk2, dAw = dA + (int)g.sAk1 - g.K2 * (int)g.sAk2;
+  const int dB = kq * (int)g.sBk1 + krem * (int)g.sBk2, dBw = dB + (int)g.sBk1 - g.K2 * (int)g.sBk2;
+  int a_mm[LA], a_kk[LA], b_nn[LB], b_kk[LB], ak2[LA], bk2[LB];
   bool a_ok[LA], b_ok[LB];
-  KIdx ak[LA], bk[LB];
+  int oa[LA], ob[LB];  // element offsets from the batch's operand base (host checks they fit)
 #pragma unroll
   for (int s = 0; s < LA; ++s) {
     const int e = tid + NTHR * s;
     if (a_kfast) { a_kk[s] = e % BK; a_mm[s] = e / BK; } else { a_mm[s] = e % BM; a_kk[s] = e / BM; }
     const int m = m0 + a_mm[s];
     a_ok[s] = m < g.M;
-    a_row[s] = a_ok[s] ? off2(m, g.M2, g.sAm1, g.sAm2) : 0;
-    ak[s].init(kbeg + a_kk[s], g.K2);
+    const int k = kbeg + a_kk[s], k1 = k / g.K2;
+    ak2[s] = k - k1 * g.K2;
+    oa[s] = (a_ok[s] ? (int)off2(m, g.M2, g.sAm1, g.sAm2) : 0) + k1 * (int)g.sAk1 + ak2[s] * (int)g.sAk2;
   }
 #pragma unroll
   for (int s = 0; s < LB; ++s) {
@@ -102,10 +105,10 @@ __global__ __launch_bounds__(NTHR) void gemm2_kernel(G2Args g) {
     if (b_nfast) { b_nn[s] = e % BN; b_kk[s] = e / BN; } else { b_kk[s] = e % BK; b_nn[s] = e / BK; }
     const int n = n0 + b_nn[s];
     b_ok[s] = n < g.N;
-    b_col[s] = b_ok[s] ? off2(n, g.N2, g.sBn1, g.sBn2) : 0;
-    bk[s].init(kbeg + b_kk[s], g.K2);
+    const int k = kbeg + b_kk[s], k1 = k / g.K2;
+    bk2[s] = k - k1 * g.K2;
+    ob[s] = (b_ok[s] ? (int)off2(n, g.N2, g.sBn1, g.sBn2) : 0) + k1 * (int)g.sBk1 + bk2[s] * (int)g.sBk2;
   }
-  const int kq = BK / g.K2, krem = BK - (BK / g.K2) * g.K2;
 
   const int wave = tid / 64, lane = tid % 64;
   const int wm0 = (wave / WAVES_N) * (4 * WM), wn0 = (wave % WAVES_N) * (16 * WN);
@@ -118,17 +121,26 @@ __global__ __launch_bounds__(NTHR) void gemm2_kernel(G2Args g) {
 
   double ra[LA], rb[LB];
   auto load_tile = [&](int kt) {
+    const int klim = kend - kt;
 #pragma unroll
     for (int s = 0; s < LA; ++s) {
-      const int kk = kt + a_kk[s];
-      ra[s] = (a_ok[s] && kk < kend) ? A[a_row[s] + ak[s].off(g.sAk1, g.sAk2)] : 0.0;
-      ak[s].step(kq, krem, g.K2);
+      const bool ok = a_ok[s] && a_kk[s] < klim;
+      const double v = A[ok ? oa[s] : 0];
+      ra[s] = ok ? v : 0.0;
+      ak2[s] += krem;
+      const bool w = ak2[s] >= g.K2;
+      ak2[s] -= w ? g.K2 : 0;
+      oa[s] += w ? dAw : dA;
     }
 #pragma unroll
     for (int s = 0; s < LB; ++s) {
-      const int kk = kt + b_kk[s];
-      rb[s] = (b_ok[s] && kk < kend) ? B[bk[s].off(g.sBk1, g.sBk2) + b_col[s]] : 0.0;
-      bk[s].step(kq, krem, g.K2);
+      const bool ok = b_ok[s] && b_kk[s] < klim;
+      const double v = B[ok ? ob[s] : 0];
+      rb[s] = ok ? v : 0.0;
+      bk2[s] += krem;
+      const bool w = bk2[s] >= g.K2;
+      bk2[s] -= w ? g.K2 : 0;
+      ob[s] += w ? dBw : dB;
     }
   };
   auto store_tile = [&](int buf) {
@@ -145,7 +157,7 @@ __global__ __launch_bounds__(NTHR) void gemm2_kernel(G2Args g) {
   }
   __syncthreads();
   for (int t = 0; t < nkt; ++t) {
-    const int cur = t & 1;
+    const int cur = NBUF == 2 ? (t & 1) : 0;
     if (t + 1 < nkt) load_tile(kbeg + (t + 1) * BK);
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
@@ -160,7 +172,8 @@ __global__ __launch_bounds__(NTHR) void gemm2_kernel(G2Args g) {
         for (int c = 0; c < WN; ++c)
           acc[r][c] = __builtin_amdgcn_mfma_f64_4x4x4f64(fa[r], fb[c], acc[r][c], 0, 0, 0);
     }
-    if (t + 1 < nkt) store_tile(cur ^ 1);
+    if (NBUF == 1) __syncthreads();  // single buffer: every wave is done reading it
+    if (t + 1 < nkt) store_tile(NBUF == 2 ? (cur ^ 1) : 0);
     __syncthreads();
   }
   // acc[r][c] at this lane is C[wm0 + 4r + lx][wn0 + 16c + 4lb + ly]
@@ -214,18 +227,33 @@ __global__ __launch_bounds__(256) void splitk_reduce(G2Args g) {
   }
 }
 
-template <int WM, int WN, int WAVES_M, int WAVES_N>
+template <int WM, int WN, int WAVES_M, int WAVES_N, int BK, int NBUF>
 void launch(hipStream_t s, G2Args a, int nbatch) {
   constexpr int BM = 4 * WM * WAVES_M, BN = 16 * WN * WAVES_N;
   dim3 grid((a.N + BN - 1) / BN, (a.M + BM - 1) / BM, (unsigned)(nbatch * a.ksplit));
-  gemm2_kernel<WM, WN, WAVES_M, WAVES_N><<<grid, NTHR, 0, s>>>(a);
+  require((long)grid.x * grid.y * grid.z < (1L << 31), IGA_EINVAL, "gemm2: grid too large");
+  gemm2_kernel<WM, WN, WAVES_M, WAVES_N, BK, NBUF><<<grid, NTHR, 0, s>>>(a);
 }
 
 }  // namespace
 
+// Largest element offset of a two-level index over [0, ext) (nonnegative strides).
+static long span(int ext, int inner, long s1, long s2) {
+  if (ext <= 0) return 0;
+  return (long)((ext - 1) / inner) * s1 + (long)(std::min(ext, inner) - 1) * s2;
+}
+
 void gemm2(hipStream_t s, const Gemm2& d, double* work, size_t work_len) {
   if (d.M <= 0 || d.N <= 0 || d.nb1 <= 0 || d.nb2 <= 0) return;
   require(d.M2 >= 1 && d.N2 >= 1 && d.K2 >= 1, IGA_EINVAL, "gemm2: inner extents must be >= 1");
+  require(d.sAm1 >= 0 && d.sAm2 >= 0 && d.sAk1 >= 0 && d.sAk2 >= 0 && d.sBk1 >= 0 && d.sBk2 >= 0 &&
+              d.sBn1 >= 0 && d.sBn2 >= 0,
+          IGA_EINVAL, "gemm2: operand strides must be nonnegative");
+  // the kernel addresses A and B with 32-bit element offsets from each batch's base
+  const long kA = span(d.K, d.K2, d.sAk1, d.sAk2) + 64L * (d.sAk1 + d.sAk2);
+  const long kB = span(d.K, d.K2, d.sBk1, d.sBk2) + 64L * (d.sBk1 + d.sBk2);
+  require(span(d.M, d.M2, d.sAm1, d.sAm2) + kA < (1L << 31) && span(d.N, d.N2, d.sBn1, d.sBn2) + kB < (1L << 31),
+          IGA_EINVAL, "gemm2: operand too large for 32-bit offsets");
   const long nb = (long)d.nb1 * d.nb2;
   G2Args a{d.M, d.N, std::max(d.K, 0), d.M2, d.N2, d.K2, d.A, d.sAm1, d.sAm2, d.sAk1, d.sAk2, d.B, d.sBk1,
            d.sBk2, d.sBn1, d.sBn2, d.C, d.sCm1, d.sCm2, d.sCn1, d.sCn2, d.nb2, (int)nb, d.sAb1, d.sAb2, d.sBb1,
@@ -239,23 +267,24 @@ void gemm2(hipStream_t s, const Gemm2& d, double* work, size_t work_len) {
   else { BM = 64; BN = 64; variant = 0; }
   const long tiles = (long)((d.M + BM - 1) / BM) * ((d.N + BN - 1) / BN) * nb;
   // split K when the tiles cannot fill the chip and the contraction is long
-  if (work && tiles < 256 && d.K >= 8 * BK) {
-    int ks = (int)std::min<long>((512 + tiles - 1) / tiles, d.K / (4 * BK));
+  constexpr int KALIGN = 32;  // split-K chunks are whole K tiles of every variant
+  if (work && tiles < 256 && d.K >= 4 * KALIGN) {
+    int ks = (int)std::min<long>((512 + tiles - 1) / tiles, d.K / (2 * KALIGN));
     while (ks > 1 && (size_t)ks * nb * d.M * d.N > work_len) --ks;
     if (ks > 1) {
       a.ksplit = ks;
-      a.kchunk = ((d.K + ks - 1) / ks + BK - 1) / BK * BK;
+      a.kchunk = ((d.K + ks - 1) / ks + KALIGN - 1) / KALIGN * KALIGN;
       a.ksplit = (d.K + a.kchunk - 1) / a.kchunk;
       a.work = work;
     }
   }
   require((long)nb * a.ksplit <= 65535, IGA_EINVAL, "gemm2: batch too large");
   switch (variant) {
-    case 2: launch<4, 4, 1, 4>(s, a, (int)nb); break;
-    case 1: launch<8, 2, 1, 4>(s, a, (int)nb); break;
-    case 3: launch<8, 2, 4, 1>(s, a, (int)nb); break;
-    case 4: launch<8, 4, 2, 2>(s, a, (int)nb); break;
-    default: launch<8, 2, 2, 2>(s, a, (int)nb); break;
+    case 2: launch<4, 4, 1, 4, 16, 2>(s, a, (int)nb); break;
+    case 1: launch<8, 2, 1, 4, 16, 2>(s, a, (int)nb); break;
+    case 3: launch<8, 2, 4, 1, 16, 2>(s, a, (int)nb); break;
+    case 4: launch<8, 4, 2, 2, 16, 2>(s, a, (int)nb); break;
+    default: launch<8, 2, 2, 2, 16, 2>(s, a, (int)nb); break;
   }
   IGA_HIP(hipGetLastError());
   if (a.ksplit > 1) {
