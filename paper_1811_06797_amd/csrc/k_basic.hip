@@ -362,10 +362,19 @@ __global__ void copy2d_kernel(int m, int k, const double* in, long si, long sj, 
   }
 }
 
-__global__ void diag_kernel(int k, const double* H, double* out, int mode) {
+__global__ void diag_kernel(int k, const double* H, long step, double* out, int mode) {
   for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < k; j += gridDim.x * blockDim.x) {
-    const double v = H[(long)j * k + j];
+    const double v = H[(long)j * step];
     out[j] = mode ? (v > 0.0 ? 1.0 / sqrt(v) : 0.0) : v;
+  }
+}
+
+// out[j] = sum_i A[i][j] B[i][j] (one thread per column, fixed order)
+__global__ void coldot_kernel(int m, int k, const double* A, long lda, const double* B, long ldb, double* out) {
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < k; j += gridDim.x * blockDim.x) {
+    double a = 0.0;
+    for (int i = 0; i < m; ++i) a = fma(A[(long)i * lda + j], B[(long)i * ldb + j], a);
+    out[j] = a;
   }
 }
 
@@ -421,11 +430,19 @@ void copy2d(hipStream_t s, int m, int k, const double* in, long si, long sj, dou
 }
 
 void diag_invsqrt(hipStream_t s, int k, const double* H, double* out) {
-  diag_kernel<<<(k + 255) / 256, 256, 0, s>>>(k, H, out, 1);
+  diag_kernel<<<(k + 255) / 256, 256, 0, s>>>(k, H, k + 1, out, 1);
   IGA_HIP(hipGetLastError());
 }
 void diag_get(hipStream_t s, int k, const double* H, double* out) {
-  diag_kernel<<<(k + 255) / 256, 256, 0, s>>>(k, H, out, 0);
+  diag_kernel<<<(k + 255) / 256, 256, 0, s>>>(k, H, k + 1, out, 0);
+  IGA_HIP(hipGetLastError());
+}
+void vec_invsqrt(hipStream_t s, int k, const double* v, double* out) {
+  diag_kernel<<<(k + 255) / 256, 256, 0, s>>>(k, v, 1, out, 1);
+  IGA_HIP(hipGetLastError());
+}
+void coldots(hipStream_t s, int m, int k, const double* A, long lda, const double* B, long ldb, double* out) {
+  coldot_kernel<<<(k + 255) / 256, 256, 0, s>>>(m, k, A, lda, B, ldb, out);
   IGA_HIP(hipGetLastError());
 }
 

@@ -221,29 +221,26 @@ __device__ inline void circle_pair(int t, int round, int nplayers, int& a, int& 
   if (a > b) { const int x = a; a = b; b = x; }
 }
 
-// One round of the one-sided block Jacobi method: workgroup t takes the block pair (I, J)
-// of the round-robin schedule, forms the 32 x 32 Gram matrix of those columns of B,
-// diagonalises it by cyclic Jacobi in LDS, and applies the accumulated rotation to the
-// 32 columns of B (m rows) and of V (kv rows). flags[t] = 1 if anything rotated.
-__global__ __launch_bounds__(OST) void osbj_round_kernel(double* B, int m, long ldb, double* V, int kv,
-                                                         long ldv, int nb, int round, double tol,
-                                                         double floor_col, int* flags) {
-  __shared__ double G[OSP][OSP + 1];
-  __shared__ double W[OSP][OSP + 1];
+// One round of the one-sided block Jacobi method, in three launches so that the work over
+// the m rows spreads across the chip. The round-robin schedule pairs block I with block J;
+// for each pair:
+//   osbj_gram:  partial 32 x 32 Gram matrices of the pair's columns, one per chunk of rows;
+//   osbj_rot:   their sum (fixed order), diagonalised by cyclic Jacobi in LDS by one wave,
+//               giving the rotation W (32 x 32); flags[pair] = 1 if anything rotated;
+//   osbj_apply: [B_I B_J] <- [B_I B_J] W and [V_I V_J] <- [V_I V_J] W, chunk by chunk.
+__global__ __launch_bounds__(OST) void osbj_gram_kernel(const double* B, int m, long ldb, int nb, int round,
+                                                        int chunk, double* P) {
   __shared__ double T[OSR][OSP + 1];
-  __shared__ double cs[OSP / 2], sn[OSP / 2];
-  __shared__ int pp[OSP / 2], qq[OSP / 2];
-  __shared__ int rot_any, rot_sweep;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, pair = blockIdx.x, c = blockIdx.y;
   int I, J;
-  circle_pair(blockIdx.x, round, nb, I, J);
-  auto col = [&](int c) { return c < OSB ? I * OSB + c : J * OSB + (c - OSB); };
-  // Gram of the pair's columns, 4 entries per thread
+  circle_pair(pair, round, nb, I, J);
+  auto col = [&](int q) { return q < OSB ? I * OSB + q : J * OSB + (q - OSB); };
+  const int rb = c * chunk, re = min(m, rb + chunk);
   double acc[4] = {0, 0, 0, 0};
-  for (int r0 = 0; r0 < m; r0 += OSR) {
+  for (int r0 = rb; r0 < re; r0 += OSR) {
     for (int e = tid; e < OSR * OSP; e += OST) {
-      const int rr = e / OSP, c = e % OSP, row = r0 + rr;
-      T[rr][c] = row < m ? B[(long)row * ldb + col(c)] : 0.0;
+      const int rr = e / OSP, q = e % OSP, row = r0 + rr;
+      T[rr][q] = row < re ? B[(long)row * ldb + col(q)] : 0.0;
     }
     __syncthreads();
 #pragma unroll
@@ -255,16 +252,51 @@ __global__ __launch_bounds__(OST) void osbj_round_kernel(double* B, int m, long 
     }
     __syncthreads();
   }
+  double* out = P + ((long)pair * gridDim.y + c) * (OSP * OSP);
 #pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    const int e = tid + OST * s, i = e / OSP, j = e % OSP;
-    G[i][j] = acc[s];
+  for (int s = 0; s < 4; ++s) out[tid + OST * s] = acc[s];
+}
+
+constexpr int ORT = 256;  // threads per pair in osbj_rot
+// Inner Jacobi sweeps per pair and round. The pair's rotation need not diagonalise its Gram
+// matrix fully: the outer iteration revisits every pair each sweep and stops only when no
+// pair needs a rotation at the outer threshold.
+constexpr int OSBJ_INNER_SWEEPS = 1;
+
+// Gsum[pair] = sum over chunks of P[pair][chunk] (chunk order), 256 elements per workgroup,
+// eight chunks of loads in flight per thread.
+__global__ __launch_bounds__(256) void osbj_sum_kernel(const double* P, int nchunk, double* Gsum) {
+  const int pair = blockIdx.x, e = blockIdx.y * 256 + threadIdx.x;
+  const double* in = P + (long)pair * nchunk * (OSP * OSP) + e;
+  constexpr int CB = 8;
+  double a = 0.0;
+  for (int c0 = 0; c0 < nchunk; c0 += CB) {
+    double v[CB];
+#pragma unroll
+    for (int u = 0; u < CB; ++u) v[u] = c0 + u < nchunk ? in[(long)(c0 + u) * (OSP * OSP)] : 0.0;
+#pragma unroll
+    for (int u = 0; u < CB; ++u) a += v[u];
+  }
+  Gsum[(long)pair * (OSP * OSP) + e] = a;
+}
+
+__global__ __launch_bounds__(ORT) void osbj_rot_kernel(const double* Gsum, double tol, double floor_col,
+                                                       double* Wout, int* flags) {
+  __shared__ double G[OSP][OSP + 1];
+  __shared__ double W[OSP][OSP + 1];
+  __shared__ double cs[OSP / 2], sn[OSP / 2], dp[OSP / 2], dq[OSP / 2];
+  __shared__ int pp[OSP / 2], qq[OSP / 2];
+  __shared__ int rot_any, rot_sweep;
+  const int tid = threadIdx.x, pair = blockIdx.x;
+  const double* in = Gsum + (long)pair * (OSP * OSP);
+  for (int e = tid; e < OSP * OSP; e += ORT) {
+    const int i = e / OSP, j = e % OSP;
+    G[i][j] = in[e];
     W[i][j] = (i == j) ? 1.0 : 0.0;
   }
   if (tid == 0) rot_any = 0;
   __syncthreads();
-  // cyclic Jacobi on G (32 x 32), accumulating W <- W J
-  for (int sweep = 0; sweep < 20; ++sweep) {
+  for (int sweep = 0; sweep < OSBJ_INNER_SWEEPS; ++sweep) {
     if (tid == 0) rot_sweep = 0;
     __syncthreads();
     for (int r2 = 0; r2 < OSP - 1; ++r2) {
@@ -273,18 +305,21 @@ __global__ __launch_bounds__(OST) void osbj_round_kernel(double* B, int m, long 
         circle_pair(tid, r2, OSP, p, q);
         double c = 1.0, sv = 0.0;
         const double app = G[p][p], aqq = G[q][q], apq = G[p][q];
+        double np = app, nq = aqq;
         const bool negligible = app <= floor_col && aqq <= floor_col;
         if (!negligible && fabs(apq) > tol * sqrt(fabs(app * aqq))) {
           const double tau = (aqq - app) / (2.0 * apq);
           const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
           c = 1.0 / sqrt(1.0 + t * t);
           sv = t * c;
+          np = app - t * apq;
+          nq = aqq + t * apq;
           rot_sweep = 1;
         }
-        pp[tid] = p; qq[tid] = q; cs[tid] = c; sn[tid] = sv;
+        pp[tid] = p; qq[tid] = q; cs[tid] = c; sn[tid] = sv; dp[tid] = np; dq[tid] = nq;
       }
       __syncthreads();
-      for (int e = tid; e < (OSP / 2) * OSP; e += OST) {
+      for (int e = tid; e < (OSP / 2) * OSP; e += ORT) {
         const int t = e / OSP, j = e % OSP;
         const double sv = sn[t];
         if (sv == 0.0) continue;
@@ -295,7 +330,7 @@ __global__ __launch_bounds__(OST) void osbj_round_kernel(double* B, int m, long 
         G[q][j] = sv * gp + c * gq;
       }
       __syncthreads();
-      for (int e = tid; e < (OSP / 2) * OSP; e += OST) {
+      for (int e = tid; e < (OSP / 2) * OSP; e += ORT) {
         const int t = e / OSP, i = e % OSP;
         const double sv = sn[t];
         if (sv == 0.0) continue;
@@ -309,50 +344,102 @@ __global__ __launch_bounds__(OST) void osbj_round_kernel(double* B, int m, long 
         W[i][q] = sv * wp + c * wq;
       }
       __syncthreads();
+      // the rotated 2 x 2 block is diagonal by construction: store it exactly, so rounding
+      // noise in g_pq cannot trigger further rotations
+      if (tid < OSP / 2 && sn[tid] != 0.0) {
+        const int p = pp[tid], q = qq[tid];
+        G[p][q] = 0.0;
+        G[q][p] = 0.0;
+        G[p][p] = dp[tid];
+        G[q][q] = dq[tid];
+      }
+      __syncthreads();
     }
     const int any = rot_sweep;
     if (sweep == 0 && tid == 0) rot_any = any;
     __syncthreads();
     if (!any) break;
   }
-  if (!rot_any) {
-    if (tid == 0) flags[blockIdx.x] = 0;
-    return;
-  }
-  // [B_I B_J] <- [B_I B_J] W and [V_I V_J] <- [V_I V_J] W, tile by tile
-  for (int pass = 0; pass < 2; ++pass) {
-    double* X = pass == 0 ? B : V;
-    const int rows = pass == 0 ? m : kv;
-    const long ld = pass == 0 ? ldb : ldv;
-    for (int r0 = 0; r0 < rows; r0 += OSR) {
-      for (int e = tid; e < OSR * OSP; e += OST) {
-        const int rr = e / OSP, c = e % OSP, row = r0 + rr;
-        T[rr][c] = row < rows ? X[(long)row * ld + col(c)] : 0.0;
-      }
-      __syncthreads();
-      for (int e = tid; e < OSR * OSP; e += OST) {
-        const int rr = e / OSP, c = e % OSP, row = r0 + rr;
-        if (row >= rows) continue;
-        double a = 0.0;
-        for (int q = 0; q < OSP; ++q) a = fma(T[rr][q], W[q][c], a);
-        X[(long)row * ld + col(c)] = a;
-      }
-      __syncthreads();
+  double* out = Wout + (long)pair * (OSP * OSP);
+  for (int e = tid; e < OSP * OSP; e += ORT) out[e] = W[e / OSP][e % OSP];
+  if (tid == 0) flags[pair] = rot_any;
+}
+
+__global__ __launch_bounds__(OST) void osbj_apply_kernel(double* B, int m, long ldb, double* V, int kv, long ldv,
+                                                         int nb, int round, int chunk, int nchunkB,
+                                                         const double* Wg, const int* flags) {
+  __shared__ double W[OSP][OSP + 1];
+  __shared__ double T[OSR][OSP + 1];
+  const int tid = threadIdx.x, pair = blockIdx.x, c = blockIdx.y;
+  if (!flags[pair]) return;
+  int I, J;
+  circle_pair(pair, round, nb, I, J);
+  auto col = [&](int q) { return q < OSB ? I * OSB + q : J * OSB + (q - OSB); };
+  for (int e = tid; e < OSP * OSP; e += OST) W[e / OSP][e % OSP] = Wg[(long)pair * (OSP * OSP) + e];
+  const bool onB = c < nchunkB;
+  double* X = onB ? B : V;
+  const int rows = onB ? m : kv;
+  const long ld = onB ? ldb : ldv;
+  const int rb = (onB ? c : c - nchunkB) * chunk, re = min(rows, rb + chunk);
+  __syncthreads();
+  for (int r0 = rb; r0 < re; r0 += OSR) {
+    for (int e = tid; e < OSR * OSP; e += OST) {
+      const int rr = e / OSP, q = e % OSP, row = r0 + rr;
+      T[rr][q] = row < re ? X[(long)row * ld + col(q)] : 0.0;
     }
+    __syncthreads();
+    for (int e = tid; e < OSR * OSP; e += OST) {
+      const int rr = e / OSP, q = e % OSP, row = r0 + rr;
+      if (row >= re) continue;
+      double a = 0.0;
+      for (int t = 0; t < OSP; ++t) a = fma(T[rr][t], W[t][q], a);
+      X[(long)row * ld + col(q)] = a;
+    }
+    __syncthreads();
   }
-  if (tid == 0) flags[blockIdx.x] = 1;
 }
 
 }  // namespace
 
+static int osbj_chunk(int m, int nb) {
+  // rows per chunk: enough chunks that the gram and apply launches hold ~512 workgroups
+  const int npair = nb / 2;
+  const int want = std::max(1, 512 / npair);
+  int chunk = (m + want - 1) / want;
+  chunk = ((chunk + OSR - 1) / OSR) * OSR;
+  return std::max(chunk, OSR);
+}
+
+size_t osbj_work_len(int m, int kv, int nb) {
+  const int chunk = osbj_chunk(m, nb);
+  const long nchunk = (m + chunk - 1) / chunk;
+  (void)kv;
+  return (size_t)(nb / 2) * (nchunk + 2) * (OSP * OSP);
+}
+
 void osbj_round(hipStream_t s, double* B, int m, long ldb, double* V, int kv, long ldv, int nb, int round,
-                double tol, double floor_col, int* flags) {
+                double tol, double floor_col, int* flags, double* work, size_t work_len) {
   require(nb >= 2 && nb % 2 == 0, IGA_EINVAL, "osbj_round: block count must be even");
-  osbj_round_kernel<<<nb / 2, OST, 0, s>>>(B, m, ldb, V, kv, ldv, nb, round, tol, floor_col, flags);
+  require(m >= 1 && kv >= 0, IGA_EINVAL, "osbj_round: bad sizes");
+  require(work_len >= osbj_work_len(m, kv, nb), IGA_EINVAL, "osbj_round: workspace too small");
+  const int npair = nb / 2, chunk = osbj_chunk(m, nb);
+  const int nchunkB = (m + chunk - 1) / chunk, nchunkV = (kv + chunk - 1) / chunk;
+  double* P = work;
+  double* Gs = work + (size_t)npair * nchunkB * (OSP * OSP);
+  double* Wg = Gs + (size_t)npair * (OSP * OSP);
+  osbj_gram_kernel<<<dim3(npair, nchunkB), OST, 0, s>>>(B, m, ldb, nb, round, chunk, P);
+  IGA_HIP(hipGetLastError());
+  osbj_sum_kernel<<<dim3(npair, OSP * OSP / 256), 256, 0, s>>>(P, nchunkB, Gs);
+  IGA_HIP(hipGetLastError());
+  osbj_rot_kernel<<<npair, ORT, 0, s>>>(Gs, tol, floor_col, Wg, flags);
+  IGA_HIP(hipGetLastError());
+  osbj_apply_kernel<<<dim3(npair, nchunkB + nchunkV), OST, 0, s>>>(B, m, ldb, V, kv, ldv, nb, round, chunk,
+                                                                   nchunkB, Wg, flags);
   IGA_HIP(hipGetLastError());
 }
 
 int osbj_block() { return OSB; }
+int jacobi_lds_max() { return LDS_MAX_K; }
 
 void jacobi_eig(hipStream_t s, int nmat, int k, double* H, long strideH, double* W, long strideW,
                 double tol, int max_sweeps, int* sweeps_out) {

@@ -138,6 +138,10 @@ void copy2d(hipStream_t s, int m, int k, const double* in, long si, long sj, dou
 void diag_invsqrt(hipStream_t s, int k, const double* H, double* out);
 // out[j] = H[j][j]
 void diag_get(hipStream_t s, int k, const double* H, double* out);
+// out[j] = 1/sqrt(v[j]) (0 if v[j] <= 0)
+void vec_invsqrt(hipStream_t s, int k, const double* v, double* out);
+// out[j] = sum_i A[i][j] B[i][j], j < k (row-major, leading dimensions lda, ldb)
+void coldots(hipStream_t s, int m, int k, const double* A, long lda, const double* B, long ldb, double* out);
 
 // Symmetric Jacobi eigen-decomposition, one workgroup per matrix, nmat matrices of size k
 // (k <= 1024): H (in: symmetric, out: diagonal holds the eigenvalues), WT (out: row i is
@@ -148,9 +152,13 @@ void jacobi_eig(hipStream_t s, int nmat, int k, double* H, long strideH, double*
                 double tol, int max_sweeps, int* sweeps_out);
 // One round of the one-sided block Jacobi SVD on B (m x kp, kp = nb * osbj_block(), nb even)
 // with V (kv x kp) accumulated; flags[nb/2] receive 1 for pairs that rotated.
+// work holds osbj_work_len(m, kv, nb) doubles (partial Gram matrices and pair rotations).
 void osbj_round(hipStream_t s, double* B, int m, long ldb, double* V, int kv, long ldv, int nb, int round,
-                double tol, double floor_col, int* flags);
+                double tol, double floor_col, int* flags, double* work, size_t work_len);
+size_t osbj_work_len(int m, int kv, int nb);
 int osbj_block();
+// largest k for which jacobi_eig keeps the matrix in LDS
+int jacobi_lds_max();
 void transpose_square(hipStream_t s, int nmat, int k, const double* in, long sin, double* out,
                       long sout);
 // out[i][j] = in[i][idx[j]] * (scale ? scale[j] : 1), i < m, j < kout

@@ -298,12 +298,15 @@ void svd(iga_ctx* ctx, const double* A, int m, int k, long lda, bool trans, Svd&
   const double tol = 4e-16 * std::max(1.0, std::sqrt((double)m));
   const int npair = nb / 2, nround = nb - 1;
   IBuf flags(ctx, (size_t)npair * nround);
+  const size_t wlen = k::osbj_work_len(m, kp, nb);
+  DBuf work(ctx, wlen);
   std::vector<int> hf((size_t)npair * nround);
   int sweeps = 0;
   if (fro2 > 0) {
     for (int sweep = 0; sweep < 30; ++sweep) {
       for (int rd = 0; rd < nround; ++rd)
-        k::osbj_round(st, B.get(), m, kp, V.get(), kp, kp, nb, rd, tol, floor_col, flags.get() + rd * npair);
+        k::osbj_round(st, B.get(), m, kp, V.get(), kp, kp, nb, rd, tol, floor_col, flags.get() + rd * npair,
+                     work.get(), wlen);
       IGA_HIP(hipMemcpyAsync(hf.data(), flags.get(), hf.size() * sizeof(int), hipMemcpyDeviceToHost, st));
       IGA_HIP(hipStreamSynchronize(st));
       ++sweeps;
@@ -347,28 +350,45 @@ int trunc_rank(const std::vector<double>& sigma, double abs_tol, int rmax, int r
   return r;
 }
 
+// Symmetric eigen-decomposition X = Vc diag(lam) Vc^T (Vc: eigenvectors in columns, k x k).
+// Small k: two-sided cyclic Jacobi in one workgroup's LDS. Larger k (X positive
+// semidefinite here: mass and stiffness interfaces): the one-sided block Jacobi SVD of X,
+// whose right singular vectors are the eigenvectors, with lam_j = v_j^T X v_j.
+static void eig_sym(iga_ctx* ctx, int k, const double* X, double* Vc, double* lam) {
+  hipStream_t st = ctx->stream;
+  if (k <= k::jacobi_lds_max()) {
+    DBuf H(ctx, (size_t)k * k), WT(ctx, (size_t)k * k);
+    IGA_HIP(hipMemcpyAsync(H.get(), X, (size_t)k * k * sizeof(double), hipMemcpyDeviceToDevice, st));
+    k::jacobi_eig(st, 1, k, H.get(), 0, WT.get(), 0, 1e-15, 60, nullptr);
+    k::diag_get(st, k, H.get(), lam);
+    k::transpose_square(st, 1, k, WT.get(), 0, Vc, 0);
+    return;
+  }
+  Svd s;
+  svd(ctx, X, k, k, k, false, s);
+  IGA_HIP(hipMemcpyAsync(Vc, s.V.get(), (size_t)k * k * sizeof(double), hipMemcpyDeviceToDevice, st));
+  k::coldots(st, k, k, s.V.get(), k, s.B.get(), k, lam);
+}
+
 void gen_eig(iga_ctx* ctx, int k, const double* A, const double* B, double* V, double* lam) {
   hipStream_t st = ctx->stream;
-  DBuf H(ctx, (size_t)k * k), UT(ctx, (size_t)k * k), d(ctx, k), Sm(ctx, (size_t)k * k),
-      T(ctx, (size_t)k * k), C(ctx, (size_t)k * k), ZT(ctx, (size_t)k * k);
+  DBuf U(ctx, (size_t)k * k), d(ctx, k), lb(ctx, k), Sm(ctx, (size_t)k * k), T(ctx, (size_t)k * k),
+      C(ctx, (size_t)k * k), Z(ctx, (size_t)k * k);
   IBuf idx(ctx, k);
-  // B = U D U^T ; S = U D^{-1/2} (S^T B S = I)
-  IGA_HIP(hipMemcpyAsync(H.get(), B, (size_t)k * k * sizeof(double), hipMemcpyDeviceToDevice, st));
-  k::jacobi_eig(st, 1, k, H.get(), 0, UT.get(), 0, 1e-15, 60, nullptr);
-  k::diag_invsqrt(st, k, H.get(), d.get());
+  // B = U diag(lb) U^T ; S = U diag(lb)^{-1/2} (S^T B S = I)
+  eig_sym(ctx, k, B, U.get(), lb.get());
+  k::vec_invsqrt(st, k, lb.get(), d.get());
   std::vector<int> id(k);
   std::iota(id.begin(), id.end(), 0);
   IGA_HIP(hipMemcpyAsync(idx.get(), id.data(), k * sizeof(int), hipMemcpyHostToDevice, st));
-  // S[i][j] = U[i][j] d[j] = UT[j][i] d[j]: transpose UT then scale columns
-  k::transpose_square(st, 1, k, UT.get(), 0, T.get(), 0);
-  k::gather_cols(st, k, k, k, T.get(), k, idx.get(), d.get(), Sm.get(), k);
-  // C = S^T A S
+  k::gather_cols(st, k, k, k, U.get(), k, idx.get(), d.get(), Sm.get(), k);
+  // C = S^T A S, symmetrised against rounding
   k::gemm_rm(st, k, k, k, A, k, false, Sm.get(), k, false, T.get(), k);
   k::gemm_rm(st, k, k, k, Sm.get(), k, true, T.get(), k, false, C.get(), k);
-  k::jacobi_eig(st, 1, k, C.get(), 0, ZT.get(), 0, 1e-15, 60, nullptr);
-  k::diag_get(st, k, C.get(), lam);
-  // V = S Z = S ZT^T
-  k::gemm_rm(st, k, k, k, Sm.get(), k, false, ZT.get(), k, true, V, k);
+  k::symmetrize(st, 1, k, C.get(), 0);
+  eig_sym(ctx, k, C.get(), Z.get(), lam);
+  // V = S Z
+  k::gemm_rm(st, k, k, k, Sm.get(), k, false, Z.get(), k, false, V, k);
   IGA_HIP(hipStreamSynchronize(st));
 }
 
