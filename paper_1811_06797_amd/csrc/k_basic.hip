@@ -446,7 +446,26 @@ void coldots(hipStream_t s, int m, int k, const double* A, long lda, const doubl
   IGA_HIP(hipGetLastError());
 }
 
-void gemm(hipStream_t s, const Gemm& g) { launch_gemm<double>(s, g); }
+// FP64 products run on the matrix cores: the (ko, k) contraction index is the two-level K
+// of gemm2 (outer stride s*ko, inner stride s*k).
+void gemm(hipStream_t s, const Gemm& g) {
+  if (g.M <= 0 || g.N <= 0) return;
+  Gemm2 d;
+  d.M = g.M; d.N = g.N; d.K = g.K * g.Kout; d.K2 = std::max(g.K, 1);
+  d.A = g.A; d.sAm2 = g.sAm; d.sAk1 = g.sAko; d.sAk2 = g.sAk;
+  d.B = g.B; d.sBk1 = g.sBko; d.sBk2 = g.sBk; d.sBn2 = g.sBn;
+  d.C = g.C; d.sCm2 = g.sCm; d.sCn2 = g.sCn;
+  d.nb1 = g.nb1; d.nb2 = g.nb2;
+  d.sAb1 = g.sAb1; d.sAb2 = g.sAb2; d.sBb1 = g.sBb1; d.sBb2 = g.sBb2; d.sCb1 = g.sCb1; d.sCb2 = g.sCb2;
+  d.alpha = g.alpha; d.beta = g.beta;
+  if (d.K == 0) {
+    // empty contraction: C = beta C
+    require(g.nb1 == 1 && g.nb2 == 1, IGA_EINVAL, "gemm: empty batched contraction");
+    launch_gemm<double>(s, g);
+    return;
+  }
+  gemm2(s, d);
+}
 void gemm_f32(hipStream_t s, const GemmF& g) { launch_gemm<float>(s, g); }
 
 void gemm_rm(hipStream_t s, int M, int N, int K, const double* A, long lda, bool tA,

@@ -31,7 +31,7 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(int k, double* Hs, long sH, 
   if (USE_LDS)
     for (int e = tid; e < k * k; e += nt) H[(e / k) * ld + e % k] = Hg[e];
   for (int e = tid; e < k * k; e += nt) WT[e] = (e / k == e % k) ? 1.0 : 0.0;
-  __shared__ double cs[JT / 2], sn[JT / 2];
+  __shared__ double cs[JT / 2], sn[JT / 2], dp[JT / 2], dq[JT / 2];
   __shared__ int pp[JT / 2], qq[JT / 2];
   __shared__ int rotated;
   __shared__ double trace;
@@ -56,7 +56,7 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(int k, double* Hs, long sH, 
         auto player = [&](int pos) { return pos == 0 ? 0 : 1 + (pos - 1 + round) % (kk - 1); };
         int p = player(t), q = player(kk - 1 - t);
         if (p > q) { int tmp = p; p = q; q = tmp; }
-        double c = 1.0, s = 0.0;
+        double c = 1.0, s = 0.0, np = 0.0, nq = 0.0;
         if (q < k) {
           const double app = H[p * ld + p], aqq = H[q * ld + q], apq = H[p * ld + q];
           const double thr = fmax(tol * sqrt(fabs(app * aqq)), floor_abs);
@@ -67,10 +67,12 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(int k, double* Hs, long sH, 
             const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
             c = 1.0 / sqrt(1.0 + tt * tt);
             s = tt * c;
+            np = app - tt * apq;
+            nq = aqq + tt * apq;
             rotated = 1;
           }
         }
-        pp[t] = p; qq[t] = q; cs[t] = c; sn[t] = s;
+        pp[t] = p; qq[t] = q; cs[t] = c; sn[t] = s; dp[t] = np; dq[t] = nq;
       }
       __syncthreads();
       // rows p, q of H and WT
@@ -98,6 +100,17 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(int k, double* Hs, long sH, 
         const double hp = H[i * ld + p], hq = H[i * ld + q];
         H[i * ld + p] = c * hp - s * hq;
         H[i * ld + q] = s * hp + c * hq;
+      }
+      __syncthreads();
+      // each rotated 2 x 2 block is diagonal by construction: store it exactly, so that
+      // rounding noise left in h_pq cannot keep the sweeps going
+      for (int t = tid; t < npair; t += nt) {
+        if (sn[t] == 0.0) continue;
+        const int p = pp[t], q = qq[t];
+        H[p * ld + q] = 0.0;
+        H[q * ld + p] = 0.0;
+        H[p * ld + p] = dp[t];
+        H[q * ld + q] = dq[t];
       }
       __syncthreads();
     }
