@@ -1,33 +1,48 @@
 """Benchmark of the low-rank IgA optimal-control hot path on one MI355X.
 
-One step = the whole path on one synthetic workload: TT assembly of M and K
-(assemble_factors), the KKT operator (kkt_create) and the block-AMEn solve to
-a KKT relative residual below 1e-6 (amen_solve), in FP64. The workload is the
-twisted quarter annulus (radii 1, 2, seeded twist), degree 3, n = 64 free
-dofs per direction (262,144 dofs per field), beta = 1e-6, Fourier desired
-state, weight TT tolerance 1e-10. Inputs (control points, desired-state TT)
-are synthetic and seeded.
+One step = the whole path on one synthetic workload, in FP64: TT assembly of the
+Kronecker factors of M and K (assemble_factors), the KKT operator (kkt_create)
+and the block-AMEn solve (amen_solve) to the AMEn tolerance 1e-7, which puts the
+KKT relative residual below 1e-6. Workload: twisted quarter annulus (radii 1 and
+2, height 1, seeded twist), degree 3, n = 64 free dofs per direction (262,144
+dofs per field, 786,432 KKT unknowns), beta = 1e-6, Fourier desired state,
+weight TT tolerance 1e-10. Inputs (control points, desired-state TT cores) are
+seeded and synthetic and are uploaded before the timed region.
 
-Printed JSON line: metric value = local TT-matvec GFLOP/s inside the timed
-solves (algorithmic flops of every projected local matvec / their GPU time,
-HIP events on the library's stream), plus the solve time, the residual, a
-roofline object for the dominant kernel and the CPU oracle baseline.
+Printed JSON line:
+  value      local TT-matvec GFLOP/s inside the timed solves: algorithmic flops of
+             every projected local matvec (banded middle stage counted over the band
+             and the nonzero rank blocks) / their GPU time (HIP events on the
+             library stream);
+  solve_time_s, kkt_residual, per-part solve times, ranks;
+  roofline   the dominant kernel of the local TT-matvec at the microbenchmark shape
+             (r, R_M, R_K, n, p) = (32, 10, 60, 64, 3): the banded middle stage of
+             the K operator, timed by the library with HIP events on its stream;
+             traffic from the committed rocprofv3 counter summary when it was taken
+             from the current kernel source, else null;
+  cpu_baseline  the oracle's local TT-matvec (numpy FP64) at the same shape, timed on
+             the host cores of this machine on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 (vector and matrix)
-PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 (matrix cores)
+MICRO = dict(r=32, RM=10, RK=60, n=64, p=3)
+COPY_BYTES = 256 << 20
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "band_stage_K_c2shape_traffic.txt")
+KERNEL_SOURCES = ["paper_1811_06797_amd/csrc/k_gemm.hip", "paper_1811_06797_amd/csrc/localop.cpp"]
 
 
 def parse():
@@ -40,16 +55,33 @@ def parse():
     return ap.parse_args()
 
 
-def local_shapes_micro():
-    # projected local TT-matvec at the n = 64 benchmark shape (r, R_M, R_K, n, p)
-    return dict(r=32, RM=10, RK=60, n=64, p=3)
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile():
+    """HBM bytes per launch of the dominant kernel from the committed counter summary, if it
+    was taken from the current kernel sources (else None)."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    txt = open(TRAFFIC_FILE).read()
+    m_hash = re.search(r"^source_hash:\s*(\S+)", txt, re.M)
+    m_bytes = re.search(r"^traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt, re.M)
+    if not (m_hash and m_bytes) or m_hash.group(1) != kernel_source_hash():
+        return None
+    return float(m_bytes.group(1))
 
 
 def micro_bench(iga, ctx, torch, iters):
-    """Time iga_local_matvec on seeded random inputs at the benchmark shape with HIP events."""
+    """Local TT-matvec at the microbenchmark shape on seeded N(0,1) inputs; the library times
+    the banded stage of each operator with HIP events on its stream."""
     import numpy as np
     import synth
-    s = local_shapes_micro()
+    s = MICRO
     prob = synth.random_local_problem(s["r"], s["RM"], s["RK"], s["n"], s["p"], seed=1)
     dev = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda() for k, v in prob.items()}
     y = torch.empty_like(dev["x"])
@@ -57,25 +89,34 @@ def micro_bench(iga, ctx, torch, iters):
             dev["PhiR_M"], dev["PhiL_K"], dev["PhiR_K"], dev["M"], dev["K"], 1e-6, dev["x"], y)
     for _ in range(3):
         iga.local_matvec(*args)
+    # a plain device copy of known size (256 MiB read, 256 MiB written): the reference that
+    # scales the HBM counters (FETCH_SIZE, WRITE_SIZE) in a counter run of this program
+    src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
     torch.cuda.synchronize()
+    del src, dst
+    stream = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
+    iga.profile_start(ctx)
+    e0.record(stream)
     for _ in range(iters):
         iga.local_matvec(*args)
-    e1.record()
+    e1.record(stream)
+    prof = iga.profile_stop(ctx)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / iters
     flops = iga.local_matvec_flops(s["r"], s["n"], s["r"], s["p"], s["RM"], s["RM"], s["RK"], s["RK"])
-    return {"shape": s, "ms": ms, "gflops": flops / ms / 1e6, "flops": flops}, prob
+    return {"shape": dict(s), "ms": ms, "gflops": flops / ms / 1e6, "flops": flops, "profile": prof}, prob
 
 
-def cpu_baseline(prob, budget_s=15.0):
-    """The oracle's local projected matvec (numpy FP64) at the same shape, timed on the host."""
-    import numpy as np
+def cpu_baseline(prob, budget_s=12.0, max_calls=400):
+    """The oracle's local projected matvec (numpy FP64 einsum stages) at the microbenchmark
+    shape, timed on the host cores."""
     from oracle import tt
     from paper_1811_06797_amd import iga
-    s = local_shapes_micro()
+    s = MICRO
     Md = tt.banded_to_dense(prob["M"], s["p"])
     Kd = tt.banded_to_dense(prob["K"], s["p"])
     x = prob["x"]
@@ -88,7 +129,7 @@ def cpu_baseline(prob, budget_s=15.0):
         for l in (0, 2):
             tt.local_apply(prob["PhiL_K"], Kd, prob["PhiR_K"], x[l])
         calls += 1
-        if time.perf_counter() - t0 > budget_s or calls >= 50:
+        if time.perf_counter() - t0 > budget_s or calls >= max_calls:
             break
     dt = time.perf_counter() - t0
     try:
@@ -97,14 +138,16 @@ def cpu_baseline(prob, budget_s=15.0):
     except Exception:
         threads = os.cpu_count() or 1
     return {"value": flops * calls / dt / 1e9, "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
-            "sample": "%d calls of the oracle's einsum local projected matvec (3 M + 2 K applications) "
-                      "at (r, R_M, R_K, n, p) = (32, 10, 60, 64, 3), %.1f s" % (calls, dt)}
+            "sample": "%d local projected matvecs (3 M + 2 K operator applications each) of the oracle's "
+                      "numpy einsum stages at (r, R_M, R_K, n, p) = (32, 10, 60, 64, 3), %.1f s, "
+                      "os.cpu_count() = %s" % (calls, dt, os.cpu_count())}
 
 
 def main():
     a = parse()
     if a.gpus != 1:
-        print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
+        print("bench.py: this implementation runs on one GPU; multi-GPU runs are not supported "
+              "(use --gpus 1)", file=sys.stderr)
         sys.exit(2)
     import torch
     import synth
@@ -119,11 +162,15 @@ def main():
     torch.cuda.synchronize()
 
     def step():
+        t0 = time.perf_counter()
         M, K, ranks = iga.assemble_factors(ctx, geo, p, n, weight_tol=c["weight_tol"])
         kk = iga.kkt_create(ctx, M, K, beta)
-        t = time.perf_counter()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
         sol, st, rc = iga.amen_solve(ctx, kk, Y, c["tol"])
-        st["solve_wall_s"] = time.perf_counter() - t
+        t2 = time.perf_counter()
+        st["assembly_s"] = t1 - t0
+        st["solve_wall_s"] = t2 - t1
         st["rc"] = rc
         st["op_ranks"] = [iga.ttop_info(M)[1], iga.ttop_info(K)[1]]
         iga.btt_destroy(sol)
@@ -144,8 +191,13 @@ def main():
     flops = sum(s["local_matvec_flops"] for s in stats)
     t_mv = sum(s["t_local_matvec"] for s in stats)
     gflops = flops / t_mv / 1e9
-    solve_s = sum(s["solve_wall_s"] for s in stats) / len(stats)
     micro, prob = micro_bench(iga, ctx, torch, a.micro_iters)
+    prof = micro["profile"]
+    k_ms = prof["ms"][1] / max(prof["launches"][1], 1)
+    k_flops = prof["flops"][1] / max(prof["launches"][1], 1)
+    achieved = k_flops / (k_ms * 1e-3) / 1e12
+    traffic = traffic_from_profile()
+    last = stats[-1]
 
     line = {
         "metric": "local TT-matvec GFLOP/s + KKT solve time to 1e-6 residual, mixed vs FP64",
@@ -159,25 +211,28 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": "twisted quarter annulus, p=3, n=64 per direction (262,144 dofs), "
-                               "beta=1e-6, Fourier desired state, weight TT tol 1e-10, AMEn tol %g" % c["tol"],
-                   "global_batch": 1, "parallelism": "single GPU"},
-        "solve_time_s": solve_s,
+        "data": "synthetic (seeded twisted-annulus geometry and Fourier desired state)",
+        "config": {"workload": "twisted quarter annulus, degree 3, n = 64 free dofs per direction "
+                               "(262,144 per field), beta = 1e-6, Fourier desired state, weight TT tol 1e-10, "
+                               "block-AMEn tol %g, FP64" % c["tol"]},
+        "solve_time_s": sum(s["solve_wall_s"] for s in stats) / len(stats),
+        "assembly_time_s": sum(s["assembly_s"] for s in stats) / len(stats),
         "kkt_residual": max(s["residual"] for s in stats),
-        "solve": {k: stats[-1][k] for k in ("half_sweeps", "ranks", "local_solves", "local_iterations",
-                                            "local_matvecs", "t_local_matvec", "t_precond", "t_svd",
-                                            "t_interfaces", "t_krylov_other", "op_ranks")},
-        "microbench_local_matvec": micro,
-        "roofline": {"bound": "mfma", "achieved": micro["gflops"] / 1e3, "peak": PEAK_FP64_TFLOPS,
-                     "unit": "TFLOP/s", "frac": micro["gflops"] / 1e3 / PEAK_FP64_TFLOPS, "traffic": None,
-                     "kernel": "projected local TT-matvec at (r, R_M, R_K, n, p) = (32, 10, 60, 64, 3)"},
+        "solve": {k: last[k] for k in ("half_sweeps", "ranks", "local_solves", "local_iterations", "local_matvecs",
+                                       "local_matvec_flops", "t_local_matvec", "t_precond", "t_svd",
+                                       "t_interfaces", "t_krylov_other", "t_residual", "op_ranks")},
+        "microbench_local_matvec": {k: micro[k] for k in ("shape", "ms", "gflops", "flops")},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
+                     "kernel": "gemm2_kernel<8, 4, 2, 2, 16, 2>: banded middle stage of the K operator in the "
+                               "local TT-matvec at (r, R_M, R_K, n, p) = (32, 10, 60, 64, 3)",
+                     "flops_per_launch": k_flops, "ms_per_launch": k_ms, "launches": prof["launches"][1]},
     }
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(prob)
     iga.tt_destroy(Y)
     iga.ctx_destroy(ctx)
-    print(json.dumps(line))
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

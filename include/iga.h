@@ -215,6 +215,24 @@ int iga_local_matvec(iga_ctx* ctx, int r0, int n, int r1, int degree, int RM0, i
 /* Algorithmic flops of one iga_local_matvec call with these sizes. */
 double iga_local_matvec_flops(int r0, int n, int r1, int degree, int RM0, int RM1, int RK0, int RK1);
 
+/* Event timing of the banded (middle) stage of the projected local TT-matvec, the
+ * contraction of the operator core with the band of t1 = PhiL x (eq. KKT_red), for
+ * measurement. Between iga_profile_start and iga_profile_stop every local matvec on the
+ * context (inside iga_amen_solve or iga_local_matvec, FP64 form) records a HIP event pair
+ * on the context stream around that stage, per operator (index 0: M, 1: K). stop
+ * synchronises the stream and returns: stages (banded stages timed), launches (kernel
+ * launches inside them: one per nonzero rank block of the core), ms (summed event time)
+ * and flops (algorithmic flops: banded nonzeros times nonzero rank blocks). out may be
+ * NULL. Calls on one context must not overlap. */
+typedef struct {
+  long stages[2];
+  long launches[2];
+  double ms[2];
+  double flops[2];
+} iga_profile;
+int iga_profile_start(iga_ctx* ctx);
+int iga_profile_stop(iga_ctx* ctx, iga_profile* out);
+
 const char* iga_last_error(void);
 
 #ifdef __cplusplus

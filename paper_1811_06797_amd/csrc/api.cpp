@@ -173,6 +173,7 @@ void iga_ctx_destroy(iga_ctx* ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
+  for (hipEvent_t e : ctx->prof_events) (void)hipEventDestroy(e);
   release_scratch(ctx);
   release_raw_cache(ctx);
   delete ctx;
@@ -513,6 +514,40 @@ int iga_local_matvec(iga_ctx* ctx, int r0, int n, int r1, int degree, int RM0, i
     use_device(ctx);
     local_matvec_impl(ctx, r0, n, r1, degree, RM0, RM1, RK0, RK1, PhiL_M, PhiR_M, PhiL_K, PhiR_K, Mcore,
                       Kcore, beta, x, y, precision);
+    return IGA_OK;
+  });
+}
+
+int iga_profile_start(iga_ctx* ctx) {
+  return guarded([&] {
+    require(ctx != nullptr, IGA_EINVAL, "profile_start: NULL context");
+    use_device(ctx);
+    IGA_HIP(hipStreamSynchronize(ctx->stream));
+    ctx->prof.clear();
+    ctx->prof_next = 0;
+    ctx->prof_on = true;
+    return IGA_OK;
+  });
+}
+
+int iga_profile_stop(iga_ctx* ctx, iga_profile* out) {
+  return guarded([&] {
+    require(ctx != nullptr, IGA_EINVAL, "profile_stop: NULL context");
+    use_device(ctx);
+    ctx->prof_on = false;
+    IGA_HIP(hipStreamSynchronize(ctx->stream));
+    iga_profile r{};
+    for (const auto& p : ctx->prof) {
+      float ms = 0.0f;
+      IGA_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+      r.launches[p.op] += p.launches;
+      r.stages[p.op] += 1;
+      r.ms[p.op] += ms;
+      r.flops[p.op] += p.flops;
+    }
+    ctx->prof.clear();
+    ctx->prof_next = 0;
+    if (out) *out = r;
     return IGA_OK;
   });
 }

@@ -60,6 +60,17 @@ struct iga_ctx {
   hipStream_t stream = nullptr;
   std::unique_ptr<iga::Pool> pool;
   hipEvent_t ev[2] = {nullptr, nullptr};
+  // optional event timing of the banded stage of the local matvec (iga_profile_*)
+  struct ProfRec {
+    hipEvent_t a, b;
+    int op;  // 0: M, 1: K
+    int launches;
+    double flops;
+  };
+  bool prof_on = false;
+  std::vector<ProfRec> prof;
+  std::vector<hipEvent_t> prof_events;  // created events, reused
+  size_t prof_next = 0;                 // next unused entry of prof_events
 };
 
 namespace iga {

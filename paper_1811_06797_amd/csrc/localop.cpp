@@ -10,6 +10,16 @@
 
 namespace iga {
 
+// An event from the context's reusable set (created on first use).
+static hipEvent_t prof_event(iga_ctx* ctx) {
+  if (ctx->prof_next == ctx->prof_events.size()) {
+    hipEvent_t e;
+    IGA_HIP(hipEventCreate(&e));
+    ctx->prof_events.push_back(e);
+  }
+  return ctx->prof_events[ctx->prof_next++];
+}
+
 double band_nnz(int n, int p) {
   double s = 0;
   for (int i = 0; i < n; ++i) s += std::min(n - 1, i + p) - std::max(0, i - p) + 1;
@@ -37,7 +47,7 @@ double local_flops(const LocalOp& L) {
 static void op_apply_mfma(iga_ctx* ctx, const OpView& A, const std::vector<RankBlock>& blocks,
                           const double* PhiL, const double* PhiR, int r0o, int r0, int r1, int r1o, int ncol,
                           const double* x, long xcs, double* z, long zcs, DBuf& t1, DBuf& t2,
-                          DBuf& wk, LocalWork::PadKey& pad) {
+                          DBuf& wk, LocalWork::PadKey& pad, int op_id) {
   hipStream_t st = ctx->stream;
   const int n = A.n, p = A.p, b = 2 * p + 1, R0 = A.R0, R1 = A.R1;
   const long S2 = (long)r0o * r1;         // one (c) slab of (a', b)
@@ -60,6 +70,12 @@ static void op_apply_mfma(iga_ctx* ctx, const OpView& A, const std::vector<RankB
   g1.nb1 = ncol; g1.sBb1 = xcs; g1.sCb1 = S2;
   k::gemm2(st, g1);
   // stage 2: per rank block, batched over rows i
+  hipEvent_t pa = nullptr, pb = nullptr;
+  if (ctx->prof_on) {
+    pa = prof_event(ctx);
+    pb = prof_event(ctx);
+    IGA_HIP(hipEventRecord(pa, st));
+  }
   for (const RankBlock& rb : blocks) {
     k::Gemm2 g2;
     g2.M = rb.nb; g2.N = (int)S1; g2.K = rb.na * b; g2.K2 = rb.na;
@@ -69,6 +85,12 @@ static void op_apply_mfma(iga_ctx* ctx, const OpView& A, const std::vector<RankB
     g2.C = t2.get() + rb.b0 * S1; g2.sCm2 = S1; g2.sCn2 = 1;
     g2.nb1 = n; g2.sAb1 = (long)b * R1; g2.sBb1 = SJ; g2.sCb1 = (long)R1 * S1;
     k::gemm2(st, g2);
+  }
+  if (ctx->prof_on) {
+    IGA_HIP(hipEventRecord(pb, st));
+    double nz = 0;
+    for (const RankBlock& rb : blocks) nz += (double)rb.na * rb.nb;
+    ctx->prof.push_back({pa, pb, op_id, (int)blocks.size(), 2.0 * r0o * r1 * ncol * nz * band_nnz(n, p)});
   }
   // stage 3: z[c][(a' i)][b'] = sum_{(g, b)} t2[i][g][c][a'][b] PhiR[g][b'][b]
   k::Gemm2 g3;
@@ -88,9 +110,9 @@ void local_matvec(iga_ctx* ctx, const LocalOp& L, const double* x, double* y, Lo
   const long osz = (long)r0o * L.n * r1o;  // one output column
   w.z.ensure(ctx, (size_t)5 * osz);
   op_apply_mfma(ctx, L.M, L.Mblocks, L.PhiL_M, L.PhiR_M, r0o, L.r0, L.r1, r1o, 3, x, colsz, w.z.get(), osz,
-                w.tM, w.tM2, w.split, w.padM);
+                w.tM, w.tM2, w.split, w.padM, 0);
   op_apply_mfma(ctx, L.K, L.Kblocks, L.PhiL_K, L.PhiR_K, r0o, L.r0, L.r1, r1o, 2, x, 2 * colsz,
-                w.z.get() + 3 * osz, osz, w.tK, w.tK2, w.split, w.padK);
+                w.z.get() + 3 * osz, osz, w.tK, w.tK2, w.split, w.padK, 1);
   k::kkt_combine(ctx->stream, osz, L.coef, w.z.get(), w.z.get() + 3 * osz, y);
 }
 

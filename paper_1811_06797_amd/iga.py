@@ -30,7 +30,7 @@ EXPORTED = [
     "iga_ttop_get_core", "iga_ttop_destroy", "iga_tt_create", "iga_tt_wrap", "iga_tt_destroy",
     "iga_btt_create", "iga_btt_info", "iga_btt_get_core", "iga_btt_to_full", "iga_btt_destroy",
     "iga_kkt_create", "iga_kkt_destroy", "iga_kkt_apply", "iga_kkt_residual", "iga_amen_solve",
-    "iga_local_matvec", "iga_local_matvec_flops", "iga_last_error",
+    "iga_local_matvec", "iga_local_matvec_flops", "iga_profile_start", "iga_profile_stop", "iga_last_error",
 ]
 
 
@@ -72,6 +72,14 @@ class AmenStats(C.Structure):
         return out
 
 
+class Profile(C.Structure):
+    _fields_ = [("stages", C.c_long * 2), ("launches", C.c_long * 2), ("ms", C.c_double * 2),
+                ("flops", C.c_double * 2)]
+
+    def as_dict(self):
+        return {name: list(getattr(self, name)) for name, _ in self._fields_}
+
+
 P = C.c_void_p
 PD = C.POINTER(C.c_double)
 I3 = C.c_int * 3
@@ -109,6 +117,8 @@ lib.iga_local_matvec.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                                  C.c_int, P, P, P, P, P, P, C.c_double, P, P, C.c_int]
 lib.iga_local_matvec_flops.argtypes = [C.c_int] * 8
 lib.iga_local_matvec_flops.restype = C.c_double
+lib.iga_profile_start.argtypes = [P]
+lib.iga_profile_stop.argtypes = [P, C.POINTER(Profile)]
 
 
 def last_error() -> str:
@@ -298,3 +308,14 @@ def local_matvec(ctx, r0, n, r1, degree, RM0, RM1, RK0, RK1, PhiL_M, PhiR_M, Phi
 
 def local_matvec_flops(r0, n, r1, degree, RM0, RM1, RK0, RK1) -> float:
     return lib.iga_local_matvec_flops(r0, n, r1, degree, RM0, RM1, RK0, RK1)
+
+
+def profile_start(ctx):
+    _check(lib.iga_profile_start(ctx))
+
+
+def profile_stop(ctx) -> dict:
+    """Per operator (index 0: M, 1: K): banded stages timed, kernel launches, summed ms, flops."""
+    out = Profile()
+    _check(lib.iga_profile_stop(ctx, C.byref(out)))
+    return out.as_dict()
