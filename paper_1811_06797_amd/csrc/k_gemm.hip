@@ -27,6 +27,28 @@ namespace {
 
 constexpr int NTHR = 256;
 
+// Source of the zeros that pad partial tiles.
+__device__ const double kZero[1] = {0.0};
+
+// Tile of the wide variant used for M <= 64 with many column tiles (the banded stage of the
+// local matvec): 64 x (32 WN) outputs, K step BK, NBUF LDS buffers.
+#ifndef IGA_WIDE_WN
+#define IGA_WIDE_WN 4
+#endif
+#ifndef IGA_WIDE_BK
+#define IGA_WIDE_BK 16
+#endif
+#ifndef IGA_WIDE_NBUF
+#define IGA_WIDE_NBUF 2
+#endif
+// K tiles of global loads kept in flight (1 or 2), for the wide variant and for the others
+#ifndef IGA_WIDE_PREFETCH
+#define IGA_WIDE_PREFETCH 2
+#endif
+#ifndef IGA_PREFETCH
+#define IGA_PREFETCH 1
+#endif
+
 struct G2Args {
   int M, N, K, M2, N2, K2;
   const double* A;
@@ -51,7 +73,7 @@ __device__ __forceinline__ long off2(int idx, int inner, long s_outer, long s_in
 // half-wave reads for one MFMA operand fall into disjoint halves of the 64 banks.
 constexpr int lds_pad(int w) { return ((16 - w % 32) + 32) % 32; }
 
-template <int WM, int WN, int WAVES_M, int WAVES_N, int BK, int NBUF>
+template <int WM, int WN, int WAVES_M, int WAVES_N, int BK, int NBUF, int PF>
 __global__ __launch_bounds__(NTHR) void gemm2_kernel(G2Args g) {
   constexpr int BM = 4 * WM * WAVES_M, BN = 16 * WN * WAVES_N;
   constexpr int LA = BM * BK / NTHR, LB = BN * BK / NTHR;
@@ -81,8 +103,9 @@ __global__ __launch_bounds__(NTHR) void gemm2_kernel(G2Args g) {
   const bool b_nfast = (g.sBn2 == 1 && g.N2 > 1) || (g.N2 == 1 && g.sBn1 == 1);
   // Each thread loads LA elements of the A tile and LB of the B tile per K step, at offsets
   // advanced incrementally: k = k1 * K2 + k2 moves by BK = kq * K2 + krem, with one carry
-  // into k1 when k2 wraps. Out-of-range elements read the (valid) operand base and are
-  // replaced by zero, so the loads need no branches.
+  // into k1 when k2 wraps. Out-of-range elements are read from a zero word instead, so the
+  // loads need neither branches nor a select on the loaded value (which would make each
+  // load wait for its data right after issue).
   const int kq = BK / g.K2, krem = BK - kq * g.K2;
   const int dA = kq * (int)g.sAk1 + krem * (int)g.sAk2, dAw = dA + (int)g.sAk1 - g.K2 * (int)g.sAk2;
   const int dB = kq * (int)g.sBk1 + krem * (int)g.sBk2, dBw = dB + (int)g.sBk1 - g.K2 * (int)g.sBk2;
@@ -119,14 +142,12 @@ __global__ __launch_bounds__(NTHR) void gemm2_kernel(G2Args g) {
 #pragma unroll
     for (int j = 0; j < WN; ++j) acc[i][j] = 0.0;
 
-  double ra[LA], rb[LB];
-  auto load_tile = [&](int kt) {
+  auto load_tile = [&](int kt, double (&ra)[LA], double (&rb)[LB]) {
     const int klim = kend - kt;
 #pragma unroll
     for (int s = 0; s < LA; ++s) {
       const bool ok = a_ok[s] && a_kk[s] < klim;
-      const double v = A[ok ? oa[s] : 0];
-      ra[s] = ok ? v : 0.0;
+      ra[s] = *(ok ? A + oa[s] : kZero);
       ak2[s] += krem;
       const bool w = ak2[s] >= g.K2;
       ak2[s] -= w ? g.K2 : 0;
@@ -135,46 +156,81 @@ __global__ __launch_bounds__(NTHR) void gemm2_kernel(G2Args g) {
 #pragma unroll
     for (int s = 0; s < LB; ++s) {
       const bool ok = b_ok[s] && b_kk[s] < klim;
-      const double v = B[ok ? ob[s] : 0];
-      rb[s] = ok ? v : 0.0;
+      rb[s] = *(ok ? B + ob[s] : kZero);
       bk2[s] += krem;
       const bool w = bk2[s] >= g.K2;
       bk2[s] -= w ? g.K2 : 0;
       ob[s] += w ? dBw : dB;
     }
   };
-  auto store_tile = [&](int buf) {
+  auto store_tile = [&](int buf, const double (&ra)[LA], const double (&rb)[LB]) {
 #pragma unroll
     for (int s = 0; s < LA; ++s) As[buf][a_kk[s]][a_mm[s]] = ra[s];
 #pragma unroll
     for (int s = 0; s < LB; ++s) Bs[buf][b_kk[s]][b_nn[s]] = rb[s];
   };
-
-  const int nkt = (kend - kbeg + BK - 1) / BK;
-  if (nkt > 0) {
-    load_tile(kbeg);
-    store_tile(0);
-  }
-  __syncthreads();
-  for (int t = 0; t < nkt; ++t) {
-    const int cur = NBUF == 2 ? (t & 1) : 0;
-    if (t + 1 < nkt) load_tile(kbeg + (t + 1) * BK);
+  // The fragments of K step ks + 4 are read from LDS while the MFMAs of step ks issue.
+  auto compute = [&](int cur) {
+    double fa[2][WM], fb[2][WN];
+#pragma unroll
+    for (int r = 0; r < WM; ++r) fa[0][r] = As[cur][lx][wm0 + r * 4 + ly];
+#pragma unroll
+    for (int c = 0; c < WN; ++c) fb[0][c] = Bs[cur][lx][wn0 + c * 16 + lb * 4 + ly];
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
-      double fa[WM], fb[WN];
+      const int h = (ks / 4) & 1;
+      if (ks + 4 < BK) {
 #pragma unroll
-      for (int r = 0; r < WM; ++r) fa[r] = As[cur][ks + lx][wm0 + r * 4 + ly];
+        for (int r = 0; r < WM; ++r) fa[h ^ 1][r] = As[cur][ks + 4 + lx][wm0 + r * 4 + ly];
 #pragma unroll
-      for (int c = 0; c < WN; ++c) fb[c] = Bs[cur][ks + lx][wn0 + c * 16 + lb * 4 + ly];
+        for (int c = 0; c < WN; ++c) fb[h ^ 1][c] = Bs[cur][ks + 4 + lx][wn0 + c * 16 + lb * 4 + ly];
+      }
 #pragma unroll
       for (int r = 0; r < WM; ++r)
 #pragma unroll
         for (int c = 0; c < WN; ++c)
-          acc[r][c] = __builtin_amdgcn_mfma_f64_4x4x4f64(fa[r], fb[c], acc[r][c], 0, 0, 0);
+          acc[r][c] = __builtin_amdgcn_mfma_f64_4x4x4f64(fa[h][r], fb[h][c], acc[r][c], 0, 0, 0);
     }
-    if (NBUF == 1) __syncthreads();  // single buffer: every wave is done reading it
-    if (t + 1 < nkt) store_tile(NBUF == 2 ? (cur ^ 1) : 0);
+  };
+
+  const int nkt = (kend - kbeg + BK - 1) / BK;
+  double ra0[LA], rb0[LB];
+  if constexpr (PF == 2) {
+    // two K tiles of global loads in flight: register sets 0 and 1 alternate, LDS buffers
+    // 0 and 1 alternate; tile t is in LDS buffer t % 2 when it is multiplied
+    static_assert(NBUF == 2, "prefetch depth 2 needs two LDS buffers");
+    double ra1[LA], rb1[LB];
+    if (nkt > 0) {
+      load_tile(kbeg, ra0, rb0);
+      store_tile(0, ra0, rb0);
+    }
+    if (nkt > 1) load_tile(kbeg + BK, ra1, rb1);
     __syncthreads();
+    for (int t = 0; t < nkt; t += 2) {
+      if (t + 2 < nkt) load_tile(kbeg + (t + 2) * BK, ra0, rb0);
+      compute(0);
+      if (t + 1 < nkt) store_tile(1, ra1, rb1);
+      __syncthreads();
+      if (t + 1 >= nkt) break;
+      if (t + 3 < nkt) load_tile(kbeg + (t + 3) * BK, ra1, rb1);
+      compute(1);
+      if (t + 2 < nkt) store_tile(0, ra0, rb0);
+      __syncthreads();
+    }
+  } else {
+    if (nkt > 0) {
+      load_tile(kbeg, ra0, rb0);
+      store_tile(0, ra0, rb0);
+    }
+    __syncthreads();
+    for (int t = 0; t < nkt; ++t) {
+      const int cur = NBUF == 2 ? (t & 1) : 0;
+      if (t + 1 < nkt) load_tile(kbeg + (t + 1) * BK, ra0, rb0);
+      compute(cur);
+      if (NBUF == 1) __syncthreads();  // single buffer: every wave is done reading it
+      if (t + 1 < nkt) store_tile(NBUF == 2 ? (cur ^ 1) : 0, ra0, rb0);
+      __syncthreads();
+    }
   }
   // acc[r][c] at this lane is C[wm0 + 4r + lx][wn0 + 16c + 4lb + ly]
   if (g.ksplit > 1) {
@@ -227,12 +283,12 @@ __global__ __launch_bounds__(256) void splitk_reduce(G2Args g) {
   }
 }
 
-template <int WM, int WN, int WAVES_M, int WAVES_N, int BK, int NBUF>
+template <int WM, int WN, int WAVES_M, int WAVES_N, int BK, int NBUF, int PF>
 void launch(hipStream_t s, G2Args a, int nbatch) {
   constexpr int BM = 4 * WM * WAVES_M, BN = 16 * WN * WAVES_N;
   dim3 grid((a.N + BN - 1) / BN, (a.M + BM - 1) / BM, (unsigned)(nbatch * a.ksplit));
   require((long)grid.x * grid.y * grid.z < (1L << 31), IGA_EINVAL, "gemm2: grid too large");
-  gemm2_kernel<WM, WN, WAVES_M, WAVES_N, BK, NBUF><<<grid, NTHR, 0, s>>>(a);
+  gemm2_kernel<WM, WN, WAVES_M, WAVES_N, BK, NBUF, PF><<<grid, NTHR, 0, s>>>(a);
 }
 
 }  // namespace
@@ -263,7 +319,9 @@ void gemm2(hipStream_t s, const Gemm2& d, double* work, size_t work_len) {
   if (d.M <= 16) { BM = 16; BN = 256; variant = 2; }
   else if (d.M <= 32) { BM = 32; BN = 128; variant = 1; }
   else if (d.N <= 32) { BM = 128; BN = 32; variant = 3; }
-  else if (d.M <= 64 && (long)((d.N + 127) / 128) * nb >= 512) { BM = 64; BN = 128; variant = 4; }
+  else if (d.M <= 64 && (long)((d.N + 32 * IGA_WIDE_WN - 1) / (32 * IGA_WIDE_WN)) * nb >= 512) {
+    BM = 64; BN = 32 * IGA_WIDE_WN; variant = 4;
+  }
   else { BM = 64; BN = 64; variant = 0; }
   const long tiles = (long)((d.M + BM - 1) / BM) * ((d.N + BN - 1) / BN) * nb;
   // split K when the tiles cannot fill the chip and the contraction is long
@@ -280,11 +338,11 @@ void gemm2(hipStream_t s, const Gemm2& d, double* work, size_t work_len) {
   }
   require((long)nb * a.ksplit <= 65535, IGA_EINVAL, "gemm2: batch too large");
   switch (variant) {
-    case 2: launch<4, 4, 1, 4, 16, 2>(s, a, (int)nb); break;
-    case 1: launch<8, 2, 1, 4, 16, 2>(s, a, (int)nb); break;
-    case 3: launch<8, 2, 4, 1, 16, 2>(s, a, (int)nb); break;
-    case 4: launch<8, 4, 2, 2, 16, 2>(s, a, (int)nb); break;
-    default: launch<8, 2, 2, 2, 16, 2>(s, a, (int)nb); break;
+    case 2: launch<4, 4, 1, 4, 16, 2, IGA_PREFETCH>(s, a, (int)nb); break;
+    case 1: launch<8, 2, 1, 4, 16, 2, IGA_PREFETCH>(s, a, (int)nb); break;
+    case 3: launch<8, 2, 4, 1, 16, 2, IGA_PREFETCH>(s, a, (int)nb); break;
+    case 4: launch<8, IGA_WIDE_WN, 2, 2, IGA_WIDE_BK, IGA_WIDE_NBUF, IGA_WIDE_PREFETCH>(s, a, (int)nb); break;
+    default: launch<8, 2, 2, 2, 16, 2, IGA_PREFETCH>(s, a, (int)nb); break;
   }
   IGA_HIP(hipGetLastError());
   if (a.ksplit > 1) {
