@@ -116,7 +116,7 @@ typedef struct {
   int ranks[2];                /* r_1, r_2 of the solution */
   long long local_solves;
   long long local_iterations;  /* preconditioned Krylov iterations, all local solves */
-  long long local_matvecs;     /* projected local matvecs (each = 3 M + 2 K applications) */
+  long long local_matvecs;     /* FP64 projected local matvecs (each = 3 M + 2 K applications) */
   double local_matvec_flops;   /* algorithmic flops of those matvecs */
   double t_total;
   double t_local_matvec;       /* time inside the projected local matvec kernels */
@@ -125,6 +125,13 @@ typedef struct {
   double t_interfaces;
   double t_svd;
   double t_residual;
+  /* mixed form (precision IGA_FP32): local matvecs with FP32 contractions inside the
+   * refinement's inner solves, their algorithmic flops and time, and refinement steps
+   * (each followed by an FP64 local residual); zero in the FP64 form */
+  long long local_matvecs_fp32;
+  double local_matvec_flops_fp32;
+  double t_local_matvec_fp32;
+  long long refinements;
 } iga_amen_stats;
 
 /* Context on GPU `device`; hip_stream is a hipStream_t (NULL: the default stream). */
@@ -218,17 +225,17 @@ double iga_local_matvec_flops(int r0, int n, int r1, int degree, int RM0, int RM
 /* Event timing of the banded (middle) stage of the projected local TT-matvec, the
  * contraction of the operator core with the band of t1 = PhiL x (eq. KKT_red), for
  * measurement. Between iga_profile_start and iga_profile_stop every local matvec on the
- * context (inside iga_amen_solve or iga_local_matvec, FP64 form) records a HIP event pair
- * on the context stream around that stage, per operator (index 0: M, 1: K). stop
- * synchronises the stream and returns: stages (banded stages timed), launches (kernel
- * launches inside them: one per nonzero rank block of the core), ms (summed event time)
- * and flops (algorithmic flops: banded nonzeros times nonzero rank blocks). out may be
- * NULL. Calls on one context must not overlap. */
+ * context (inside iga_amen_solve or iga_local_matvec) records a HIP event pair on the
+ * context stream around that stage, per operator and precision (index 0: M FP64, 1: K FP64,
+ * 2: M FP32, 3: K FP32). stop synchronises the stream and returns: stages (banded stages
+ * timed), launches (kernel launches inside them: one per nonzero rank block of the core),
+ * ms (summed event time) and flops (algorithmic flops: banded nonzeros times nonzero rank
+ * blocks). out may be NULL. Calls on one context must not overlap. */
 typedef struct {
-  long stages[2];
-  long launches[2];
-  double ms[2];
-  double flops[2];
+  long stages[4];
+  long launches[4];
+  double ms[4];
+  double flops[4];
 } iga_profile;
 int iga_profile_start(iga_ctx* ctx);
 int iga_profile_stop(iga_ctx* ctx, iga_profile* out);

@@ -106,7 +106,7 @@ class Amen {
   Amen(iga_ctx* ctx, const iga_kkt* kkt, const iga_tt* Y, double tol, const iga_amen_opts& o)
       : ctx_(ctx), st_(ctx->stream), kkt_(kkt), Y_(Y), tol_(tol), o_(o),
         t_mv_(ctx->stream), t_pc_(ctx->stream), t_if_(ctx->stream), t_svd_(ctx->stream),
-        t_kr_(ctx->stream) {
+        t_kr_(ctx->stream), t_mv32_(ctx->stream) {
     for (int d = 0; d < 3; ++d) n_[d] = kkt->M->n[d];
     g_ = std::sqrt(kkt->beta);
     ops_[0] = kkt->M;
@@ -115,6 +115,17 @@ class Amen {
     ry_[0] = 1; ry_[3] = 1;
     ry_[1] = Y->r[1]; ry_[2] = Y->r[2];
     rng_.seed(o.seed);
+    lowp_ = o.precision == IGA_FP32;
+    if (lowp_) {
+      // FP32 copies of the operator cores, fixed for the whole solve
+      for (int op = 0; op < 2; ++op)
+        for (int d = 0; d < 3; ++d) {
+          const OpCore& c = ops_[op]->core[d];
+          const long sz = (long)c.R0 * c.n * (2 * ops_[op]->p + 1) * c.R1;
+          fcore_[op][d].reset(ctx, sz);
+          k::to_f32(st_, sz, c.data.get(), fcore_[op][d].get());
+        }
+    }
   }
 
   int run(const iga_btt* x0, iga_btt** sol, iga_amen_stats* stats);
@@ -188,10 +199,16 @@ class Amen {
   DBuf KV_, KZ_, w_, h_, red_, bl_, tmp_;
   LocalWork lw_;
   std::mt19937_64 rng_;
+  // mixed-precision form: FP32 operands of the current local operator; inside the
+  // refinement's inner solve (lp_inner_) every local matvec contracts in FP32
+  bool lowp_ = false, lp_inner_ = false;
+  FBuf fcore_[2][3], fPL_[2], fPR_[2], fx_, fy_;
+  void lowp_operands(int d, LocalOp& L);
+  int refine_solve(int d, const LocalOp& L, double bn, double ltol, double res0);
   // statistics
-  EventTimer t_mv_, t_pc_, t_if_, t_svd_, t_kr_;
-  long long n_solves_ = 0, n_iters_ = 0, n_mv_ = 0;
-  double flops_ = 0;
+  EventTimer t_mv_, t_pc_, t_if_, t_svd_, t_kr_, t_mv32_;
+  long long n_solves_ = 0, n_iters_ = 0, n_mv_ = 0, n_mv32_ = 0, n_refine_ = 0;
+  double flops_ = 0, flops32_ = 0;
   double max_res_ = 0;
   double bnorm_ = 1.0;  // norm of the local right-hand side of the last solve
   DBuf xk_;
@@ -350,11 +367,68 @@ void Amen::rhs_local(int d, Frame left, Frame right, double* out) {
 
 void Amen::matvec(const LocalOp& L, const double* x, double* y) {
   g_phase = "matvec";
+  if (lp_inner_) {
+    // FP32 contractions on FP32 copies of x; the Krylov vectors stay FP64
+    const long N = L.size(), No = L.out_size();
+    fx_.ensure(ctx_, N);
+    fy_.ensure(ctx_, No);
+    const int id = t_mv32_.begin();
+    k::to_f32(st_, N, x, fx_.get());
+    local_matvec_f32(ctx_, L, fx_.get(), fy_.get(), lw_);
+    k::to_f64(st_, No, fy_.get(), y);
+    t_mv32_.end(id);
+    ++n_mv32_;
+    flops32_ += local_flops(L);
+    return;
+  }
   const int id = t_mv_.begin();
   local_matvec(ctx_, L, x, y, lw_);
   t_mv_.end(id);
   ++n_mv_;
   flops_ += local_flops(L);
+}
+
+// FP32 copies of the interfaces of the current local operator (the cores were converted
+// once for the solve).
+void Amen::lowp_operands(int d, LocalOp& L) {
+  for (int op = 0; op < 2; ++op) {
+    const long sl = (long)R(op, d) * r_[d] * r_[d], sr = (long)R(op, d + 1) * r_[d + 1] * r_[d + 1];
+    fPL_[op].ensure(ctx_, sl);
+    fPR_[op].ensure(ctx_, sr);
+    k::to_f32(st_, sl, PL_[op][d].get(), fPL_[op].get());
+    k::to_f32(st_, sr, PR_[op][d].get(), fPR_[op].get());
+  }
+  L.fPhiL_M = fPL_[0].get(); L.fPhiR_M = fPR_[0].get();
+  L.fPhiL_K = fPL_[1].get(); L.fPhiR_K = fPR_[1].get();
+  L.M.Af = fcore_[0][d].get();
+  L.K.Af = fcore_[1][d].get();
+}
+
+// Mixed-precision local solve by iterative refinement: the FP64 residual r = b - A x (in
+// tmp_ on entry, relative norm res0) is reduced by an inner FGMRES whose matvecs contract
+// in FP32, the correction is added in FP64, and the FP64 residual is recomputed, until it
+// is <= ltol. The inner solve asks for what FP32 contractions can deliver (relative 2e-5)
+// or the remaining factor, whichever is larger. Returns the inner iterations.
+int Amen::refine_solve(int d, const LocalOp& L, double bn, double ltol, double res0) {
+  const long N = L.size();
+  DBuf e(ctx_, N), r(ctx_, N);
+  double res = res0;
+  int its = 0;
+  IGA_HIP(hipMemcpyAsync(r.get(), tmp_.get(), N * sizeof(double), hipMemcpyDeviceToDevice, st_));
+  for (int ref = 0; ref < 20 && res > ltol; ++ref) {
+    const double rn = res * bn;
+    const double inner = std::max(ltol / res, 2e-5);
+    k::fill(st_, N, 0.0, e.get());
+    lp_inner_ = true;
+    its += fgmres(L, r.get(), e.get(), rn, inner * rn);
+    lp_inner_ = false;
+    k::axpby(st_, N, 1.0, e.get(), 1.0, X_[d].get());
+    matvec(L, X_[d].get(), r.get());
+    k::axpby(st_, N, 1.0, bl_.get(), -1.0, r.get());
+    res = std::sqrt(norm2_host(ctx_, N, r.get())) / bn;
+    ++n_refine_;
+  }
+  return its;
 }
 
 void Amen::residual_proj(int d, Frame left, Frame right, double* out) {
@@ -558,7 +632,12 @@ double Amen::solve_local(int d) {
   const double ltol = o_.local_tol;
   if (res > ltol) {
     setup_precond(d);
-    n_iters_ += fgmres(L, bl_.get(), X_[d].get(), bn, ltol * bn);
+    if (lowp_) {
+      lowp_operands(d, L);
+      n_iters_ += refine_solve(d, L, bn, ltol, res);
+    } else {
+      n_iters_ += fgmres(L, bl_.get(), X_[d].get(), bn, ltol * bn);
+    }
   }
   return res;
 }
@@ -1003,6 +1082,10 @@ int Amen::run(const iga_btt* x0, iga_btt** sol, iga_amen_stats* stats) {
     stats->t_krylov_other = t_kr_.total();
     stats->t_interfaces = t_if_.total();
     stats->t_svd = t_svd_.total();
+    stats->local_matvecs_fp32 = n_mv32_;
+    stats->local_matvec_flops_fp32 = flops32_;
+    stats->t_local_matvec_fp32 = t_mv32_.total();
+    stats->refinements = n_refine_;
     const auto t2 = std::chrono::steady_clock::now();
     stats->residual = kkt_residual_impl(ctx_, kkt_, Y_, out.get());
     stats->t_residual = std::chrono::duration<double>(std::chrono::steady_clock::now() - t2).count();

@@ -175,7 +175,8 @@ __global__ void axpby_kernel(long n, double a, const double* x, double b, double
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
     y[i] = (b == 0.0) ? a * x[i] : a * x[i] + b * y[i];
 }
-__global__ void fill_kernel(long n, double v, double* y) {
+template <class T>
+__global__ void fill_kernel(long n, T v, T* y) {
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
     y[i] = v;
 }
@@ -489,7 +490,12 @@ void axpby(hipStream_t s, long n, double a, const double* x, double b, double* y
 }
 void fill(hipStream_t s, long n, double v, double* y) {
   if (n <= 0) return;
-  fill_kernel<<<grid_for(n), 256, 0, s>>>(n, v, y);
+  fill_kernel<double><<<grid_for(n), 256, 0, s>>>(n, v, y);
+  IGA_HIP(hipGetLastError());
+}
+void fill_f32(hipStream_t s, long n, float v, float* y) {
+  if (n <= 0) return;
+  fill_kernel<float><<<grid_for(n), 256, 0, s>>>(n, v, y);
   IGA_HIP(hipGetLastError());
 }
 void scale(hipStream_t s, long n, double a, double* y) {

@@ -1,0 +1,282 @@
+// FP32 batched GEMM on the CDNA4 matrix cores, with the two-level index maps of gemm2
+// (k_gemm.hip): the contractions of the mixed-precision local operator.
+//
+// C[b][m][n] = alpha * sum_k A[b][m][k] B[b][k][n] + beta * C[b][m][n], FP32 inputs and
+// FP32 accumulation. Each wave owns a (16 WM) x (16 WN) block of C and issues
+// v_mfma_f32_16x16x4f32 (one 16x16x4 product, 2048 flops). Operand lane layout
+// (lane l = 16 q + t, q = l / 16, t = l % 16):
+//   A[t][q] and B[q][t] (K = 4 per instruction); C[4 q + v][t], v = 0..3 in the four
+//   accumulator registers.
+// Four waves form the workgroup tile; K is staged through LDS 16 deep, double-buffered,
+// with the next tile's global loads in flight during the current tile's products.
+#include <algorithm>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace iga {
+namespace k {
+namespace {
+
+constexpr int NT = 256, BKF = 16;
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ const float kZeroF[1] = {0.0f};
+
+struct G2FArgs {
+  int M, N, K, M2, N2, K2;
+  const float* A;
+  long sAm1, sAm2, sAk1, sAk2;
+  const float* B;
+  long sBk1, sBk2, sBn1, sBn2;
+  float* C;
+  long sCm1, sCm2, sCn1, sCn2;
+  int nb2, nbatch;
+  long sAb1, sAb2, sBb1, sBb2, sCb1, sCb2;
+  float alpha, beta;
+  int ksplit, kchunk;
+  float* work;
+};
+
+__device__ __forceinline__ long off2f(int idx, int inner, long s_outer, long s_inner) {
+  const int o = idx / inner;
+  return (long)o * s_outer + (long)(idx - o * inner) * s_inner;
+}
+
+// Row pitch (floats) of the LDS tiles: 16 mod 64, so the four k rows one MFMA operand read
+// touches start 16 banks apart.
+constexpr int lds_padf(int w) { return ((16 - w % 64) + 64) % 64; }
+
+template <int WM, int WN, int WAVES_M, int WAVES_N>
+__global__ __launch_bounds__(NT) void gemm2f_kernel(G2FArgs g) {
+  constexpr int BM = 16 * WM * WAVES_M, BN = 16 * WN * WAVES_N;
+  constexpr int LA = BM * BKF / NT, LB = BN * BKF / NT;
+  static_assert(WAVES_M * WAVES_N == 4, "four waves");
+  static_assert(LA >= 1 && LB >= 1, "tile too small");
+  __shared__ float As[2][BKF][BM + lds_padf(BM)];
+  __shared__ float Bs[2][BKF][BN + lds_padf(BN)];
+  // XCD-contiguous renumbering of the workgroups (as in gemm2)
+  const int gx = gridDim.x, gy = gridDim.y;
+  const int total = gx * gy * gridDim.z;
+  const int lin = (blockIdx.z * gy + blockIdx.y) * gx + blockIdx.x;
+  const int xcd = lin % 8, q8 = lin / 8, base = total / 8, rem = total % 8;
+  const int tile = (xcd < rem ? xcd * (base + 1) : rem * (base + 1) + (xcd - rem) * base) + q8;
+  const int bx = tile % gx, by = (tile / gx) % gy, bz = tile / (gx * gy);
+  const int split = bz / g.nbatch, bb = bz - split * g.nbatch;
+  const int b1 = bb / g.nb2, b2 = bb - b1 * g.nb2;
+  const float* A = g.A + b1 * g.sAb1 + b2 * g.sAb2;
+  const float* B = g.B + b1 * g.sBb1 + b2 * g.sBb2;
+  const int m0 = by * BM, n0 = bx * BN;
+  const int tid = threadIdx.x;
+  const int kbeg = split * g.kchunk;
+  const int kend = min(g.K, kbeg + g.kchunk);
+
+  const bool a_kfast = (g.sAk2 == 1 && g.K2 > 1) || (g.K2 == 1 && g.sAk1 == 1);
+  const bool b_nfast = (g.sBn2 == 1 && g.N2 > 1) || (g.N2 == 1 && g.sBn1 == 1);
+  const int kq = BKF / g.K2, krem = BKF - kq * g.K2;
+  const int dA = kq * (int)g.sAk1 + krem * (int)g.sAk2, dAw = dA + (int)g.sAk1 - g.K2 * (int)g.sAk2;
+  const int dB = kq * (int)g.sBk1 + krem * (int)g.sBk2, dBw = dB + (int)g.sBk1 - g.K2 * (int)g.sBk2;
+  int a_mm[LA], a_kk[LA], b_nn[LB], b_kk[LB], ak2[LA], bk2[LB], oa[LA], ob[LB];
+  bool a_ok[LA], b_ok[LB];
+#pragma unroll
+  for (int s = 0; s < LA; ++s) {
+    const int e = tid + NT * s;
+    if (a_kfast) { a_kk[s] = e % BKF; a_mm[s] = e / BKF; } else { a_mm[s] = e % BM; a_kk[s] = e / BM; }
+    const int m = m0 + a_mm[s];
+    a_ok[s] = m < g.M;
+    const int k = kbeg + a_kk[s], k1 = k / g.K2;
+    ak2[s] = k - k1 * g.K2;
+    oa[s] = (a_ok[s] ? (int)off2f(m, g.M2, g.sAm1, g.sAm2) : 0) + k1 * (int)g.sAk1 + ak2[s] * (int)g.sAk2;
+  }
+#pragma unroll
+  for (int s = 0; s < LB; ++s) {
+    const int e = tid + NT * s;
+    if (b_nfast) { b_nn[s] = e % BN; b_kk[s] = e / BN; } else { b_kk[s] = e % BKF; b_nn[s] = e / BKF; }
+    const int n = n0 + b_nn[s];
+    b_ok[s] = n < g.N;
+    const int k = kbeg + b_kk[s], k1 = k / g.K2;
+    bk2[s] = k - k1 * g.K2;
+    ob[s] = (b_ok[s] ? (int)off2f(n, g.N2, g.sBn1, g.sBn2) : 0) + k1 * (int)g.sBk1 + bk2[s] * (int)g.sBk2;
+  }
+
+  const int wave = tid / 64, lane = tid % 64;
+  const int wm0 = (wave / WAVES_N) * (16 * WM), wn0 = (wave % WAVES_N) * (16 * WN);
+  const int lq = lane / 16, lt = lane % 16;
+  f4 acc[WM][WN];
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j) acc[i][j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+
+  float ra[LA], rb[LB];
+  auto load_tile = [&](int kt) {
+    const int klim = kend - kt;
+#pragma unroll
+    for (int s = 0; s < LA; ++s) {
+      const bool ok = a_ok[s] && a_kk[s] < klim;
+      ra[s] = *(ok ? A + oa[s] : kZeroF);
+      ak2[s] += krem;
+      const bool w = ak2[s] >= g.K2;
+      ak2[s] -= w ? g.K2 : 0;
+      oa[s] += w ? dAw : dA;
+    }
+#pragma unroll
+    for (int s = 0; s < LB; ++s) {
+      const bool ok = b_ok[s] && b_kk[s] < klim;
+      rb[s] = *(ok ? B + ob[s] : kZeroF);
+      bk2[s] += krem;
+      const bool w = bk2[s] >= g.K2;
+      bk2[s] -= w ? g.K2 : 0;
+      ob[s] += w ? dBw : dB;
+    }
+  };
+  auto store_tile = [&](int buf) {
+#pragma unroll
+    for (int s = 0; s < LA; ++s) As[buf][a_kk[s]][a_mm[s]] = ra[s];
+#pragma unroll
+    for (int s = 0; s < LB; ++s) Bs[buf][b_kk[s]][b_nn[s]] = rb[s];
+  };
+
+  const int nkt = (kend - kbeg + BKF - 1) / BKF;
+  if (nkt > 0) {
+    load_tile(kbeg);
+    store_tile(0);
+  }
+  __syncthreads();
+  for (int t = 0; t < nkt; ++t) {
+    const int cur = t & 1;
+    if (t + 1 < nkt) load_tile(kbeg + (t + 1) * BKF);
+#pragma unroll
+    for (int ks = 0; ks < BKF; ks += 4) {
+      float fa[WM], fb[WN];
+#pragma unroll
+      for (int r = 0; r < WM; ++r) fa[r] = As[cur][ks + lq][wm0 + 16 * r + lt];
+#pragma unroll
+      for (int c = 0; c < WN; ++c) fb[c] = Bs[cur][ks + lq][wn0 + 16 * c + lt];
+#pragma unroll
+      for (int r = 0; r < WM; ++r)
+#pragma unroll
+        for (int c = 0; c < WN; ++c)
+          acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[r], fb[c], acc[r][c], 0, 0, 0);
+    }
+    if (t + 1 < nkt) store_tile(cur ^ 1);
+    __syncthreads();
+  }
+  // acc[r][c][v] at this lane is C[wm0 + 16 r + 4 lq + v][wn0 + 16 c + lt]
+  if (g.ksplit > 1) {
+    float* W = g.work + ((long)split * g.nbatch + bb) * (long)g.M * g.N;
+#pragma unroll
+    for (int r = 0; r < WM; ++r)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = m0 + wm0 + 16 * r + 4 * lq + v;
+        if (m >= g.M) continue;
+#pragma unroll
+        for (int c = 0; c < WN; ++c) {
+          const int n = n0 + wn0 + 16 * c + lt;
+          if (n < g.N) W[(long)m * g.N + n] = acc[r][c][v];
+        }
+      }
+    return;
+  }
+  float* C = g.C + b1 * g.sCb1 + b2 * g.sCb2;
+#pragma unroll
+  for (int r = 0; r < WM; ++r)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int m = m0 + wm0 + 16 * r + 4 * lq + v;
+      if (m >= g.M) continue;
+      const long crow = off2f(m, g.M2, g.sCm1, g.sCm2);
+#pragma unroll
+      for (int c = 0; c < WN; ++c) {
+        const int n = n0 + wn0 + 16 * c + lt;
+        if (n >= g.N) continue;
+        float* p = C + crow + off2f(n, g.N2, g.sCn1, g.sCn2);
+        float val = g.alpha * acc[r][c][v];
+        if (g.beta != 0.0f) val += g.beta * *p;
+        *p = val;
+      }
+    }
+}
+
+__global__ __launch_bounds__(256) void splitk_reduce_f(G2FArgs g) {
+  const long MN = (long)g.M * g.N;
+  const long total = MN * g.nbatch;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const int bb = e / MN;
+    const long mn = e - bb * MN;
+    const int m = mn / g.N, n = mn - (long)m * g.N;
+    float s = 0.0f;
+    for (int sp = 0; sp < g.ksplit; ++sp) s += g.work[((long)sp * g.nbatch + bb) * MN + mn];
+    const int b1 = bb / g.nb2, b2 = bb - b1 * g.nb2;
+    float* p = g.C + b1 * g.sCb1 + b2 * g.sCb2 + off2f(m, g.M2, g.sCm1, g.sCm2) + off2f(n, g.N2, g.sCn1, g.sCn2);
+    float v = g.alpha * s;
+    if (g.beta != 0.0f) v += g.beta * *p;
+    *p = v;
+  }
+}
+
+template <int WM, int WN, int WAVES_M, int WAVES_N>
+void launchf(hipStream_t s, G2FArgs a, int nbatch) {
+  constexpr int BM = 16 * WM * WAVES_M, BN = 16 * WN * WAVES_N;
+  dim3 grid((a.N + BN - 1) / BN, (a.M + BM - 1) / BM, (unsigned)(nbatch * a.ksplit));
+  require((long)grid.x * grid.y * grid.z < (1L << 31), IGA_EINVAL, "gemm2_f32: grid too large");
+  gemm2f_kernel<WM, WN, WAVES_M, WAVES_N><<<grid, NT, 0, s>>>(a);
+}
+
+long spanf(int ext, int inner, long s1, long s2) {
+  if (ext <= 0) return 0;
+  return (long)((ext - 1) / inner) * s1 + (long)(std::min(ext, inner) - 1) * s2;
+}
+
+}  // namespace
+
+void gemm2_f32(hipStream_t s, const Gemm2F& d, float* work, size_t work_len) {
+  if (d.M <= 0 || d.N <= 0 || d.nb1 <= 0 || d.nb2 <= 0) return;
+  require(d.M2 >= 1 && d.N2 >= 1 && d.K2 >= 1, IGA_EINVAL, "gemm2_f32: inner extents must be >= 1");
+  require(d.sAm1 >= 0 && d.sAm2 >= 0 && d.sAk1 >= 0 && d.sAk2 >= 0 && d.sBk1 >= 0 && d.sBk2 >= 0 &&
+              d.sBn1 >= 0 && d.sBn2 >= 0,
+          IGA_EINVAL, "gemm2_f32: operand strides must be nonnegative");
+  const long kA = spanf(d.K, d.K2, d.sAk1, d.sAk2) + 64L * (d.sAk1 + d.sAk2);
+  const long kB = spanf(d.K, d.K2, d.sBk1, d.sBk2) + 64L * (d.sBk1 + d.sBk2);
+  require(spanf(d.M, d.M2, d.sAm1, d.sAm2) + kA < (1L << 31) && spanf(d.N, d.N2, d.sBn1, d.sBn2) + kB < (1L << 31),
+          IGA_EINVAL, "gemm2_f32: operand too large for 32-bit offsets");
+  const long nb = (long)d.nb1 * d.nb2;
+  G2FArgs a{d.M, d.N, std::max(d.K, 0), d.M2, d.N2, d.K2, d.A, d.sAm1, d.sAm2, d.sAk1, d.sAk2, d.B, d.sBk1,
+            d.sBk2, d.sBn1, d.sBn2, d.C, d.sCm1, d.sCm2, d.sCn1, d.sCn2, d.nb2, (int)nb, d.sAb1, d.sAb2, d.sBb1,
+            d.sBb2, d.sCb1, d.sCb2, d.alpha, d.beta, 1, std::max(d.K, 0), nullptr};
+  int BM, BN, variant;
+  if (d.M <= 16) { BM = 16; BN = 256; variant = 2; }
+  else if (d.M <= 32) { BM = 32; BN = 128; variant = 1; }
+  else if (d.N <= 32) { BM = 128; BN = 32; variant = 3; }
+  else if (d.M <= 64 && (long)((d.N + 127) / 128) * nb >= 512) { BM = 64; BN = 128; variant = 4; }
+  else { BM = 64; BN = 64; variant = 0; }
+  const long tiles = (long)((d.M + BM - 1) / BM) * ((d.N + BN - 1) / BN) * nb;
+  if (work && tiles < 256 && d.K >= 4 * 32) {
+    int ks = (int)std::min<long>((512 + tiles - 1) / tiles, d.K / 64);
+    while (ks > 1 && (size_t)ks * nb * d.M * d.N > work_len) --ks;
+    if (ks > 1) {
+      a.kchunk = ((d.K + ks - 1) / ks + BKF - 1) / BKF * BKF;
+      a.ksplit = (d.K + a.kchunk - 1) / a.kchunk;
+      a.work = work;
+    }
+  }
+  require((long)nb * a.ksplit <= 65535, IGA_EINVAL, "gemm2_f32: batch too large");
+  switch (variant) {
+    case 2: launchf<1, 4, 1, 4>(s, a, (int)nb); break;
+    case 1: launchf<2, 2, 1, 4>(s, a, (int)nb); break;
+    case 3: launchf<2, 2, 4, 1>(s, a, (int)nb); break;
+    case 4: launchf<2, 4, 2, 2>(s, a, (int)nb); break;
+    default: launchf<2, 2, 2, 2>(s, a, (int)nb); break;
+  }
+  IGA_HIP(hipGetLastError());
+  if (a.ksplit > 1) {
+    const long total = (long)d.M * d.N * nb;
+    splitk_reduce_f<<<(unsigned)std::min<long>((total + 255) / 256, 4096), 256, 0, s>>>(a);
+    IGA_HIP(hipGetLastError());
+  }
+}
+
+}  // namespace k
+}  // namespace iga

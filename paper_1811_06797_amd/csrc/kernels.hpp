@@ -43,6 +43,23 @@ void gemm2(hipStream_t s, const Gemm2& g);
 // along K (partials summed in a fixed order, so results are deterministic).
 void gemm2(hipStream_t s, const Gemm2& g, double* work, size_t work_len);
 
+// The same product in FP32 on the matrix cores (FP32 inputs, FP32 accumulation), for the
+// mixed-precision form (k_gemm32.hip); identical index maps.
+struct Gemm2F {
+  int M = 0, N = 0, K = 0;
+  int M2 = 1 << 30, N2 = 1 << 30, K2 = 1 << 30;
+  const float* A = nullptr;
+  long sAm1 = 0, sAm2 = 0, sAk1 = 0, sAk2 = 0;
+  const float* B = nullptr;
+  long sBk1 = 0, sBk2 = 0, sBn1 = 0, sBn2 = 0;
+  float* C = nullptr;
+  long sCm1 = 0, sCm2 = 0, sCn1 = 0, sCn2 = 0;
+  int nb1 = 1, nb2 = 1;
+  long sAb1 = 0, sAb2 = 0, sBb1 = 0, sBb2 = 0, sCb1 = 0, sCb2 = 0;
+  float alpha = 1.0f, beta = 0.0f;
+};
+void gemm2_f32(hipStream_t s, const Gemm2F& g, float* work, size_t work_len);
+
 // Row-major convenience: C (MxN, ldc) = alpha op(A) op(B) + beta C, op = transpose if t*.
 void gemm_rm(hipStream_t s, int M, int N, int K, const double* A, long lda, bool tA,
              const double* B, long ldb, bool tB, double* C, long ldc, double alpha = 1.0,
@@ -94,6 +111,7 @@ void gemm_f32(hipStream_t s, const GemmF& g);
 // y = a x + b y (n doubles)
 void axpby(hipStream_t s, long n, double a, const double* x, double b, double* y);
 void fill(hipStream_t s, long n, double v, double* y);
+void fill_f32(hipStream_t s, long n, float v, float* y);
 void scale(hipStream_t s, long n, double a, double* y);
 void to_f32(hipStream_t s, long n, const double* x, float* y);
 void to_f64(hipStream_t s, long n, const float* x, double* y);

@@ -39,15 +39,32 @@ double local_flops(const LocalOp& L) {
          op_flops(L.K, L.out0(), L.r0, L.out1(), L.r1, 2, nb);
 }
 
+// Element-type plumbing of the staged apply: the FP64 and FP32 matrix-core GEMMs.
+template <class T> struct Prec;
+template <> struct Prec<double> {
+  using G = k::Gemm2;
+  static void gemm(hipStream_t s, const G& g, double* w, size_t n) { k::gemm2(s, g, w, n); }
+  static void zero(hipStream_t s, long n, double* y) { k::fill(s, n, 0.0, y); }
+  static constexpr int prof_base = 0;
+};
+template <> struct Prec<float> {
+  using G = k::Gemm2F;
+  static void gemm(hipStream_t s, const G& g, float* w, size_t n) { k::gemm2_f32(s, g, w, n); }
+  static void zero(hipStream_t s, long n, float* y) { k::fill_f32(s, n, 0.0f, y); }
+  static constexpr int prof_base = 2;
+};
+
 // One operator of the local matvec on matrix cores: for the ncol columns c of x
 //   z[c][a'][i][b'] = sum PhiL[d][a'][a] A[d][i][i+o-p][g] x[c][a][i+o-p][b] PhiR[g][b'][b].
 // Stage 1 writes t1[j + p][d][c][a'][b] (p zero slices on both ends of j), so that the
 // banded stage is, for every row i, one dense GEMM over (o, d) whose B operand is the
 // contiguous window of slices j = i-p .. i+p; one GEMM per nonzero rank block.
-static void op_apply_mfma(iga_ctx* ctx, const OpView& A, const std::vector<RankBlock>& blocks,
-                          const double* PhiL, const double* PhiR, int r0o, int r0, int r1, int r1o, int ncol,
-                          const double* x, long xcs, double* z, long zcs, DBuf& t1, DBuf& t2,
-                          DBuf& wk, LocalWork::PadKey& pad, int op_id) {
+template <class T>
+static void op_apply(iga_ctx* ctx, const OpView& A, const T* core, const std::vector<RankBlock>& blocks,
+                     const T* PhiL, const T* PhiR, int r0o, int r0, int r1, int r1o, int ncol, const T* x,
+                     long xcs, T* z, long zcs, DevBuf<T>& t1, DevBuf<T>& t2, DevBuf<T>& wk,
+                     LocalWork::PadKey& pad, int op_id) {
+  using G = typename Prec<T>::G;
   hipStream_t st = ctx->stream;
   const int n = A.n, p = A.p, b = 2 * p + 1, R0 = A.R0, R1 = A.R1;
   const long S2 = (long)r0o * r1;         // one (c) slab of (a', b)
@@ -57,18 +74,18 @@ static void op_apply_mfma(iga_ctx* ctx, const OpView& A, const std::vector<RankB
   t2.ensure(ctx, (size_t)n * R1 * S1);
   // the p zero slices at both ends of j are never written by stage 1: fill them once per layout
   if (p > 0 && (pad.gen != t1.gen() || pad.sj != SJ || pad.n != n || pad.p != p)) {
-    k::fill(st, p * SJ, 0.0, t1.get());
-    k::fill(st, p * SJ, 0.0, t1.get() + (long)(n + p) * SJ);
+    Prec<T>::zero(st, p * SJ, t1.get());
+    Prec<T>::zero(st, p * SJ, t1.get() + (long)(n + p) * SJ);
     pad.gen = t1.gen(); pad.sj = SJ; pad.n = n; pad.p = p;
   }
   // stage 1: one GEMM per column c with rows (d, a'): t1[j+p][d][c][a'][b] = sum_a PhiL[d][a'][a] x[c][a][j][b]
-  k::Gemm2 g1;
+  G g1;
   g1.M = R0 * r0o; g1.N = n * r1; g1.N2 = r1; g1.K = r0;
   g1.A = PhiL; g1.sAm1 = (long)r0o * r0; g1.sAm2 = r0; g1.sAk2 = 1;
   g1.B = x; g1.sBk2 = (long)n * r1; g1.sBn1 = r1; g1.sBn2 = 1;
   g1.C = t1.get() + p * SJ; g1.M2 = r0o; g1.sCm1 = S1; g1.sCm2 = r1; g1.sCn1 = SJ; g1.sCn2 = 1;
   g1.nb1 = ncol; g1.sBb1 = xcs; g1.sCb1 = S2;
-  k::gemm2(st, g1);
+  Prec<T>::gemm(st, g1, nullptr, 0);
   // stage 2: per rank block, batched over rows i
   hipEvent_t pa = nullptr, pb = nullptr;
   if (ctx->prof_on) {
@@ -77,23 +94,24 @@ static void op_apply_mfma(iga_ctx* ctx, const OpView& A, const std::vector<RankB
     IGA_HIP(hipEventRecord(pa, st));
   }
   for (const RankBlock& rb : blocks) {
-    k::Gemm2 g2;
+    G g2;
     g2.M = rb.nb; g2.N = (int)S1; g2.K = rb.na * b; g2.K2 = rb.na;
-    g2.A = A.A + (long)rb.a0 * n * b * R1 + rb.b0;
+    g2.A = core + (long)rb.a0 * n * b * R1 + rb.b0;
     g2.sAm2 = 1; g2.sAk1 = R1; g2.sAk2 = (long)n * b * R1;
     g2.B = t1.get() + rb.a0 * S1; g2.sBk1 = SJ; g2.sBk2 = S1; g2.sBn2 = 1;
     g2.C = t2.get() + rb.b0 * S1; g2.sCm2 = S1; g2.sCn2 = 1;
     g2.nb1 = n; g2.sAb1 = (long)b * R1; g2.sBb1 = SJ; g2.sCb1 = (long)R1 * S1;
-    k::gemm2(st, g2);
+    Prec<T>::gemm(st, g2, nullptr, 0);
   }
   if (ctx->prof_on) {
     IGA_HIP(hipEventRecord(pb, st));
     double nz = 0;
     for (const RankBlock& rb : blocks) nz += (double)rb.na * rb.nb;
-    ctx->prof.push_back({pa, pb, op_id, (int)blocks.size(), 2.0 * r0o * r1 * ncol * nz * band_nnz(n, p)});
+    ctx->prof.push_back({pa, pb, Prec<T>::prof_base + op_id, (int)blocks.size(),
+                         2.0 * r0o * r1 * ncol * nz * band_nnz(n, p)});
   }
   // stage 3: z[c][(a' i)][b'] = sum_{(g, b)} t2[i][g][c][a'][b] PhiR[g][b'][b]
-  k::Gemm2 g3;
+  G g3;
   g3.M = r0o * n; g3.M2 = n; g3.N = r1o; g3.K = R1 * r1; g3.K2 = r1;
   g3.A = t2.get(); g3.sAm1 = r1; g3.sAm2 = (long)R1 * S1; g3.sAk1 = S1; g3.sAk2 = 1;
   g3.B = PhiR; g3.sBk1 = (long)r1o * r1; g3.sBk2 = 1; g3.sBn2 = r1;
@@ -101,7 +119,7 @@ static void op_apply_mfma(iga_ctx* ctx, const OpView& A, const std::vector<RankB
   g3.nb1 = ncol; g3.sAb1 = S2; g3.sCb1 = zcs;
   const size_t wlen = (size_t)16 * ncol * r0o * n * r1o;
   wk.ensure(ctx, wlen);
-  k::gemm2(st, g3, wk.get(), wlen);
+  Prec<T>::gemm(st, g3, wk.get(), wlen);
 }
 
 void local_matvec(iga_ctx* ctx, const LocalOp& L, const double* x, double* y, LocalWork& w) {
@@ -109,52 +127,25 @@ void local_matvec(iga_ctx* ctx, const LocalOp& L, const double* x, double* y, Lo
   const int r0o = L.out0(), r1o = L.out1();
   const long osz = (long)r0o * L.n * r1o;  // one output column
   w.z.ensure(ctx, (size_t)5 * osz);
-  op_apply_mfma(ctx, L.M, L.Mblocks, L.PhiL_M, L.PhiR_M, r0o, L.r0, L.r1, r1o, 3, x, colsz, w.z.get(), osz,
-                w.tM, w.tM2, w.split, w.padM, 0);
-  op_apply_mfma(ctx, L.K, L.Kblocks, L.PhiL_K, L.PhiR_K, r0o, L.r0, L.r1, r1o, 2, x, 2 * colsz,
-                w.z.get() + 3 * osz, osz, w.tK, w.tK2, w.split, w.padK, 1);
+  op_apply<double>(ctx, L.M, L.M.A, L.Mblocks, L.PhiL_M, L.PhiR_M, r0o, L.r0, L.r1, r1o, 3, x, colsz, w.z.get(),
+                   osz, w.tM, w.tM2, w.split, w.padM, 0);
+  op_apply<double>(ctx, L.K, L.K.A, L.Kblocks, L.PhiL_K, L.PhiR_K, r0o, L.r0, L.r1, r1o, 2, x, 2 * colsz,
+                   w.z.get() + 3 * osz, osz, w.tK, w.tK2, w.split, w.padK, 1);
   k::kkt_combine(ctx->stream, osz, L.coef, w.z.get(), w.z.get() + 3 * osz, y);
 }
 
-static void apply_f32(iga_ctx* ctx, const OpView& A, const float* PhiL, const float* PhiR, int r0, int r1,
-                      int ncol, const float* x, long xcs, float* t2, float* t1, float* out, long ocs) {
-  const int n = A.n;
-  const long colsz = (long)r0 * n * r1;
-  k::GemmF g;
-  g.M = r0; g.N = n * r1; g.K = r0;
-  g.A = PhiL; g.sAm = r0; g.sAk = 1;
-  g.B = x; g.sBk = (long)n * r1; g.sBn = 1;
-  g.C = t1; g.sCm = (long)n * r1; g.sCn = 1;
-  g.nb1 = A.R0; g.nb2 = ncol;
-  g.sAb1 = (long)r0 * r0; g.sBb2 = xcs;
-  g.sCb1 = ncol * colsz; g.sCb2 = colsz;
-  k::gemm_f32(ctx->stream, g);
-  k::BandF b;
-  b.n = n; b.p = A.p; b.R0 = A.R0; b.R1 = A.R1; b.rev = false;
-  b.m = ncol * r0; b.c = r1;
-  b.A = A.Af; b.lo = A.lo_R1; b.hi = A.hi_R1;
-  b.in = t1; b.out = t2;
-  k::band_f32(ctx->stream, b);
-  k::GemmF h;
-  h.M = r0 * n; h.N = r1; h.K = r1; h.Kout = A.R1;
-  h.A = t2; h.sAm = r1; h.sAk = 1; h.sAko = ncol * colsz;
-  h.B = PhiR; h.sBk = 1; h.sBn = r1; h.sBko = (long)r1 * r1;
-  h.C = out; h.sCm = r1; h.sCn = 1;
-  h.nb1 = ncol; h.sAb1 = colsz; h.sCb1 = ocs;
-  k::gemm_f32(ctx->stream, h);
-}
-
 void local_matvec_f32(iga_ctx* ctx, const LocalOp& L, const float* x, float* y, LocalWork& w) {
+  require(L.M.Af && L.K.Af && L.fPhiL_M && L.fPhiR_M && L.fPhiL_K && L.fPhiR_K, IGA_EINVAL,
+          "local_matvec_f32: FP32 operands missing");
   const long colsz = (long)L.r0 * L.n * L.r1;
-  w.ftM.ensure(ctx, (size_t)L.M.R1 * 3 * colsz);
-  w.ftK.ensure(ctx, (size_t)L.K.R1 * 2 * colsz);
-  w.ft1.ensure(ctx, (size_t)std::max(L.M.R0 * 3, L.K.R0 * 2) * colsz);
-  w.fz.ensure(ctx, (size_t)5 * colsz);
-  apply_f32(ctx, L.M, L.fPhiL_M, L.fPhiR_M, L.r0, L.r1, 3, x, colsz, w.ftM.get(), w.ft1.get(), w.fz.get(),
-            colsz);
-  apply_f32(ctx, L.K, L.fPhiL_K, L.fPhiR_K, L.r0, L.r1, 2, x, 2 * colsz, w.ftK.get(), w.ft1.get(),
-            w.fz.get() + 3 * colsz, colsz);
-  k::kkt_combine_f32(ctx->stream, colsz, L.coef, w.fz.get(), w.fz.get() + 3 * colsz, y);
+  const int r0o = L.out0(), r1o = L.out1();
+  const long osz = (long)r0o * L.n * r1o;
+  w.fz.ensure(ctx, (size_t)5 * osz);
+  op_apply<float>(ctx, L.M, L.M.Af, L.Mblocks, L.fPhiL_M, L.fPhiR_M, r0o, L.r0, L.r1, r1o, 3, x, colsz,
+                  w.fz.get(), osz, w.ftM, w.ftM2, w.fsplit, w.fpadM, 0);
+  op_apply<float>(ctx, L.K, L.K.Af, L.Kblocks, L.fPhiL_K, L.fPhiR_K, r0o, L.r0, L.r1, r1o, 2, x, 2 * colsz,
+                  w.fz.get() + 3 * osz, osz, w.ftK, w.ftK2, w.fsplit, w.fpadK, 1);
+  k::kkt_combine_f32(ctx->stream, osz, L.coef, w.fz.get(), w.fz.get() + 3 * osz, y);
 }
 
 // ---- raw-buffer entry point (dense rank blocks) ----

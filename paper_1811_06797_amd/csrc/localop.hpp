@@ -37,8 +37,8 @@ struct LocalOp {
 struct LocalWork {
   DBuf tM, tK, tM2, tK2, z, split;  // split: split-K partials of the short-output stages
   // layout (generation of tM / tK, slice size, n, p) whose zero end slices are in place
-  struct PadKey { unsigned gen = ~0u; long sj = -1; int n = -1, p = -1; } padM, padK;
-  FBuf ftM, ftK, fz, ft1, fx, fy;
+  struct PadKey { unsigned gen = ~0u; long sj = -1; int n = -1, p = -1; } padM, padK, fpadM, fpadK;
+  FBuf ftM, ftK, ftM2, ftK2, fz, fsplit, fx, fy;  // FP32 counterparts
 };
 
 // y = A_loc x (FP64); x: [3][r0][n][r1], y: [3][r0o][n][r1o]

@@ -62,7 +62,9 @@ class AmenStats(C.Structure):
                 ("local_iterations", C.c_longlong), ("local_matvecs", C.c_longlong),
                 ("local_matvec_flops", C.c_double), ("t_total", C.c_double), ("t_local_matvec", C.c_double),
                 ("t_precond", C.c_double), ("t_krylov_other", C.c_double), ("t_interfaces", C.c_double),
-                ("t_svd", C.c_double), ("t_residual", C.c_double)]
+                ("t_svd", C.c_double), ("t_residual", C.c_double), ("local_matvecs_fp32", C.c_longlong),
+                ("local_matvec_flops_fp32", C.c_double), ("t_local_matvec_fp32", C.c_double),
+                ("refinements", C.c_longlong)]
 
     def as_dict(self):
         out = {}
@@ -73,8 +75,8 @@ class AmenStats(C.Structure):
 
 
 class Profile(C.Structure):
-    _fields_ = [("stages", C.c_long * 2), ("launches", C.c_long * 2), ("ms", C.c_double * 2),
-                ("flops", C.c_double * 2)]
+    _fields_ = [("stages", C.c_long * 4), ("launches", C.c_long * 4), ("ms", C.c_double * 4),
+                ("flops", C.c_double * 4)]
 
     def as_dict(self):
         return {name: list(getattr(self, name)) for name, _ in self._fields_}
@@ -315,7 +317,8 @@ def profile_start(ctx):
 
 
 def profile_stop(ctx) -> dict:
-    """Per operator (index 0: M, 1: K): banded stages timed, kernel launches, summed ms, flops."""
+    """Per operator and precision (0: M FP64, 1: K FP64, 2: M FP32, 3: K FP32): banded stages
+    timed, kernel launches, summed ms, flops."""
     out = Profile()
     _check(lib.iga_profile_stop(ctx, C.byref(out)))
     return out.as_dict()
