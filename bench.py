@@ -15,6 +15,9 @@ Printed JSON line:
              and the nonzero rank blocks) / their GPU time (HIP events on the
              library stream);
   solve_time_s, kkt_residual, per-part solve times, ranks;
+  mixed_vs_fp64  the same solve in the mixed form (FP32 local contractions inside FP64
+             iterative refinement) and in FP64, from one assembly: solve times,
+             residuals and the state difference;
   roofline   the dominant kernel of the local TT-matvec at the microbenchmark shape
              (r, R_M, R_K, n, p) = (32, 10, 60, 64, 3): the banded middle stage of
              the K operator, timed by the library with HIP events on its stream;
@@ -39,6 +42,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 (matrix cores)
+PEAK_FP32_TFLOPS = 157.3  # MI355X dense FP32 (matrix cores)
 MICRO = dict(r=32, RM=10, RK=60, n=64, p=3)
 COPY_BYTES = 256 << 20
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "band_stage_K_c2shape_traffic.txt")
@@ -76,6 +80,48 @@ def traffic_from_profile():
     return float(m_bytes.group(1))
 
 
+def mixed_compare(iga, ctx, torch, geo, c, Y, steps):
+    """The c2 solve in the mixed form (FP32 local contractions, FP64 refinement) and in FP64
+    from the same assembled operators: solve times, residuals, state difference."""
+    n, p, beta = c["n"], c["degree"], c["beta"]
+    M, K, _ = iga.assemble_factors(ctx, geo, p, n, weight_tol=c["weight_tol"])
+    kk = iga.kkt_create(ctx, M, K, beta)
+    out = {}
+    fulls = {}
+    for name, prec in (("fp64", iga.FP64), ("mixed", iga.FP32)):
+        times, sts = [], []
+        for i in range(steps + 1):  # the first solve is a warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sol, st, rc = iga.amen_solve(ctx, kk, Y, c["tol"], precision=prec)
+            t1 = time.perf_counter()
+            if i > 0:
+                times.append(t1 - t0)
+                sts.append(st)
+            if i == steps:
+                fulls[name] = iga.btt_to_full(ctx, sol).cpu().numpy()
+            iga.btt_destroy(sol)
+        last = sts[-1]
+        d = {"solve_time_s": sum(times) / len(times), "kkt_residual": max(x["residual"] for x in sts),
+             "half_sweeps": last["half_sweeps"], "ranks": last["ranks"], "local_iterations": last["local_iterations"]}
+        if prec == iga.FP32:
+            d["refinements"] = last["refinements"]
+            d["local_matvecs_fp32"] = last["local_matvecs_fp32"]
+            d["local_matvec_gflops_fp32"] = (sum(x["local_matvec_flops_fp32"] for x in sts)
+                                             / sum(x["t_local_matvec_fp32"] for x in sts) / 1e9)
+        d["local_matvec_gflops_fp64"] = (sum(x["local_matvec_flops"] for x in sts)
+                                         / sum(x["t_local_matvec"] for x in sts) / 1e9)
+        out[name] = d
+    import numpy as np
+    y64, y32 = fulls["fp64"][0], fulls["mixed"][0]
+    out["mixed"]["state_rel_diff_vs_fp64"] = float(np.linalg.norm(y32 - y64) / np.linalg.norm(y64))
+    out["mixed"]["speedup_vs_fp64"] = out["fp64"]["solve_time_s"] / out["mixed"]["solve_time_s"]
+    iga.kkt_destroy(kk)
+    iga.ttop_destroy(M)
+    iga.ttop_destroy(K)
+    return out
+
+
 def micro_bench(iga, ctx, torch, iters):
     """Local TT-matvec at the microbenchmark shape on seeded N(0,1) inputs; the library times
     the banded stage of each operator with HIP events on its stream."""
@@ -108,7 +154,23 @@ def micro_bench(iga, ctx, torch, iters):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / iters
     flops = iga.local_matvec_flops(s["r"], s["n"], s["r"], s["p"], s["RM"], s["RM"], s["RK"], s["RK"])
-    return {"shape": dict(s), "ms": ms, "gflops": flops / ms / 1e6, "flops": flops, "profile": prof}, prob
+    # the same product in the mixed form (operands converted to FP32 inside each call)
+    for _ in range(3):
+        iga.local_matvec(*args, iga.FP32)
+    torch.cuda.synchronize()
+    iga.profile_start(ctx)
+    e0.record(stream)
+    for _ in range(iters):
+        iga.local_matvec(*args, iga.FP32)
+    e1.record(stream)
+    prof32 = iga.profile_stop(ctx)
+    torch.cuda.synchronize()
+    ms32 = e0.elapsed_time(e1) / iters
+    return {"shape": dict(s), "ms": ms, "gflops": flops / ms / 1e6, "flops": flops, "profile": prof,
+            "fp32": {"ms": ms32, "gflops": flops / ms32 / 1e6,
+                     "band_K_tflops": prof32["flops"][3] / (prof32["ms"][3] * 1e-3) / 1e12 if prof32["ms"][3] else None,
+                     "band_K_frac_of_fp32_peak": (prof32["flops"][3] / (prof32["ms"][3] * 1e-3) / 1e12
+                                                  / PEAK_FP32_TFLOPS) if prof32["ms"][3] else None}}, prob
 
 
 def cpu_baseline(prob, budget_s=12.0, max_calls=400):
@@ -191,6 +253,7 @@ def main():
     flops = sum(s["local_matvec_flops"] for s in stats)
     t_mv = sum(s["t_local_matvec"] for s in stats)
     gflops = flops / t_mv / 1e9
+    mixed = mixed_compare(iga, ctx, torch, geo, c, Y, max(1, min(a.steps, 3)))
     micro, prob = micro_bench(iga, ctx, torch, a.micro_iters)
     prof = micro["profile"]
     k_ms = prof["ms"][1] / max(prof["launches"][1], 1)
@@ -221,10 +284,11 @@ def main():
         "solve": {k: last[k] for k in ("half_sweeps", "ranks", "local_solves", "local_iterations", "local_matvecs",
                                        "local_matvec_flops", "t_local_matvec", "t_precond", "t_svd",
                                        "t_interfaces", "t_krylov_other", "t_residual", "op_ranks")},
-        "microbench_local_matvec": {k: micro[k] for k in ("shape", "ms", "gflops", "flops")},
+        "mixed_vs_fp64": mixed,
+        "microbench_local_matvec": {k: micro[k] for k in ("shape", "ms", "gflops", "flops", "fp32")},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
-                     "kernel": "gemm2_kernel<8, 4, 2, 2, 16, 2>: banded middle stage of the K operator in the "
+                     "kernel": "gemm2_kernel<8, 4, 2, 2, 16, 2, 2>: banded middle stage of the K operator in the "
                                "local TT-matvec at (r, R_M, R_K, n, p) = (32, 10, 60, 64, 3)",
                      "flops_per_launch": k_flops, "ms_per_launch": k_ms, "launches": prof["launches"][1]},
     }
