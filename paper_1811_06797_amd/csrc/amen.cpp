@@ -192,7 +192,13 @@ class Amen {
   DBuf ZL_[2][3], ZR_[2][3];  // (Z, A, X), A in {M, K}
   DBuf ZYL_[3], ZYR_[3];      // (Z, M, Y)
   // preconditioner of the current core
-  DBuf VL_, lamL_, VR_, lamR_;
+  // per core: eigen-data of the left and right interface pairs, with the interface version
+  // they were computed from (an interface changes only when its neighbour core is updated)
+  DBuf VLc_[3], lamLc_[3], VRc_[3], lamRc_[3];
+  unsigned verL_[4] = {0, 0, 0, 0}, verR_[4] = {0, 0, 0, 0};
+  unsigned cverL_[3] = {~0u, ~0u, ~0u}, cverR_[3] = {~0u, ~0u, ~0u};
+  int crL_[3] = {-1, -1, -1}, crR_[3] = {-1, -1, -1};
+  const double *VL_ = nullptr, *lamL_ = nullptr, *VR_ = nullptr, *lamR_ = nullptr;
   int pc_r0_ = 0, pc_r1_ = 0, pc_d_ = 0;
   DBuf pt1_, pt2_, pt3_;
   // Krylov workspace
@@ -259,6 +265,7 @@ void Amen::right_orth_plain(DBuf* cores, int* ranks, int d, bool prev_is_ell) {
 }
 
 void Amen::init_interfaces() {
+  for (int d = 0; d < 4; ++d) { ++verL_[d]; ++verR_[d]; }
   for (int op = 0; op < 3; ++op) {
     PL_[op][0] = ones1();
     PR_[op][2] = ones1();
@@ -278,6 +285,7 @@ void Amen::init_interfaces() {
 void Amen::update_right(int d) {
   g_phase = "update_right";
   const int id = t_if_.begin();
+  ++verR_[d - 1];
   const int r0 = r_[d], r1 = r_[d + 1];
   for (int op = 0; op < 3; ++op) {
     PR_[op][d - 1].reset(ctx_, (size_t)R(op, d) * r0 * r0);
@@ -305,6 +313,7 @@ void Amen::update_right(int d) {
 void Amen::update_left(int d) {
   g_phase = "update_left";
   const int id = t_if_.begin();
+  ++verL_[d + 1];
   const int r0 = r_[d], r1 = r_[d + 1];
   for (int op = 0; op < 3; ++op) {
     PL_[op][d + 1].reset(ctx_, (size_t)R(op, d + 1) * r1 * r1);
@@ -445,30 +454,40 @@ void Amen::setup_precond(int d) {
   const int id = t_pc_.begin();
   const int r0 = r_[d], r1 = r_[d + 1];
   pc_d_ = d; pc_r0_ = r0; pc_r1_ = r1;
-  VL_.ensure(ctx_, (size_t)r0 * r0);
-  lamL_.ensure(ctx_, r0);
-  VR_.ensure(ctx_, (size_t)r1 * r1);
-  lamR_.ensure(ctx_, r1);
-  if (d == 0) {
-    k::fill(st_, 1, 1.0, VL_.get());
-    k::fill(st_, 1, 0.0, lamL_.get());
-  } else {
-    // Kref left interface: slot 0 = K-part, slot 1 = M-part
-    DBuf H(ctx_, (size_t)2 * r0 * r0);
-    IGA_HIP(hipMemcpyAsync(H.get(), PL_[2][d].get(), (size_t)2 * r0 * r0 * 8, hipMemcpyDeviceToDevice, st_));
-    k::symmetrize(st_, 2, r0, H.get(), (long)r0 * r0);
-    gen_eig(ctx_, r0, H.get(), H.get() + (long)r0 * r0, VL_.get(), lamL_.get());
+  if (cverL_[d] != verL_[d] || crL_[d] != r0) {
+    VLc_[d].reset(ctx_, (size_t)r0 * r0);
+    lamLc_[d].reset(ctx_, r0);
+    if (d == 0) {
+      k::fill(st_, 1, 1.0, VLc_[d].get());
+      k::fill(st_, 1, 0.0, lamLc_[d].get());
+    } else {
+      // Kref left interface: slot 0 = K-part, slot 1 = M-part
+      DBuf H(ctx_, (size_t)2 * r0 * r0);
+      IGA_HIP(hipMemcpyAsync(H.get(), PL_[2][d].get(), (size_t)2 * r0 * r0 * 8, hipMemcpyDeviceToDevice, st_));
+      k::symmetrize(st_, 2, r0, H.get(), (long)r0 * r0);
+      gen_eig(ctx_, r0, H.get(), H.get() + (long)r0 * r0, VLc_[d].get(), lamLc_[d].get());
+    }
+    cverL_[d] = verL_[d];
+    crL_[d] = r0;
   }
-  if (d == 2) {
-    k::fill(st_, 1, 1.0, VR_.get());
-    k::fill(st_, 1, 0.0, lamR_.get());
-  } else {
-    // right interface: slot 0 = M-part, slot 1 = K-part
-    DBuf H(ctx_, (size_t)2 * r1 * r1);
-    IGA_HIP(hipMemcpyAsync(H.get(), PR_[2][d].get(), (size_t)2 * r1 * r1 * 8, hipMemcpyDeviceToDevice, st_));
-    k::symmetrize(st_, 2, r1, H.get(), (long)r1 * r1);
-    gen_eig(ctx_, r1, H.get() + (long)r1 * r1, H.get(), VR_.get(), lamR_.get());
+  if (cverR_[d] != verR_[d] || crR_[d] != r1) {
+    VRc_[d].reset(ctx_, (size_t)r1 * r1);
+    lamRc_[d].reset(ctx_, r1);
+    if (d == 2) {
+      k::fill(st_, 1, 1.0, VRc_[d].get());
+      k::fill(st_, 1, 0.0, lamRc_[d].get());
+    } else {
+      // right interface: slot 0 = M-part, slot 1 = K-part
+      DBuf H(ctx_, (size_t)2 * r1 * r1);
+      IGA_HIP(hipMemcpyAsync(H.get(), PR_[2][d].get(), (size_t)2 * r1 * r1 * 8, hipMemcpyDeviceToDevice, st_));
+      k::symmetrize(st_, 2, r1, H.get(), (long)r1 * r1);
+      gen_eig(ctx_, r1, H.get() + (long)r1 * r1, H.get(), VRc_[d].get(), lamRc_[d].get());
+    }
+    cverR_[d] = verR_[d];
+    crR_[d] = r1;
   }
+  VL_ = VLc_[d].get(); lamL_ = lamLc_[d].get();
+  VR_ = VRc_[d].get(); lamR_ = lamRc_[d].get();
   t_pc_.end(id);
 }
 
@@ -490,7 +509,7 @@ void Amen::apply_precond(const double* v, double* z) {
     // mode a: out[l][a'][(j b)] = sum_a VL(a, a') in[l][a][(j b)]
     k::Gemm ga;
     ga.M = r0; ga.N = n * r1; ga.K = r0;
-    ga.A = VL_.get(); ga.sAm = tr ? 1 : r0; ga.sAk = tr ? r0 : 1;
+    ga.A = VL_; ga.sAm = tr ? 1 : r0; ga.sAk = tr ? r0 : 1;
     ga.B = src; ga.sBk = (long)n * r1; ga.sBn = 1;
     ga.C = pt2_.get(); ga.sCm = (long)n * r1; ga.sCn = 1;
     ga.nb1 = 3; ga.sBb1 = e; ga.sCb1 = e;
@@ -509,12 +528,12 @@ void Amen::apply_precond(const double* v, double* z) {
     k::Gemm gb;
     gb.M = 3 * r0 * n; gb.N = r1; gb.K = r1;
     gb.A = jout; gb.sAm = r1; gb.sAk = 1;
-    gb.B = VR_.get(); gb.sBk = tr ? r1 : 1; gb.sBn = tr ? 1 : r1;
+    gb.B = VR_; gb.sBk = tr ? r1 : 1; gb.sBn = tr ? 1 : r1;
     gb.C = bout; gb.sCm = r1; gb.sCn = 1;
     k::gemm(st_, gb);
     if (!tr) k::scale3(st_, e, 1.0, g_, 1.0 / g_, z);  // D^{-1}: to the scaled unknowns
     if (tr) {
-      k::fd_solve(st_, r0, n, r1, lamL_.get(), kkt_->lamn[pc_d_].get(), lamR_.get(), kkt_->beta, 1.0,
+      k::fd_solve(st_, r0, n, r1, lamL_, kkt_->lamn[pc_d_].get(), lamR_, kkt_->beta, 1.0,
                   pt2_.get());
       std::swap(pt1_, pt2_);
     }

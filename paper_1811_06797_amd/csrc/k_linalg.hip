@@ -10,29 +10,34 @@ namespace k {
 namespace {
 
 constexpr int JT = 512;        // threads per Jacobi workgroup
-constexpr int LDS_MAX_K = 120; // H kept in LDS up to this size ((k+1)*k*8 bytes)
+constexpr int LDS_MAX_K = 120;      // H kept in LDS up to this size ((k+1)*k*8 bytes)
+constexpr int LDS_BOTH_MAX_K = 96;  // H and the eigenvector rows both in LDS up to this size
 
-// Parallel cyclic Jacobi with round-robin pairing (circle method): in every
-// round the k/2 disjoint pairs (p, q) are rotated at once; H <- J^T H J by a
-// row pass then a column pass, and the eigenvectors are accumulated as rows of
-// WT (WT <- J^T WT, i.e. W <- W J). A rotation is skipped when
-// |h_pq| <= max(tol * sqrt(|h_pp h_qq|), 1e-30 trace), or when both h_pp and h_qq are
-// below 1e-28 trace (directions at the rounding level of the largest one).
-template <bool USE_LDS>
+// Parallel cyclic Jacobi with round-robin pairing (circle method): in every round the k/2
+// disjoint pairs (p, q) are rotated at once, H <- J^T H J, and the eigenvectors are
+// accumulated as rows of WT (WT <- J^T WT, i.e. W <- W J). After the rotation parameters of
+// the round are known, one pass updates H by 2 x 2 blocks {p_t1, q_t1} x {p_t2, q_t2} (rows
+// by rotation t1 and columns by rotation t2 together; the blocks are disjoint and cover H)
+// and rows p, q of WT. A rotation is skipped when |h_pq| <= max(tol * sqrt(|h_pp h_qq|),
+// 1e-30 trace), or when both h_pp and h_qq are below 1e-28 trace (directions at the
+// rounding level of the largest one). A rotated diagonal block is stored exactly (zero
+// off-diagonal, closed-form diagonal), so rounding noise in h_pq cannot keep sweeps going.
+// MODE 0: H and WT in global memory; 1: H in LDS; 2: H and WT in LDS.
+template <int MODE>
 __global__ __launch_bounds__(JT) void jacobi_kernel(int k, double* Hs, long sH, double* WTs,
                                                     long sW, double tol, int max_sweeps,
                                                     int* sweeps_out) {
   extern __shared__ double lds[];
   double* Hg = Hs + blockIdx.x * sH;
-  double* WT = WTs + blockIdx.x * sW;
+  double* WTg = WTs + blockIdx.x * sW;
   const int tid = threadIdx.x, nt = blockDim.x;
-  const int ld = USE_LDS ? k + 1 : k;
-  double* H = USE_LDS ? lds : Hg;
-  if (USE_LDS)
+  const int ld = MODE >= 1 ? k + 1 : k;
+  double* H = MODE >= 1 ? lds : Hg;
+  double* WT = MODE == 2 ? lds + (size_t)(k + 1) * k : WTg;
+  if (MODE >= 1)
     for (int e = tid; e < k * k; e += nt) H[(e / k) * ld + e % k] = Hg[e];
   for (int e = tid; e < k * k; e += nt) WT[e] = (e / k == e % k) ? 1.0 : 0.0;
   __shared__ double cs[JT / 2], sn[JT / 2], dp[JT / 2], dq[JT / 2];
-  __shared__ int pp[JT / 2], qq[JT / 2];
   __shared__ int rotated;
   __shared__ double trace;
   __syncthreads();
@@ -46,21 +51,25 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(int k, double* Hs, long sH, 
   const double floor_col = 1e-28 * trace;
   const int kk = k + (k & 1);
   const int npair = kk / 2;
+  // circle method: position 0 fixed, positions 1..kk-1 rotate
+  auto pair_of = [&](int t, int round, int& p, int& q) {
+    auto player = [&](int pos) { return pos == 0 ? 0 : 1 + (pos - 1 + round) % (kk - 1); };
+    p = player(t);
+    q = player(kk - 1 - t);
+    if (p > q) { const int x = p; p = q; q = x; }
+  };
   int sweeps = 0;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     if (tid == 0) rotated = 0;
     __syncthreads();
     for (int round = 0; round < kk - 1; ++round) {
       for (int t = tid; t < npair; t += nt) {
-        // circle method: position 0 fixed, positions 1..kk-1 rotate
-        auto player = [&](int pos) { return pos == 0 ? 0 : 1 + (pos - 1 + round) % (kk - 1); };
-        int p = player(t), q = player(kk - 1 - t);
-        if (p > q) { int tmp = p; p = q; q = tmp; }
+        int p, q;
+        pair_of(t, round, p, q);
         double c = 1.0, s = 0.0, np = 0.0, nq = 0.0;
         if (q < k) {
           const double app = H[p * ld + p], aqq = H[q * ld + q], apq = H[p * ld + q];
           const double thr = fmax(tol * sqrt(fabs(app * aqq)), floor_abs);
-          // columns at the rounding level of the largest are not rotated among themselves
           const bool negligible = fabs(app) <= floor_col && fabs(aqq) <= floor_col;
           if (!negligible && fabs(apq) > thr) {
             const double tau = (aqq - app) / (2.0 * apq);
@@ -72,45 +81,48 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(int k, double* Hs, long sH, 
             rotated = 1;
           }
         }
-        pp[t] = p; qq[t] = q; cs[t] = c; sn[t] = s; dp[t] = np; dq[t] = nq;
+        cs[t] = c; sn[t] = s; dp[t] = np; dq[t] = nq;
       }
       __syncthreads();
-      // rows p, q of H and WT
+      // H by 2 x 2 blocks
+      for (int blk = tid; blk < npair * npair; blk += nt) {
+        const int t1 = blk / npair, t2 = blk - t1 * npair;
+        const double s1 = sn[t1], s2 = sn[t2];
+        if (s1 == 0.0 && s2 == 0.0) continue;
+        int p1, q1, p2, q2;
+        pair_of(t1, round, p1, q1);
+        pair_of(t2, round, p2, q2);
+        if (t1 == t2) {
+          H[p1 * ld + p1] = dp[t1];
+          H[q1 * ld + q1] = dq[t1];
+          H[p1 * ld + q1] = 0.0;
+          H[q1 * ld + p1] = 0.0;
+          continue;
+        }
+        const double c1 = cs[t1], c2 = cs[t2];
+        const bool hq1 = q1 < k, hq2 = q2 < k;  // q = k is the padding index of odd k (never rotated)
+        const double a = H[p1 * ld + p2];
+        const double bq = hq2 ? H[p1 * ld + q2] : 0.0;
+        const double cp = hq1 ? H[q1 * ld + p2] : 0.0;
+        const double d = (hq1 && hq2) ? H[q1 * ld + q2] : 0.0;
+        const double a1 = c1 * a - s1 * cp, c1p = s1 * a + c1 * cp;
+        const double b1 = c1 * bq - s1 * d, d1 = s1 * bq + c1 * d;
+        H[p1 * ld + p2] = c2 * a1 - s2 * b1;
+        if (hq2) H[p1 * ld + q2] = s2 * a1 + c2 * b1;
+        if (hq1) H[q1 * ld + p2] = c2 * c1p - s2 * d1;
+        if (hq1 && hq2) H[q1 * ld + q2] = s2 * c1p + c2 * d1;
+      }
+      // rows p, q of WT
       for (int e = tid; e < npair * k; e += nt) {
         const int t = e / k, j = e - t * k;
         const double s = sn[t];
         if (s == 0.0) continue;
         const double c = cs[t];
-        const int p = pp[t], q = qq[t];
-        const double hp = H[p * ld + j], hq = H[q * ld + j];
-        H[p * ld + j] = c * hp - s * hq;
-        H[q * ld + j] = s * hp + c * hq;
+        int p, q;
+        pair_of(t, round, p, q);
         const double wp = WT[p * k + j], wq = WT[q * k + j];
         WT[p * k + j] = c * wp - s * wq;
         WT[q * k + j] = s * wp + c * wq;
-      }
-      __syncthreads();
-      // columns p, q of H
-      for (int e = tid; e < npair * k; e += nt) {
-        const int t = e / k, i = e - t * k;
-        const double s = sn[t];
-        if (s == 0.0) continue;
-        const double c = cs[t];
-        const int p = pp[t], q = qq[t];
-        const double hp = H[i * ld + p], hq = H[i * ld + q];
-        H[i * ld + p] = c * hp - s * hq;
-        H[i * ld + q] = s * hp + c * hq;
-      }
-      __syncthreads();
-      // each rotated 2 x 2 block is diagonal by construction: store it exactly, so that
-      // rounding noise left in h_pq cannot keep the sweeps going
-      for (int t = tid; t < npair; t += nt) {
-        if (sn[t] == 0.0) continue;
-        const int p = pp[t], q = qq[t];
-        H[p * ld + q] = 0.0;
-        H[q * ld + p] = 0.0;
-        H[p * ld + p] = dp[t];
-        H[q * ld + q] = dq[t];
       }
       __syncthreads();
     }
@@ -118,8 +130,10 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(int k, double* Hs, long sH, 
     ++sweeps;
     __syncthreads();
   }
-  if (USE_LDS)
+  if (MODE >= 1)
     for (int e = tid; e < k * k; e += nt) Hg[e] = H[(e / k) * ld + e % k];
+  if (MODE == 2)
+    for (int e = tid; e < k * k; e += nt) WTg[e] = WT[e];
   if (tid == 0 && sweeps_out) sweeps_out[blockIdx.x] = sweeps;
 }
 
@@ -270,7 +284,8 @@ __global__ __launch_bounds__(OST) void osbj_gram_kernel(const double* B, int m, 
   for (int s = 0; s < 4; ++s) out[tid + OST * s] = acc[s];
 }
 
-constexpr int ORT = 256;  // threads per pair in osbj_rot
+constexpr int ORT = 256;  // threads per pair in osbj_rot: one per 2 x 2 block of the 32 x 32 Gram matrix
+static_assert(ORT == (OSP / 2) * (OSP / 2), "one thread per 2 x 2 block");
 // Inner Jacobi sweeps per pair and round. The pair's rotation need not diagonalise its Gram
 // matrix fully: the outer iteration revisits every pair each sweep and stops only when no
 // pair needs a rotation at the outer threshold.
@@ -298,7 +313,6 @@ __global__ __launch_bounds__(ORT) void osbj_rot_kernel(const double* Gsum, doubl
   __shared__ double G[OSP][OSP + 1];
   __shared__ double W[OSP][OSP + 1];
   __shared__ double cs[OSP / 2], sn[OSP / 2], dp[OSP / 2], dq[OSP / 2];
-  __shared__ int pp[OSP / 2], qq[OSP / 2];
   __shared__ int rot_any, rot_sweep;
   const int tid = threadIdx.x, pair = blockIdx.x;
   const double* in = Gsum + (long)pair * (OSP * OSP);
@@ -309,6 +323,13 @@ __global__ __launch_bounds__(ORT) void osbj_rot_kernel(const double* Gsum, doubl
   }
   if (tid == 0) rot_any = 0;
   __syncthreads();
+  // Each round: the 16 disjoint rotations (p_t, q_t) of the round-robin schedule are found by
+  // threads 0..15; then thread (t1, t2) applies rows of rotation t1 and columns of rotation t2
+  // to the 2 x 2 block {p_t1, q_t1} x {p_t2, q_t2} of G at once (the blocks are disjoint and
+  // cover G), and rows i = tid / 16, tid / 16 + 16 of W take rotation tid % 16. Diagonal blocks
+  // of rotated pairs are stored exactly (zero off-diagonal, closed-form diagonal), so rounding
+  // noise in g_pq cannot trigger further rotations.
+  const int t1 = tid / (OSP / 2), t2 = tid % (OSP / 2);
   for (int sweep = 0; sweep < OSBJ_INNER_SWEEPS; ++sweep) {
     if (tid == 0) rot_sweep = 0;
     __syncthreads();
@@ -329,42 +350,41 @@ __global__ __launch_bounds__(ORT) void osbj_rot_kernel(const double* Gsum, doubl
           nq = aqq + t * apq;
           rot_sweep = 1;
         }
-        pp[tid] = p; qq[tid] = q; cs[tid] = c; sn[tid] = sv; dp[tid] = np; dq[tid] = nq;
+        cs[tid] = c; sn[tid] = sv; dp[tid] = np; dq[tid] = nq;
       }
       __syncthreads();
-      for (int e = tid; e < (OSP / 2) * OSP; e += ORT) {
-        const int t = e / OSP, j = e % OSP;
-        const double sv = sn[t];
-        if (sv == 0.0) continue;
-        const double c = cs[t];
-        const int p = pp[t], q = qq[t];
-        const double gp = G[p][j], gq = G[q][j];
-        G[p][j] = c * gp - sv * gq;
-        G[q][j] = sv * gp + c * gq;
-      }
-      __syncthreads();
-      for (int e = tid; e < (OSP / 2) * OSP; e += ORT) {
-        const int t = e / OSP, i = e % OSP;
-        const double sv = sn[t];
-        if (sv == 0.0) continue;
-        const double c = cs[t];
-        const int p = pp[t], q = qq[t];
-        const double gp = G[i][p], gq = G[i][q];
-        G[i][p] = c * gp - sv * gq;
-        G[i][q] = sv * gp + c * gq;
-        const double wp = W[i][p], wq = W[i][q];
-        W[i][p] = c * wp - sv * wq;
-        W[i][q] = sv * wp + c * wq;
-      }
-      __syncthreads();
-      // the rotated 2 x 2 block is diagonal by construction: store it exactly, so rounding
-      // noise in g_pq cannot trigger further rotations
-      if (tid < OSP / 2 && sn[tid] != 0.0) {
-        const int p = pp[tid], q = qq[tid];
-        G[p][q] = 0.0;
-        G[q][p] = 0.0;
-        G[p][p] = dp[tid];
-        G[q][q] = dq[tid];
+      {
+        int p1, q1, p2, q2;
+        circle_pair(t1, r2, OSP, p1, q1);
+        circle_pair(t2, r2, OSP, p2, q2);
+        const double c1 = cs[t1], s1 = sn[t1], c2 = cs[t2], s2 = sn[t2];
+        if (s1 != 0.0 || s2 != 0.0) {
+          if (t1 == t2) {
+            G[p1][p1] = dp[t1];
+            G[q1][q1] = dq[t1];
+            G[p1][q1] = 0.0;
+            G[q1][p1] = 0.0;
+          } else {
+            const double a = G[p1][p2], bq = G[p1][q2], cp = G[q1][p2], d = G[q1][q2];
+            // rows (rotation t1), then columns (rotation t2)
+            const double a1 = c1 * a - s1 * cp, c1p = s1 * a + c1 * cp;
+            const double b1 = c1 * bq - s1 * d, d1 = s1 * bq + c1 * d;
+            G[p1][p2] = c2 * a1 - s2 * b1;
+            G[p1][q2] = s2 * a1 + c2 * b1;
+            G[q1][p2] = c2 * c1p - s2 * d1;
+            G[q1][q2] = s2 * c1p + c2 * d1;
+          }
+        }
+        // W <- W J: rows tid / 16 and tid / 16 + 16, rotation tid % 16
+        if (s2 != 0.0) {
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int i = t1 + h * (OSP / 2);
+            const double wp = W[i][p2], wq = W[i][q2];
+            W[i][p2] = c2 * wp - s2 * wq;
+            W[i][q2] = s2 * wp + c2 * wq;
+          }
+        }
       }
       __syncthreads();
     }
@@ -457,18 +477,23 @@ int jacobi_lds_max() { return LDS_MAX_K; }
 void jacobi_eig(hipStream_t s, int nmat, int k, double* H, long strideH, double* W, long strideW,
                 double tol, int max_sweeps, int* sweeps_out) {
   require(k >= 1 && k <= 1024, IGA_EINVAL, "jacobi_eig: k out of range");
-  if (k <= LDS_MAX_K) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    IGA_HIP(hipFuncSetAttribute((const void*)jacobi_kernel<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (LDS_MAX_K + 1) * LDS_MAX_K * (int)sizeof(double)));
+    IGA_HIP(hipFuncSetAttribute((const void*)jacobi_kernel<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                ((LDS_BOTH_MAX_K + 1) * LDS_BOTH_MAX_K + LDS_BOTH_MAX_K * LDS_BOTH_MAX_K) *
+                                    (int)sizeof(double)));
+    attr_set = true;
+  }
+  if (k <= LDS_BOTH_MAX_K) {
+    const size_t lds = ((size_t)(k + 1) * k + (size_t)k * k) * sizeof(double);
+    jacobi_kernel<2><<<nmat, JT, lds, s>>>(k, H, strideH, W, strideW, tol, max_sweeps, sweeps_out);
+  } else if (k <= LDS_MAX_K) {
     const size_t lds = (size_t)(k + 1) * k * sizeof(double);
-    static bool attr_set = false;
-    if (!attr_set) {
-      IGA_HIP(hipFuncSetAttribute((const void*)jacobi_kernel<true>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (LDS_MAX_K + 1) * LDS_MAX_K * (int)sizeof(double)));
-      attr_set = true;
-    }
-    jacobi_kernel<true><<<nmat, JT, lds, s>>>(k, H, strideH, W, strideW, tol, max_sweeps, sweeps_out);
+    jacobi_kernel<1><<<nmat, JT, lds, s>>>(k, H, strideH, W, strideW, tol, max_sweeps, sweeps_out);
   } else {
-    jacobi_kernel<false><<<nmat, JT, 0, s>>>(k, H, strideH, W, strideW, tol, max_sweeps, sweeps_out);
+    jacobi_kernel<0><<<nmat, JT, 0, s>>>(k, H, strideH, W, strideW, tol, max_sweeps, sweeps_out);
   }
   IGA_HIP(hipGetLastError());
 }
