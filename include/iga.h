@@ -163,6 +163,13 @@ int iga_ttop_info(const iga_ttop* op, int* n, int* R, int* degree);
 int iga_ttop_get_core(iga_ctx* ctx, const iga_ttop* op, int d, double* host_out);
 void iga_ttop_destroy(iga_ttop* op);
 
+/* TT of a full tensor [n0][n1][n2] (device, FP64, caller-owned, read only) by sequential
+ * truncated SVDs (Section 5, eq. tt; the TT-SVD of the weight tensors in Section 3) with
+ * relative Frobenius tolerance rel_tol (split as rel_tol / sqrt(2) per unfolding; 0 keeps
+ * every nonzero singular value up to rounding). *out is owned by the caller
+ * (iga_tt_destroy). Synchronises. */
+int iga_tt_from_full(iga_ctx* ctx, const int n[3], const double* full, double rel_tol, iga_tt** out);
+
 /* TT vectors. iga_tt_create copies host cores; iga_tt_wrap wraps caller-owned
  * device cores without copying (they must outlive the handle). r[0]=r[3]=1. */
 int iga_tt_create(iga_ctx* ctx, const int n[3], const int r[4], const double* const host_cores[3],
@@ -218,6 +225,29 @@ int iga_local_matvec(iga_ctx* ctx, int r0, int n, int r1, int degree, int RM0, i
                      int RK1, const double* PhiL_M, const double* PhiR_M, const double* PhiL_K,
                      const double* PhiR_K, const double* Mcore, const double* Kcore, double beta,
                      const double* x, double* y, int precision);
+
+/* Reduced cost of the control problem at a solution f = (y, u, lambda) of the KKT
+ * system (Section 4, eq. optimization1 with time removed):
+ *   J = 1/2 (y - yhat)^T M (y - yhat) + beta/2 u^T M u, in FP64 on expanded vectors. */
+int iga_objective(iga_ctx* ctx, const iga_kkt* kkt, const iga_tt* yhat, const iga_btt* f, double* J);
+
+/* Gradient of the reduced cost with respect to the desired-state coefficients: at the
+ * optimum dJ/dyhat = -M (y - yhat) (derivative of the Lagrangian of Section 4 in yhat).
+ * grad: device, [n0][n1][n2] FP64, caller-owned. Synchronises. */
+int iga_grad_yhat(iga_ctx* ctx, const iga_kkt* kkt, const iga_tt* yhat, const iga_btt* f, double* grad);
+
+/* Gradient of the reduced cost with respect to the geometry control points (the derivative
+ * of the Lagrangian J + lambda^T (K y - M u) at f along the geometry). M and K depend on the
+ * geometry through the weights omega and Q interpolated in the space of Section 3 (eqs.
+ * weightEquationSystem, weightEquationSolve); the gradient is that of this discretisation
+ * with untruncated weight tensors (weight_tol and weight_rmax of opts are not used; p_interp
+ * and nquad are). geo, degree, n: as for iga_assemble_factors; f: the solution for the
+ * operators assembled from geo (and beta). grad: host, [3][ncp0][ncp1][ncp2] FP64 (same
+ * layout as geo->ctrl), caller-owned. Needs about 2 GB of device workspace plus the grid
+ * arrays. Synchronises. */
+int iga_grad_geometry(iga_ctx* ctx, const iga_geometry* geo, int degree, const int n[3],
+                      const iga_assembly_opts* opts, double beta, const iga_tt* yhat, const iga_btt* f,
+                      double* grad);
 
 /* Algorithmic flops of one iga_local_matvec call with these sizes. */
 double iga_local_matvec_flops(int r0, int n, int r1, int degree, int RM0, int RM1, int RK0, int RK1);

@@ -79,6 +79,10 @@ void Pool::release(void* p) {
 
 void release_scratch(iga_ctx* ctx);
 void release_raw_cache(iga_ctx* ctx);
+int objective_impl(iga_ctx* ctx, const iga_kkt* kkt, const iga_tt* Y, const iga_btt* f, double* J, double* grad);
+iga_tt* tt_from_full_impl(iga_ctx* ctx, const int n[3], const double* full, double rel_tol);
+int grad_geometry_impl(iga_ctx* ctx, const iga_geometry* geo, int p, const int n[3], const iga_assembly_opts* opts,
+                       double beta, const iga_tt* Y, const iga_btt* f, double* grad);
 int assemble_impl(iga_ctx* ctx, const iga_geometry* geo, int p, const int n[3],
                   const iga_assembly_opts* opts, iga_ttop** M, iga_ttop** K, int* ranks_out);
 int amen_impl(iga_ctx* ctx, const iga_kkt* kkt, const iga_tt* yhat, double tol,
@@ -278,6 +282,16 @@ int iga_tt_create(iga_ctx* ctx, const int n[3], const int r[4], const double* co
     }
     IGA_HIP(hipStreamSynchronize(ctx->stream));
     *out = t.release();
+    return IGA_OK;
+  });
+}
+
+int iga_tt_from_full(iga_ctx* ctx, const int n[3], const double* full, double rel_tol, iga_tt** out) {
+  return guarded([&] {
+    require(ctx && n && full && out, IGA_EINVAL, "tt_from_full: NULL argument");
+    *out = nullptr;
+    use_device(ctx);
+    *out = tt_from_full_impl(ctx, n, full, rel_tol);
     return IGA_OK;
   });
 }
@@ -515,6 +529,33 @@ int iga_local_matvec(iga_ctx* ctx, int r0, int n, int r1, int degree, int RM0, i
     local_matvec_impl(ctx, r0, n, r1, degree, RM0, RM1, RK0, RK1, PhiL_M, PhiR_M, PhiL_K, PhiR_K, Mcore,
                       Kcore, beta, x, y, precision);
     return IGA_OK;
+  });
+}
+
+int iga_objective(iga_ctx* ctx, const iga_kkt* kkt, const iga_tt* yhat, const iga_btt* f, double* J) {
+  return guarded([&] {
+    require(ctx && J, IGA_EINVAL, "objective: NULL argument");
+    use_device(ctx);
+    return objective_impl(ctx, kkt, yhat, f, J, nullptr);
+  });
+}
+
+int iga_grad_yhat(iga_ctx* ctx, const iga_kkt* kkt, const iga_tt* yhat, const iga_btt* f, double* grad) {
+  return guarded([&] {
+    require(ctx && grad, IGA_EINVAL, "grad_yhat: NULL argument");
+    use_device(ctx);
+    return objective_impl(ctx, kkt, yhat, f, nullptr, grad);
+  });
+}
+
+int iga_grad_geometry(iga_ctx* ctx, const iga_geometry* geo, int degree, const int n[3],
+                      const iga_assembly_opts* opts, double beta, const iga_tt* yhat, const iga_btt* f,
+                      double* grad) {
+  return guarded([&] {
+    require(ctx && n, IGA_EINVAL, "grad_geometry: NULL argument");
+    require(beta > 0.0, IGA_EINVAL, "grad_geometry: beta must be > 0");
+    use_device(ctx);
+    return grad_geometry_impl(ctx, geo, degree, n, opts, beta, yhat, f, grad);
   });
 }
 

@@ -15,11 +15,13 @@
 //    beta_j in direction k (eq. stiffnessFinal).
 #include <algorithm>
 #include <cmath>
+#include <memory>
 #include <vector>
 
 #include "common.hpp"
 #include "kernels.hpp"
 #include "ttops.hpp"
+#include "assemble.hpp"
 
 namespace iga {
 
@@ -81,14 +83,6 @@ DBuf upload(iga_ctx* ctx, const double* h, size_t n) {
   IGA_HIP(hipStreamSynchronize(ctx->stream));
   return b;
 }
-
-struct Dir {
-  int n, N, E, nt;
-  std::vector<double> ksol, kint, grev, qpts, qw;
-  DBuf dksol, dkint, dgrev, dqpts, dqw;
-  DBuf Bv, Bd, Bt;  // [Q][N] values, derivatives; [Q][nt] interpolation basis
-  DBuf Binv;        // [nt][nt]
-};
 
 struct TT3 {
   int r[4] = {1, 0, 0, 1};
@@ -170,8 +164,102 @@ void opcore_setup_blocks(iga_ctx* ctx, OpCore& c, const std::vector<RankBlock>& 
 
 int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
 
+// TT of a full tensor [n0][n1][n2] (device) by the sequential truncated SVDs used for the
+// weights, relative Frobenius tolerance rel_tol split as rel_tol / sqrt(2) per unfolding.
+iga_tt* tt_from_full_impl(iga_ctx* ctx, const int n[3], const double* full, double rel_tol) {
+  require(n[0] >= 1 && n[1] >= 1 && n[2] >= 1, IGA_EINVAL, "tt_from_full: bad sizes");
+  require(rel_tol >= 0.0 && rel_tol < 1.0, IGA_EINVAL, "tt_from_full: tolerance must be in [0, 1)");
+  const long N = (long)n[0] * n[1] * n[2];
+  const double fro = std::sqrt(norm2_host(ctx, N, full));
+  std::unique_ptr<iga_tt> t(new iga_tt());
+  t->ctx = ctx;
+  for (int d = 0; d < 3; ++d) t->n[d] = n[d];
+  TT3 tt;
+  tt_svd3(ctx, full, n, std::max(rel_tol, 1e-15) / std::sqrt(2.0) * fro, 0, tt);
+  for (int d = 0; d < 4; ++d) t->r[d] = tt.r[d];
+  for (int d = 0; d < 3; ++d) {
+    t->own[d] = std::move(tt.core[d]);
+    t->core[d] = t->own[d].get();
+  }
+  IGA_HIP(hipStreamSynchronize(ctx->stream));
+  return t.release();
+}
+
+void setup_spaces(iga_ctx* ctx, int p, const int n[3], int pt, int nq, SpaceDir dir[3]) {
+  hipStream_t st = ctx->stream;
+  std::vector<double> gx, gw;
+  gauss_legendre(nq, gx, gw);
+  for (int d = 0; d < 3; ++d) {
+    SpaceDir& D = dir[d];
+    D.n = n[d]; D.N = n[d] + 2; D.E = D.N - p; D.nt = D.E + pt;
+    D.ksol = uniform_open_knots(D.N, p);
+    D.kint = uniform_open_knots(D.nt, pt);
+    D.grev = greville(D.kint, pt);
+    for (int e = 0; e < D.E; ++e) {
+      const double a = double(e) / D.E, h = 1.0 / D.E;
+      for (int q = 0; q < nq; ++q) {
+        D.qpts.push_back(a + 0.5 * h * (gx[q] + 1.0));
+        D.qw.push_back(0.5 * h * gw[q]);
+      }
+    }
+    D.dksol = upload(ctx, D.ksol.data(), D.ksol.size());
+    D.dkint = upload(ctx, D.kint.data(), D.kint.size());
+    D.dgrev = upload(ctx, D.grev.data(), D.grev.size());
+    D.dqpts = upload(ctx, D.qpts.data(), D.qpts.size());
+    D.dqw = upload(ctx, D.qw.data(), D.qw.size());
+    const int Q = D.E * nq;
+    D.Bv.reset(ctx, (size_t)Q * D.N);
+    D.Bd.reset(ctx, (size_t)Q * D.N);
+    D.Bt.reset(ctx, (size_t)Q * D.nt);
+    k::bspline_tabulate(st, D.dksol.get(), (int)D.ksol.size(), p, D.dqpts.get(), Q, 0, D.Bv.get());
+    k::bspline_tabulate(st, D.dksol.get(), (int)D.ksol.size(), p, D.dqpts.get(), Q, 1, D.Bd.get());
+    k::bspline_tabulate(st, D.dkint.get(), (int)D.kint.size(), pt, D.dqpts.get(), Q, 0, D.Bt.get());
+    // collocation matrix of the interpolation space at its Greville points, and its inverse
+    DBuf Bc(ctx, (size_t)D.nt * D.nt), work(ctx, (size_t)2 * D.nt * D.nt);
+    IBuf sing(ctx, 1);
+    k::bspline_tabulate(st, D.dkint.get(), (int)D.kint.size(), pt, D.dgrev.get(), D.nt, 0, Bc.get());
+    D.Binv.reset(ctx, (size_t)D.nt * D.nt);
+    k::invert(st, D.nt, Bc.get(), D.Binv.get(), work.get(), sing.get());
+    int singular = 0;
+    IGA_HIP(hipMemcpyAsync(&singular, sing.get(), sizeof(int), hipMemcpyDeviceToHost, st));
+    IGA_HIP(hipStreamSynchronize(st));
+    require(!singular, IGA_EINVAL, "collocation matrix of the interpolation space is singular");
+  }
+
+}
+
+void geometry_tables(iga_ctx* ctx, const iga_geometry* geo, const SpaceDir dir[3], GeometryTables& gt) {
+  hipStream_t st = ctx->stream;
+  for (int d = 0; d < 3; ++d) {
+    const int nk = geo->ncp[d] + geo->degree + 1;
+    const int ntd = dir[d].nt;
+    gt.gk[d] = upload(ctx, geo->knots[d], nk);
+    gt.Bv[d].reset(ctx, (size_t)ntd * geo->ncp[d]);
+    gt.Bd[d].reset(ctx, (size_t)ntd * geo->ncp[d]);
+    k::bspline_tabulate(st, gt.gk[d].get(), nk, geo->degree, dir[d].dgrev.get(), ntd, 0, gt.Bv[d].get());
+    k::bspline_tabulate(st, gt.gk[d].get(), nk, geo->degree, dir[d].dgrev.get(), ntd, 1, gt.Bd[d].get());
+    gt.bv[d] = gt.Bv[d].get();
+    gt.bd[d] = gt.Bd[d].get();
+  }
+  gt.ctrl = upload(ctx, geo->ctrl, (size_t)3 * geo->ncp[0] * geo->ncp[1] * geo->ncp[2]);
+}
+
+void check_geometry(const iga_geometry* geo) {
+  require(geo != nullptr && geo->ctrl != nullptr, IGA_EINVAL, "geometry: NULL argument");
+  require(geo->degree >= 1 && geo->degree <= 15, IGA_EINVAL, "geometry degree must be in 1..15");
+  for (int d = 0; d < 3; ++d) {
+    require(geo->ncp[d] > geo->degree && geo->knots[d], IGA_EINVAL, "geometry: bad control net");
+    const int nk = geo->ncp[d] + geo->degree + 1;
+    const double* t = geo->knots[d];
+    for (int i = 0; i + 1 < nk; ++i) require(t[i] <= t[i + 1], IGA_EINVAL, "geometry knots must be non-decreasing");
+    require(t[0] == 0.0 && t[nk - 1] == 1.0, IGA_EINVAL, "geometry knots must span [0, 1]");
+  }
+}
+
+
+
 // Banded factor core [R0][n][2p+1][R1] of one weight TT core for one derivative type.
-static void build_factor(iga_ctx* ctx, const Dir& D, int p, int nq, const double* Wcore, int R0, int R1,
+static void build_factor(iga_ctx* ctx, const SpaceDir& D, int p, int nq, const double* Wcore, int R0, int R1,
                          bool di, bool dj, double* out) {
   hipStream_t st = ctx->stream;
   const int Q = D.E * nq, b = 2 * p + 1;
@@ -212,76 +300,21 @@ int assemble_impl(iga_ctx* ctx, const iga_geometry* geo, int p, const int n[3],
   hipStream_t st = ctx->stream;
   const int b = 2 * p + 1;
 
-  // geometry knots must be open on [0, 1]
-  for (int d = 0; d < 3; ++d) {
-    const int nk = geo->ncp[d] + geo->degree + 1;
-    const double* t = geo->knots[d];
-    for (int i = 0; i + 1 < nk; ++i) require(t[i] <= t[i + 1], IGA_EINVAL, "geometry knots must be non-decreasing");
-    require(t[0] == 0.0 && t[nk - 1] == 1.0, IGA_EINVAL, "geometry knots must span [0, 1]");
-  }
+  check_geometry(geo);  // geometry knots must be open on [0, 1]
 
-  std::vector<double> gx, gw;
-  gauss_legendre(nq, gx, gw);
-  Dir dir[3];
-  for (int d = 0; d < 3; ++d) {
-    Dir& D = dir[d];
-    D.n = n[d]; D.N = n[d] + 2; D.E = D.N - p; D.nt = D.E + pt;
-    D.ksol = uniform_open_knots(D.N, p);
-    D.kint = uniform_open_knots(D.nt, pt);
-    D.grev = greville(D.kint, pt);
-    for (int e = 0; e < D.E; ++e) {
-      const double a = double(e) / D.E, h = 1.0 / D.E;
-      for (int q = 0; q < nq; ++q) {
-        D.qpts.push_back(a + 0.5 * h * (gx[q] + 1.0));
-        D.qw.push_back(0.5 * h * gw[q]);
-      }
-    }
-    D.dksol = upload(ctx, D.ksol.data(), D.ksol.size());
-    D.dkint = upload(ctx, D.kint.data(), D.kint.size());
-    D.dgrev = upload(ctx, D.grev.data(), D.grev.size());
-    D.dqpts = upload(ctx, D.qpts.data(), D.qpts.size());
-    D.dqw = upload(ctx, D.qw.data(), D.qw.size());
-    const int Q = D.E * nq;
-    D.Bv.reset(ctx, (size_t)Q * D.N);
-    D.Bd.reset(ctx, (size_t)Q * D.N);
-    D.Bt.reset(ctx, (size_t)Q * D.nt);
-    k::bspline_tabulate(st, D.dksol.get(), (int)D.ksol.size(), p, D.dqpts.get(), Q, 0, D.Bv.get());
-    k::bspline_tabulate(st, D.dksol.get(), (int)D.ksol.size(), p, D.dqpts.get(), Q, 1, D.Bd.get());
-    k::bspline_tabulate(st, D.dkint.get(), (int)D.kint.size(), pt, D.dqpts.get(), Q, 0, D.Bt.get());
-    // collocation matrix of the interpolation space at its Greville points, and its inverse
-    DBuf Bc(ctx, (size_t)D.nt * D.nt), work(ctx, (size_t)2 * D.nt * D.nt);
-    IBuf sing(ctx, 1);
-    k::bspline_tabulate(st, D.dkint.get(), (int)D.kint.size(), pt, D.dgrev.get(), D.nt, 0, Bc.get());
-    D.Binv.reset(ctx, (size_t)D.nt * D.nt);
-    k::invert(st, D.nt, Bc.get(), D.Binv.get(), work.get(), sing.get());
-    int singular = 0;
-    IGA_HIP(hipMemcpyAsync(&singular, sing.get(), sizeof(int), hipMemcpyDeviceToHost, st));
-    IGA_HIP(hipStreamSynchronize(st));
-    require(!singular, IGA_EINVAL, "collocation matrix of the interpolation space is singular");
-  }
+  SpaceDir dir[3];
+  setup_spaces(ctx, p, n, pt, nq, dir);
 
   // 1. weights on the Greville grid
   const int nt[3] = {dir[0].nt, dir[1].nt, dir[2].nt};
   const long G = (long)nt[0] * nt[1] * nt[2];
   DBuf fields(ctx, (size_t)7 * G);
   {
-    DBuf gk[3], Bv[3], Bd[3];
-    const double* bv[3];
-    const double* bd[3];
-    for (int d = 0; d < 3; ++d) {
-      const int nk = geo->ncp[d] + geo->degree + 1;
-      gk[d] = upload(ctx, geo->knots[d], nk);
-      Bv[d].reset(ctx, (size_t)nt[d] * geo->ncp[d]);
-      Bd[d].reset(ctx, (size_t)nt[d] * geo->ncp[d]);
-      k::bspline_tabulate(st, gk[d].get(), nk, geo->degree, dir[d].dgrev.get(), nt[d], 0, Bv[d].get());
-      k::bspline_tabulate(st, gk[d].get(), nk, geo->degree, dir[d].dgrev.get(), nt[d], 1, Bd[d].get());
-      bv[d] = Bv[d].get();
-      bd[d] = Bd[d].get();
-    }
-    DBuf ctrl = upload(ctx, geo->ctrl, (size_t)3 * geo->ncp[0] * geo->ncp[1] * geo->ncp[2]);
+    GeometryTables gt;
+    geometry_tables(ctx, geo, dir, gt);
     IBuf bad(ctx, 1);
     IGA_HIP(hipMemsetAsync(bad.get(), 0, sizeof(int), st));
-    k::geometry_weights(st, nt, geo->ncp, bv, bd, ctrl.get(), fields.get(), bad.get());
+    k::geometry_weights(st, nt, geo->ncp, gt.bv, gt.bd, gt.ctrl.get(), fields.get(), bad.get());
     int nbad = 0;
     IGA_HIP(hipMemcpyAsync(&nbad, bad.get(), sizeof(int), hipMemcpyDeviceToHost, st));
     IGA_HIP(hipStreamSynchronize(st));

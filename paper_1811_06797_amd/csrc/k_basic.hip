@@ -370,6 +370,14 @@ __global__ void diag_kernel(int k, const double* H, long step, double* out, int 
   }
 }
 
+__global__ void scale_rows_kernel(int m, int k, const double* sc, double* A, long lda) {
+  const long total = (long)m * k;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const int i = e / k, j = e - (long)i * k;
+    A[(long)i * lda + j] *= sc[i];
+  }
+}
+
 // out[j] = sum_i A[i][j] B[i][j] (one thread per column, fixed order)
 __global__ void coldot_kernel(int m, int k, const double* A, long lda, const double* B, long ldb, double* out) {
   for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < k; j += gridDim.x * blockDim.x) {
@@ -440,6 +448,12 @@ void diag_get(hipStream_t s, int k, const double* H, double* out) {
 }
 void vec_invsqrt(hipStream_t s, int k, const double* v, double* out) {
   diag_kernel<<<(k + 255) / 256, 256, 0, s>>>(k, v, 1, out, 1);
+  IGA_HIP(hipGetLastError());
+}
+void scale_rows(hipStream_t s, int m, int k, const double* sc, double* A, long lda) {
+  const long total = (long)m * k;
+  if (total <= 0) return;
+  scale_rows_kernel<<<(unsigned)std::min<long>((total + 255) / 256, 4096), 256, 0, s>>>(m, k, sc, A, lda);
   IGA_HIP(hipGetLastError());
 }
 void coldots(hipStream_t s, int m, int k, const double* A, long lda, const double* B, long ldb, double* out) {

@@ -158,8 +158,20 @@ void diag_invsqrt(hipStream_t s, int k, const double* H, double* out);
 void diag_get(hipStream_t s, int k, const double* H, double* out);
 // out[j] = 1/sqrt(v[j]) (0 if v[j] <= 0)
 void vec_invsqrt(hipStream_t s, int k, const double* v, double* out);
+// A[i][j] *= sc[i] (m x k, row-major, leading dimension lda)
+void scale_rows(hipStream_t s, int m, int k, const double* sc, double* A, long lda);
 // out[j] = sum_i A[i][j] B[i][j], j < k (row-major, leading dimensions lda, ldb)
 void coldots(hipStream_t s, int m, int k, const double* A, long lda, const double* B, long ldb, double* out);
+
+// Reduced-cost gradient kernels (k_adjoint.hip). f: 9 fields at npts points, fstride apart
+// (e = y - yhat, u, lambda, d_0..2 lambda, d_0..2 y); P: 10 outputs, pstride apart:
+// P_w = e^2/2 + beta u^2/2 - lambda u, then P_kl = (d_l lambda)(d_k y) at 1 + 3k + l.
+void adjoint_pointwise(hipStream_t s, long npts, const double* f, long fstride, double beta, double* P,
+                       long pstride);
+// T[3a+b][g] = H_w(g) d omega/d J_ab + sum_kl H_kl(g) d q_kl/d J_ab on the grid np (tables as
+// for geometry_weights); H: [10][G] in the order of P.
+void geometry_adjoint(hipStream_t s, const int np[3], const int ncp[3], const double* const Bv[3],
+                      const double* const Bd[3], const double* ctrl, const double* H, double* T);
 
 // Symmetric Jacobi eigen-decomposition, one workgroup per matrix, nmat matrices of size k
 // (k <= 1024): H (in: symmetric, out: diagonal holds the eigenvalues), WT (out: row i is

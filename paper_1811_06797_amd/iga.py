@@ -27,10 +27,11 @@ _NAMES = {EINVAL: "IGA_EINVAL", ENOMEM: "IGA_ENOMEM", EHIP: "IGA_EHIP", EGEOM: "
 
 EXPORTED = [
     "iga_ctx_create", "iga_ctx_destroy", "iga_assemble_factors", "iga_ttop_create", "iga_ttop_info",
-    "iga_ttop_get_core", "iga_ttop_destroy", "iga_tt_create", "iga_tt_wrap", "iga_tt_destroy",
+    "iga_ttop_get_core", "iga_ttop_destroy", "iga_tt_create", "iga_tt_wrap", "iga_tt_from_full", "iga_tt_destroy",
     "iga_btt_create", "iga_btt_info", "iga_btt_get_core", "iga_btt_to_full", "iga_btt_destroy",
     "iga_kkt_create", "iga_kkt_destroy", "iga_kkt_apply", "iga_kkt_residual", "iga_amen_solve",
-    "iga_local_matvec", "iga_local_matvec_flops", "iga_profile_start", "iga_profile_stop", "iga_last_error",
+    "iga_local_matvec", "iga_local_matvec_flops", "iga_profile_start", "iga_profile_stop", "iga_objective",
+    "iga_grad_yhat", "iga_grad_geometry", "iga_last_error",
 ]
 
 
@@ -100,6 +101,7 @@ lib.iga_ttop_destroy.argtypes = [P]
 lib.iga_ttop_destroy.restype = None
 lib.iga_tt_create.argtypes = [P, I3, I4, PD * 3, C.POINTER(P)]
 lib.iga_tt_wrap.argtypes = [P, I3, I4, PD * 3, C.POINTER(P)]
+lib.iga_tt_from_full.argtypes = [P, I3, P, C.c_double, C.POINTER(P)]
 lib.iga_tt_destroy.argtypes = [P]
 lib.iga_tt_destroy.restype = None
 lib.iga_btt_create.argtypes = [P, I3, I4, C.c_int, PD * 3, C.POINTER(P)]
@@ -119,6 +121,10 @@ lib.iga_local_matvec.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                                  C.c_int, P, P, P, P, P, P, C.c_double, P, P, C.c_int]
 lib.iga_local_matvec_flops.argtypes = [C.c_int] * 8
 lib.iga_local_matvec_flops.restype = C.c_double
+lib.iga_objective.argtypes = [P, P, P, P, PD]
+lib.iga_grad_yhat.argtypes = [P, P, P, P, P]
+lib.iga_grad_geometry.argtypes = [P, C.POINTER(Geometry), C.c_int, I3, C.POINTER(AssemblyOpts), C.c_double, P, P,
+                                  PD]
 lib.iga_profile_start.argtypes = [P]
 lib.iga_profile_stop.argtypes = [P, C.POINTER(Profile)]
 
@@ -322,3 +328,43 @@ def profile_stop(ctx) -> dict:
     out = Profile()
     _check(lib.iga_profile_stop(ctx, C.byref(out)))
     return out.as_dict()
+
+
+def objective(ctx, kkt, yhat, f) -> float:
+    """J = 1/2 (y - yhat)^T M (y - yhat) + beta/2 u^T M u at the solution handle f."""
+    out = C.c_double()
+    _check(lib.iga_objective(ctx, kkt, yhat, f, C.byref(out)))
+    return out.value
+
+
+def grad_yhat(ctx, kkt, yhat, f, n):
+    """dJ/dyhat = -M (y - yhat) as a CUDA tensor of shape n (FP64)."""
+    import torch
+    out = torch.empty(tuple(n), dtype=torch.float64, device="cuda")
+    _check(lib.iga_grad_yhat(ctx, kkt, yhat, f, C.c_void_p(out.data_ptr())))
+    return out
+
+
+def grad_geometry(ctx, geo, degree: int, n, beta: float, yhat, f, p_interp: int = 0, nquad: int = 0):
+    """dJ/d(control points), numpy array shaped like geo.ctrl."""
+    knots = [_host(k) for k in geo.knots]
+    ctrl = _host(geo.ctrl)
+    g = Geometry()
+    g.degree = int(geo.degree)
+    for d in range(3):
+        g.ncp[d] = int(ctrl.shape[1 + d])
+        g.knots[d] = _dptr(knots[d])
+    g.ctrl = _dptr(ctrl)
+    o = AssemblyOpts(int(p_interp), int(nquad), 0.0, 0)
+    nn = I3(*[int(v) for v in (n if hasattr(n, "__len__") else (n, n, n))])
+    out = np.zeros(ctrl.shape, dtype=np.float64)
+    _check(lib.iga_grad_geometry(ctx, C.byref(g), int(degree), nn, C.byref(o), float(beta), yhat, f, _dptr(out)))
+    return out
+
+
+def tt_from_full(ctx, full, rel_tol: float = 0.0):
+    """TT (library handle) of a contiguous FP64 CUDA tensor of shape (n0, n1, n2)."""
+    assert full.is_cuda and full.dtype.is_floating_point and full.dim() == 3 and full.is_contiguous()
+    out = P()
+    _check(lib.iga_tt_from_full(ctx, I3(*full.shape), C.c_void_p(full.data_ptr()), float(rel_tol), C.byref(out)))
+    return out

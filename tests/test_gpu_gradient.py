@@ -1,0 +1,117 @@
+"""Gradients of the reduced cost (differentiation form): the library's dJ/dyhat and dJ/dC
+against the oracle. The oracle's reduced cost J(yhat, C) is its own direct KKT solve with the
+interpolated-weight matrices (the discretisation the library differentiates); central
+differences of it (h = 1e-6 on the control points) pin the geometry gradient, and its
+-M (y - yhat) and central differences in yhat pin the desired-state gradient."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import assembly, kkt as okkt, tt
+from tests.gpu_util import rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_J(geo, p, n, beta, yh_full):
+    M, K = assembly.assemble(geo, n, p, mode="interp")
+    y, u, lam = okkt.solve_direct(M, K, beta, yh_full.ravel())
+    return okkt.objective(M, y, u, yh_full.ravel(), beta), M, (y, u, lam)
+
+
+def _gpu(gpu_ctx, geo, p, n, beta, yc, tol=1e-11):
+    from paper_1811_06797_amd import iga
+    M, K, _ = iga.assemble_factors(gpu_ctx, geo, p, n, weight_tol=0.0)
+    kk = iga.kkt_create(gpu_ctx, M, K, beta)
+    Y = iga.tt_create(gpu_ctx, yc)
+    sol, st, rc = iga.amen_solve(gpu_ctx, kk, Y, tol, kick_rank=4, nswp=12)
+    assert rc == 0, st
+    try:
+        J = iga.objective(gpu_ctx, kk, Y, sol)
+        gy = iga.grad_yhat(gpu_ctx, kk, Y, sol, (n, n, n)).cpu().numpy()
+        gC = iga.grad_geometry(gpu_ctx, geo, p, n, beta, Y, sol)
+    finally:
+        for h, f in ((sol, iga.btt_destroy), (Y, iga.tt_destroy), (kk, iga.kkt_destroy), (M, iga.ttop_destroy),
+                     (K, iga.ttop_destroy)):
+            f(h)
+    return J, gy, gC
+
+
+def _with_ctrl(geo, ctrl):
+    return synth.Geometry(geo.degree, geo.knots, np.ascontiguousarray(ctrl), geo.name)
+
+
+@pytest.fixture(scope="module")
+def small_case():
+    geo = synth.twisted_annulus(seed=1)
+    p, n, beta = 2, 6, 1e-2
+    yc = synth.yhat_fourier(n, p, seed=2, modes=3)
+    return geo, p, n, beta, yc, tt.tt_full(yc)
+
+
+def test_objective_and_yhat_gradient_match_oracle(gpu_ctx, small_case):
+    geo, p, n, beta, yc, yh = small_case
+    J, gy, gC = _gpu(gpu_ctx, geo, p, n, beta, yc)
+    Jo, Mo, (y, u, lam) = _oracle_J(geo, p, n, beta, yh)
+    print("J", J, Jo, flush=True)
+    assert abs(J - Jo) <= 1e-9 * abs(Jo)
+    assert rel_err(gy.ravel(), -(Mo @ (y - yh.ravel()))) < 1e-8
+    # directional central difference of the oracle's reduced cost in yhat
+    rng = np.random.default_rng(7)
+    v = rng.standard_normal(yh.shape)
+    h = 1e-4
+    fd = (_oracle_J(geo, p, n, beta, yh + h * v)[0] - _oracle_J(geo, p, n, beta, yh - h * v)[0]) / (2 * h)
+    print("yhat directional", np.sum(gy * v), fd, flush=True)
+    assert abs(np.sum(gy * v) - fd) <= 1e-7 * max(abs(fd), 1e-3 * abs(Jo))
+
+
+def test_geometry_gradient_matches_central_differences(gpu_ctx, small_case):
+    geo, p, n, beta, yc, yh = small_case
+    J, gy, gC = _gpu(gpu_ctx, geo, p, n, beta, yc)
+    assert gC.shape == geo.ctrl.shape and np.all(np.isfinite(gC))
+    h = 1e-6
+    rng = np.random.default_rng(11)
+    dirs = [rng.standard_normal(geo.ctrl.shape) for _ in range(2)]
+    for idx in [(0, 0, 0, 0), (1, 3, 4, 5), (2, 7, 2, 6), (0, 4, 7, 3)]:
+        e = np.zeros(geo.ctrl.shape)
+        e[idx] = 1.0
+        dirs.append(e)
+    for v in dirs:
+        Jp = _oracle_J(_with_ctrl(geo, geo.ctrl + h * v), p, n, beta, yh)[0]
+        Jm = _oracle_J(_with_ctrl(geo, geo.ctrl - h * v), p, n, beta, yh)[0]
+        fd = (Jp - Jm) / (2 * h)
+        g = float(np.sum(gC * v))
+        print("geometry directional", g, fd, flush=True)
+        assert abs(g - fd) <= 1e-5 * max(abs(fd), 1e-4 * abs(J))
+
+
+def test_geometry_gradient_n16_identity_cube(gpu_ctx):
+    """c1 geometry (unit cube, trilinear control net), p = 2, n = 16: one random direction of
+    control-point motion against the oracle's central difference."""
+    geo, yc, c = synth.config("c1")
+    p, n, beta = c["degree"], c["n"], c["beta"]
+    J, gy, gC = _gpu(gpu_ctx, geo, p, n, beta, yc, tol=1e-10)
+    yh = tt.tt_full(yc)
+    rng = np.random.default_rng(5)
+    v = rng.standard_normal(geo.ctrl.shape)
+    h = 1e-6
+    Jp = _oracle_J(_with_ctrl(geo, geo.ctrl + h * v), p, n, beta, yh)[0]
+    Jm = _oracle_J(_with_ctrl(geo, geo.ctrl - h * v), p, n, beta, yh)[0]
+    fd = (Jp - Jm) / (2 * h)
+    g = float(np.sum(gC * v))
+    print("n16 directional", g, fd, "J", J, flush=True)
+    assert abs(g - fd) <= 1e-5 * max(abs(fd), 1e-4 * abs(J))
+
+
+def test_autograd_function_returns_library_gradients(gpu_ctx, small_case):
+    import torch
+    from paper_1811_06797_amd import autodiff, iga
+    geo, p, n, beta, yc, yh = small_case
+    yt = torch.tensor(yh, dtype=torch.float64, requires_grad=True)
+    ct = torch.tensor(geo.ctrl, dtype=torch.float64, requires_grad=True)
+    J = autodiff.reduced_cost(yt, ct, gpu_ctx, geo.knots, geo.degree, p, beta, 1e-11, kick_rank=4, nswp=12)
+    J.backward()
+    J2, gy, gC = _gpu(gpu_ctx, geo, p, n, beta, yc)
+    assert abs(J.item() - J2) <= 1e-9 * abs(J2)
+    assert rel_err(yt.grad.numpy().ravel(), gy.ravel()) < 1e-7
+    assert rel_err(ct.grad.numpy().ravel(), gC.ravel()) < 1e-7
