@@ -18,6 +18,8 @@ Printed JSON line:
   mixed_vs_fp64  the same solve in the mixed form (FP32 local contractions inside FP64
              iterative refinement) and in FP64, from one assembly: solve times,
              residuals and the state difference;
+  differentiation  times of the reduced cost, its desired-state gradient and its
+             control-point gradient at the FP64 solution;
   roofline   the dominant kernel of the local TT-matvec at the microbenchmark shape
              (r, R_M, R_K, n, p) = (32, 10, 60, 64, 3): the banded middle stage of
              the K operator, timed by the library with HIP events on its stream;
@@ -112,6 +114,25 @@ def mixed_compare(iga, ctx, torch, geo, c, Y, steps):
         d["local_matvec_gflops_fp64"] = (sum(x["local_matvec_flops"] for x in sts)
                                          / sum(x["t_local_matvec"] for x in sts) / 1e9)
         out[name] = d
+    # differentiation form on the FP64 solution of the same operators
+    sol, st, rc = iga.amen_solve(ctx, kk, Y, c["tol"])
+    grads = {}
+    for name, fn in (("objective", lambda: iga.objective(ctx, kk, Y, sol)),
+                     ("grad_yhat", lambda: iga.grad_yhat(ctx, kk, Y, sol, (n, n, n))),
+                     ("grad_geometry", lambda: iga.grad_geometry(ctx, geo, p, n, beta, Y, sol))):
+        fn()  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        val = fn()
+        torch.cuda.synchronize()
+        grads[name + "_s"] = time.perf_counter() - t0
+        if name == "objective":
+            grads["objective"] = val
+        if name == "grad_geometry":
+            import numpy as _np
+            grads["grad_geometry_norm"] = float(_np.linalg.norm(val))
+    iga.btt_destroy(sol)
+    out["differentiation"] = grads
     import numpy as np
     y64, y32 = fulls["fp64"][0], fulls["mixed"][0]
     out["mixed"]["state_rel_diff_vs_fp64"] = float(np.linalg.norm(y32 - y64) / np.linalg.norm(y64))
@@ -284,7 +305,8 @@ def main():
         "solve": {k: last[k] for k in ("half_sweeps", "ranks", "local_solves", "local_iterations", "local_matvecs",
                                        "local_matvec_flops", "t_local_matvec", "t_precond", "t_svd",
                                        "t_interfaces", "t_krylov_other", "t_residual", "op_ranks")},
-        "mixed_vs_fp64": mixed,
+        "mixed_vs_fp64": {k: v for k, v in mixed.items() if k != "differentiation"},
+        "differentiation": mixed["differentiation"],
         "microbench_local_matvec": {k: micro[k] for k in ("shape", "ms", "gflops", "flops", "fp32")},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
