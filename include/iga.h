@@ -47,7 +47,7 @@ extern "C" {
 #define IGA_EHIP (-3)    /* a HIP runtime call failed */
 #define IGA_EGEOM (-4)   /* det grad G <= 0 at an interpolation point: the map folds */
 #define IGA_ENOCONV (-5) /* block AMEn stopped at nswp sweeps above tolerance */
-#define IGA_ERANK (-6)   /* a rank cap was reached (weight_rmax or r_max) */
+#define IGA_ERANK (-6)   /* block AMEn stopped above tolerance with a solution rank at r_max */
 
 #define IGA_FP64 0
 #define IGA_FP32 1
@@ -207,7 +207,8 @@ int iga_kkt_residual(iga_ctx* ctx, const iga_kkt* kkt, const iga_tt* yhat, const
  * preconditioned GMRES, enriching with a residual direction and moving the
  * component index by a truncated SVD (eqs. svd1, svd2). Stops when every local
  * residual of a half-sweep is <= tol (relative) or after nswp half-sweeps
- * (IGA_ENOCONV; *sol is still returned). x0 (nullable) is the initial guess.
+ * (IGA_ENOCONV, or IGA_ERANK when a solution rank is at r_max; *sol is still returned).
+ * x0 (nullable) is the initial guess.
  * stats (nullable) receives the statistics above. */
 int iga_amen_solve(iga_ctx* ctx, const iga_kkt* kkt, const iga_tt* yhat, double tol,
                    const iga_amen_opts* opts, const iga_btt* x0, iga_btt** sol,
@@ -248,6 +249,30 @@ int iga_grad_yhat(iga_ctx* ctx, const iga_kkt* kkt, const iga_tt* yhat, const ig
 int iga_grad_geometry(iga_ctx* ctx, const iga_geometry* geo, int degree, const int n[3],
                       const iga_assembly_opts* opts, double beta, const iga_tt* yhat, const iga_btt* f,
                       double* grad);
+
+/* Batching form: the projected local TT-matvecs of many independent problems of uneven
+ * sizes (each as in iga_local_matvec, eq. KKT_red) in one call. Each of the three
+ * contraction stages of all problems is one persistent grouped launch per tile shape
+ * (workgroups walk a shared list of tiles of all products); autotune != 0 times the tile
+ * shapes on the first call for each size bucket and keeps the fastest for the context.
+ * Results do not depend on the tile shape chosen. precision: IGA_FP64 or IGA_FP32 (operands
+ * converted in one launch, contractions in FP32, results converted back). Operands as in
+ * iga_local_matvec (device, FP64, caller-owned); y of different problems must not overlap.
+ * Synchronises. */
+typedef struct {
+  int r0, n, r1, degree, RM0, RM1, RK0, RK1;
+  const double* PhiL_M;
+  const double* PhiR_M;
+  const double* PhiL_K;
+  const double* PhiR_K;
+  const double* Mcore;
+  const double* Kcore;
+  double beta;
+  const double* x;
+  double* y;
+} iga_local_problem;
+int iga_local_matvec_batched(iga_ctx* ctx, int nprob, const iga_local_problem* probs, int precision,
+                             int autotune);
 
 /* Algorithmic flops of one iga_local_matvec call with these sizes. */
 double iga_local_matvec_flops(int r0, int n, int r1, int degree, int RM0, int RM1, int RK0, int RK1);

@@ -1110,7 +1110,11 @@ int Amen::run(const iga_btt* x0, iga_btt** sol, iga_amen_stats* stats) {
     stats->t_residual = std::chrono::duration<double>(std::chrono::steady_clock::now() - t2).count();
   }
   *sol = out.release();
-  return converged ? IGA_OK : IGA_ENOCONV;
+  if (converged) return IGA_OK;
+  // not converged: IGA_ERANK when a solution rank sits at the cap (r_max plus the enrichment)
+  bool capped = false;
+  for (int d = 1; d < 3; ++d) capped = capped || r_[d] >= o_.r_max;
+  return capped ? IGA_ERANK : IGA_ENOCONV;
 }
 
 }  // namespace

@@ -8,6 +8,7 @@
 
 #include "common.hpp"
 #include "kernels.hpp"
+#include "localop.hpp"
 #include "ttops.hpp"
 
 namespace iga {
@@ -180,6 +181,7 @@ void iga_ctx_destroy(iga_ctx* ctx) {
   for (hipEvent_t e : ctx->prof_events) (void)hipEventDestroy(e);
   release_scratch(ctx);
   release_raw_cache(ctx);
+  release_batch_cache(ctx);
   delete ctx;
 }
 
@@ -528,6 +530,25 @@ int iga_local_matvec(iga_ctx* ctx, int r0, int n, int r1, int degree, int RM0, i
     use_device(ctx);
     local_matvec_impl(ctx, r0, n, r1, degree, RM0, RM1, RK0, RK1, PhiL_M, PhiR_M, PhiL_K, PhiR_K, Mcore,
                       Kcore, beta, x, y, precision);
+    return IGA_OK;
+  });
+}
+
+int iga_local_matvec_batched(iga_ctx* ctx, int nprob, const iga_local_problem* probs, int precision,
+                             int autotune) {
+  return guarded([&] {
+    require(ctx && (nprob == 0 || probs), IGA_EINVAL, "local_matvec_batched: NULL argument");
+    require(nprob >= 0 && nprob <= 4096, IGA_EINVAL, "local_matvec_batched: nprob out of range");
+    require(precision == IGA_FP64 || precision == IGA_FP32, IGA_EINVAL, "local_matvec_batched: bad precision");
+    use_device(ctx);
+    std::vector<BatchProblem> P(nprob);
+    for (int i = 0; i < nprob; ++i) {
+      const iga_local_problem& q = probs[i];
+      require(q.degree >= 1 && q.degree <= 7, IGA_EINVAL, "local_matvec_batched: degree out of range");
+      P[i] = BatchProblem{q.r0, q.n, q.r1, q.degree, q.RM0, q.RM1, q.RK0, q.RK1, q.PhiL_M, q.PhiR_M, q.PhiL_K,
+                          q.PhiR_K, q.Mcore, q.Kcore, q.beta, q.x, q.y};
+    }
+    if (nprob > 0) local_matvec_batched_impl(ctx, P, precision, autotune != 0);
     return IGA_OK;
   });
 }

@@ -293,6 +293,40 @@ __global__ void kkt_combine_kernel(long e, T k02, T m11, T m12, T k20, T m21, co
   }
 }
 
+// Grouped forms for the batched local operator: blockIdx.y selects the item.
+template <typename T>
+__global__ void fill_segments_kernel(const Segment* seg, T* base) {
+  const Segment sg = seg[blockIdx.y];
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < sg.len; i += (long)gridDim.x * blockDim.x)
+    base[sg.off + i] = T(0);
+}
+
+template <typename T>
+__global__ void combine_grouped_kernel(const CombineItem* items, const T* zbase) {
+  const CombineItem it = items[blockIdx.y];
+  const T* zM = zbase + it.z_off;
+  const T* zK = zM + 3 * it.e;
+  T* y = static_cast<T*>(it.y);
+  const T k02 = T(it.coef.k02), m11 = T(it.coef.m11), m12 = T(it.coef.m12), k20 = T(it.coef.k20),
+          m21 = T(it.coef.m21);
+  const long e = it.e;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < e; i += (long)gridDim.x * blockDim.x) {
+    const T a0 = zM[i], a1 = zM[e + i], a2 = zM[2 * e + i];
+    const T b0 = zK[i], b2 = zK[e + i];
+    y[i] = a0 + k02 * b2;
+    y[e + i] = m11 * a1 + m12 * a2;
+    y[2 * e + i] = k20 * b0 + m21 * a1;
+  }
+}
+
+__global__ void convert_segments_kernel(const ConvSegment* seg, int to_f32) {
+  const ConvSegment sg = seg[blockIdx.y];
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < sg.len; i += (long)gridDim.x * blockDim.x) {
+    if (to_f32) static_cast<float*>(sg.dst)[i] = (float)static_cast<const double*>(sg.src)[i];
+    else static_cast<double*>(sg.dst)[i] = (double)static_cast<const float*>(sg.src)[i];
+  }
+}
+
 __global__ void scale3_kernel(long e, double s0, double s1, double s2, double* y) {
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < 3 * e; i += (long)gridDim.x * blockDim.x) {
     const int c = i / e;
@@ -392,6 +426,42 @@ __global__ void coldot_kernel(int m, int k, const double* A, long lda, const dou
 void kkt_combine(hipStream_t s, long e, const KktCoef& c, const double* zM, const double* zK, double* y) {
   if (e <= 0) return;
   kkt_combine_kernel<double><<<grid_for(e), 256, 0, s>>>(e, c.k02, c.m11, c.m12, c.k20, c.m21, zM, zK, y);
+  IGA_HIP(hipGetLastError());
+}
+
+void fill_segments(hipStream_t s, int nseg, long maxlen, const Segment* dev_seg, double* base) {
+  if (nseg <= 0 || maxlen <= 0) return;
+  require(nseg <= 65535, IGA_EINVAL, "fill_segments: too many segments");
+  dim3 g((unsigned)std::min<long>((maxlen + 255) / 256, 1024), nseg);
+  fill_segments_kernel<double><<<g, 256, 0, s>>>(dev_seg, base);
+  IGA_HIP(hipGetLastError());
+}
+void fill_segments_f32(hipStream_t s, int nseg, long maxlen, const Segment* dev_seg, float* base) {
+  if (nseg <= 0 || maxlen <= 0) return;
+  require(nseg <= 65535, IGA_EINVAL, "fill_segments: too many segments");
+  dim3 g((unsigned)std::min<long>((maxlen + 255) / 256, 1024), nseg);
+  fill_segments_kernel<float><<<g, 256, 0, s>>>(dev_seg, base);
+  IGA_HIP(hipGetLastError());
+}
+void combine_grouped(hipStream_t s, int nitem, long maxe, const CombineItem* dev_items, const double* zbase) {
+  if (nitem <= 0 || maxe <= 0) return;
+  require(nitem <= 65535, IGA_EINVAL, "combine_grouped: too many items");
+  dim3 g((unsigned)std::min<long>((maxe + 255) / 256, 1024), nitem);
+  combine_grouped_kernel<double><<<g, 256, 0, s>>>(dev_items, zbase);
+  IGA_HIP(hipGetLastError());
+}
+void combine_grouped_f32(hipStream_t s, int nitem, long maxe, const CombineItem* dev_items, const float* zbase) {
+  if (nitem <= 0 || maxe <= 0) return;
+  require(nitem <= 65535, IGA_EINVAL, "combine_grouped: too many items");
+  dim3 g((unsigned)std::min<long>((maxe + 255) / 256, 1024), nitem);
+  combine_grouped_kernel<float><<<g, 256, 0, s>>>(dev_items, zbase);
+  IGA_HIP(hipGetLastError());
+}
+void convert_segments(hipStream_t s, int nseg, long maxlen, const ConvSegment* dev_seg, bool to_f32) {
+  if (nseg <= 0 || maxlen <= 0) return;
+  require(nseg <= 65535, IGA_EINVAL, "convert_segments: too many segments");
+  dim3 g((unsigned)std::min<long>((maxlen + 255) / 256, 1024), nseg);
+  convert_segments_kernel<<<g, 256, 0, s>>>(dev_seg, to_f32 ? 1 : 0);
   IGA_HIP(hipGetLastError());
 }
 

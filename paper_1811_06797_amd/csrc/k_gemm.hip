@@ -17,6 +17,7 @@
 // Operand lane layout of v_mfma_f64_4x4x4 (lane = 16x + 4b + y, b = block):
 //   A_b[i][k] in lane 16k + 4b + i;  B_b[k][j] in lane 16k + 4b + j;  C_b[i][j] in lane 16i + 4b + j.
 #include <algorithm>
+#include <cstring>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -73,23 +74,24 @@ __device__ __forceinline__ long off2(int idx, int inner, long s_outer, long s_in
 // half-wave reads for one MFMA operand fall into disjoint halves of the 64 banks.
 constexpr int lds_pad(int w) { return ((16 - w % 32) + 32) % 32; }
 
+// LDS tiles of one workgroup.
+template <int BM, int BN, int BK, int NBUF>
+struct TileLds {
+  double As[NBUF][BK][BM + lds_pad(BM)];
+  double Bs[NBUF][BK][BN + lds_pad(BN)];
+};
+
+// One BM x BN output tile (column tile bx, row tile by, batch and split index bz) of the
+// product g.
 template <int WM, int WN, int WAVES_M, int WAVES_N, int BK, int NBUF, int PF>
-__global__ __launch_bounds__(NTHR) void gemm2_kernel(G2Args g) {
+__device__ __forceinline__ void gemm2_tile(const G2Args& g, int bx, int by, int bz,
+                                           TileLds<4 * WM * WAVES_M, 16 * WN * WAVES_N, BK, NBUF>& L) {
   constexpr int BM = 4 * WM * WAVES_M, BN = 16 * WN * WAVES_N;
   constexpr int LA = BM * BK / NTHR, LB = BN * BK / NTHR;
   static_assert(WAVES_M * WAVES_N == 4, "four waves");
   static_assert(LA >= 1 && LB >= 1, "tile too small");
-  __shared__ double As[NBUF][BK][BM + lds_pad(BM)];
-  __shared__ double Bs[NBUF][BK][BN + lds_pad(BN)];
-  // Workgroups are dealt to the 8 XCDs round-robin by linear id; renumber them so that each
-  // XCD (own L2) works through one contiguous range of (batch, m-tile, n-tile), where
-  // neighbouring tiles share operand rows and columns.
-  const int gx = gridDim.x, gy = gridDim.y;
-  const int total = gx * gy * gridDim.z;
-  const int lin = (blockIdx.z * gy + blockIdx.y) * gx + blockIdx.x;
-  const int xcd = lin % 8, q = lin / 8, base = total / 8, rem = total % 8;
-  const int tile = (xcd < rem ? xcd * (base + 1) : rem * (base + 1) + (xcd - rem) * base) + q;
-  const int bx = tile % gx, by = (tile / gx) % gy, bz = tile / (gx * gy);
+  auto& As = L.As;
+  auto& Bs = L.Bs;
   const int split = bz / g.nbatch, bb = bz - split * g.nbatch;
   const int b1 = bb / g.nb2, b2 = bb - b1 * g.nb2;
   const double* A = g.A + b1 * g.sAb1 + b2 * g.sAb2;
@@ -265,6 +267,42 @@ __global__ __launch_bounds__(NTHR) void gemm2_kernel(G2Args g) {
   }
 }
 
+template <int WM, int WN, int WAVES_M, int WAVES_N, int BK, int NBUF, int PF>
+__global__ __launch_bounds__(NTHR) void gemm2_kernel(G2Args g) {
+  __shared__ TileLds<4 * WM * WAVES_M, 16 * WN * WAVES_N, BK, NBUF> L;
+  // Workgroups are dealt to the 8 XCDs round-robin by linear id; renumber them so that each
+  // XCD (own L2) works through one contiguous range of (batch, m-tile, n-tile), where
+  // neighbouring tiles share operand rows and columns.
+  const int gx = gridDim.x, gy = gridDim.y;
+  const int total = gx * gy * gridDim.z;
+  const int lin = (blockIdx.z * gy + blockIdx.y) * gx + blockIdx.x;
+  const int xcd = lin % 8, q = lin / 8, base = total / 8, rem = total % 8;
+  const int tile = (xcd < rem ? xcd * (base + 1) : rem * (base + 1) + (xcd - rem) * base) + q;
+  gemm2_tile<WM, WN, WAVES_M, WAVES_N, BK, NBUF, PF>(g, tile % gx, (tile / gx) % gy, tile / (gx * gy), L);
+}
+
+// Many independent products in one persistent launch: workgroup w takes the tiles
+// w, w + gridDim.x, ... of the concatenated tile lists (product i owns the tiles
+// [prefix[i], prefix[i + 1])), so every workgroup ends after at most ceil(total / grid) tiles.
+template <int WM, int WN, int WAVES_M, int WAVES_N, int BK, int NBUF, int PF>
+__global__ __launch_bounds__(NTHR) void gemm2_grouped_kernel(const G2Args* gs, const int* prefix, int ngemm,
+                                                             int total) {
+  constexpr int BM = 4 * WM * WAVES_M, BN = 16 * WN * WAVES_N;
+  __shared__ TileLds<BM, BN, BK, NBUF> L;
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    int lo = 0, hi = ngemm;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) / 2;
+      if (prefix[mid] <= t) lo = mid; else hi = mid;
+    }
+    const G2Args g = gs[lo];
+    const int local = t - prefix[lo];
+    const int gx = (g.N + BN - 1) / BN, gy = (g.M + BM - 1) / BM;
+    __syncthreads();  // the previous tile is done with the LDS buffers
+    gemm2_tile<WM, WN, WAVES_M, WAVES_N, BK, NBUF, PF>(g, local % gx, (local / gx) % gy, local / (gx * gy), L);
+  }
+}
+
 // C = alpha * sum_s work[s] + beta * C, splits summed in order.
 __global__ __launch_bounds__(256) void splitk_reduce(G2Args g) {
   const long MN = (long)g.M * g.N;
@@ -299,8 +337,8 @@ static long span(int ext, int inner, long s1, long s2) {
   return (long)((ext - 1) / inner) * s1 + (long)(std::min(ext, inner) - 1) * s2;
 }
 
-void gemm2(hipStream_t s, const Gemm2& d, double* work, size_t work_len) {
-  if (d.M <= 0 || d.N <= 0 || d.nb1 <= 0 || d.nb2 <= 0) return;
+// Validates d and fills the kernel's argument block (no split).
+static G2Args make_args(const Gemm2& d) {
   require(d.M2 >= 1 && d.N2 >= 1 && d.K2 >= 1, IGA_EINVAL, "gemm2: inner extents must be >= 1");
   require(d.sAm1 >= 0 && d.sAm2 >= 0 && d.sAk1 >= 0 && d.sAk2 >= 0 && d.sBk1 >= 0 && d.sBk2 >= 0 &&
               d.sBn1 >= 0 && d.sBn2 >= 0,
@@ -311,18 +349,77 @@ void gemm2(hipStream_t s, const Gemm2& d, double* work, size_t work_len) {
   require(span(d.M, d.M2, d.sAm1, d.sAm2) + kA < (1L << 31) && span(d.N, d.N2, d.sBn1, d.sBn2) + kB < (1L << 31),
           IGA_EINVAL, "gemm2: operand too large for 32-bit offsets");
   const long nb = (long)d.nb1 * d.nb2;
-  G2Args a{d.M, d.N, std::max(d.K, 0), d.M2, d.N2, d.K2, d.A, d.sAm1, d.sAm2, d.sAk1, d.sAk2, d.B, d.sBk1,
-           d.sBk2, d.sBn1, d.sBn2, d.C, d.sCm1, d.sCm2, d.sCn1, d.sCn2, d.nb2, (int)nb, d.sAb1, d.sAb2, d.sBb1,
-           d.sBb2, d.sCb1, d.sCb2, d.alpha, d.beta, 1, std::max(d.K, 0), nullptr};
-  // tile shape by output shape
-  int BM, BN, variant;
-  if (d.M <= 16) { BM = 16; BN = 256; variant = 2; }
-  else if (d.M <= 32) { BM = 32; BN = 128; variant = 1; }
-  else if (d.N <= 32) { BM = 128; BN = 32; variant = 3; }
-  else if (d.M <= 64 && (long)((d.N + 32 * IGA_WIDE_WN - 1) / (32 * IGA_WIDE_WN)) * nb >= 512) {
-    BM = 64; BN = 32 * IGA_WIDE_WN; variant = 4;
+  require(nb <= 65535, IGA_EINVAL, "gemm2: batch too large");
+  return G2Args{d.M, d.N, std::max(d.K, 0), d.M2, d.N2, d.K2, d.A, d.sAm1, d.sAm2, d.sAk1, d.sAk2, d.B, d.sBk1,
+                d.sBk2, d.sBn1, d.sBn2, d.C, d.sCm1, d.sCm2, d.sCn1, d.sCn2, d.nb2, (int)nb, d.sAb1, d.sAb2,
+                d.sBb1, d.sBb2, d.sCb1, d.sCb2, d.alpha, d.beta, 1, std::max(d.K, 0), nullptr};
+}
+
+// Output tile of each variant: 0: 64 x 64, 1: 32 x 128, 2: 16 x 256, 3: 128 x 32, 4: 64 x (32 WIDE_WN).
+static void variant_tile(int v, int& BM, int& BN) {
+  switch (v) {
+    case 1: BM = 32; BN = 128; break;
+    case 2: BM = 16; BN = 256; break;
+    case 3: BM = 128; BN = 32; break;
+    case 4: BM = 64; BN = 32 * IGA_WIDE_WN; break;
+    default: BM = 64; BN = 64; break;
   }
-  else { BM = 64; BN = 64; variant = 0; }
+}
+
+int gemm2_variants() { return 5; }
+
+int gemm2_pick(const Gemm2& d) {
+  const long nb = (long)d.nb1 * d.nb2;
+  if (d.M <= 16) return 2;
+  if (d.M <= 32) return 1;
+  if (d.N <= 32) return 3;
+  if (d.M <= 64 && (long)((d.N + 32 * IGA_WIDE_WN - 1) / (32 * IGA_WIDE_WN)) * nb >= 512) return 4;
+  return 0;
+}
+
+size_t gemm2_desc_bytes() { return sizeof(G2Args); }
+
+long gemm2_prepare(const Gemm2& d, int variant, void* host_desc) {
+  G2Args a = make_args(d);
+  std::memcpy(host_desc, &a, sizeof(G2Args));
+  if (d.M <= 0 || d.N <= 0 || d.nb1 <= 0 || d.nb2 <= 0) return 0;
+  int BM, BN;
+  variant_tile(variant, BM, BN);
+  return (long)((d.M + BM - 1) / BM) * ((d.N + BN - 1) / BN) * a.nbatch;
+}
+
+template <int WM, int WN, int WAVES_M, int WAVES_N, int BK, int NBUF, int PF>
+static void launch_grouped(hipStream_t s, const void* desc, const int* prefix, int ngemm, long total) {
+  // persistent: a few workgroups per CU, each walking its share of the tiles
+  const unsigned grid = (unsigned)std::min<long>(total, 1024);
+  gemm2_grouped_kernel<WM, WN, WAVES_M, WAVES_N, BK, NBUF, PF>
+      <<<grid, NTHR, 0, s>>>(static_cast<const G2Args*>(desc), prefix, ngemm, (int)total);
+}
+
+void gemm2_grouped(hipStream_t s, int variant, const void* dev_desc, const int* dev_prefix, int ngemm, long total) {
+  if (ngemm <= 0 || total <= 0) return;
+  require(total < (1L << 31), IGA_EINVAL, "gemm2_grouped: too many tiles");
+  switch (variant) {
+    case 2: launch_grouped<4, 4, 1, 4, 16, 2, IGA_PREFETCH>(s, dev_desc, dev_prefix, ngemm, total); break;
+    case 1: launch_grouped<8, 2, 1, 4, 16, 2, IGA_PREFETCH>(s, dev_desc, dev_prefix, ngemm, total); break;
+    case 3: launch_grouped<8, 2, 4, 1, 16, 2, IGA_PREFETCH>(s, dev_desc, dev_prefix, ngemm, total); break;
+    case 4:
+      launch_grouped<8, IGA_WIDE_WN, 2, 2, IGA_WIDE_BK, IGA_WIDE_NBUF, IGA_WIDE_PREFETCH>(s, dev_desc, dev_prefix,
+                                                                                         ngemm, total);
+      break;
+    default: launch_grouped<8, 2, 2, 2, 16, 2, IGA_PREFETCH>(s, dev_desc, dev_prefix, ngemm, total); break;
+  }
+  IGA_HIP(hipGetLastError());
+}
+
+void gemm2(hipStream_t s, const Gemm2& d, double* work, size_t work_len) {
+  if (d.M <= 0 || d.N <= 0 || d.nb1 <= 0 || d.nb2 <= 0) return;
+  G2Args a = make_args(d);
+  const long nb = a.nbatch;
+  // tile shape by output shape
+  const int variant = gemm2_pick(d);
+  int BM, BN;
+  variant_tile(variant, BM, BN);
   const long tiles = (long)((d.M + BM - 1) / BM) * ((d.N + BN - 1) / BN) * nb;
   // split K when the tiles cannot fill the chip and the contraction is long
   constexpr int KALIGN = 32;  // split-K chunks are whole K tiles of every variant

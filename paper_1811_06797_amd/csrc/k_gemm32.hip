@@ -10,6 +10,7 @@
 // Four waves form the workgroup tile; K is staged through LDS 16 deep, double-buffered,
 // with the next tile's global loads in flight during the current tile's products.
 #include <algorithm>
+#include <cstring>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -48,21 +49,22 @@ __device__ __forceinline__ long off2f(int idx, int inner, long s_outer, long s_i
 // touches start 16 banks apart.
 constexpr int lds_padf(int w) { return ((16 - w % 64) + 64) % 64; }
 
+template <int BM, int BN>
+struct TileLdsF {
+  float As[2][BKF][BM + lds_padf(BM)];
+  float Bs[2][BKF][BN + lds_padf(BN)];
+};
+
+// One BM x BN output tile (column tile bx, row tile by, batch and split index bz).
 template <int WM, int WN, int WAVES_M, int WAVES_N>
-__global__ __launch_bounds__(NT) void gemm2f_kernel(G2FArgs g) {
+__device__ __forceinline__ void gemm2f_tile(const G2FArgs& g, int bx, int by, int bz,
+                                            TileLdsF<16 * WM * WAVES_M, 16 * WN * WAVES_N>& L) {
   constexpr int BM = 16 * WM * WAVES_M, BN = 16 * WN * WAVES_N;
   constexpr int LA = BM * BKF / NT, LB = BN * BKF / NT;
   static_assert(WAVES_M * WAVES_N == 4, "four waves");
   static_assert(LA >= 1 && LB >= 1, "tile too small");
-  __shared__ float As[2][BKF][BM + lds_padf(BM)];
-  __shared__ float Bs[2][BKF][BN + lds_padf(BN)];
-  // XCD-contiguous renumbering of the workgroups (as in gemm2)
-  const int gx = gridDim.x, gy = gridDim.y;
-  const int total = gx * gy * gridDim.z;
-  const int lin = (blockIdx.z * gy + blockIdx.y) * gx + blockIdx.x;
-  const int xcd = lin % 8, q8 = lin / 8, base = total / 8, rem = total % 8;
-  const int tile = (xcd < rem ? xcd * (base + 1) : rem * (base + 1) + (xcd - rem) * base) + q8;
-  const int bx = tile % gx, by = (tile / gx) % gy, bz = tile / (gx * gy);
+  auto& As = L.As;
+  auto& Bs = L.Bs;
   const int split = bz / g.nbatch, bb = bz - split * g.nbatch;
   const int b1 = bb / g.nb2, b2 = bb - b1 * g.nb2;
   const float* A = g.A + b1 * g.sAb1 + b2 * g.sAb2;
@@ -200,6 +202,38 @@ __global__ __launch_bounds__(NT) void gemm2f_kernel(G2FArgs g) {
     }
 }
 
+template <int WM, int WN, int WAVES_M, int WAVES_N>
+__global__ __launch_bounds__(NT) void gemm2f_kernel(G2FArgs g) {
+  __shared__ TileLdsF<16 * WM * WAVES_M, 16 * WN * WAVES_N> L;
+  // XCD-contiguous renumbering of the workgroups (as in gemm2)
+  const int gx = gridDim.x, gy = gridDim.y;
+  const int total = gx * gy * gridDim.z;
+  const int lin = (blockIdx.z * gy + blockIdx.y) * gx + blockIdx.x;
+  const int xcd = lin % 8, q8 = lin / 8, base = total / 8, rem = total % 8;
+  const int tile = (xcd < rem ? xcd * (base + 1) : rem * (base + 1) + (xcd - rem) * base) + q8;
+  gemm2f_tile<WM, WN, WAVES_M, WAVES_N>(g, tile % gx, (tile / gx) % gy, tile / (gx * gy), L);
+}
+
+// Persistent grouped form (see gemm2_grouped_kernel).
+template <int WM, int WN, int WAVES_M, int WAVES_N>
+__global__ __launch_bounds__(NT) void gemm2f_grouped_kernel(const G2FArgs* gs, const int* prefix, int ngemm,
+                                                            int total) {
+  constexpr int BM = 16 * WM * WAVES_M, BN = 16 * WN * WAVES_N;
+  __shared__ TileLdsF<BM, BN> L;
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    int lo = 0, hi = ngemm;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) / 2;
+      if (prefix[mid] <= t) lo = mid; else hi = mid;
+    }
+    const G2FArgs g = gs[lo];
+    const int local = t - prefix[lo];
+    const int gx = (g.N + BN - 1) / BN, gy = (g.M + BM - 1) / BM;
+    __syncthreads();
+    gemm2f_tile<WM, WN, WAVES_M, WAVES_N>(g, local % gx, (local / gx) % gy, local / (gx * gy), L);
+  }
+}
+
 __global__ __launch_bounds__(256) void splitk_reduce_f(G2FArgs g) {
   const long MN = (long)g.M * g.N;
   const long total = MN * g.nbatch;
@@ -232,8 +266,7 @@ long spanf(int ext, int inner, long s1, long s2) {
 
 }  // namespace
 
-void gemm2_f32(hipStream_t s, const Gemm2F& d, float* work, size_t work_len) {
-  if (d.M <= 0 || d.N <= 0 || d.nb1 <= 0 || d.nb2 <= 0) return;
+static G2FArgs make_args_f(const Gemm2F& d) {
   require(d.M2 >= 1 && d.N2 >= 1 && d.K2 >= 1, IGA_EINVAL, "gemm2_f32: inner extents must be >= 1");
   require(d.sAm1 >= 0 && d.sAm2 >= 0 && d.sAk1 >= 0 && d.sAk2 >= 0 && d.sBk1 >= 0 && d.sBk2 >= 0 &&
               d.sBn1 >= 0 && d.sBn2 >= 0,
@@ -243,15 +276,69 @@ void gemm2_f32(hipStream_t s, const Gemm2F& d, float* work, size_t work_len) {
   require(spanf(d.M, d.M2, d.sAm1, d.sAm2) + kA < (1L << 31) && spanf(d.N, d.N2, d.sBn1, d.sBn2) + kB < (1L << 31),
           IGA_EINVAL, "gemm2_f32: operand too large for 32-bit offsets");
   const long nb = (long)d.nb1 * d.nb2;
-  G2FArgs a{d.M, d.N, std::max(d.K, 0), d.M2, d.N2, d.K2, d.A, d.sAm1, d.sAm2, d.sAk1, d.sAk2, d.B, d.sBk1,
-            d.sBk2, d.sBn1, d.sBn2, d.C, d.sCm1, d.sCm2, d.sCn1, d.sCn2, d.nb2, (int)nb, d.sAb1, d.sAb2, d.sBb1,
-            d.sBb2, d.sCb1, d.sCb2, d.alpha, d.beta, 1, std::max(d.K, 0), nullptr};
-  int BM, BN, variant;
-  if (d.M <= 16) { BM = 16; BN = 256; variant = 2; }
-  else if (d.M <= 32) { BM = 32; BN = 128; variant = 1; }
-  else if (d.N <= 32) { BM = 128; BN = 32; variant = 3; }
-  else if (d.M <= 64 && (long)((d.N + 127) / 128) * nb >= 512) { BM = 64; BN = 128; variant = 4; }
-  else { BM = 64; BN = 64; variant = 0; }
+  require(nb <= 65535, IGA_EINVAL, "gemm2_f32: batch too large");
+  return G2FArgs{d.M, d.N, std::max(d.K, 0), d.M2, d.N2, d.K2, d.A, d.sAm1, d.sAm2, d.sAk1, d.sAk2, d.B, d.sBk1,
+                 d.sBk2, d.sBn1, d.sBn2, d.C, d.sCm1, d.sCm2, d.sCn1, d.sCn2, d.nb2, (int)nb, d.sAb1, d.sAb2,
+                 d.sBb1, d.sBb2, d.sCb1, d.sCb2, d.alpha, d.beta, 1, std::max(d.K, 0), nullptr};
+}
+
+static void variant_tile_f(int v, int& BM, int& BN) {
+  switch (v) {
+    case 1: BM = 32; BN = 128; break;
+    case 2: BM = 16; BN = 256; break;
+    case 3: BM = 128; BN = 32; break;
+    case 4: BM = 64; BN = 128; break;
+    default: BM = 64; BN = 64; break;
+  }
+}
+
+int gemm2f_pick(const Gemm2F& d) {
+  const long nb = (long)d.nb1 * d.nb2;
+  if (d.M <= 16) return 2;
+  if (d.M <= 32) return 1;
+  if (d.N <= 32) return 3;
+  if (d.M <= 64 && (long)((d.N + 127) / 128) * nb >= 512) return 4;
+  return 0;
+}
+
+size_t gemm2f_desc_bytes() { return sizeof(G2FArgs); }
+
+long gemm2f_prepare(const Gemm2F& d, int variant, void* host_desc) {
+  G2FArgs a = make_args_f(d);
+  std::memcpy(host_desc, &a, sizeof(G2FArgs));
+  if (d.M <= 0 || d.N <= 0 || d.nb1 <= 0 || d.nb2 <= 0) return 0;
+  int BM, BN;
+  variant_tile_f(variant, BM, BN);
+  return (long)((d.M + BM - 1) / BM) * ((d.N + BN - 1) / BN) * a.nbatch;
+}
+
+template <int WM, int WN, int WAVES_M, int WAVES_N>
+static void launch_grouped_f(hipStream_t s, const void* desc, const int* prefix, int ngemm, long total) {
+  const unsigned grid = (unsigned)std::min<long>(total, 1024);
+  gemm2f_grouped_kernel<WM, WN, WAVES_M, WAVES_N>
+      <<<grid, NT, 0, s>>>(static_cast<const G2FArgs*>(desc), prefix, ngemm, (int)total);
+}
+
+void gemm2f_grouped(hipStream_t s, int variant, const void* dev_desc, const int* dev_prefix, int ngemm, long total) {
+  if (ngemm <= 0 || total <= 0) return;
+  require(total < (1L << 31), IGA_EINVAL, "gemm2f_grouped: too many tiles");
+  switch (variant) {
+    case 2: launch_grouped_f<1, 4, 1, 4>(s, dev_desc, dev_prefix, ngemm, total); break;
+    case 1: launch_grouped_f<2, 2, 1, 4>(s, dev_desc, dev_prefix, ngemm, total); break;
+    case 3: launch_grouped_f<2, 2, 4, 1>(s, dev_desc, dev_prefix, ngemm, total); break;
+    case 4: launch_grouped_f<2, 4, 2, 2>(s, dev_desc, dev_prefix, ngemm, total); break;
+    default: launch_grouped_f<2, 2, 2, 2>(s, dev_desc, dev_prefix, ngemm, total); break;
+  }
+  IGA_HIP(hipGetLastError());
+}
+
+void gemm2_f32(hipStream_t s, const Gemm2F& d, float* work, size_t work_len) {
+  if (d.M <= 0 || d.N <= 0 || d.nb1 <= 0 || d.nb2 <= 0) return;
+  G2FArgs a = make_args_f(d);
+  const long nb = a.nbatch;
+  const int variant = gemm2f_pick(d);
+  int BM, BN;
+  variant_tile_f(variant, BM, BN);
   const long tiles = (long)((d.M + BM - 1) / BM) * ((d.N + BN - 1) / BN) * nb;
   if (work && tiles < 256 && d.K >= 4 * 32) {
     int ks = (int)std::min<long>((512 + tiles - 1) / tiles, d.K / 64);

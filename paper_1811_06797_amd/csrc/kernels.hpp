@@ -42,6 +42,17 @@ void gemm2(hipStream_t s, const Gemm2& g);
 // Same, with a workspace of work_len doubles that lets short-output, long-K products be split
 // along K (partials summed in a fixed order, so results are deterministic).
 void gemm2(hipStream_t s, const Gemm2& g, double* work, size_t work_len);
+// Grouped form: many independent products with one tile variant in one persistent launch.
+// gemm2_prepare validates a product, writes its argument block (gemm2_desc_bytes() bytes)
+// to host_desc and returns its tile count for the variant; gemm2_grouped runs ngemm blocks
+// copied to device memory, with dev_prefix[i] = sum of the tile counts before product i
+// (ngemm + 1 entries, the last = total). Every variant accumulates K in the same order, so
+// the result does not depend on the variant.
+int gemm2_variants();
+int gemm2_pick(const Gemm2& g);  // the variant the single-product form uses
+size_t gemm2_desc_bytes();
+long gemm2_prepare(const Gemm2& g, int variant, void* host_desc);
+void gemm2_grouped(hipStream_t s, int variant, const void* dev_desc, const int* dev_prefix, int ngemm, long total);
 
 // The same product in FP32 on the matrix cores (FP32 inputs, FP32 accumulation), for the
 // mixed-precision form (k_gemm32.hip); identical index maps.
@@ -59,6 +70,11 @@ struct Gemm2F {
   float alpha = 1.0f, beta = 0.0f;
 };
 void gemm2_f32(hipStream_t s, const Gemm2F& g, float* work, size_t work_len);
+// grouped FP32 form, as gemm2_prepare / gemm2_grouped
+int gemm2f_pick(const Gemm2F& g);
+size_t gemm2f_desc_bytes();
+long gemm2f_prepare(const Gemm2F& g, int variant, void* host_desc);
+void gemm2f_grouped(hipStream_t s, int variant, const void* dev_desc, const int* dev_prefix, int ngemm, long total);
 
 // Row-major convenience: C (MxN, ldc) = alpha op(A) op(B) + beta C, op = transpose if t*.
 void gemm_rm(hipStream_t s, int M, int N, int K, const double* A, long lda, bool tA,
@@ -139,6 +155,28 @@ struct KktCoef {
 };
 void kkt_combine(hipStream_t s, long e, const KktCoef& c, const double* zM, const double* zK, double* y);
 void kkt_combine_f32(hipStream_t s, long e, const KktCoef& c, const float* zM, const float* zK, float* y);
+// Grouped helpers of the batched local operator (one launch for all items; blockIdx.y = item).
+struct Segment {
+  long off, len;  // base[off .. off + len) = 0
+};
+void fill_segments(hipStream_t s, int nseg, long maxlen, const Segment* dev_seg, double* base);
+void fill_segments_f32(hipStream_t s, int nseg, long maxlen, const Segment* dev_seg, float* base);
+struct CombineItem {
+  long z_off;  // zM at zbase + z_off ([3][e]), zK right after it ([2][e])
+  long e;
+  void* y;     // [3][e] output
+  KktCoef coef;
+};
+void combine_grouped(hipStream_t s, int nitem, long maxe, const CombineItem* dev_items, const double* zbase);
+void combine_grouped_f32(hipStream_t s, int nitem, long maxe, const CombineItem* dev_items, const float* zbase);
+struct ConvSegment {
+  const void* src;
+  void* dst;
+  long len;
+};
+// dst = (float) src (to_f32) or (double) src for every segment
+void convert_segments(hipStream_t s, int nseg, long maxlen, const ConvSegment* dev_seg, bool to_f32);
+
 // y[l][.] *= scale[l] for the three components of a [3][e] vector
 void scale3(hipStream_t s, long e, double s0, double s1, double s2, double* y);
 // Fast-diagonalisation solve of the per-mode 3x3 KKT blocks [[1,0,k],[0,c,-1],[k,-1,0]],

@@ -2,6 +2,10 @@
 #include "localop.hpp"
 
 #include <algorithm>
+#include <tuple>
+#include <map>
+#include <cstring>
+#include <array>
 #include <memory>
 #include <unordered_map>
 #include <vector>
@@ -230,6 +234,327 @@ void local_matvec_impl(iga_ctx* ctx, int r0, int n, int r1, int p, int RM0, int 
   L.fPhiL_K = C.fPhi[2].get(); L.fPhiR_K = C.fPhi[3].get();
   local_matvec_f32(ctx, L, C.fx.get(), C.fy.get(), C.w);
   k::to_f64(st, xz, C.fy.get(), y);
+}
+
+}  // namespace iga
+
+// ---- batched local operators: many independent problems, one grouped launch per stage ----
+
+namespace iga {
+
+namespace {
+
+struct BatchCache {
+  DBuf ws;              // FP64 intermediates (t1, t2, z) of all problems
+  FBuf fws;             // FP32 operand copies
+  FBuf fws2;            // FP32 intermediates
+  DBuf stage;           // device copy of the descriptor block (bytes, rounded up to doubles)
+  std::vector<char> host;
+  std::map<long, int> tuned;  // (precision, stage, size bucket) -> fastest tile variant
+};
+std::unordered_map<iga_ctx*, std::unique_ptr<BatchCache>> g_batch;
+
+int log2_bucket(long x) {
+  int b = 0;
+  while ((1L << b) < x && b < 30) ++b;
+  return b;
+}
+
+template <class T> struct GroupedOps;
+template <> struct GroupedOps<double> {
+  using G = k::Gemm2;
+  static int pick(const G& g) { return k::gemm2_pick(g); }
+  static size_t bytes() { return k::gemm2_desc_bytes(); }
+  static long prepare(const G& g, int v, void* h) { return k::gemm2_prepare(g, v, h); }
+  static void launch(hipStream_t s, int v, const void* d, const int* pre, int n, long t) {
+    k::gemm2_grouped(s, v, d, pre, n, t);
+  }
+  static void fill(hipStream_t s, int n, long m, const k::Segment* seg, double* b) { k::fill_segments(s, n, m, seg, b); }
+  static void combine(hipStream_t s, int n, long m, const k::CombineItem* it, const double* z) {
+    k::combine_grouped(s, n, m, it, z);
+  }
+  static constexpr int prec = 0;
+};
+template <> struct GroupedOps<float> {
+  using G = k::Gemm2F;
+  static int pick(const G& g) { return k::gemm2f_pick(g); }
+  static size_t bytes() { return k::gemm2f_desc_bytes(); }
+  static long prepare(const G& g, int v, void* h) { return k::gemm2f_prepare(g, v, h); }
+  static void launch(hipStream_t s, int v, const void* d, const int* pre, int n, long t) {
+    k::gemm2f_grouped(s, v, d, pre, n, t);
+  }
+  static void fill(hipStream_t s, int n, long m, const k::Segment* seg, float* b) { k::fill_segments_f32(s, n, m, seg, b); }
+  static void combine(hipStream_t s, int n, long m, const k::CombineItem* it, const float* z) {
+    k::combine_grouped_f32(s, n, m, it, z);
+  }
+  static constexpr int prec = 1;
+};
+
+struct ProbPtrs {  // operands of one problem in the working precision
+  const void* PhiL[2];
+  const void* PhiR[2];
+  const void* core[2];
+  const void* x;
+  void* y;
+};
+
+// Appends bytes to the host staging block at an aligned offset; returns the offset.
+size_t stage_append(std::vector<char>& h, const void* src, size_t n) {
+  size_t off = (h.size() + 255) / 256 * 256;
+  h.resize(off + n);
+  std::memcpy(h.data() + off, src, n);
+  return off;
+}
+
+template <class T>
+void batched_run(iga_ctx* ctx, const std::vector<BatchProblem>& P, const std::vector<ProbPtrs>& ptr,
+                 DevBuf<T>& ws, BatchCache& C, bool autotune) {
+  using Ops = GroupedOps<T>;
+  using G = typename Ops::G;
+  hipStream_t st = ctx->stream;
+  const int np = (int)P.size();
+  // workspace layout: per problem z (5 output columns), then per operator t1 and t2
+  std::vector<long> zoff(np), t1off(2 * np), t2off(2 * np);
+  long total = 0;
+  for (int i = 0; i < np; ++i) {
+    const BatchProblem& q = P[i];
+    const long osz = (long)q.r0 * q.n * q.r1;
+    zoff[i] = total;
+    total += 5 * osz;
+    for (int o = 0; o < 2; ++o) {
+      const int ncol = o == 0 ? 3 : 2, R0 = o == 0 ? q.RM0 : q.RK0, R1 = o == 0 ? q.RM1 : q.RK1;
+      const long S1 = (long)ncol * q.r0 * q.r1, SJ = (long)R0 * S1;
+      t1off[2 * i + o] = total;
+      total += (long)(q.n + 2 * q.p) * SJ;
+      t2off[2 * i + o] = total;
+      total += (long)q.n * R1 * S1;
+    }
+  }
+  ws.ensure(ctx, (size_t)total);
+  T* base = ws.get();
+  // products of the three stages, and the pad segments / combine items
+  std::vector<G> gemms[3];
+  std::vector<k::Segment> segs;
+  std::vector<k::CombineItem> comb;
+  long maxseg = 0, maxe = 0;
+  for (int i = 0; i < np; ++i) {
+    const BatchProblem& q = P[i];
+    const int n = q.n, p = q.p, b = 2 * p + 1, r0 = q.r0, r1 = q.r1;
+    const long osz = (long)r0 * n * r1, colsz = osz;
+    for (int o = 0; o < 2; ++o) {
+      const int ncol = o == 0 ? 3 : 2, R0 = o == 0 ? q.RM0 : q.RK0, R1 = o == 0 ? q.RM1 : q.RK1;
+      const long S2 = (long)r0 * r1, S1 = ncol * S2, SJ = (long)R0 * S1;
+      T* t1 = base + t1off[2 * i + o];
+      T* t2 = base + t2off[2 * i + o];
+      const T* x = static_cast<const T*>(ptr[i].x);
+      const long xcs = o == 0 ? colsz : 2 * colsz;  // K takes columns 0 and 2
+      T* z = base + zoff[i] + (o == 0 ? 0 : 3 * osz);
+      if (p > 0) {
+        segs.push_back({t1off[2 * i + o], p * SJ});
+        segs.push_back({t1off[2 * i + o] + (long)(n + p) * SJ, p * SJ});
+        maxseg = std::max(maxseg, p * SJ);
+      }
+      G g1;
+      g1.M = R0 * r0; g1.N = n * r1; g1.N2 = r1; g1.K = r0;
+      g1.A = static_cast<const T*>(ptr[i].PhiL[o]); g1.sAm1 = (long)r0 * r0; g1.sAm2 = r0; g1.sAk2 = 1;
+      g1.B = x; g1.sBk2 = (long)n * r1; g1.sBn1 = r1; g1.sBn2 = 1;
+      g1.C = t1 + p * SJ; g1.M2 = r0; g1.sCm1 = S1; g1.sCm2 = r1; g1.sCn1 = SJ; g1.sCn2 = 1;
+      g1.nb1 = ncol; g1.sBb1 = xcs; g1.sCb1 = S2;
+      gemms[0].push_back(g1);
+      G g2;
+      g2.M = R1; g2.N = (int)S1; g2.K = R0 * b; g2.K2 = R0;
+      g2.A = static_cast<const T*>(ptr[i].core[o]);
+      g2.sAm2 = 1; g2.sAk1 = R1; g2.sAk2 = (long)n * b * R1;
+      g2.B = t1; g2.sBk1 = SJ; g2.sBk2 = S1; g2.sBn2 = 1;
+      g2.C = t2; g2.sCm2 = S1; g2.sCn2 = 1;
+      g2.nb1 = n; g2.sAb1 = (long)b * R1; g2.sBb1 = SJ; g2.sCb1 = (long)R1 * S1;
+      gemms[1].push_back(g2);
+      G g3;
+      g3.M = r0 * n; g3.M2 = n; g3.N = r1; g3.K = R1 * r1; g3.K2 = r1;
+      g3.A = t2; g3.sAm1 = r1; g3.sAm2 = (long)R1 * S1; g3.sAk1 = S1; g3.sAk2 = 1;
+      g3.B = static_cast<const T*>(ptr[i].PhiR[o]); g3.sBk1 = (long)r1 * r1; g3.sBk2 = 1; g3.sBn2 = r1;
+      g3.C = z; g3.sCm1 = (long)n * r1; g3.sCm2 = r1; g3.sCn2 = 1;
+      g3.nb1 = ncol; g3.sAb1 = S2; g3.sCb1 = osz;
+      gemms[2].push_back(g3);
+    }
+    k::KktCoef cf;
+    cf.m11 = q.beta;
+    comb.push_back({zoff[i], osz, ptr[i].y, cf});
+    maxe = std::max(maxe, osz);
+  }
+  auto key_of = [&](int s, const G& g) {
+    return (long)Ops::prec * 100000000L + s * 1000000L + log2_bucket(g.M) * 10000L + log2_bucket(g.N) * 100L +
+           log2_bucket((long)g.K * g.nb1 * g.nb2);
+  };
+  const size_t db = Ops::bytes();
+  // stages the descriptor block of a list of products for one variant; returns (desc, prefix) offsets
+  auto stage_group = [&](std::vector<char>& h, const std::vector<const G*>& list, int v, size_t& doff,
+                         size_t& poff, long& tiles) {
+    std::vector<char> d(db * list.size());
+    std::vector<int> pre(list.size() + 1, 0);
+    tiles = 0;
+    for (size_t j = 0; j < list.size(); ++j) {
+      pre[j] = (int)tiles;
+      tiles += Ops::prepare(*list[j], v, d.data() + j * db);
+    }
+    pre[list.size()] = (int)tiles;
+    doff = stage_append(h, d.data(), d.size());
+    poff = stage_append(h, pre.data(), pre.size() * sizeof(int));
+  };
+  auto upload = [&](const std::vector<char>& h) -> const char* {
+    C.stage.ensure(ctx, (h.size() + 7) / 8);
+    IGA_HIP(hipMemcpyAsync(C.stage.get(), h.data(), h.size(), hipMemcpyHostToDevice, st));
+    IGA_HIP(hipStreamSynchronize(st));
+    return reinterpret_cast<const char*>(C.stage.get());
+  };
+  // pads, once per call (the intermediates are shared with other calls)
+  {
+    std::vector<char> h;
+    const size_t so = segs.empty() ? 0 : stage_append(h, segs.data(), segs.size() * sizeof(k::Segment));
+    if (!segs.empty()) {
+      const char* d = upload(h);
+      Ops::fill(st, (int)segs.size(), maxseg, reinterpret_cast<const k::Segment*>(d + so), base);
+      IGA_HIP(hipStreamSynchronize(st));
+    }
+  }
+  for (int s = 0; s < 3; ++s) {
+    // buckets of this stage
+    std::map<long, std::vector<const G*>> buckets;
+    for (const G& g : gemms[s]) buckets[key_of(s, g)].push_back(&g);
+    if (autotune) {
+      for (auto& kv : buckets) {
+        if (C.tuned.count(kv.first)) continue;
+        float best = 1e30f;
+        int bestv = Ops::pick(*kv.second[0]);
+        for (int v = 0; v < k::gemm2_variants(); ++v) {
+          std::vector<char> h;
+          size_t doff, poff;
+          long tiles;
+          stage_group(h, kv.second, v, doff, poff, tiles);
+          const char* d = upload(h);
+          hipEvent_t e0, e1;
+          IGA_HIP(hipEventCreate(&e0));
+          IGA_HIP(hipEventCreate(&e1));
+          IGA_HIP(hipEventRecord(e0, st));
+          Ops::launch(st, v, d + doff, reinterpret_cast<const int*>(d + poff), (int)kv.second.size(), tiles);
+          IGA_HIP(hipEventRecord(e1, st));
+          IGA_HIP(hipEventSynchronize(e1));
+          float ms = 0.0f;
+          IGA_HIP(hipEventElapsedTime(&ms, e0, e1));
+          IGA_HIP(hipEventDestroy(e0));
+          IGA_HIP(hipEventDestroy(e1));
+          if (ms < best) { best = ms; bestv = v; }
+        }
+        C.tuned[kv.first] = bestv;
+      }
+    }
+    // groups by variant: one grouped launch each
+    std::map<int, std::vector<const G*>> groups;
+    for (auto& kv : buckets) {
+      auto it = C.tuned.find(kv.first);
+      const int v = it != C.tuned.end() ? it->second : Ops::pick(*kv.second[0]);
+      auto& dst = groups[v];
+      dst.insert(dst.end(), kv.second.begin(), kv.second.end());
+    }
+    std::vector<char> h;
+    std::vector<std::tuple<int, size_t, size_t, long, int>> launches;
+    for (auto& kv : groups) {
+      size_t doff, poff;
+      long tiles;
+      stage_group(h, kv.second, kv.first, doff, poff, tiles);
+      launches.emplace_back(kv.first, doff, poff, tiles, (int)kv.second.size());
+    }
+    const char* d = upload(h);
+    for (auto& L : launches)
+      Ops::launch(st, std::get<0>(L), d + std::get<1>(L), reinterpret_cast<const int*>(d + std::get<2>(L)),
+                  std::get<4>(L), std::get<3>(L));
+    IGA_HIP(hipStreamSynchronize(st));  // the staging block is reused by the next stage
+  }
+  {
+    std::vector<char> h;
+    const size_t co = stage_append(h, comb.data(), comb.size() * sizeof(k::CombineItem));
+    const char* d = upload(h);
+    Ops::combine(st, (int)comb.size(), maxe, reinterpret_cast<const k::CombineItem*>(d + co), base);
+    IGA_HIP(hipStreamSynchronize(st));
+  }
+}
+
+}  // namespace
+
+void release_batch_cache(iga_ctx* ctx) { g_batch.erase(ctx); }
+
+void local_matvec_batched_impl(iga_ctx* ctx, const std::vector<BatchProblem>& P, int precision, bool autotune) {
+  auto& cp = g_batch[ctx];
+  if (!cp) cp.reset(new BatchCache());
+  BatchCache& C = *cp;
+  for (const BatchProblem& q : P) {
+    require(q.r0 >= 1 && q.r1 >= 1 && q.n >= 1 && q.p >= 0 && q.RM0 >= 1 && q.RM1 >= 1 && q.RK0 >= 1 &&
+                q.RK1 >= 1,
+            IGA_EINVAL, "local_matvec_batched: bad sizes");
+    require(q.PhiL_M && q.PhiR_M && q.PhiL_K && q.PhiR_K && q.Mcore && q.Kcore && q.x && q.y, IGA_EINVAL,
+            "local_matvec_batched: NULL operand");
+  }
+  const int np = (int)P.size();
+  std::vector<ProbPtrs> ptr(np);
+  if (precision == IGA_FP64) {
+    for (int i = 0; i < np; ++i) {
+      const BatchProblem& q = P[i];
+      ptr[i] = ProbPtrs{{q.PhiL_M, q.PhiL_K}, {q.PhiR_M, q.PhiR_K}, {q.Mcore, q.Kcore}, q.x, q.y};
+    }
+    batched_run<double>(ctx, P, ptr, C.ws, C, autotune);
+    return;
+  }
+  // FP32: convert every operand in one grouped launch, contract, convert the results back
+  hipStream_t st = ctx->stream;
+  std::vector<long> off(np * 8 + 1, 0);
+  std::vector<k::ConvSegment> in, out;
+  long pos = 0, maxlen = 0;
+  std::vector<std::array<long, 8>> at(np);
+  for (int i = 0; i < np; ++i) {
+    const BatchProblem& q = P[i];
+    const int b = 2 * q.p + 1;
+    const long len[8] = {(long)q.RM0 * q.r0 * q.r0, (long)q.RM1 * q.r1 * q.r1, (long)q.RK0 * q.r0 * q.r0,
+                         (long)q.RK1 * q.r1 * q.r1, (long)q.RM0 * q.n * b * q.RM1, (long)q.RK0 * q.n * b * q.RK1,
+                         3L * q.r0 * q.n * q.r1, 3L * q.r0 * q.n * q.r1};
+    for (int j = 0; j < 8; ++j) {
+      at[i][j] = pos;
+      pos += (len[j] + 63) / 64 * 64;
+      maxlen = std::max(maxlen, len[j]);
+    }
+  }
+  C.fws.ensure(ctx, (size_t)pos);
+  float* fb = C.fws.get();
+  for (int i = 0; i < np; ++i) {
+    const BatchProblem& q = P[i];
+    const int b = 2 * q.p + 1;
+    const double* src[7] = {q.PhiL_M, q.PhiR_M, q.PhiL_K, q.PhiR_K, q.Mcore, q.Kcore, q.x};
+    const long len[7] = {(long)q.RM0 * q.r0 * q.r0, (long)q.RM1 * q.r1 * q.r1, (long)q.RK0 * q.r0 * q.r0,
+                         (long)q.RK1 * q.r1 * q.r1, (long)q.RM0 * q.n * b * q.RM1, (long)q.RK0 * q.n * b * q.RK1,
+                         3L * q.r0 * q.n * q.r1};
+    for (int j = 0; j < 7; ++j) in.push_back({src[j], fb + at[i][j], len[j]});
+    out.push_back({fb + at[i][7], q.y, 3L * q.r0 * q.n * q.r1});
+    ptr[i] = ProbPtrs{{fb + at[i][0], fb + at[i][2]}, {fb + at[i][1], fb + at[i][3]}, {fb + at[i][4], fb + at[i][5]},
+                      fb + at[i][6], fb + at[i][7]};
+  }
+  {
+    std::vector<char> h;
+    const size_t o = stage_append(h, in.data(), in.size() * sizeof(k::ConvSegment));
+    C.stage.ensure(ctx, (h.size() + 7) / 8);
+    IGA_HIP(hipMemcpyAsync(C.stage.get(), h.data(), h.size(), hipMemcpyHostToDevice, st));
+    k::convert_segments(st, (int)in.size(), maxlen,
+                        reinterpret_cast<const k::ConvSegment*>(reinterpret_cast<const char*>(C.stage.get()) + o), true);
+    IGA_HIP(hipStreamSynchronize(st));
+  }
+  batched_run<float>(ctx, P, ptr, C.fws2, C, autotune);
+  {
+    std::vector<char> h;
+    const size_t o = stage_append(h, out.data(), out.size() * sizeof(k::ConvSegment));
+    C.stage.ensure(ctx, (h.size() + 7) / 8);
+    IGA_HIP(hipMemcpyAsync(C.stage.get(), h.data(), h.size(), hipMemcpyHostToDevice, st));
+    k::convert_segments(st, (int)out.size(), maxlen,
+                        reinterpret_cast<const k::ConvSegment*>(reinterpret_cast<const char*>(C.stage.get()) + o), false);
+    IGA_HIP(hipStreamSynchronize(st));
+  }
 }
 
 }  // namespace iga

@@ -45,6 +45,19 @@ struct LocalWork {
 void local_matvec(iga_ctx* ctx, const LocalOp& L, const double* x, double* y, LocalWork& w);
 // Same product with every contraction in FP32 (x, y FP32); needs the f* fields and Af views.
 void local_matvec_f32(iga_ctx* ctx, const LocalOp& L, const float* x, float* y, LocalWork& w);
+// One independent problem of the batched form (dense rank blocks, square interfaces).
+struct BatchProblem {
+  int r0, n, r1, p, RM0, RM1, RK0, RK1;
+  const double *PhiL_M, *PhiR_M, *PhiL_K, *PhiR_K, *Mcore, *Kcore;
+  double beta;
+  const double* x;
+  double* y;
+};
+// y_i = A_i x_i for every problem; each stage of all problems is one grouped matrix-core
+// launch per tile variant (variants tuned per size bucket when autotune is set).
+void local_matvec_batched_impl(iga_ctx* ctx, const std::vector<BatchProblem>& P, int precision, bool autotune);
+void release_batch_cache(iga_ctx* ctx);
+
 // Algorithmic flops of local_matvec: banded middle stage counted over the band's
 // nonzero entries and over the nonzero rank blocks only.
 double local_flops(const LocalOp& L);

@@ -30,7 +30,7 @@ EXPORTED = [
     "iga_ttop_get_core", "iga_ttop_destroy", "iga_tt_create", "iga_tt_wrap", "iga_tt_from_full", "iga_tt_destroy",
     "iga_btt_create", "iga_btt_info", "iga_btt_get_core", "iga_btt_to_full", "iga_btt_destroy",
     "iga_kkt_create", "iga_kkt_destroy", "iga_kkt_apply", "iga_kkt_residual", "iga_amen_solve",
-    "iga_local_matvec", "iga_local_matvec_flops", "iga_profile_start", "iga_profile_stop", "iga_objective",
+    "iga_local_matvec", "iga_local_matvec_batched", "iga_local_matvec_flops", "iga_profile_start", "iga_profile_stop", "iga_objective",
     "iga_grad_yhat", "iga_grad_geometry", "iga_last_error",
 ]
 
@@ -73,6 +73,13 @@ class AmenStats(C.Structure):
             v = getattr(self, name)
             out[name] = list(v) if name == "ranks" else v
         return out
+
+
+class LocalProblem(C.Structure):
+    _fields_ = [("r0", C.c_int), ("n", C.c_int), ("r1", C.c_int), ("degree", C.c_int), ("RM0", C.c_int),
+                ("RM1", C.c_int), ("RK0", C.c_int), ("RK1", C.c_int), ("PhiL_M", C.c_void_p), ("PhiR_M", C.c_void_p),
+                ("PhiL_K", C.c_void_p), ("PhiR_K", C.c_void_p), ("Mcore", C.c_void_p), ("Kcore", C.c_void_p),
+                ("beta", C.c_double), ("x", C.c_void_p), ("y", C.c_void_p)]
 
 
 class Profile(C.Structure):
@@ -119,6 +126,7 @@ lib.iga_amen_solve.argtypes = [P, P, P, C.c_double, C.POINTER(AmenOpts), P, C.PO
                                C.POINTER(AmenStats)]
 lib.iga_local_matvec.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                                  C.c_int, P, P, P, P, P, P, C.c_double, P, P, C.c_int]
+lib.iga_local_matvec_batched.argtypes = [P, C.c_int, C.POINTER(LocalProblem), C.c_int, C.c_int]
 lib.iga_local_matvec_flops.argtypes = [C.c_int] * 8
 lib.iga_local_matvec_flops.restype = C.c_double
 lib.iga_objective.argtypes = [P, P, P, P, PD]
@@ -299,7 +307,7 @@ def amen_solve(ctx, kkt, yhat, tol: float, x0=None, raise_on_noconv: bool = Fals
     st = AmenStats()
     sol = P()
     rc = lib.iga_amen_solve(ctx, kkt, yhat, float(tol), C.byref(o), x0, C.byref(sol), C.byref(st))
-    if rc != OK and not (rc == ENOCONV and not raise_on_noconv and sol):
+    if rc != OK and not (rc in (ENOCONV, ERANK) and not raise_on_noconv and sol):
         raise IgaError(rc, last_error())
     return sol, st.as_dict(), rc
 
@@ -368,3 +376,20 @@ def tt_from_full(ctx, full, rel_tol: float = 0.0):
     out = P()
     _check(lib.iga_tt_from_full(ctx, I3(*full.shape), C.c_void_p(full.data_ptr()), float(rel_tol), C.byref(out)))
     return out
+
+
+
+def local_matvec_batched(ctx, problems, precision=FP64, autotune=True):
+    """problems: list of dicts with keys r0, n, r1, degree, RM0, RM1, RK0, RK1, beta and CUDA FP64
+    tensors PhiL_M, PhiR_M, PhiL_K, PhiR_K, Mcore, Kcore, x, y (y is written)."""
+    arr = (LocalProblem * max(len(problems), 1))()
+    for i, q in enumerate(problems):
+        e = arr[i]
+        for k in ("r0", "n", "r1", "degree", "RM0", "RM1", "RK0", "RK1"):
+            setattr(e, k, int(q[k]))
+        e.beta = float(q["beta"])
+        for k in ("PhiL_M", "PhiR_M", "PhiL_K", "PhiR_K", "Mcore", "Kcore", "x", "y"):
+            t = q[k]
+            assert t.is_cuda and t.dtype.is_floating_point and t.is_contiguous()
+            setattr(e, k, t.data_ptr())
+    _check(lib.iga_local_matvec_batched(ctx, len(problems), arr, int(precision), int(bool(autotune))))

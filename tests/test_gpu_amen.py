@@ -164,3 +164,13 @@ def test_mixed_precision_matches_fp64_n64(gpu_ctx):
     print("fp64", st64, "\nmixed", st32, flush=True)
     assert rc64 == 0 and rc32 == 0 and res64 < 1e-6 and res32 < 1e-6
     assert rel_err(f32[0], f64[0]) < 1e-5
+
+
+def test_rank_cap_is_reported(gpu_ctx):
+    """A rank cap below what the tolerance needs ends the sweeps with IGA_ERANK and a solution."""
+    from paper_1811_06797_amd import iga
+    geo = synth.twisted_annulus(seed=1)
+    p, n = 3, 12
+    f, st, rc, res, r = _solve(gpu_ctx, geo, p, n, 1e-6, synth.yhat_fourier(n, p, seed=2), 1e-10, r_max=3,
+                               nswp=4)
+    assert rc == iga.ERANK and st["converged"] == 0 and max(r[1], r[2]) >= 3
