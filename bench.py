@@ -20,6 +20,7 @@ Printed JSON line:
              residuals and the state difference;
   differentiation  times of the reduced cost, its desired-state gradient and its
              control-point gradient at the FP64 solution;
+  batching   64 uneven local TT-matvecs, one call per problem versus one batched call;
   roofline   the dominant kernel of the local TT-matvec at the microbenchmark shape
              (r, R_M, R_K, n, p) = (32, 10, 60, 64, 3): the banded middle stage of
              the K operator, timed by the library with HIP events on its stream;
@@ -140,6 +141,53 @@ def mixed_compare(iga, ctx, torch, geo, c, Y, steps):
     iga.kkt_destroy(kk)
     iga.ttop_destroy(M)
     iga.ttop_destroy(K)
+    return out
+
+
+def batching_bench(iga, ctx, torch, nprob=64, seed=100, iters=3):
+    """Batching form: the local TT-matvecs of nprob problems with uneven shapes drawn like the
+    batched workload (n in {32,48,64,96,128}, degree in {2,3}, ranks r ~ U{8..32}, R_M ~ U{1..6},
+    R_K ~ U{3..24}, beta log-uniform in [1e-8, 1e-2]) on seeded N(0,1) operands: one problem per
+    call versus one batched call (grouped launches, autotuned tiles), FP64 and FP32."""
+    import numpy as np
+    import synth
+    rng = np.random.default_rng(seed)
+    probs, flops = [], 0.0
+    for i in range(nprob):
+        n = int(rng.choice([32, 48, 64, 96, 128]))
+        p = int(rng.choice([2, 3]))
+        r = int(rng.integers(8, 33))
+        RM = int(rng.integers(1, 7))
+        RK = int(rng.integers(3, 25))
+        beta = float(10.0 ** rng.uniform(-8, -2))
+        prob = synth.random_local_problem(r, RM, RK, n, p, seed=seed + i)
+        dev = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda() for k, v in prob.items()}
+        probs.append(dict(r0=r, n=n, r1=r, degree=p, RM0=RM, RM1=RM, RK0=RK, RK1=RK, beta=beta, PhiL_M=dev["PhiL_M"],
+                          PhiR_M=dev["PhiR_M"], PhiL_K=dev["PhiL_K"], PhiR_K=dev["PhiR_K"], Mcore=dev["M"],
+                          Kcore=dev["K"], x=dev["x"], y=torch.empty_like(dev["x"])))
+        flops += iga.local_matvec_flops(r, n, r, p, RM, RM, RK, RK)
+    out = {"problems": nprob, "flops_per_pass": flops}
+    for name, prec in (("fp64", iga.FP64), ("fp32", iga.FP32)):
+        def seq():
+            for q in probs:
+                iga.local_matvec(ctx, q["r0"], q["n"], q["r1"], q["degree"], q["RM0"], q["RM1"], q["RK0"], q["RK1"],
+                                 q["PhiL_M"], q["PhiR_M"], q["PhiL_K"], q["PhiR_K"], q["Mcore"], q["Kcore"],
+                                 q["beta"], q["x"], q["y"], prec)
+        seq()
+        iga.local_matvec_batched(ctx, probs, prec, autotune=True)  # tunes the buckets once
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(iters):
+            seq()
+        torch.cuda.synchronize()
+        ts = (time.perf_counter() - t0) / iters
+        t0 = time.perf_counter()
+        for _ in range(iters):
+            iga.local_matvec_batched(ctx, probs, prec, autotune=True)
+        torch.cuda.synchronize()
+        tb = (time.perf_counter() - t0) / iters
+        out[name] = {"one_call_per_problem_s": ts, "batched_s": tb, "speedup": ts / tb,
+                     "batched_gflops": flops / tb / 1e9, "one_call_per_problem_gflops": flops / ts / 1e9}
     return out
 
 
@@ -275,6 +323,7 @@ def main():
     t_mv = sum(s["t_local_matvec"] for s in stats)
     gflops = flops / t_mv / 1e9
     mixed = mixed_compare(iga, ctx, torch, geo, c, Y, max(1, min(a.steps, 3)))
+    batching = batching_bench(iga, ctx, torch)
     micro, prob = micro_bench(iga, ctx, torch, a.micro_iters)
     prof = micro["profile"]
     k_ms = prof["ms"][1] / max(prof["launches"][1], 1)
@@ -307,6 +356,7 @@ def main():
                                        "t_interfaces", "t_krylov_other", "t_residual", "op_ranks")},
         "mixed_vs_fp64": {k: v for k, v in mixed.items() if k != "differentiation"},
         "differentiation": mixed["differentiation"],
+        "batching": batching,
         "microbench_local_matvec": {k: micro[k] for k in ("shape", "ms", "gflops", "flops", "fp32")},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
