@@ -360,7 +360,7 @@ def main():
         "microbench_local_matvec": {k: micro[k] for k in ("shape", "ms", "gflops", "flops", "fp32")},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
-                     "kernel": "gemm2_kernel<8, 4, 2, 2, 16, 2, 2>: banded middle stage of the K operator in the "
+                     "kernel": "gemm2_kernel<8, 4, 2, 2, 16, 2, 2, true>: banded middle stage of the K operator in the "
                                "local TT-matvec at (r, R_M, R_K, n, p) = (32, 10, 60, 64, 3)",
                      "flops_per_launch": k_flops, "ms_per_launch": k_ms, "launches": prof["launches"][1]},
     }

@@ -116,6 +116,18 @@ class Amen {
     ry_[1] = Y->r[1]; ry_[2] = Y->r[2];
     rng_.seed(o.seed);
     lowp_ = o.precision == IGA_FP32;
+    // dense cores re-laid as [n][2p+1][R0][R1] once per solve: the banded stage of the
+    // local matvec then contracts over one (R0, 2p+1) index instead of two nested ones
+    for (int op = 0; op < 2; ++op)
+      for (int d = 0; d < 3; ++d) {
+        const OpCore& c = ops_[op]->core[d];
+        const bool dense = c.blocks.size() == 1 && c.blocks[0].na == c.R0 && c.blocks[0].nb == c.R1;
+        if (!dense) continue;
+        const int b = 2 * ops_[op]->p + 1;
+        const int dims[4] = {c.R0, c.n, b, c.R1}, perm[4] = {1, 2, 0, 3};
+        rcore_[op][d].reset(ctx, (long)c.R0 * c.n * b * c.R1);
+        k::permute4(st_, c.data.get(), dims, perm, rcore_[op][d].get());
+      }
     if (lowp_) {
       // FP32 copies of the operator cores, fixed for the whole solve
       for (int op = 0; op < 2; ++op)
@@ -209,6 +221,7 @@ class Amen {
   // refinement's inner solve (lp_inner_) every local matvec contracts in FP32
   bool lowp_ = false, lp_inner_ = false;
   FBuf fcore_[2][3], fPL_[2], fPR_[2], fx_, fy_;
+  DBuf rcore_[2][3];  // re-laid dense cores (null for block-structured ones)
   void lowp_operands(int d, LocalOp& L);
   int refine_solve(int d, const LocalOp& L, double bn, double ltol, double res0);
   // statistics
@@ -341,6 +354,8 @@ LocalOp Amen::make_op(int d, Frame left, Frame right) const {
   LocalOp L;
   L.M = view(0, d);
   L.K = view(1, d);
+  L.M.Ar = rcore_[0][d].get();
+  L.K.Ar = rcore_[1][d].get();
   L.Mblocks = ops_[0]->core[d].blocks;
   L.Kblocks = ops_[1]->core[d].blocks;
   L.r0 = r_[d]; L.n = n_[d]; L.r1 = r_[d + 1];

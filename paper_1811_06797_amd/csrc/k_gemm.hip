@@ -83,7 +83,7 @@ struct TileLds {
 
 // One BM x BN output tile (column tile bx, row tile by, batch and split index bz) of the
 // product g.
-template <int WM, int WN, int WAVES_M, int WAVES_N, int BK, int NBUF, int PF>
+template <int WM, int WN, int WAVES_M, int WAVES_N, int BK, int NBUF, int PF, bool K1 = false>
 __device__ __forceinline__ void gemm2_tile(const G2Args& g, int bx, int by, int bz,
                                            TileLds<4 * WM * WAVES_M, 16 * WN * WAVES_N, BK, NBUF>& L) {
   constexpr int BM = 4 * WM * WAVES_M, BN = 16 * WN * WAVES_N;
@@ -150,19 +150,27 @@ __device__ __forceinline__ void gemm2_tile(const G2Args& g, int bx, int by, int 
     for (int s = 0; s < LA; ++s) {
       const bool ok = a_ok[s] && a_kk[s] < klim;
       ra[s] = *(ok ? A + oa[s] : kZero);
-      ak2[s] += krem;
-      const bool w = ak2[s] >= g.K2;
-      ak2[s] -= w ? g.K2 : 0;
-      oa[s] += w ? dAw : dA;
+      if constexpr (K1) {
+        oa[s] += dA;  // single-level K: constant stride
+      } else {
+        ak2[s] += krem;
+        const bool w = ak2[s] >= g.K2;
+        ak2[s] -= w ? g.K2 : 0;
+        oa[s] += w ? dAw : dA;
+      }
     }
 #pragma unroll
     for (int s = 0; s < LB; ++s) {
       const bool ok = b_ok[s] && b_kk[s] < klim;
       rb[s] = *(ok ? B + ob[s] : kZero);
-      bk2[s] += krem;
-      const bool w = bk2[s] >= g.K2;
-      bk2[s] -= w ? g.K2 : 0;
-      ob[s] += w ? dBw : dB;
+      if constexpr (K1) {
+        ob[s] += dB;
+      } else {
+        bk2[s] += krem;
+        const bool w = bk2[s] >= g.K2;
+        bk2[s] -= w ? g.K2 : 0;
+        ob[s] += w ? dBw : dB;
+      }
     }
   };
   auto store_tile = [&](int buf, const double (&ra)[LA], const double (&rb)[LB]) {
@@ -267,7 +275,7 @@ __device__ __forceinline__ void gemm2_tile(const G2Args& g, int bx, int by, int 
   }
 }
 
-template <int WM, int WN, int WAVES_M, int WAVES_N, int BK, int NBUF, int PF>
+template <int WM, int WN, int WAVES_M, int WAVES_N, int BK, int NBUF, int PF, bool K1>
 __global__ __launch_bounds__(NTHR) void gemm2_kernel(G2Args g) {
   __shared__ TileLds<4 * WM * WAVES_M, 16 * WN * WAVES_N, BK, NBUF> L;
   // Workgroups are dealt to the 8 XCDs round-robin by linear id; renumber them so that each
@@ -278,7 +286,7 @@ __global__ __launch_bounds__(NTHR) void gemm2_kernel(G2Args g) {
   const int lin = (blockIdx.z * gy + blockIdx.y) * gx + blockIdx.x;
   const int xcd = lin % 8, q = lin / 8, base = total / 8, rem = total % 8;
   const int tile = (xcd < rem ? xcd * (base + 1) : rem * (base + 1) + (xcd - rem) * base) + q;
-  gemm2_tile<WM, WN, WAVES_M, WAVES_N, BK, NBUF, PF>(g, tile % gx, (tile / gx) % gy, tile / (gx * gy), L);
+  gemm2_tile<WM, WN, WAVES_M, WAVES_N, BK, NBUF, PF, K1>(g, tile % gx, (tile / gx) % gy, tile / (gx * gy), L);
 }
 
 // Many independent products in one persistent launch: workgroup w takes the tiles
@@ -326,7 +334,11 @@ void launch(hipStream_t s, G2Args a, int nbatch) {
   constexpr int BM = 4 * WM * WAVES_M, BN = 16 * WN * WAVES_N;
   dim3 grid((a.N + BN - 1) / BN, (a.M + BM - 1) / BM, (unsigned)(nbatch * a.ksplit));
   require((long)grid.x * grid.y * grid.z < (1L << 31), IGA_EINVAL, "gemm2: grid too large");
-  gemm2_kernel<WM, WN, WAVES_M, WAVES_N, BK, NBUF, PF><<<grid, NTHR, 0, s>>>(a);
+  // a single-level K index (inner extent covering K) advances operands by a constant stride
+  if (a.K2 >= a.K)
+    gemm2_kernel<WM, WN, WAVES_M, WAVES_N, BK, NBUF, PF, true><<<grid, NTHR, 0, s>>>(a);
+  else
+    gemm2_kernel<WM, WN, WAVES_M, WAVES_N, BK, NBUF, PF, false><<<grid, NTHR, 0, s>>>(a);
 }
 
 }  // namespace
@@ -355,18 +367,20 @@ static G2Args make_args(const Gemm2& d) {
                 d.sBb1, d.sBb2, d.sCb1, d.sCb2, d.alpha, d.beta, 1, std::max(d.K, 0), nullptr};
 }
 
-// Output tile of each variant: 0: 64 x 64, 1: 32 x 128, 2: 16 x 256, 3: 128 x 32, 4: 64 x (32 WIDE_WN).
+// Output tile of each variant: 0: 64 x 64, 1: 32 x 128, 2: 16 x 256, 3: 128 x 32, 4: 64 x (32 WIDE_WN),
+// 5: 80 x 64.
 static void variant_tile(int v, int& BM, int& BN) {
   switch (v) {
     case 1: BM = 32; BN = 128; break;
     case 2: BM = 16; BN = 256; break;
     case 3: BM = 128; BN = 32; break;
     case 4: BM = 64; BN = 32 * IGA_WIDE_WN; break;
+    case 5: BM = 80; BN = 64; break;
     default: BM = 64; BN = 64; break;
   }
 }
 
-int gemm2_variants() { return 5; }
+int gemm2_variants() { return 6; }
 
 int gemm2_pick(const Gemm2& d) {
   const long nb = (long)d.nb1 * d.nb2;
@@ -374,6 +388,7 @@ int gemm2_pick(const Gemm2& d) {
   if (d.M <= 32) return 1;
   if (d.N <= 32) return 3;
   if (d.M <= 64 && (long)((d.N + 32 * IGA_WIDE_WN - 1) / (32 * IGA_WIDE_WN)) * nb >= 512) return 4;
+  if (d.M > 64 && d.M <= 80) return 5;  // one 80-row tile instead of 64 + 16
   return 0;
 }
 
@@ -407,6 +422,7 @@ void gemm2_grouped(hipStream_t s, int variant, const void* dev_desc, const int* 
       launch_grouped<8, IGA_WIDE_WN, 2, 2, IGA_WIDE_BK, IGA_WIDE_NBUF, IGA_WIDE_PREFETCH>(s, dev_desc, dev_prefix,
                                                                                          ngemm, total);
       break;
+    case 5: launch_grouped<10, 2, 2, 2, 16, 2, IGA_PREFETCH>(s, dev_desc, dev_prefix, ngemm, total); break;
     default: launch_grouped<8, 2, 2, 2, 16, 2, IGA_PREFETCH>(s, dev_desc, dev_prefix, ngemm, total); break;
   }
   IGA_HIP(hipGetLastError());
@@ -439,6 +455,7 @@ void gemm2(hipStream_t s, const Gemm2& d, double* work, size_t work_len) {
     case 1: launch<8, 2, 1, 4, 16, 2, IGA_PREFETCH>(s, a, (int)nb); break;
     case 3: launch<8, 2, 4, 1, 16, 2, IGA_PREFETCH>(s, a, (int)nb); break;
     case 4: launch<8, IGA_WIDE_WN, 2, 2, IGA_WIDE_BK, IGA_WIDE_NBUF, IGA_WIDE_PREFETCH>(s, a, (int)nb); break;
+    case 5: launch<10, 2, 2, 2, 16, 2, IGA_PREFETCH>(s, a, (int)nb); break;
     default: launch<8, 2, 2, 2, 16, 2, IGA_PREFETCH>(s, a, (int)nb); break;
   }
   IGA_HIP(hipGetLastError());

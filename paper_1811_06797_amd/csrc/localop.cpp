@@ -64,7 +64,7 @@ template <> struct Prec<float> {
 // banded stage is, for every row i, one dense GEMM over (o, d) whose B operand is the
 // contiguous window of slices j = i-p .. i+p; one GEMM per nonzero rank block.
 template <class T>
-static void op_apply(iga_ctx* ctx, const OpView& A, const T* core, const std::vector<RankBlock>& blocks,
+static void op_apply(iga_ctx* ctx, const OpView& A, const T* core, const T* relaid, const std::vector<RankBlock>& blocks,
                      const T* PhiL, const T* PhiR, int r0o, int r0, int r1, int r1o, int ncol, const T* x,
                      long xcs, T* z, long zcs, DevBuf<T>& t1, DevBuf<T>& t2, DevBuf<T>& wk,
                      LocalWork::PadKey& pad, int op_id) {
@@ -97,15 +97,28 @@ static void op_apply(iga_ctx* ctx, const OpView& A, const T* core, const std::ve
     pb = prof_event(ctx);
     IGA_HIP(hipEventRecord(pa, st));
   }
-  for (const RankBlock& rb : blocks) {
+  const bool dense = blocks.size() == 1 && blocks[0].na == R0 && blocks[0].nb == R1;
+  if (dense && relaid) {
+    // core [i][o][d][g]: for row i the contraction index k = o R0 + d has constant strides
+    // (R1 in the core, S1 in t1, whose slice i + o starts at (i + o) SJ = i SJ + o R0 S1)
     G g2;
-    g2.M = rb.nb; g2.N = (int)S1; g2.K = rb.na * b; g2.K2 = rb.na;
-    g2.A = core + (long)rb.a0 * n * b * R1 + rb.b0;
-    g2.sAm2 = 1; g2.sAk1 = R1; g2.sAk2 = (long)n * b * R1;
-    g2.B = t1.get() + rb.a0 * S1; g2.sBk1 = SJ; g2.sBk2 = S1; g2.sBn2 = 1;
-    g2.C = t2.get() + rb.b0 * S1; g2.sCm2 = S1; g2.sCn2 = 1;
-    g2.nb1 = n; g2.sAb1 = (long)b * R1; g2.sBb1 = SJ; g2.sCb1 = (long)R1 * S1;
+    g2.M = R1; g2.N = (int)S1; g2.K = R0 * b;
+    g2.A = relaid; g2.sAm2 = 1; g2.sAk2 = R1;
+    g2.B = t1.get(); g2.sBk2 = S1; g2.sBn2 = 1;
+    g2.C = t2.get(); g2.sCm2 = S1; g2.sCn2 = 1;
+    g2.nb1 = n; g2.sAb1 = (long)b * R0 * R1; g2.sBb1 = SJ; g2.sCb1 = (long)R1 * S1;
     Prec<T>::gemm(st, g2, nullptr, 0);
+  } else {
+    for (const RankBlock& rb : blocks) {
+      G g2;
+      g2.M = rb.nb; g2.N = (int)S1; g2.K = rb.na * b; g2.K2 = rb.na;
+      g2.A = core + (long)rb.a0 * n * b * R1 + rb.b0;
+      g2.sAm2 = 1; g2.sAk1 = R1; g2.sAk2 = (long)n * b * R1;
+      g2.B = t1.get() + rb.a0 * S1; g2.sBk1 = SJ; g2.sBk2 = S1; g2.sBn2 = 1;
+      g2.C = t2.get() + rb.b0 * S1; g2.sCm2 = S1; g2.sCn2 = 1;
+      g2.nb1 = n; g2.sAb1 = (long)b * R1; g2.sBb1 = SJ; g2.sCb1 = (long)R1 * S1;
+      Prec<T>::gemm(st, g2, nullptr, 0);
+    }
   }
   if (ctx->prof_on) {
     IGA_HIP(hipEventRecord(pb, st));
@@ -131,9 +144,9 @@ void local_matvec(iga_ctx* ctx, const LocalOp& L, const double* x, double* y, Lo
   const int r0o = L.out0(), r1o = L.out1();
   const long osz = (long)r0o * L.n * r1o;  // one output column
   w.z.ensure(ctx, (size_t)5 * osz);
-  op_apply<double>(ctx, L.M, L.M.A, L.Mblocks, L.PhiL_M, L.PhiR_M, r0o, L.r0, L.r1, r1o, 3, x, colsz, w.z.get(),
+  op_apply<double>(ctx, L.M, L.M.A, L.M.Ar, L.Mblocks, L.PhiL_M, L.PhiR_M, r0o, L.r0, L.r1, r1o, 3, x, colsz, w.z.get(),
                    osz, w.tM, w.tM2, w.split, w.padM, 0);
-  op_apply<double>(ctx, L.K, L.K.A, L.Kblocks, L.PhiL_K, L.PhiR_K, r0o, L.r0, L.r1, r1o, 2, x, 2 * colsz,
+  op_apply<double>(ctx, L.K, L.K.A, L.K.Ar, L.Kblocks, L.PhiL_K, L.PhiR_K, r0o, L.r0, L.r1, r1o, 2, x, 2 * colsz,
                    w.z.get() + 3 * osz, osz, w.tK, w.tK2, w.split, w.padK, 1);
   k::kkt_combine(ctx->stream, osz, L.coef, w.z.get(), w.z.get() + 3 * osz, y);
 }
@@ -145,9 +158,9 @@ void local_matvec_f32(iga_ctx* ctx, const LocalOp& L, const float* x, float* y, 
   const int r0o = L.out0(), r1o = L.out1();
   const long osz = (long)r0o * L.n * r1o;
   w.fz.ensure(ctx, (size_t)5 * osz);
-  op_apply<float>(ctx, L.M, L.M.Af, L.Mblocks, L.fPhiL_M, L.fPhiR_M, r0o, L.r0, L.r1, r1o, 3, x, colsz,
+  op_apply<float>(ctx, L.M, L.M.Af, (const float*)nullptr, L.Mblocks, L.fPhiL_M, L.fPhiR_M, r0o, L.r0, L.r1, r1o, 3, x, colsz,
                   w.fz.get(), osz, w.ftM, w.ftM2, w.fsplit, w.fpadM, 0);
-  op_apply<float>(ctx, L.K, L.K.Af, L.Kblocks, L.fPhiL_K, L.fPhiR_K, r0o, L.r0, L.r1, r1o, 2, x, 2 * colsz,
+  op_apply<float>(ctx, L.K, L.K.Af, (const float*)nullptr, L.Kblocks, L.fPhiL_K, L.fPhiR_K, r0o, L.r0, L.r1, r1o, 2, x, 2 * colsz,
                   w.fz.get() + 3 * osz, osz, w.ftK, w.ftK2, w.fsplit, w.fpadK, 1);
   k::kkt_combine_f32(ctx->stream, osz, L.coef, w.fz.get(), w.fz.get() + 3 * osz, y);
 }
@@ -160,6 +173,7 @@ struct RawCache {
   int RM0 = -1, RM1 = -1, RK0 = -1, RK1 = -1;
   LocalWork w;
   FBuf fPhi[4], fM, fK, fx, fy;
+  DBuf rM, rK;  // cores re-laid for the banded stage
 };
 std::unordered_map<iga_ctx*, std::unique_ptr<RawCache>> g_raw;
 RawCache& raw_cache(iga_ctx* ctx) {
@@ -212,6 +226,14 @@ void local_matvec_impl(iga_ctx* ctx, int r0, int n, int r1, int p, int RM0, int 
   L.Mblocks = {RankBlock{0, RM0, 0, RM1}};
   L.Kblocks = {RankBlock{0, RK0, 0, RK1}};
   if (precision == IGA_FP64) {
+    // cores re-laid as [n][2p+1][R0][R1] for the banded stage
+    const int dimsM[4] = {RM0, n, 2 * p + 1, RM1}, dimsK[4] = {RK0, n, 2 * p + 1, RK1}, perm[4] = {1, 2, 0, 3};
+    C.rM.ensure(ctx, (size_t)RM0 * n * (2 * p + 1) * RM1);
+    C.rK.ensure(ctx, (size_t)RK0 * n * (2 * p + 1) * RK1);
+    k::permute4(ctx->stream, Mcore, dimsM, perm, C.rM.get());
+    k::permute4(ctx->stream, Kcore, dimsK, perm, C.rK.get());
+    L.M.Ar = C.rM.get();
+    L.K.Ar = C.rK.get();
     local_matvec(ctx, L, x, y, C.w);
     return;
   }
@@ -264,6 +286,7 @@ template <class T> struct GroupedOps;
 template <> struct GroupedOps<double> {
   using G = k::Gemm2;
   static int pick(const G& g) { return k::gemm2_pick(g); }
+  static int variants() { return k::gemm2_variants(); }
   static size_t bytes() { return k::gemm2_desc_bytes(); }
   static long prepare(const G& g, int v, void* h) { return k::gemm2_prepare(g, v, h); }
   static void launch(hipStream_t s, int v, const void* d, const int* pre, int n, long t) {
@@ -278,6 +301,7 @@ template <> struct GroupedOps<double> {
 template <> struct GroupedOps<float> {
   using G = k::Gemm2F;
   static int pick(const G& g) { return k::gemm2f_pick(g); }
+  static int variants() { return 5; }
   static size_t bytes() { return k::gemm2f_desc_bytes(); }
   static long prepare(const G& g, int v, void* h) { return k::gemm2f_prepare(g, v, h); }
   static void launch(hipStream_t s, int v, const void* d, const int* pre, int n, long t) {
@@ -426,7 +450,7 @@ void batched_run(iga_ctx* ctx, const std::vector<BatchProblem>& P, const std::ve
         if (C.tuned.count(kv.first)) continue;
         float best = 1e30f;
         int bestv = Ops::pick(*kv.second[0]);
-        for (int v = 0; v < k::gemm2_variants(); ++v) {
+        for (int v = 0; v < Ops::variants(); ++v) {
           std::vector<char> h;
           size_t doff, poff;
           long tiles;
