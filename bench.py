@@ -15,9 +15,9 @@ Printed JSON line:
              and the nonzero rank blocks) / their GPU time (HIP events on the
              library stream);
   solve_time_s, kkt_residual, per-part solve times, ranks;
-  mixed_vs_fp64  the same solve in the mixed form (FP32 local contractions inside FP64
-             iterative refinement) and in FP64, from one assembly: solve times,
-             residuals and the state difference;
+  mixed_vs_fp64  the same solve in the mixed forms (FP32 local contractions, or BF16
+             products with FP32 accumulation, inside FP64 iterative refinement) and in
+             FP64, from one assembly: solve times, residuals and the state differences;
   differentiation  times of the reduced cost, its desired-state gradient and its
              control-point gradient at the FP64 solution;
   batching   64 uneven local TT-matvecs, one call per problem versus one batched call;
@@ -46,6 +46,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 (matrix cores)
 PEAK_FP32_TFLOPS = 157.3  # MI355X dense FP32 (matrix cores)
+PEAK_BF16_TFLOPS = 2500.0  # MI355X dense BF16 (matrix cores)
 MICRO = dict(r=32, RM=10, RK=60, n=64, p=3)
 COPY_BYTES = 256 << 20
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "band_stage_K_c2shape_traffic.txt")
@@ -84,14 +85,15 @@ def traffic_from_profile():
 
 
 def mixed_compare(iga, ctx, torch, geo, c, Y, steps):
-    """The c2 solve in the mixed form (FP32 local contractions, FP64 refinement) and in FP64
-    from the same assembled operators: solve times, residuals, state difference."""
+    """The c2 solve in the mixed forms (FP32 local contractions or BF16 products, FP64
+    refinement) and in FP64 from the same assembled operators: solve times, residuals, state
+    differences."""
     n, p, beta = c["n"], c["degree"], c["beta"]
     M, K, _ = iga.assemble_factors(ctx, geo, p, n, weight_tol=c["weight_tol"])
     kk = iga.kkt_create(ctx, M, K, beta)
     out = {}
     fulls = {}
-    for name, prec in (("fp64", iga.FP64), ("mixed", iga.FP32)):
+    for name, prec in (("fp64", iga.FP64), ("mixed", iga.FP32), ("mixed_bf16", iga.BF16)):
         times, sts = [], []
         for i in range(steps + 1):  # the first solve is a warm-up
             torch.cuda.synchronize()
@@ -107,7 +109,7 @@ def mixed_compare(iga, ctx, torch, geo, c, Y, steps):
         last = sts[-1]
         d = {"solve_time_s": sum(times) / len(times), "kkt_residual": max(x["residual"] for x in sts),
              "half_sweeps": last["half_sweeps"], "ranks": last["ranks"], "local_iterations": last["local_iterations"]}
-        if prec == iga.FP32:
+        if prec != iga.FP64:
             d["refinements"] = last["refinements"]
             d["local_matvecs_fp32"] = last["local_matvecs_fp32"]
             d["local_matvec_gflops_fp32"] = (sum(x["local_matvec_flops_fp32"] for x in sts)
@@ -135,9 +137,11 @@ def mixed_compare(iga, ctx, torch, geo, c, Y, steps):
     iga.btt_destroy(sol)
     out["differentiation"] = grads
     import numpy as np
-    y64, y32 = fulls["fp64"][0], fulls["mixed"][0]
-    out["mixed"]["state_rel_diff_vs_fp64"] = float(np.linalg.norm(y32 - y64) / np.linalg.norm(y64))
-    out["mixed"]["speedup_vs_fp64"] = out["fp64"]["solve_time_s"] / out["mixed"]["solve_time_s"]
+    y64 = fulls["fp64"][0]
+    for name in ("mixed", "mixed_bf16"):
+        yl = fulls[name][0]
+        out[name]["state_rel_diff_vs_fp64"] = float(np.linalg.norm(yl - y64) / np.linalg.norm(y64))
+        out[name]["speedup_vs_fp64"] = out["fp64"]["solve_time_s"] / out[name]["solve_time_s"]
     iga.kkt_destroy(kk)
     iga.ttop_destroy(M)
     iga.ttop_destroy(K)
@@ -223,23 +227,25 @@ def micro_bench(iga, ctx, torch, iters):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / iters
     flops = iga.local_matvec_flops(s["r"], s["n"], s["r"], s["p"], s["RM"], s["RM"], s["RK"], s["RK"])
-    # the same product in the mixed form (operands converted to FP32 inside each call)
-    for _ in range(3):
-        iga.local_matvec(*args, iga.FP32)
-    torch.cuda.synchronize()
-    iga.profile_start(ctx)
-    e0.record(stream)
-    for _ in range(iters):
-        iga.local_matvec(*args, iga.FP32)
-    e1.record(stream)
-    prof32 = iga.profile_stop(ctx)
-    torch.cuda.synchronize()
-    ms32 = e0.elapsed_time(e1) / iters
-    return {"shape": dict(s), "ms": ms, "gflops": flops / ms / 1e6, "flops": flops, "profile": prof,
-            "fp32": {"ms": ms32, "gflops": flops / ms32 / 1e6,
-                     "band_K_tflops": prof32["flops"][3] / (prof32["ms"][3] * 1e-3) / 1e12 if prof32["ms"][3] else None,
-                     "band_K_frac_of_fp32_peak": (prof32["flops"][3] / (prof32["ms"][3] * 1e-3) / 1e12
-                                                  / PEAK_FP32_TFLOPS) if prof32["ms"][3] else None}}, prob
+    out = {"shape": dict(s), "ms": ms, "gflops": flops / ms / 1e6, "flops": flops, "profile": prof}
+    # the same product in the mixed forms (operands converted to FP32 inside each call; BF16
+    # rounds them once more as the products stage them)
+    for name, prec, slot, peak in (("fp32", iga.FP32, 3, PEAK_FP32_TFLOPS), ("bf16", iga.BF16, 5, PEAK_BF16_TFLOPS)):
+        for _ in range(3):
+            iga.local_matvec(*args, prec)
+        torch.cuda.synchronize()
+        iga.profile_start(ctx)
+        e0.record(stream)
+        for _ in range(iters):
+            iga.local_matvec(*args, prec)
+        e1.record(stream)
+        pr = iga.profile_stop(ctx)
+        torch.cuda.synchronize()
+        msl = e0.elapsed_time(e1) / iters
+        band = pr["flops"][slot] / (pr["ms"][slot] * 1e-3) / 1e12 if pr["ms"][slot] else None
+        out[name] = {"ms": msl, "gflops": flops / msl / 1e6, "band_K_tflops": band,
+                     "band_K_frac_of_%s_peak" % name: band / peak if band else None}
+    return out, prob
 
 
 def cpu_baseline(prob, budget_s=12.0, max_calls=400):
@@ -357,7 +363,7 @@ def main():
         "mixed_vs_fp64": {k: v for k, v in mixed.items() if k != "differentiation"},
         "differentiation": mixed["differentiation"],
         "batching": batching,
-        "microbench_local_matvec": {k: micro[k] for k in ("shape", "ms", "gflops", "flops", "fp32")},
+        "microbench_local_matvec": {k: micro[k] for k in ("shape", "ms", "gflops", "flops", "fp32", "bf16")},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
                      "kernel": "gemm2_kernel<8, 4, 2, 2, 16, 2, 2, true>: banded middle stage of the K operator in the "

@@ -51,6 +51,7 @@ extern "C" {
 
 #define IGA_FP64 0
 #define IGA_FP32 1
+#define IGA_BF16 2
 
 typedef struct iga_ctx iga_ctx;
 typedef struct iga_tt iga_tt;     /* TT vector, 3 cores on the device        */
@@ -90,8 +91,9 @@ typedef struct {
  * disable); local_tol: relative tolerance of each local solve (default tol/10);
  * local_maxit: maximum preconditioned GMRES iterations per local solve
  * (default 400); local_restart: GMRES restart length (default 40);
- * precision: IGA_FP64, or IGA_FP32 for the mixed form (local contractions in
- * FP32 inside an FP64 iterative refinement); init_rank: rank of the random
+ * precision: IGA_FP64, or IGA_FP32 / IGA_BF16 for the mixed form (local contractions
+ * in FP32, or with operands rounded to bfloat16 and FP32 accumulation, inside an FP64
+ * iterative refinement of each local solve); init_rank: rank of the random
  * initial guess when x0 is NULL (default 2); seed: its seed; verbose: print
  * one line per half-sweep to stderr. */
 typedef struct {
@@ -125,9 +127,10 @@ typedef struct {
   double t_interfaces;
   double t_svd;
   double t_residual;
-  /* mixed form (precision IGA_FP32): local matvecs with FP32 contractions inside the
-   * refinement's inner solves, their algorithmic flops and time, and refinement steps
-   * (each followed by an FP64 local residual); zero in the FP64 form */
+  /* mixed form (precision IGA_FP32 or IGA_BF16): local matvecs with low-precision
+   * contractions (FP32 or BF16 products, as chosen) inside the refinement's inner solves,
+   * their algorithmic flops and time, and refinement steps (each followed by an FP64 local
+   * residual); zero in the FP64 form */
   long long local_matvecs_fp32;
   double local_matvec_flops_fp32;
   double t_local_matvec_fp32;
@@ -220,7 +223,9 @@ int iga_amen_solve(iga_ctx* ctx, const iga_kkt* kkt, const iga_tt* yhat, double 
  * combined into y = [M x0 + K x2; beta M x1 - M x2; K x0 - M x1].
  * x, y: dev [3][r0][n][r1]; PhiL_*: dev [R_{d-1}][r0][r0]; PhiR_*: dev [R_d][r1][r1];
  * Mcore, Kcore: dev banded [R_{d-1}][n][2p+1][R_d] (dense in the rank indices).
- * precision: IGA_FP64 or IGA_FP32 (inputs are FP64; FP32 converts them first).
+ * precision: IGA_FP64, IGA_FP32 or IGA_BF16 (inputs are FP64; FP32 converts them to FP32
+ * first, BF16 likewise and then rounds every contraction operand to bfloat16, accumulating
+ * in FP32).
  * Enqueued on the context stream; returns immediately. */
 int iga_local_matvec(iga_ctx* ctx, int r0, int n, int r1, int degree, int RM0, int RM1, int RK0,
                      int RK1, const double* PhiL_M, const double* PhiR_M, const double* PhiL_K,
@@ -282,15 +287,16 @@ double iga_local_matvec_flops(int r0, int n, int r1, int degree, int RM0, int RM
  * measurement. Between iga_profile_start and iga_profile_stop every local matvec on the
  * context (inside iga_amen_solve or iga_local_matvec) records a HIP event pair on the
  * context stream around that stage, per operator and precision (index 0: M FP64, 1: K FP64,
- * 2: M FP32, 3: K FP32). stop synchronises the stream and returns: stages (banded stages
+ * 2: M FP32, 3: K FP32, 4: M BF16, 5: K BF16). stop synchronises the stream and returns:
+ * stages (banded stages
  * timed), launches (kernel launches inside them: one per nonzero rank block of the core),
  * ms (summed event time) and flops (algorithmic flops: banded nonzeros times nonzero rank
  * blocks). out may be NULL. Calls on one context must not overlap. */
 typedef struct {
-  long stages[4];
-  long launches[4];
-  double ms[4];
-  double flops[4];
+  long stages[6];
+  long launches[6];
+  double ms[6];
+  double flops[6];
 } iga_profile;
 int iga_profile_start(iga_ctx* ctx);
 int iga_profile_stop(iga_ctx* ctx, iga_profile* out);

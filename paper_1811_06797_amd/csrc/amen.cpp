@@ -115,7 +115,8 @@ class Amen {
     ry_[0] = 1; ry_[3] = 1;
     ry_[1] = Y->r[1]; ry_[2] = Y->r[2];
     rng_.seed(o.seed);
-    lowp_ = o.precision == IGA_FP32;
+    lowp_ = o.precision == IGA_FP32 || o.precision == IGA_BF16;
+    bf16_ = o.precision == IGA_BF16;
     // dense cores re-laid as [n][2p+1][R0][R1] once per solve: the banded stage of the
     // local matvec then contracts over one (R0, 2p+1) index instead of two nested ones
     for (int op = 0; op < 2; ++op)
@@ -220,6 +221,7 @@ class Amen {
   // mixed-precision form: FP32 operands of the current local operator; inside the
   // refinement's inner solve (lp_inner_) every local matvec contracts in FP32
   bool lowp_ = false, lp_inner_ = false;
+  bool bf16_ = false;  // inner products on BF16 matrix cores instead of FP32
   FBuf fcore_[2][3], fPL_[2], fPR_[2], fx_, fy_;
   DBuf rcore_[2][3];  // re-laid dense cores (null for block-structured ones)
   void lowp_operands(int d, LocalOp& L);
@@ -392,13 +394,13 @@ void Amen::rhs_local(int d, Frame left, Frame right, double* out) {
 void Amen::matvec(const LocalOp& L, const double* x, double* y) {
   g_phase = "matvec";
   if (lp_inner_) {
-    // FP32 contractions on FP32 copies of x; the Krylov vectors stay FP64
+    // FP32 (or BF16-product) contractions on FP32 copies of x; the Krylov vectors stay FP64
     const long N = L.size(), No = L.out_size();
     fx_.ensure(ctx_, N);
     fy_.ensure(ctx_, No);
     const int id = t_mv32_.begin();
     k::to_f32(st_, N, x, fx_.get());
-    local_matvec_f32(ctx_, L, fx_.get(), fy_.get(), lw_);
+    local_matvec_f32(ctx_, L, fx_.get(), fy_.get(), lw_, bf16_);
     k::to_f64(st_, No, fy_.get(), y);
     t_mv32_.end(id);
     ++n_mv32_;
@@ -430,18 +432,21 @@ void Amen::lowp_operands(int d, LocalOp& L) {
 
 // Mixed-precision local solve by iterative refinement: the FP64 residual r = b - A x (in
 // tmp_ on entry, relative norm res0) is reduced by an inner FGMRES whose matvecs contract
-// in FP32, the correction is added in FP64, and the FP64 residual is recomputed, until it
-// is <= ltol. The inner solve asks for what FP32 contractions can deliver (relative 2e-5)
-// or the remaining factor, whichever is larger. Returns the inner iterations.
+// in FP32 (or on BF16 products), the correction is added in FP64, and the FP64 residual is
+// recomputed, until it is <= ltol. The inner solve asks for what the low-precision operator
+// can deliver (relative 2e-5 for FP32; 1e-2 for BF16, whose operands carry a relative
+// rounding of 2^-9 per stage) or the remaining factor, whichever is larger. Returns the
+// inner iterations.
 int Amen::refine_solve(int d, const LocalOp& L, double bn, double ltol, double res0) {
   const long N = L.size();
   DBuf e(ctx_, N), r(ctx_, N);
   double res = res0;
   int its = 0;
   IGA_HIP(hipMemcpyAsync(r.get(), tmp_.get(), N * sizeof(double), hipMemcpyDeviceToDevice, st_));
+  const double floor = bf16_ ? 1e-2 : 2e-5;
   for (int ref = 0; ref < 20 && res > ltol; ++ref) {
     const double rn = res * bn;
-    const double inner = std::max(ltol / res, 2e-5);
+    const double inner = std::max(ltol / res, floor);
     k::fill(st_, N, 0.0, e.get());
     lp_inner_ = true;
     its += fgmres(L, r.get(), e.get(), rn, inner * rn);
@@ -1145,7 +1150,8 @@ int amen_impl(iga_ctx* ctx, const iga_kkt* kkt, const iga_tt* yhat, double tol, 
   if (o.local_maxit <= 0) o.local_maxit = 400;
   if (o.local_restart <= 0) o.local_restart = 40;
   if (o.init_rank <= 0) o.init_rank = 2;
-  require(o.precision == IGA_FP64 || o.precision == IGA_FP32, IGA_EINVAL, "amen_solve: bad precision");
+  require(o.precision == IGA_FP64 || o.precision == IGA_FP32 || o.precision == IGA_BF16, IGA_EINVAL,
+          "amen_solve: bad precision");
   Amen a(ctx, kkt, yhat, tol, o);
   return a.run(x0, sol, stats);
 }

@@ -526,7 +526,8 @@ int iga_local_matvec(iga_ctx* ctx, int r0, int n, int r1, int degree, int RM0, i
             "local_matvec: NULL argument");
     require(r0 >= 1 && r1 >= 1 && n >= 1 && degree >= 0 && RM0 >= 1 && RM1 >= 1 && RK0 >= 1 && RK1 >= 1,
             IGA_EINVAL, "local_matvec: sizes must be positive");
-    require(precision == IGA_FP64 || precision == IGA_FP32, IGA_EINVAL, "local_matvec: bad precision");
+    require(precision == IGA_FP64 || precision == IGA_FP32 || precision == IGA_BF16, IGA_EINVAL,
+            "local_matvec: bad precision");
     use_device(ctx);
     local_matvec_impl(ctx, r0, n, r1, degree, RM0, RM1, RK0, RK1, PhiL_M, PhiR_M, PhiL_K, PhiR_K, Mcore,
                       Kcore, beta, x, y, precision);

@@ -63,7 +63,7 @@ struct iga_ctx {
   // optional event timing of the banded stage of the local matvec (iga_profile_*)
   struct ProfRec {
     hipEvent_t a, b;
-    int op;  // 0: M, 1: K
+    int op;  // 0: M, 1: K (FP64); 2, 3: FP32; 4, 5: BF16 products
     int launches;
     double flops;
   };

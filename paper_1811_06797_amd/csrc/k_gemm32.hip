@@ -1,14 +1,18 @@
-// FP32 batched GEMM on the CDNA4 matrix cores, with the two-level index maps of gemm2
-// (k_gemm.hip): the contractions of the mixed-precision local operator.
+// FP32-storage batched GEMMs on the CDNA4 matrix cores, with the two-level index maps of
+// gemm2 (k_gemm.hip): the contractions of the mixed-precision local operator.
 //
-// C[b][m][n] = alpha * sum_k A[b][m][k] B[b][k][n] + beta * C[b][m][n], FP32 inputs and
-// FP32 accumulation. Each wave owns a (16 WM) x (16 WN) block of C and issues
-// v_mfma_f32_16x16x4f32 (one 16x16x4 product, 2048 flops). Operand lane layout
-// (lane l = 16 q + t, q = l / 16, t = l % 16):
-//   A[t][q] and B[q][t] (K = 4 per instruction); C[4 q + v][t], v = 0..3 in the four
-//   accumulator registers.
-// Four waves form the workgroup tile; K is staged through LDS 16 deep, double-buffered,
-// with the next tile's global loads in flight during the current tile's products.
+// C[b][m][n] = alpha * sum_k A[b][m][k] B[b][k][n] + beta * C[b][m][n] with FP32 operands in
+// memory and FP32 accumulation, in one of two product precisions:
+//  * FP32: v_mfma_f32_16x16x4f32 (one 16x16x4 product, 2048 flops). Lane layout (lane
+//    l = 16 q + t, q = l / 16, t = l % 16): A[t][q] and B[q][t]; C[4 q + v][t], v = 0..3.
+//  * BF16: operands are rounded to bfloat16 (nearest, ties to even) as they are staged into
+//    LDS, and v_mfma_f32_16x16x32_bf16 (16x16x32, 16384 flops) multiplies them. Lane
+//    layout: A[t][8 q + e] and B[8 q + e][t], e = 0..7 in one 16-byte register quadruple;
+//    C as above. LDS holds the tiles in groups of 8 consecutive k per row, so that each
+//    operand is one 16-byte LDS read.
+// Each wave owns a (16 WM) x (16 WN) block of C; four waves form the workgroup tile; K is
+// staged through LDS (16 deep in FP32, 32 in BF16), double-buffered, with the next tile's
+// global loads in flight during the current tile's products.
 #include <algorithm>
 #include <cstring>
 
@@ -19,9 +23,10 @@ namespace iga {
 namespace k {
 namespace {
 
-constexpr int NT = 256, BKF = 16;
+constexpr int NT = 256, BKF = 16, BKH = 32;
 
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef short s8 __attribute__((ext_vector_type(8)));
 
 __device__ const float kZeroF[1] = {0.0f};
 
@@ -45,24 +50,38 @@ __device__ __forceinline__ long off2f(int idx, int inner, long s_outer, long s_i
   return (long)o * s_outer + (long)(idx - o * inner) * s_inner;
 }
 
+// Nearest bfloat16 of a finite float, ties to even: the upper 16 bits after adding half an
+// ulp of the result (less one when the result's last bit is 0).
+__device__ __forceinline__ short to_bf16(float x) {
+  const unsigned u = __float_as_uint(x);
+  return (short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
 // Row pitch (floats) of the LDS tiles: 16 mod 64, so the four k rows one MFMA operand read
 // touches start 16 banks apart.
 constexpr int lds_padf(int w) { return ((16 - w % 64) + 64) % 64; }
 
-template <int BM, int BN>
+template <int BM, int BN, bool BF>
 struct TileLdsF {
   float As[2][BKF][BM + lds_padf(BM)];
   float Bs[2][BKF][BN + lds_padf(BN)];
 };
+// BF16 tiles: [buffer][k / 8][row][k % 8], one spare row per k group
+template <int BM, int BN>
+struct TileLdsF<BM, BN, true> {
+  alignas(16) short As[2][BKH / 8][BM + 1][8];
+  alignas(16) short Bs[2][BKH / 8][BN + 1][8];
+};
 
 // One BM x BN output tile (column tile bx, row tile by, batch and split index bz).
-template <int WM, int WN, int WAVES_M, int WAVES_N>
+template <int WM, int WN, int WAVES_M, int WAVES_N, bool BF>
 __device__ __forceinline__ void gemm2f_tile(const G2FArgs& g, int bx, int by, int bz,
-                                            TileLdsF<16 * WM * WAVES_M, 16 * WN * WAVES_N>& L) {
+                                            TileLdsF<16 * WM * WAVES_M, 16 * WN * WAVES_N, BF>& L) {
   constexpr int BM = 16 * WM * WAVES_M, BN = 16 * WN * WAVES_N;
-  constexpr int LA = BM * BKF / NT, LB = BN * BKF / NT;
+  constexpr int BK = BF ? BKH : BKF;
+  constexpr int LA = BM * BK / NT, LB = BN * BK / NT;
   static_assert(WAVES_M * WAVES_N == 4, "four waves");
-  static_assert(LA >= 1 && LB >= 1, "tile too small");
+  static_assert(LA >= 1 && LB >= 1 && LA * NT == BM * BK && LB * NT == BN * BK, "tile does not split evenly");
   auto& As = L.As;
   auto& Bs = L.Bs;
   const int split = bz / g.nbatch, bb = bz - split * g.nbatch;
@@ -76,7 +95,7 @@ __device__ __forceinline__ void gemm2f_tile(const G2FArgs& g, int bx, int by, in
 
   const bool a_kfast = (g.sAk2 == 1 && g.K2 > 1) || (g.K2 == 1 && g.sAk1 == 1);
   const bool b_nfast = (g.sBn2 == 1 && g.N2 > 1) || (g.N2 == 1 && g.sBn1 == 1);
-  const int kq = BKF / g.K2, krem = BKF - kq * g.K2;
+  const int kq = BK / g.K2, krem = BK - kq * g.K2;
   const int dA = kq * (int)g.sAk1 + krem * (int)g.sAk2, dAw = dA + (int)g.sAk1 - g.K2 * (int)g.sAk2;
   const int dB = kq * (int)g.sBk1 + krem * (int)g.sBk2, dBw = dB + (int)g.sBk1 - g.K2 * (int)g.sBk2;
   int a_mm[LA], a_kk[LA], b_nn[LB], b_kk[LB], ak2[LA], bk2[LB], oa[LA], ob[LB];
@@ -84,7 +103,7 @@ __device__ __forceinline__ void gemm2f_tile(const G2FArgs& g, int bx, int by, in
 #pragma unroll
   for (int s = 0; s < LA; ++s) {
     const int e = tid + NT * s;
-    if (a_kfast) { a_kk[s] = e % BKF; a_mm[s] = e / BKF; } else { a_mm[s] = e % BM; a_kk[s] = e / BM; }
+    if (a_kfast) { a_kk[s] = e % BK; a_mm[s] = e / BK; } else { a_mm[s] = e % BM; a_kk[s] = e / BM; }
     const int m = m0 + a_mm[s];
     a_ok[s] = m < g.M;
     const int k = kbeg + a_kk[s], k1 = k / g.K2;
@@ -94,7 +113,7 @@ __device__ __forceinline__ void gemm2f_tile(const G2FArgs& g, int bx, int by, in
 #pragma unroll
   for (int s = 0; s < LB; ++s) {
     const int e = tid + NT * s;
-    if (b_nfast) { b_nn[s] = e % BN; b_kk[s] = e / BN; } else { b_kk[s] = e % BKF; b_nn[s] = e / BKF; }
+    if (b_nfast) { b_nn[s] = e % BN; b_kk[s] = e / BN; } else { b_kk[s] = e % BK; b_nn[s] = e / BK; }
     const int n = n0 + b_nn[s];
     b_ok[s] = n < g.N;
     const int k = kbeg + b_kk[s], k1 = k / g.K2;
@@ -134,13 +153,20 @@ __device__ __forceinline__ void gemm2f_tile(const G2FArgs& g, int bx, int by, in
     }
   };
   auto store_tile = [&](int buf) {
+    if constexpr (BF) {
 #pragma unroll
-    for (int s = 0; s < LA; ++s) As[buf][a_kk[s]][a_mm[s]] = ra[s];
+      for (int s = 0; s < LA; ++s) As[buf][a_kk[s] >> 3][a_mm[s]][a_kk[s] & 7] = to_bf16(ra[s]);
 #pragma unroll
-    for (int s = 0; s < LB; ++s) Bs[buf][b_kk[s]][b_nn[s]] = rb[s];
+      for (int s = 0; s < LB; ++s) Bs[buf][b_kk[s] >> 3][b_nn[s]][b_kk[s] & 7] = to_bf16(rb[s]);
+    } else {
+#pragma unroll
+      for (int s = 0; s < LA; ++s) As[buf][a_kk[s]][a_mm[s]] = ra[s];
+#pragma unroll
+      for (int s = 0; s < LB; ++s) Bs[buf][b_kk[s]][b_nn[s]] = rb[s];
+    }
   };
 
-  const int nkt = (kend - kbeg + BKF - 1) / BKF;
+  const int nkt = (kend - kbeg + BK - 1) / BK;
   if (nkt > 0) {
     load_tile(kbeg);
     store_tile(0);
@@ -148,19 +174,33 @@ __device__ __forceinline__ void gemm2f_tile(const G2FArgs& g, int bx, int by, in
   __syncthreads();
   for (int t = 0; t < nkt; ++t) {
     const int cur = t & 1;
-    if (t + 1 < nkt) load_tile(kbeg + (t + 1) * BKF);
+    if (t + 1 < nkt) load_tile(kbeg + (t + 1) * BK);
+    if constexpr (BF) {
+      // one 16x16x32 product per block: this lane's k group is lq
+      s8 fa[WM], fb[WN];
 #pragma unroll
-    for (int ks = 0; ks < BKF; ks += 4) {
-      float fa[WM], fb[WN];
+      for (int r = 0; r < WM; ++r) fa[r] = *reinterpret_cast<const s8*>(&As[cur][lq][wm0 + 16 * r + lt][0]);
 #pragma unroll
-      for (int r = 0; r < WM; ++r) fa[r] = As[cur][ks + lq][wm0 + 16 * r + lt];
-#pragma unroll
-      for (int c = 0; c < WN; ++c) fb[c] = Bs[cur][ks + lq][wn0 + 16 * c + lt];
+      for (int c = 0; c < WN; ++c) fb[c] = *reinterpret_cast<const s8*>(&Bs[cur][lq][wn0 + 16 * c + lt][0]);
 #pragma unroll
       for (int r = 0; r < WM; ++r)
 #pragma unroll
         for (int c = 0; c < WN; ++c)
-          acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[r], fb[c], acc[r][c], 0, 0, 0);
+          acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[r], fb[c], acc[r][c], 0, 0, 0);
+    } else {
+#pragma unroll
+      for (int ks = 0; ks < BK; ks += 4) {
+        float fa[WM], fb[WN];
+#pragma unroll
+        for (int r = 0; r < WM; ++r) fa[r] = As[cur][ks + lq][wm0 + 16 * r + lt];
+#pragma unroll
+        for (int c = 0; c < WN; ++c) fb[c] = Bs[cur][ks + lq][wn0 + 16 * c + lt];
+#pragma unroll
+        for (int r = 0; r < WM; ++r)
+#pragma unroll
+          for (int c = 0; c < WN; ++c)
+            acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[r], fb[c], acc[r][c], 0, 0, 0);
+      }
     }
     if (t + 1 < nkt) store_tile(cur ^ 1);
     __syncthreads();
@@ -202,16 +242,16 @@ __device__ __forceinline__ void gemm2f_tile(const G2FArgs& g, int bx, int by, in
     }
 }
 
-template <int WM, int WN, int WAVES_M, int WAVES_N>
+template <int WM, int WN, int WAVES_M, int WAVES_N, bool BF>
 __global__ __launch_bounds__(NT) void gemm2f_kernel(G2FArgs g) {
-  __shared__ TileLdsF<16 * WM * WAVES_M, 16 * WN * WAVES_N> L;
+  __shared__ TileLdsF<16 * WM * WAVES_M, 16 * WN * WAVES_N, BF> L;
   // XCD-contiguous renumbering of the workgroups (as in gemm2)
   const int gx = gridDim.x, gy = gridDim.y;
   const int total = gx * gy * gridDim.z;
   const int lin = (blockIdx.z * gy + blockIdx.y) * gx + blockIdx.x;
   const int xcd = lin % 8, q8 = lin / 8, base = total / 8, rem = total % 8;
   const int tile = (xcd < rem ? xcd * (base + 1) : rem * (base + 1) + (xcd - rem) * base) + q8;
-  gemm2f_tile<WM, WN, WAVES_M, WAVES_N>(g, tile % gx, (tile / gx) % gy, tile / (gx * gy), L);
+  gemm2f_tile<WM, WN, WAVES_M, WAVES_N, BF>(g, tile % gx, (tile / gx) % gy, tile / (gx * gy), L);
 }
 
 // Persistent grouped form (see gemm2_grouped_kernel).
@@ -219,7 +259,7 @@ template <int WM, int WN, int WAVES_M, int WAVES_N>
 __global__ __launch_bounds__(NT) void gemm2f_grouped_kernel(const G2FArgs* gs, const int* prefix, int ngemm,
                                                             int total) {
   constexpr int BM = 16 * WM * WAVES_M, BN = 16 * WN * WAVES_N;
-  __shared__ TileLdsF<BM, BN> L;
+  __shared__ TileLdsF<BM, BN, false> L;
   for (int t = blockIdx.x; t < total; t += gridDim.x) {
     int lo = 0, hi = ngemm;
     while (hi - lo > 1) {
@@ -230,7 +270,7 @@ __global__ __launch_bounds__(NT) void gemm2f_grouped_kernel(const G2FArgs* gs, c
     const int local = t - prefix[lo];
     const int gx = (g.N + BN - 1) / BN, gy = (g.M + BM - 1) / BM;
     __syncthreads();
-    gemm2f_tile<WM, WN, WAVES_M, WAVES_N>(g, local % gx, (local / gx) % gy, local / (gx * gy), L);
+    gemm2f_tile<WM, WN, WAVES_M, WAVES_N, false>(g, local % gx, (local / gx) % gy, local / (gx * gy), L);
   }
 }
 
@@ -252,11 +292,14 @@ __global__ __launch_bounds__(256) void splitk_reduce_f(G2FArgs g) {
 }
 
 template <int WM, int WN, int WAVES_M, int WAVES_N>
-void launchf(hipStream_t s, G2FArgs a, int nbatch) {
+void launchf(hipStream_t s, G2FArgs a, int nbatch, bool bf16) {
   constexpr int BM = 16 * WM * WAVES_M, BN = 16 * WN * WAVES_N;
   dim3 grid((a.N + BN - 1) / BN, (a.M + BM - 1) / BM, (unsigned)(nbatch * a.ksplit));
   require((long)grid.x * grid.y * grid.z < (1L << 31), IGA_EINVAL, "gemm2_f32: grid too large");
-  gemm2f_kernel<WM, WN, WAVES_M, WAVES_N><<<grid, NT, 0, s>>>(a);
+  if (bf16)
+    gemm2f_kernel<WM, WN, WAVES_M, WAVES_N, true><<<grid, NT, 0, s>>>(a);
+  else
+    gemm2f_kernel<WM, WN, WAVES_M, WAVES_N, false><<<grid, NT, 0, s>>>(a);
 }
 
 long spanf(int ext, int inner, long s1, long s2) {
@@ -332,7 +375,7 @@ void gemm2f_grouped(hipStream_t s, int variant, const void* dev_desc, const int*
   IGA_HIP(hipGetLastError());
 }
 
-void gemm2_f32(hipStream_t s, const Gemm2F& d, float* work, size_t work_len) {
+static void gemm2_fstore(hipStream_t s, const Gemm2F& d, float* work, size_t work_len, bool bf16) {
   if (d.M <= 0 || d.N <= 0 || d.nb1 <= 0 || d.nb2 <= 0) return;
   G2FArgs a = make_args_f(d);
   const long nb = a.nbatch;
@@ -344,18 +387,19 @@ void gemm2_f32(hipStream_t s, const Gemm2F& d, float* work, size_t work_len) {
     int ks = (int)std::min<long>((512 + tiles - 1) / tiles, d.K / 64);
     while (ks > 1 && (size_t)ks * nb * d.M * d.N > work_len) --ks;
     if (ks > 1) {
-      a.kchunk = ((d.K + ks - 1) / ks + BKF - 1) / BKF * BKF;
+      const int bk = bf16 ? BKH : BKF;
+      a.kchunk = ((d.K + ks - 1) / ks + bk - 1) / bk * bk;
       a.ksplit = (d.K + a.kchunk - 1) / a.kchunk;
       a.work = work;
     }
   }
   require((long)nb * a.ksplit <= 65535, IGA_EINVAL, "gemm2_f32: batch too large");
   switch (variant) {
-    case 2: launchf<1, 4, 1, 4>(s, a, (int)nb); break;
-    case 1: launchf<2, 2, 1, 4>(s, a, (int)nb); break;
-    case 3: launchf<2, 2, 4, 1>(s, a, (int)nb); break;
-    case 4: launchf<2, 4, 2, 2>(s, a, (int)nb); break;
-    default: launchf<2, 2, 2, 2>(s, a, (int)nb); break;
+    case 2: launchf<1, 4, 1, 4>(s, a, (int)nb, bf16); break;
+    case 1: launchf<2, 2, 1, 4>(s, a, (int)nb, bf16); break;
+    case 3: launchf<2, 2, 4, 1>(s, a, (int)nb, bf16); break;
+    case 4: launchf<2, 4, 2, 2>(s, a, (int)nb, bf16); break;
+    default: launchf<2, 2, 2, 2>(s, a, (int)nb, bf16); break;
   }
   IGA_HIP(hipGetLastError());
   if (a.ksplit > 1) {
@@ -363,6 +407,14 @@ void gemm2_f32(hipStream_t s, const Gemm2F& d, float* work, size_t work_len) {
     splitk_reduce_f<<<(unsigned)std::min<long>((total + 255) / 256, 4096), 256, 0, s>>>(a);
     IGA_HIP(hipGetLastError());
   }
+}
+
+void gemm2_f32(hipStream_t s, const Gemm2F& d, float* work, size_t work_len) {
+  gemm2_fstore(s, d, work, work_len, false);
+}
+
+void gemm2_bf16(hipStream_t s, const Gemm2F& d, float* work, size_t work_len) {
+  gemm2_fstore(s, d, work, work_len, true);
 }
 
 }  // namespace k

@@ -70,6 +70,8 @@ struct Gemm2F {
   float alpha = 1.0f, beta = 0.0f;
 };
 void gemm2_f32(hipStream_t s, const Gemm2F& g, float* work, size_t work_len);
+// same products with the operands rounded to bfloat16 and BF16 matrix-core products (FP32 accumulation)
+void gemm2_bf16(hipStream_t s, const Gemm2F& g, float* work, size_t work_len);
 // grouped FP32 form, as gemm2_prepare / gemm2_grouped
 int gemm2f_pick(const Gemm2F& g);
 size_t gemm2f_desc_bytes();

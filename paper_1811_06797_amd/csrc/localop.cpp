@@ -47,13 +47,19 @@ double local_flops(const LocalOp& L) {
 template <class T> struct Prec;
 template <> struct Prec<double> {
   using G = k::Gemm2;
-  static void gemm(hipStream_t s, const G& g, double* w, size_t n) { k::gemm2(s, g, w, n); }
+  static void gemm(hipStream_t s, const G& g, double* w, size_t n, bool) { k::gemm2(s, g, w, n); }
   static void zero(hipStream_t s, long n, double* y) { k::fill(s, n, 0.0, y); }
   static constexpr int prof_base = 0;
 };
 template <> struct Prec<float> {
   using G = k::Gemm2F;
-  static void gemm(hipStream_t s, const G& g, float* w, size_t n) { k::gemm2_f32(s, g, w, n); }
+  // FP32 storage; products in FP32 or, with bf16, on BF16 matrix cores
+  static void gemm(hipStream_t s, const G& g, float* w, size_t n, bool bf16) {
+    if (bf16)
+      k::gemm2_bf16(s, g, w, n);
+    else
+      k::gemm2_f32(s, g, w, n);
+  }
   static void zero(hipStream_t s, long n, float* y) { k::fill_f32(s, n, 0.0f, y); }
   static constexpr int prof_base = 2;
 };
@@ -67,7 +73,7 @@ template <class T>
 static void op_apply(iga_ctx* ctx, const OpView& A, const T* core, const T* relaid, const std::vector<RankBlock>& blocks,
                      const T* PhiL, const T* PhiR, int r0o, int r0, int r1, int r1o, int ncol, const T* x,
                      long xcs, T* z, long zcs, DevBuf<T>& t1, DevBuf<T>& t2, DevBuf<T>& wk,
-                     LocalWork::PadKey& pad, int op_id) {
+                     LocalWork::PadKey& pad, int op_id, bool bf16 = false) {
   using G = typename Prec<T>::G;
   hipStream_t st = ctx->stream;
   const int n = A.n, p = A.p, b = 2 * p + 1, R0 = A.R0, R1 = A.R1;
@@ -89,7 +95,7 @@ static void op_apply(iga_ctx* ctx, const OpView& A, const T* core, const T* rela
   g1.B = x; g1.sBk2 = (long)n * r1; g1.sBn1 = r1; g1.sBn2 = 1;
   g1.C = t1.get() + p * SJ; g1.M2 = r0o; g1.sCm1 = S1; g1.sCm2 = r1; g1.sCn1 = SJ; g1.sCn2 = 1;
   g1.nb1 = ncol; g1.sBb1 = xcs; g1.sCb1 = S2;
-  Prec<T>::gemm(st, g1, nullptr, 0);
+  Prec<T>::gemm(st, g1, nullptr, 0, bf16);
   // stage 2: per rank block, batched over rows i
   hipEvent_t pa = nullptr, pb = nullptr;
   if (ctx->prof_on) {
@@ -107,7 +113,7 @@ static void op_apply(iga_ctx* ctx, const OpView& A, const T* core, const T* rela
     g2.B = t1.get(); g2.sBk2 = S1; g2.sBn2 = 1;
     g2.C = t2.get(); g2.sCm2 = S1; g2.sCn2 = 1;
     g2.nb1 = n; g2.sAb1 = (long)b * R0 * R1; g2.sBb1 = SJ; g2.sCb1 = (long)R1 * S1;
-    Prec<T>::gemm(st, g2, nullptr, 0);
+    Prec<T>::gemm(st, g2, nullptr, 0, bf16);
   } else {
     for (const RankBlock& rb : blocks) {
       G g2;
@@ -117,14 +123,14 @@ static void op_apply(iga_ctx* ctx, const OpView& A, const T* core, const T* rela
       g2.B = t1.get() + rb.a0 * S1; g2.sBk1 = SJ; g2.sBk2 = S1; g2.sBn2 = 1;
       g2.C = t2.get() + rb.b0 * S1; g2.sCm2 = S1; g2.sCn2 = 1;
       g2.nb1 = n; g2.sAb1 = (long)b * R1; g2.sBb1 = SJ; g2.sCb1 = (long)R1 * S1;
-      Prec<T>::gemm(st, g2, nullptr, 0);
+      Prec<T>::gemm(st, g2, nullptr, 0, bf16);
     }
   }
   if (ctx->prof_on) {
     IGA_HIP(hipEventRecord(pb, st));
     double nz = 0;
     for (const RankBlock& rb : blocks) nz += (double)rb.na * rb.nb;
-    ctx->prof.push_back({pa, pb, Prec<T>::prof_base + op_id, (int)blocks.size(),
+    ctx->prof.push_back({pa, pb, Prec<T>::prof_base + (bf16 ? 2 : 0) + op_id, (int)blocks.size(),
                          2.0 * r0o * r1 * ncol * nz * band_nnz(n, p)});
   }
   // stage 3: z[c][(a' i)][b'] = sum_{(g, b)} t2[i][g][c][a'][b] PhiR[g][b'][b]
@@ -136,7 +142,7 @@ static void op_apply(iga_ctx* ctx, const OpView& A, const T* core, const T* rela
   g3.nb1 = ncol; g3.sAb1 = S2; g3.sCb1 = zcs;
   const size_t wlen = (size_t)16 * ncol * r0o * n * r1o;
   wk.ensure(ctx, wlen);
-  Prec<T>::gemm(st, g3, wk.get(), wlen);
+  Prec<T>::gemm(st, g3, wk.get(), wlen, bf16);
 }
 
 void local_matvec(iga_ctx* ctx, const LocalOp& L, const double* x, double* y, LocalWork& w) {
@@ -151,7 +157,7 @@ void local_matvec(iga_ctx* ctx, const LocalOp& L, const double* x, double* y, Lo
   k::kkt_combine(ctx->stream, osz, L.coef, w.z.get(), w.z.get() + 3 * osz, y);
 }
 
-void local_matvec_f32(iga_ctx* ctx, const LocalOp& L, const float* x, float* y, LocalWork& w) {
+void local_matvec_f32(iga_ctx* ctx, const LocalOp& L, const float* x, float* y, LocalWork& w, bool bf16) {
   require(L.M.Af && L.K.Af && L.fPhiL_M && L.fPhiR_M && L.fPhiL_K && L.fPhiR_K, IGA_EINVAL,
           "local_matvec_f32: FP32 operands missing");
   const long colsz = (long)L.r0 * L.n * L.r1;
@@ -159,9 +165,9 @@ void local_matvec_f32(iga_ctx* ctx, const LocalOp& L, const float* x, float* y, 
   const long osz = (long)r0o * L.n * r1o;
   w.fz.ensure(ctx, (size_t)5 * osz);
   op_apply<float>(ctx, L.M, L.M.Af, (const float*)nullptr, L.Mblocks, L.fPhiL_M, L.fPhiR_M, r0o, L.r0, L.r1, r1o, 3, x, colsz,
-                  w.fz.get(), osz, w.ftM, w.ftM2, w.fsplit, w.fpadM, 0);
+                  w.fz.get(), osz, w.ftM, w.ftM2, w.fsplit, w.fpadM, 0, bf16);
   op_apply<float>(ctx, L.K, L.K.Af, (const float*)nullptr, L.Kblocks, L.fPhiL_K, L.fPhiR_K, r0o, L.r0, L.r1, r1o, 2, x, 2 * colsz,
-                  w.fz.get() + 3 * osz, osz, w.ftK, w.ftK2, w.fsplit, w.fpadK, 1);
+                  w.fz.get() + 3 * osz, osz, w.ftK, w.ftK2, w.fsplit, w.fpadK, 1, bf16);
   k::kkt_combine_f32(ctx->stream, osz, L.coef, w.fz.get(), w.fz.get() + 3 * osz, y);
 }
 
@@ -237,7 +243,8 @@ void local_matvec_impl(iga_ctx* ctx, int r0, int n, int r1, int p, int RM0, int 
     local_matvec(ctx, L, x, y, C.w);
     return;
   }
-  // FP32: convert every operand, contract in FP32, convert the result back
+  // FP32 / BF16: convert every operand to FP32, contract (BF16 products round the operands
+  // once more as they are staged), convert the result back
   hipStream_t st = ctx->stream;
   const int b = 2 * p + 1;
   const long szs[4] = {(long)RM0 * r0 * r0, (long)RM1 * r1 * r1, (long)RK0 * r0 * r0, (long)RK1 * r1 * r1};
@@ -254,7 +261,7 @@ void local_matvec_impl(iga_ctx* ctx, int r0, int n, int r1, int p, int RM0, int 
   L.M.Af = C.fM.get(); L.K.Af = C.fK.get();
   L.fPhiL_M = C.fPhi[0].get(); L.fPhiR_M = C.fPhi[1].get();
   L.fPhiL_K = C.fPhi[2].get(); L.fPhiR_K = C.fPhi[3].get();
-  local_matvec_f32(ctx, L, C.fx.get(), C.fy.get(), C.w);
+  local_matvec_f32(ctx, L, C.fx.get(), C.fy.get(), C.w, precision == IGA_BF16);
   k::to_f64(st, xz, C.fy.get(), y);
 }
 

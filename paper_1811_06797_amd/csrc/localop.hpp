@@ -43,8 +43,9 @@ struct LocalWork {
 
 // y = A_loc x (FP64); x: [3][r0][n][r1], y: [3][r0o][n][r1o]
 void local_matvec(iga_ctx* ctx, const LocalOp& L, const double* x, double* y, LocalWork& w);
-// Same product with every contraction in FP32 (x, y FP32); needs the f* fields and Af views.
-void local_matvec_f32(iga_ctx* ctx, const LocalOp& L, const float* x, float* y, LocalWork& w);
+// Same product on FP32 operands (x, y FP32; needs the f* fields and Af views), every
+// contraction in FP32 or, with bf16, with its operands rounded to bfloat16 and FP32 accumulation.
+void local_matvec_f32(iga_ctx* ctx, const LocalOp& L, const float* x, float* y, LocalWork& w, bool bf16 = false);
 // One independent problem of the batched form (dense rank blocks, square interfaces).
 struct BatchProblem {
   int r0, n, r1, p, RM0, RM1, RK0, RK1;

@@ -21,7 +21,7 @@ if not os.path.exists(LIB_PATH):
 lib = C.CDLL(LIB_PATH)
 
 OK, EINVAL, ENOMEM, EHIP, EGEOM, ENOCONV, ERANK = 0, -1, -2, -3, -4, -5, -6
-FP64, FP32 = 0, 1
+FP64, FP32, BF16 = 0, 1, 2
 _NAMES = {EINVAL: "IGA_EINVAL", ENOMEM: "IGA_ENOMEM", EHIP: "IGA_EHIP", EGEOM: "IGA_EGEOM",
           ENOCONV: "IGA_ENOCONV", ERANK: "IGA_ERANK"}
 
@@ -83,8 +83,8 @@ class LocalProblem(C.Structure):
 
 
 class Profile(C.Structure):
-    _fields_ = [("stages", C.c_long * 4), ("launches", C.c_long * 4), ("ms", C.c_double * 4),
-                ("flops", C.c_double * 4)]
+    _fields_ = [("stages", C.c_long * 6), ("launches", C.c_long * 6), ("ms", C.c_double * 6),
+                ("flops", C.c_double * 6)]
 
     def as_dict(self):
         return {name: list(getattr(self, name)) for name, _ in self._fields_}
@@ -331,8 +331,8 @@ def profile_start(ctx):
 
 
 def profile_stop(ctx) -> dict:
-    """Per operator and precision (0: M FP64, 1: K FP64, 2: M FP32, 3: K FP32): banded stages
-    timed, kernel launches, summed ms, flops."""
+    """Per operator and precision (0: M FP64, 1: K FP64, 2: M FP32, 3: K FP32, 4: M BF16,
+    5: K BF16): banded stages timed, kernel launches, summed ms, flops."""
     out = Profile()
     _check(lib.iga_profile_stop(ctx, C.byref(out)))
     return out.as_dict()

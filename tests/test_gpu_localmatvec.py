@@ -69,6 +69,72 @@ def test_local_matvec_benchmark_shape(gpu_ctx):
     assert rel_err(yf, ref) < FP32_TOL
 
 
+# BF16 form: every contraction operand is rounded to bfloat16 (relative 2^-9 = 2e-3) and
+# products accumulate in FP32. Against the exact FP64 product the three stages compound to a
+# relative error of about sqrt(3) * sqrt(2) * 2e-3 = 5e-3; the bar leaves a factor 6.
+BF16_TOL = 3e-2
+
+
+def _bf16(a):
+    """Nearest bfloat16 (ties to even) of the FP32 rounding of a, returned in FP64."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _reference_bf16(prob, p, beta):
+    """The BF16 form's arithmetic written out: each stage's operands rounded to bfloat16,
+    exact products, intermediates stored in FP32."""
+    f32 = lambda a: np.asarray(a, dtype=np.float32).astype(np.float64)
+
+    def apply(PhiL, A, PhiR, x):
+        t1 = f32(np.einsum("pxa,ajb->pxjb", _bf16(PhiL), _bf16(x), optimize=True))
+        t2 = f32(np.einsum("pijq,pxjb->qxib", _bf16(A), _bf16(t1), optimize=True))
+        return f32(np.einsum("qxib,qyb->xiy", _bf16(t2), _bf16(PhiR), optimize=True))
+
+    Md = tt.banded_to_dense(prob["M"], p)
+    Kd = tt.banded_to_dense(prob["K"], p)
+    x = prob["x"]
+    Mf = [apply(prob["PhiL_M"], Md, prob["PhiR_M"], x[l]) for l in range(3)]
+    Kf = [apply(prob["PhiL_K"], Kd, prob["PhiR_K"], x[l]) for l in range(3)]
+    return np.stack(kkt_rows(Mf, Kf, beta))
+
+
+def test_bf16_rounding_helper():
+    """The test's rounding: exact values stay, halfway cases go to the even neighbour."""
+    one_ulp = 2.0 ** -7  # bfloat16 spacing in [1, 2)
+    v = np.array([1.0, 1.0 + one_ulp, 1.0 + one_ulp / 2, 1.0 + 1.5 * one_ulp, -3.0, 0.0])
+    assert np.array_equal(_bf16(v), [1.0, 1.0 + one_ulp, 1.0, 1.0 + 2 * one_ulp, -3.0, 0.0])
+
+
+@pytest.mark.parametrize("r,RM,RK,n,p,rr", [(3, 1, 2, 5, 1, None), (5, 2, 3, 9, 2, None), (7, 3, 5, 13, 3, 4),
+                                             (1, 1, 3, 6, 2, 4), (17, 2, 9, 23, 3, None), (40, 3, 20, 37, 3, 24)])
+def test_local_matvec_bf16_matches_oracle(gpu_ctx, r, RM, RK, n, p, rr):
+    """Against the exact product (rounding bound) and against the written-out BF16 arithmetic:
+    the kernel's FP32 intermediates differ from the FP64-accumulated ones by ~1e-7, which moves
+    a bfloat16 rounding only for values within that of a midpoint, so 1e-3 is ample there."""
+    from paper_1811_06797_amd import iga
+    prob = synth.random_local_problem(r, RM, RK, n, p, seed=r + n, r_right=rr)
+    beta = 1e-3
+    y = _run(gpu_ctx, prob, r, n, p, RM, RK, beta, iga.BF16, rr)
+    exact = rel_err(y, _reference(prob, p, beta))
+    assert exact < BF16_TOL
+    assert exact > 1e-5  # the products really are in reduced precision
+    assert rel_err(y, _reference_bf16(prob, p, beta)) < 1e-3
+
+
+def test_local_matvec_bf16_benchmark_shape(gpu_ctx):
+    """At (32, 10, 60, 64, 3), with millions of intermediates, the midpoint moves average
+    out: the product matches the written-out BF16 arithmetic to 2e-4 (an unrounded operand
+    would leave ~1e-3)."""
+    from paper_1811_06797_amd import iga
+    r, RM, RK, n, p = 32, 10, 60, 64, 3
+    prob = synth.random_local_problem(r, RM, RK, n, p, seed=1)
+    y = _run(gpu_ctx, prob, r, n, p, RM, RK, 1e-6, iga.BF16)
+    assert rel_err(y, _reference(prob, p, 1e-6)) < BF16_TOL
+    assert rel_err(y, _reference_bf16(prob, p, 1e-6)) < 2e-4
+
+
 def test_local_matvec_flops_formula():
     from paper_1811_06797_amd import iga
     r, RM, RK, n, p = 32, 10, 60, 64, 3
