@@ -19,6 +19,9 @@ approximately or in another order:
                    row sampling for large n; 1-D factor matrices.
 * ``kkt``       -- the stationary KKT system of the control problem
                    (Section 4, time dropped), direct solve, objective.
+* ``parabolic`` -- the time-dependent KKT system of Section 4 (implicit
+                   Euler, rectangle rule, y_0 = 0): block matrix with the
+                   time-difference matrix C, direct solve, objective.
 * ``tt``        -- TT/TT-matrix expansion, TT-SVD, the frame matrix of
                    Section 5 and the projected local operator by its
                    definition F^T A F.
