@@ -51,6 +51,7 @@ extern "C" {
 
 #define IGA_FP64 0
 #define IGA_FP32 1
+#define IGA_MAX_TIME_STEPS 64  /* largest nt of iga_kkt_create_parabolic */
 #define IGA_BF16 2
 
 typedef struct iga_ctx iga_ctx;
@@ -185,8 +186,11 @@ void iga_tt_destroy(iga_tt* t);
 int iga_btt_create(iga_ctx* ctx, const int n[3], const int r[4], int ell_core,
                    const double* const host_cores[3], iga_btt** out);
 int iga_btt_info(const iga_btt* x, int* n, int* r, int* ell_core);
+/* Number of components (blocks) of x: 3 for the stationary system, 3 nt for the
+ * time-dependent one; IGA_EINVAL for NULL. Core ell_core holds [nblk][r][n][r']. */
+int iga_btt_blocks(const iga_btt* x);
 int iga_btt_get_core(iga_ctx* ctx, const iga_btt* x, int d, double* host_out);
-/* Expands the three components into dev_out [3][n1][n2][n3] (tests, residuals). */
+/* Expands the components into dev_out [nblk][n1][n2][n3] (tests, residuals). */
 int iga_btt_to_full(iga_ctx* ctx, const iga_btt* x, double* dev_out);
 void iga_btt_destroy(iga_btt* x);
 
@@ -194,13 +198,28 @@ void iga_btt_destroy(iga_btt* x);
  * problem (eq. KKTSystem with one time step, tau = 1). beta > 0. M and K
  * must share n and degree and outlive the handle. */
 int iga_kkt_create(iga_ctx* ctx, const iga_ttop* M, const iga_ttop* K, double beta, iga_kkt** out);
+
+/* KKT operator of the time-dependent control problem (Section 4, eq. KKTSystem): implicit
+ * Euler with nt steps of length tau (1 <= nt <= IGA_MAX_TIME_STEPS, tau > 0), y_0 = 0,
+ *   [tau calM, 0, calK^T; 0, tau beta calM, -tau calM; calK, -tau calM, 0] [y; u; lambda]
+ *     = [tau calM yhat; 0; 0],
+ * calM = I_nt (x) M, calK = I_nt (x) tau K + C (x) M, C lower bidiagonal (1 on the diagonal,
+ * -1 below), the desired state the same at every step. The time index is carried in the
+ * block index of the solution: 3 nt blocks y_1..y_nt, u_1..u_nt, lambda_1..lambda_nt.
+ * Accepted by iga_kkt_apply, iga_kkt_residual and iga_amen_solve (precision IGA_FP64);
+ * the reduced-cost functions take stationary handles only. */
+int iga_kkt_create_parabolic(iga_ctx* ctx, const iga_ttop* M, const iga_ttop* K, double beta, int nt,
+                             double tau, iga_kkt** out);
+/* Number of solution blocks of the system (3, or 3 nt); IGA_EINVAL for NULL. */
+int iga_kkt_blocks(const iga_kkt* kkt);
 void iga_kkt_destroy(iga_kkt* kkt);
 
 /* y = A x exactly, without rounding: y has ranks (R^M_d + R^K_d) r_d and its
  * component index at the core of x (eqs. M_kron, K_kron, KKTSystem). */
 int iga_kkt_apply(iga_ctx* ctx, const iga_kkt* kkt, const iga_btt* x, iga_btt** y);
 
-/* ||A f - b|| / ||b|| with b = [M yhat; 0; 0], in FP64 on expanded vectors. */
+/* ||A f - b|| / ||b|| with b = [M yhat; 0; 0] (time-dependent: [tau calM yhat; 0; 0]), in
+ * FP64 on expanded vectors. */
 int iga_kkt_residual(iga_ctx* ctx, const iga_kkt* kkt, const iga_tt* yhat, const iga_btt* f,
                      double* rel_residual);
 

@@ -1,9 +1,10 @@
-// Block-AMEn solver of the stationary KKT system (Section 5, eqs. btt, svd1, svd2,
-// frame, ttlin, KKT_red).
+// Block-AMEn solver of the KKT system (Section 5, eqs. btt, svd1, svd2, frame, ttlin,
+// KKT_red), stationary or time-dependent (Section 4, eq. KKTSystem).
 //
-// The solution (y, u, lambda) is one block-TT whose component index l sits in the
-// core being updated. Each local step projects the three block rows onto the
-// frame of the current solution (the interfaces Phi = X^T A X of M and K,
+// The solution (y, u, lambda) -- for the time-dependent system (y_t, u_t, lambda_t) of
+// every step -- is one block-TT whose component index l sits in the core being updated.
+// Each local step projects the block rows onto the frame of the current solution (the
+// interfaces Phi = X^T A X of M and K,
 // contracted core by core) and solves the reduced KKT system. Then the core is
 // split by a truncated SVD, the left (or right) factor becomes the new
 // orthonormal core, and the rest -- carrying l -- is multiplied into the next core.
@@ -22,7 +23,8 @@
 //   with the dominant separable part of omega, whose projection is a Kronecker
 //   sum and is inverted by fast diagonalisation (generalised eigenvectors of the
 //   left interface pair, the univariate factor pair and the right interface pair;
-//   the 3x3 KKT block of every mode is solved exactly);
+//   the 3x3 KKT block of every mode is solved exactly; in the time-dependent system
+//   the 3 nt x 3 nt block of every spatial mode, by a tridiagonal elimination in time);
 // * rank adaptivity by residual enrichment (AMEn, Dolgov & Savostyanov): a
 //   rank-rho TT Z tracks the residual; its projection onto (X-left, Z-right)
 //   frames (forward sweep) or (Z-left, X-right) frames (backward) supplies rho
@@ -109,6 +111,9 @@ class Amen {
         t_kr_(ctx->stream), t_mv32_(ctx->stream) {
     for (int d = 0; d < 3; ++d) n_[d] = kkt->M->n[d];
     g_ = std::sqrt(kkt->beta);
+    nb_ = kkt->nblk;
+    ntb_ = nb_ / 3;
+    if (kkt->nt > 0) block_tables();
     ops_[0] = kkt->M;
     ops_[1] = kkt->K;
     ops_[2] = kkt->Kref;
@@ -199,6 +204,13 @@ class Amen {
   int ell_ = 0;
   int kick_ = 4;
   double g_;  // sqrt(beta): scaled unknowns are (y, g u, lambda / g)
+  int nb_ = 3;   // solution blocks: 3, or 3 nt for the time-dependent system
+  int ntb_ = 1;  // blocks per component (time steps)
+  // time-dependent system: K column ranges and the combination tables of the local operator
+  int nkr_ = 0, kb_[2] = {0, 0}, kn_[2] = {0, 0};
+  IBuf toff_, tsrc_;
+  DBuf tcoef_;
+  void block_tables();
   DBuf X_[3], Z_[3];
   DBuf PL_[3][3], PR_[3][3];  // (X, A, X), A in {M, K, Kref}
   DBuf YL_[3], YR_[3];        // (X, M, Y)
@@ -264,7 +276,7 @@ void Amen::right_orth_plain(DBuf* cores, int* ranks, int d, bool prev_is_ell) {
   k::gather_cols(st_, r0, r0, k, s.V.get(), s.p, didx.get(), dsg.get(), F.get(), k);
   // previous core [.][n'][r0] times F (r0 x k)
   const int rp = ranks[d - 1], np = n_[d - 1];
-  const int nl = prev_is_ell ? 3 : 1;
+  const int nl = prev_is_ell ? nb_ : 1;
   DBuf pc(ctx_, (size_t)nl * rp * np * k);
   k::Gemm g;
   g.M = rp * np; g.N = k; g.K = r0;
@@ -352,6 +364,54 @@ void Amen::update_left(int d) {
   t_if_.end(id);
 }
 
+// Tables of the local operator of the time-dependent system: output block o of A D x is
+// sum_l cM[o][l] D_l M x_l + cK[o][l] D_l K x_l, D = (1, 1/g, g) per component (the scaled
+// unknowns); K acts on the ranges of consecutive blocks where cK has entries.
+void Amen::block_tables() {
+  const int nb = nb_;
+  const std::vector<double>& cM = kkt_->cM;
+  const std::vector<double>& cK = kkt_->cK;
+  std::vector<int> kcol(nb, 0), kpos(nb, -1);
+  for (int o = 0; o < nb; ++o)
+    for (int l = 0; l < nb; ++l)
+      if (cK[(size_t)o * nb + l] != 0.0) kcol[l] = 1;
+  nkr_ = 0;
+  int pos = 0;
+  for (int l = 0; l < nb; ++l) {
+    if (!kcol[l]) continue;
+    if (l == 0 || !kcol[l - 1]) {
+      require(nkr_ < 2, IGA_EINVAL, "amen: more than two stiffness column ranges");
+      kb_[nkr_] = l;
+      kn_[nkr_] = 0;
+      ++nkr_;
+    }
+    ++kn_[nkr_ - 1];
+    kpos[l] = pos++;
+  }
+  auto D = [&](int l) {
+    const int c = l / ntb_;
+    return c == 0 ? 1.0 : (c == 1 ? 1.0 / g_ : g_);
+  };
+  std::vector<int> toff(nb + 1, 0), src;
+  std::vector<double> coef;
+  for (int o = 0; o < nb; ++o) {
+    toff[o] = (int)src.size();
+    for (int l = 0; l < nb; ++l) {
+      const double m = cM[(size_t)o * nb + l], kk = cK[(size_t)o * nb + l];
+      if (m != 0.0) { src.push_back(l); coef.push_back(m * D(l)); }
+      if (kk != 0.0) { src.push_back(nb + kpos[l]); coef.push_back(kk * D(l)); }
+    }
+  }
+  toff[nb] = (int)src.size();
+  toff_.reset(ctx_, toff.size());
+  tsrc_.reset(ctx_, std::max<size_t>(src.size(), 1));
+  tcoef_.reset(ctx_, std::max<size_t>(coef.size(), 1));
+  IGA_HIP(hipMemcpyAsync(toff_.get(), toff.data(), toff.size() * sizeof(int), hipMemcpyHostToDevice, st_));
+  IGA_HIP(hipMemcpyAsync(tsrc_.get(), src.data(), src.size() * sizeof(int), hipMemcpyHostToDevice, st_));
+  IGA_HIP(hipMemcpyAsync(tcoef_.get(), coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice, st_));
+  IGA_HIP(hipStreamSynchronize(st_));
+}
+
 LocalOp Amen::make_op(int d, Frame left, Frame right) const {
   LocalOp L;
   L.M = view(0, d);
@@ -361,6 +421,12 @@ LocalOp Amen::make_op(int d, Frame left, Frame right) const {
   L.Mblocks = ops_[0]->core[d].blocks;
   L.Kblocks = ops_[1]->core[d].blocks;
   L.r0 = r_[d]; L.n = n_[d]; L.r1 = r_[d + 1];
+  L.nblk = nb_;
+  if (toff_.get()) {
+    L.nkr = nkr_;
+    for (int j = 0; j < 2; ++j) { L.kb[j] = kb_[j]; L.kn[j] = kn_[j]; }
+    L.toff = toff_.get(); L.src = tsrc_.get(); L.tcoef = tcoef_.get();
+  }
   // A D: columns 1 and 2 carry the factors 1/g and g of the scaled unknowns
   L.coef.k02 = g_;
   L.coef.m11 = kkt_->beta / g_;
@@ -380,7 +446,7 @@ LocalOp Amen::make_op(int d, Frame left, Frame right) const {
   return L;
 }
 
-// [F^T M yhat; 0; 0] projected with the given frames
+// [F^T M yhat; 0; 0] projected with the given frames (block o: cb[o] F^T M yhat)
 void Amen::rhs_local(int d, Frame left, Frame right, double* out) {
   const int a_out = left == FX ? r_[d] : rho_[d];
   const int b_out = right == FX ? r_[d + 1] : rho_[d + 1];
@@ -388,7 +454,12 @@ void Amen::rhs_local(int d, Frame left, Frame right, double* out) {
   const double* PL = left == FX ? YL_[d].get() : ZYL_[d].get();
   const double* PR = right == FX ? YR_[d].get() : ZYR_[d].get();
   local_apply(ctx_, view(0, d), PL, PR, a_out, ry_[d], b_out, ry_[d + 1], 1, Ycore(d), 0, out, 0, 1.0, 0.0);
-  k::fill(st_, 2 * e, 0.0, out + e);
+  const std::vector<double>& cb = kkt_->cb;
+  for (int o = nb_ - 1; o >= 1; --o) {
+    if (cb[o] == 0.0) k::fill(st_, e, 0.0, out + o * e);
+    else k::axpby(st_, e, cb[o], out, 0.0, out + o * e);
+  }
+  if (cb[0] != 1.0) k::scale(st_, e, cb[0], out);
 }
 
 void Amen::matvec(const LocalOp& L, const double* x, double* y) {
@@ -517,9 +588,9 @@ void Amen::apply_precond(const double* v, double* z) {
   const int id = t_pc_.begin();
   const int r0 = pc_r0_, r1 = pc_r1_, n = n_[pc_d_];
   const long e = (long)r0 * n * r1;
-  pt1_.ensure(ctx_, 3 * e);
-  pt2_.ensure(ctx_, 3 * e);
-  pt3_.ensure(ctx_, 3 * e);
+  pt1_.ensure(ctx_, nb_ * e);
+  pt2_.ensure(ctx_, nb_ * e);
+  pt3_.ensure(ctx_, nb_ * e);
   const double* Vn = kkt_->Vn[pc_d_].get();
   // pass 0: pt1 <- W^T v (modes a, j, b), solve the mode blocks in place;
   // pass 1: z <- W pt1
@@ -532,7 +603,7 @@ void Amen::apply_precond(const double* v, double* z) {
     ga.A = VL_; ga.sAm = tr ? 1 : r0; ga.sAk = tr ? r0 : 1;
     ga.B = src; ga.sBk = (long)n * r1; ga.sBn = 1;
     ga.C = pt2_.get(); ga.sCm = (long)n * r1; ga.sCn = 1;
-    ga.nb1 = 3; ga.sBb1 = e; ga.sCb1 = e;
+    ga.nb1 = nb_; ga.sBb1 = e; ga.sCb1 = e;
     k::gemm(st_, ga);
     // mode j: out[(l a')][i'][b] = sum_j Vn(j, i') in[(l a')][j][b]
     double* jout = tr ? pt1_.get() : pt3_.get();
@@ -541,20 +612,23 @@ void Amen::apply_precond(const double* v, double* z) {
     gj.A = Vn; gj.sAm = tr ? 1 : n; gj.sAk = tr ? n : 1;
     gj.B = pt2_.get(); gj.sBk = r1; gj.sBn = 1;
     gj.C = jout; gj.sCm = r1; gj.sCn = 1;
-    gj.nb1 = 3 * r0; gj.sBb1 = (long)n * r1; gj.sCb1 = (long)n * r1;
+    gj.nb1 = nb_ * r0; gj.sBb1 = (long)n * r1; gj.sCb1 = (long)n * r1;
     k::gemm(st_, gj);
     // mode b: out[(l a' i')][b'] = sum_b in[..][b] VR(b, b')
     double* bout = tr ? pt2_.get() : z;
     k::Gemm gb;
-    gb.M = 3 * r0 * n; gb.N = r1; gb.K = r1;
+    gb.M = nb_ * r0 * n; gb.N = r1; gb.K = r1;
     gb.A = jout; gb.sAm = r1; gb.sAk = 1;
     gb.B = VR_; gb.sBk = tr ? r1 : 1; gb.sBn = tr ? 1 : r1;
     gb.C = bout; gb.sCm = r1; gb.sCn = 1;
     k::gemm(st_, gb);
-    if (!tr) k::scale3(st_, e, 1.0, g_, 1.0 / g_, z);  // D^{-1}: to the scaled unknowns
+    if (!tr) k::scale3(st_, ntb_ * e, 1.0, g_, 1.0 / g_, z);  // D^{-1}: to the scaled unknowns
     if (tr) {
-      k::fd_solve(st_, r0, n, r1, lamL_, kkt_->lamn[pc_d_].get(), lamR_, kkt_->beta, 1.0,
-                  pt2_.get());
+      if (kkt_->nt > 0)
+        k::fd_solve_time(st_, r0, n, r1, kkt_->nt, lamL_, kkt_->lamn[pc_d_].get(), lamR_, kkt_->beta, kkt_->tau,
+                         pt2_.get(), pt3_.get());
+      else
+        k::fd_solve(st_, r0, n, r1, lamL_, kkt_->lamn[pc_d_].get(), lamR_, kkt_->beta, 1.0, pt2_.get());
       std::swap(pt1_, pt2_);
     }
   }
@@ -722,7 +796,7 @@ double Amen::local_res_of(int d, const double* xk) {
 // r_full the residual of the untruncated core (bisection; the residual decreases with k).
 template <class Recon>
 int Amen::residual_rank(int d, int kmin, int kmax, Recon recon) {
-  const long N = (long)3 * r_[d] * n_[d] * r_[d + 1];
+  const long N = (long)nb_ * r_[d] * n_[d] * r_[d + 1];
   xk_.ensure(ctx_, N);
   const double full = local_res_of(d, X_[d].get());
   const double target = std::max(0.5 * tol_, 1.5 * full);
@@ -750,21 +824,21 @@ void Amen::move_right(int d) {
   // residual projections with the solved core
   DBuf zc, rz;
   if (kick_ > 0) {
-    zc.reset(ctx_, 3L * rho_[d] * n * rho_[d + 1]);
+    zc.reset(ctx_, (long)nb_ * rho_[d] * n * rho_[d + 1]);
     residual_proj(d, FZ, FZ, zc.get());
-    rz.reset(ctx_, 3L * r0 * n * rho_[d + 1]);
+    rz.reset(ctx_, (long)nb_ * r0 * n * rho_[d + 1]);
     residual_proj(d, FX, FZ, rz.get());
   }
-  // truncated SVD of F (r0 n) x (3 r1)
-  DBuf F(ctx_, 3 * e);
+  // truncated SVD of F (r0 n) x (nb r1)
+  DBuf F(ctx_, nb_ * e);
   {
-    const int dims[4] = {3, r0, n, r1};
+    const int dims[4] = {nb_, r0, n, r1};
     const int perm[4] = {1, 2, 0, 3};
     k::permute4(st_, X_[d].get(), dims, perm, F.get());
   }
   Svd s;
-  svd(ctx_, F.get(), m, 3 * r1, 3 * r1, false, s);
-  const int K3 = 3 * r1;
+  svd(ctx_, F.get(), m, nb_ * r1, nb_ * r1, false, s);
+  const int K3 = nb_ * r1;
   const int rmax = std::min(o_.r_max, std::min(m, K3));
   int rt = 1;
   if (s.sigma[0] > 0) {
@@ -773,7 +847,7 @@ void Amen::move_right(int d) {
     DBuf Fk(ctx_, (size_t)m * K3);
     auto recon = [&](int kk, double* out) {
       k::gemm_rm(st_, m, K3, kk, s.B.get(), s.p, false, s.V.get(), s.p, true, Fk.get(), K3);
-      const int dims[4] = {r0, n, 3, r1};
+      const int dims[4] = {r0, n, nb_, r1};
       const int perm[4] = {2, 0, 1, 3};
       k::permute4(st_, Fk.get(), dims, perm, out);
     };
@@ -795,18 +869,18 @@ void Amen::move_right(int d) {
   IGA_HIP(hipMemcpyAsync(dinv.get(), inv.data(), rt * sizeof(double), hipMemcpyHostToDevice, st_));
   IGA_HIP(hipMemcpyAsync(dsg.get(), sg.data(), rt * sizeof(double), hipMemcpyHostToDevice, st_));
   DBuf U(ctx_, (size_t)m * rt);
-  k::gather_cols(st_, m, 3 * r1, rt, s.B.get(), s.p, didx.get(), dinv.get(), U.get(), rt);
-  // C = Sigma V^T: (rt x 3 r1)
-  DBuf CT(ctx_, (size_t)3 * r1 * rt), C(ctx_, (size_t)rt * 3 * r1);
-  k::gather_cols(st_, 3 * r1, 3 * r1, rt, s.V.get(), s.p, didx.get(), dsg.get(), CT.get(), rt);
-  k::copy2d(st_, rt, 3 * r1, CT.get(), 1, rt, C.get(), 3 * r1);
+  k::gather_cols(st_, m, K3, rt, s.B.get(), s.p, didx.get(), dinv.get(), U.get(), rt);
+  // C = Sigma V^T: (rt x nb r1)
+  DBuf CT(ctx_, (size_t)K3 * rt), C(ctx_, (size_t)rt * K3);
+  k::gather_cols(st_, K3, K3, rt, s.V.get(), s.p, didx.get(), dsg.get(), CT.get(), rt);
+  k::copy2d(st_, rt, K3, CT.get(), 1, rt, C.get(), K3);
   // enrichment directions orthogonal to U
   DBuf Qz;
   int q = 0;
   if (kick_ > 0 && rt < m) {
-    const int kz = 3 * rho_[d + 1];
+    const int kz = nb_ * rho_[d + 1];
     DBuf Rz(ctx_, (size_t)m * kz), T(ctx_, (size_t)rt * kz);
-    const int dims[4] = {3, r0, n, rho_[d + 1]};
+    const int dims[4] = {nb_, r0, n, rho_[d + 1]};
     const int perm[4] = {1, 2, 0, 3};
     k::permute4(st_, rz.get(), dims, perm, Rz.get());
     for (int pass = 0; pass < 2; ++pass) {
@@ -819,28 +893,28 @@ void Amen::move_right(int d) {
   DBuf Xn(ctx_, (size_t)m * rn);
   k::copy2d(st_, m, rt, U.get(), rt, 1, Xn.get(), rn);
   if (q > 0) k::copy2d(st_, m, q, Qz.get(), q, 1, Xn.get() + rt, rn);
-  // next core: [rn][3][n1][r2] = Cn (rn*3 x r1) . X_{d+1} (r1 x n1 r2), Cn = [C; 0]
+  // next core: [rn][nb][n1][r2] = Cn (rn*nb x r1) . X_{d+1} (r1 x n1 r2), Cn = [C; 0]
   const int n1 = n_[d + 1], r2 = r_[d + 2];
-  DBuf Cn(ctx_, (size_t)rn * 3 * r1), T2(ctx_, (size_t)rn * 3 * n1 * r2), Xd1(ctx_, (size_t)3 * rn * n1 * r2);
-  k::fill(st_, (long)rn * 3 * r1, 0.0, Cn.get());
-  IGA_HIP(hipMemcpyAsync(Cn.get(), C.get(), (size_t)rt * 3 * r1 * 8, hipMemcpyDeviceToDevice, st_));
-  k::gemm_rm(st_, rn * 3, n1 * r2, r1, Cn.get(), r1, false, X_[d + 1].get(), (long)n1 * r2, false, T2.get(),
+  DBuf Cn(ctx_, (size_t)rn * nb_ * r1), T2(ctx_, (size_t)rn * nb_ * n1 * r2), Xd1(ctx_, (size_t)nb_ * rn * n1 * r2);
+  k::fill(st_, (long)rn * nb_ * r1, 0.0, Cn.get());
+  IGA_HIP(hipMemcpyAsync(Cn.get(), C.get(), (size_t)rt * nb_ * r1 * 8, hipMemcpyDeviceToDevice, st_));
+  k::gemm_rm(st_, rn * nb_, n1 * r2, r1, Cn.get(), r1, false, X_[d + 1].get(), (long)n1 * r2, false, T2.get(),
              (long)n1 * r2);
   {
-    const int dims[4] = {rn, 3, n1, r2};
+    const int dims[4] = {rn, nb_, n1, r2};
     const int perm[4] = {1, 0, 2, 3};
     k::permute4(st_, T2.get(), dims, perm, Xd1.get());
   }
   // residual core update
   if (kick_ > 0) {
     const int z0 = rho_[d], z1 = rho_[d + 1];
-    DBuf Zm(ctx_, 3L * z0 * n * z1);
-    const int dims[4] = {3, z0, n, z1};
+    DBuf Zm(ctx_, (long)nb_ * z0 * n * z1);
+    const int dims[4] = {nb_, z0, n, z1};
     const int perm[4] = {1, 2, 0, 3};
     k::permute4(st_, zc.get(), dims, perm, Zm.get());
     DBuf Qn;
     int qz = 0;
-    orthonormal_columns(Zm.get(), z0 * n, 3 * z1, std::min(kick_, z0 * n), Qn, qz, 1e-14);
+    orthonormal_columns(Zm.get(), z0 * n, nb_ * z1, std::min(kick_, z0 * n), Qn, qz, 1e-14);
     if (qz == 0) {
       DBuf Rn = random_buf((size_t)z0 * n * kick_, 1.0);
       orthonormal_columns(Rn.get(), z0 * n, kick_, std::min(kick_, z0 * n), Qn, qz, 1e-14);
@@ -864,22 +938,22 @@ void Amen::move_left(int d) {
   const int sid = t_svd_.begin();
   DBuf zc, rz;
   if (kick_ > 0) {
-    zc.reset(ctx_, 3L * rho_[d] * n * rho_[d + 1]);
+    zc.reset(ctx_, (long)nb_ * rho_[d] * n * rho_[d + 1]);
     residual_proj(d, FZ, FZ, zc.get());
-    rz.reset(ctx_, 3L * rho_[d] * n * r1);
+    rz.reset(ctx_, (long)nb_ * rho_[d] * n * r1);
     residual_proj(d, FZ, FX, rz.get());
   }
-  // SVD of F^T, F = (3 r0) x (n r1)
+  // SVD of F^T, F = (nb r0) x (n r1)
   Svd s;
-  svd(ctx_, X_[d].get(), m, 3 * r0, m, /*trans=*/true, s);
-  const int K3 = 3 * r0;
+  svd(ctx_, X_[d].get(), m, nb_ * r0, m, /*trans=*/true, s);
+  const int K3 = nb_ * r0;
   const int rmax = std::min(o_.r_max, std::min(m, K3));
   int rt = 1;
   if (s.sigma[0] > 0) {
     int nz = 0;
     for (double v : s.sigma) nz += v > 1e-14 * s.sigma[0];
     auto recon = [&](int kk, double* out) {
-      // F_k = V_k B_k^T: (3 r0) x (n r1) in the natural [l][a][j][b] layout
+      // F_k = V_k B_k^T: (nb r0) x (n r1) in the natural [l][a][j][b] layout
       k::gemm_rm(st_, K3, m, kk, s.V.get(), s.p, false, s.B.get(), s.p, true, out, m);
     };
     rt = residual_rank(d, 1, std::min(rmax, std::max(nz, 1)), recon);
@@ -900,15 +974,15 @@ void Amen::move_left(int d) {
   IGA_HIP(hipMemcpyAsync(dinv.get(), inv.data(), rt * sizeof(double), hipMemcpyHostToDevice, st_));
   IGA_HIP(hipMemcpyAsync(dsg.get(), sg.data(), rt * sizeof(double), hipMemcpyHostToDevice, st_));
   DBuf U(ctx_, (size_t)m * rt);  // (n r1) x rt
-  k::gather_cols(st_, m, 3 * r0, rt, s.B.get(), s.p, didx.get(), dinv.get(), U.get(), rt);
-  DBuf C(ctx_, (size_t)3 * r0 * rt);  // (3 r0) x rt = V Sigma
-  k::gather_cols(st_, 3 * r0, 3 * r0, rt, s.V.get(), s.p, didx.get(), dsg.get(), C.get(), rt);
+  k::gather_cols(st_, m, K3, rt, s.B.get(), s.p, didx.get(), dinv.get(), U.get(), rt);
+  DBuf C(ctx_, (size_t)K3 * rt);  // (nb r0) x rt = V Sigma
+  k::gather_cols(st_, K3, K3, rt, s.V.get(), s.p, didx.get(), dsg.get(), C.get(), rt);
   DBuf Qz;
   int q = 0;
   if (kick_ > 0 && rt < m) {
-    const int kz = 3 * rho_[d];
+    const int kz = nb_ * rho_[d];
     DBuf Rz(ctx_, (size_t)m * kz), T(ctx_, (size_t)rt * kz);
-    // rz [3][z0][n][r1] viewed as (3 z0) x (n r1); transpose to (n r1) x (3 z0)
+    // rz [nb][z0][n][r1] viewed as (nb z0) x (n r1); transpose to (n r1) x (nb z0)
     k::copy2d(st_, m, kz, rz.get(), 1, m, Rz.get(), kz);
     for (int pass = 0; pass < 2; ++pass) {
       k::gemm_rm(st_, rt, kz, m, U.get(), rt, true, Rz.get(), kz, false, T.get(), kz);
@@ -923,24 +997,24 @@ void Amen::move_left(int d) {
   k::copy2d(st_, rn, m, Uall.get(), 1, rn, Xn.get(), m);  // X_d = Uall^T: [rn][n][r1]
   // previous core with l: [l][(c j)][rn] = X_{d-1}[(c j)][a] Cn[l][a][rn], Cn = [C, 0]
   const int rp = r_[d - 1], np = n_[d - 1];
-  DBuf Cn(ctx_, (size_t)3 * r0 * rn), Xp(ctx_, (size_t)3 * rp * np * rn);
-  k::fill(st_, 3L * r0 * rn, 0.0, Cn.get());
-  k::copy2d(st_, 3 * r0, rt, C.get(), rt, 1, Cn.get(), rn);
+  DBuf Cn(ctx_, (size_t)K3 * rn), Xp(ctx_, (size_t)nb_ * rp * np * rn);
+  k::fill(st_, (long)K3 * rn, 0.0, Cn.get());
+  k::copy2d(st_, K3, rt, C.get(), rt, 1, Cn.get(), rn);
   k::Gemm g;
   g.M = rp * np; g.N = rn; g.K = r0;
   g.A = X_[d - 1].get(); g.sAm = r0; g.sAk = 1;
   g.B = Cn.get(); g.sBk = rn; g.sBn = 1;
   g.C = Xp.get(); g.sCm = rn; g.sCn = 1;
-  g.nb1 = 3; g.sBb1 = (long)r0 * rn; g.sCb1 = (long)rp * np * rn;
+  g.nb1 = nb_; g.sBb1 = (long)r0 * rn; g.sCb1 = (long)rp * np * rn;
   k::gemm(st_, g);
   if (kick_ > 0) {
     const int z0 = rho_[d], z1 = rho_[d + 1];
     const int mz = n * z1;
-    DBuf Zm(ctx_, (size_t)mz * 3 * z0);
-    k::copy2d(st_, mz, 3 * z0, zc.get(), 1, mz, Zm.get(), 3 * z0);
+    DBuf Zm(ctx_, (size_t)mz * nb_ * z0);
+    k::copy2d(st_, mz, nb_ * z0, zc.get(), 1, mz, Zm.get(), nb_ * z0);
     DBuf Qn;
     int qz = 0;
-    orthonormal_columns(Zm.get(), mz, 3 * z0, std::min(kick_, mz), Qn, qz, 1e-14);
+    orthonormal_columns(Zm.get(), mz, nb_ * z0, std::min(kick_, mz), Qn, qz, 1e-14);
     if (qz == 0) {
       DBuf Rn = random_buf((size_t)mz * kick_, 1.0);
       orthonormal_columns(Rn.get(), mz, kick_, std::min(kick_, mz), Qn, qz, 1e-14);
@@ -975,7 +1049,7 @@ void Amen::move_ell_to_first() {
     const int r0 = r_[d], r1 = r_[d + 1], n = n_[d];
     const int m = n * r1;
     Svd s;
-    svd(ctx_, X_[d].get(), m, 3 * r0, m, true, s);
+    svd(ctx_, X_[d].get(), m, nb_ * r0, m, true, s);
     int rt = trunc_rank(s.sigma, 1e-14 * s.sigma[0], m);
     std::vector<int> idx(rt);
     std::vector<double> inv(rt), sg(rt);
@@ -985,22 +1059,22 @@ void Amen::move_ell_to_first() {
       sg[j] = s.sigma[j];
     }
     IBuf didx(ctx_, rt);
-    DBuf dinv(ctx_, rt), dsg(ctx_, rt), U(ctx_, (size_t)m * rt), C(ctx_, (size_t)3 * r0 * rt),
+    DBuf dinv(ctx_, rt), dsg(ctx_, rt), U(ctx_, (size_t)m * rt), C(ctx_, (size_t)nb_ * r0 * rt),
         Xn(ctx_, (size_t)rt * m);
     IGA_HIP(hipMemcpyAsync(didx.get(), idx.data(), rt * sizeof(int), hipMemcpyHostToDevice, st_));
     IGA_HIP(hipMemcpyAsync(dinv.get(), inv.data(), rt * sizeof(double), hipMemcpyHostToDevice, st_));
     IGA_HIP(hipMemcpyAsync(dsg.get(), sg.data(), rt * sizeof(double), hipMemcpyHostToDevice, st_));
-    k::gather_cols(st_, m, 3 * r0, rt, s.B.get(), s.p, didx.get(), dinv.get(), U.get(), rt);
-    k::gather_cols(st_, 3 * r0, 3 * r0, rt, s.V.get(), s.p, didx.get(), dsg.get(), C.get(), rt);
+    k::gather_cols(st_, m, nb_ * r0, rt, s.B.get(), s.p, didx.get(), dinv.get(), U.get(), rt);
+    k::gather_cols(st_, nb_ * r0, nb_ * r0, rt, s.V.get(), s.p, didx.get(), dsg.get(), C.get(), rt);
     k::copy2d(st_, rt, m, U.get(), 1, rt, Xn.get(), m);
     const int rp = r_[d - 1], np = n_[d - 1];
-    DBuf Xp(ctx_, (size_t)3 * rp * np * rt);
+    DBuf Xp(ctx_, (size_t)nb_ * rp * np * rt);
     k::Gemm g;
     g.M = rp * np; g.N = rt; g.K = r0;
     g.A = X_[d - 1].get(); g.sAm = r0; g.sAk = 1;
     g.B = C.get(); g.sBk = rt; g.sBn = 1;
     g.C = Xp.get(); g.sCm = rt; g.sCn = 1;
-    g.nb1 = 3; g.sBb1 = (long)r0 * rt; g.sCb1 = (long)rp * np * rt;
+    g.nb1 = nb_; g.sBb1 = (long)r0 * rt; g.sCb1 = (long)rp * np * rt;
     k::gemm(st_, g);
     IGA_HIP(hipStreamSynchronize(st_));
     X_[d] = std::move(Xn);
@@ -1023,12 +1097,12 @@ int Amen::run(const iga_btt* x0, iga_btt** sol, iga_amen_stats* stats) {
     for (int d = 0; d < 4; ++d) r_[d] = x0->r[d];
     ell_ = x0->ell;
     for (int d = 0; d < 3; ++d) {
-      const size_t sz = (size_t)(d == ell_ ? 3 : 1) * core_size(d);
+      const size_t sz = (size_t)(d == ell_ ? nb_ : 1) * core_size(d);
       X_[d].reset(ctx_, sz);
       IGA_HIP(hipMemcpyAsync(X_[d].get(), x0->core[d].get(), sz * 8, hipMemcpyDeviceToDevice, st_));
     }
     // to the scaled unknowns: u -> sqrt(beta) u, lambda -> lambda / sqrt(beta)
-    const long e = core_size(ell_);
+    const long e = ntb_ * core_size(ell_);
     k::scale(st_, e, g_, X_[ell_].get() + e);
     k::scale(st_, e, 1.0 / g_, X_[ell_].get() + 2 * e);
     move_ell_to_first();
@@ -1037,7 +1111,7 @@ int Amen::run(const iga_btt* x0, iga_btt** sol, iga_amen_stats* stats) {
     r_[1] = std::min(ri, n_[0]);
     r_[2] = std::min(ri, n_[2]);
     ell_ = 0;
-    X_[0] = random_buf((size_t)3 * core_size(0), 1.0);
+    X_[0] = random_buf((size_t)nb_ * core_size(0), 1.0);
     X_[1] = random_buf((size_t)core_size(1), 1.0);
     X_[2] = random_buf((size_t)core_size(2), 1.0);
     right_orth_plain(X_, r_, 2, false);
@@ -1072,14 +1146,15 @@ int Amen::run(const iga_btt* x0, iga_btt** sol, iga_amen_stats* stats) {
       iga_btt tmpx;
       tmpx.ctx = ctx_;
       tmpx.ell = ell_;
+      tmpx.nblk = nb_;
       for (int d = 0; d < 3; ++d) tmpx.n[d] = n_[d];
       for (int d = 0; d < 4; ++d) tmpx.r[d] = r_[d];
       for (int d = 0; d < 3; ++d) {
-        const size_t sz = (size_t)(d == ell_ ? 3 : 1) * core_size(d);
+        const size_t sz = (size_t)(d == ell_ ? nb_ : 1) * core_size(d);
         tmpx.core[d].reset(ctx_, sz);
         IGA_HIP(hipMemcpyAsync(tmpx.core[d].get(), X_[d].get(), sz * 8, hipMemcpyDeviceToDevice, st_));
       }
-      const long e = core_size(ell_);
+      const long e = ntb_ * core_size(ell_);
       k::scale(st_, e, 1.0 / g_, tmpx.core[ell_].get() + e);
       k::scale(st_, e, g_, tmpx.core[ell_].get() + 2 * e);
       const double gr = kkt_residual_impl(ctx_, kkt_, Y_, &tmpx);
@@ -1092,13 +1167,14 @@ int Amen::run(const iga_btt* x0, iga_btt** sol, iga_amen_stats* stats) {
   }
   // back to the plain unknowns
   {
-    const long e = core_size(ell_);
+    const long e = ntb_ * core_size(ell_);
     k::scale(st_, e, 1.0 / g_, X_[ell_].get() + e);
     k::scale(st_, e, g_, X_[ell_].get() + 2 * e);
   }
   std::unique_ptr<iga_btt> out(new iga_btt());
   out->ctx = ctx_;
   out->ell = ell_;
+  out->nblk = nb_;
   for (int d = 0; d < 3; ++d) out->n[d] = n_[d];
   for (int d = 0; d < 4; ++d) out->r[d] = r_[d];
   for (int d = 0; d < 3; ++d) out->core[d] = std::move(X_[d]);
@@ -1152,6 +1228,8 @@ int amen_impl(iga_ctx* ctx, const iga_kkt* kkt, const iga_tt* yhat, double tol, 
   if (o.init_rank <= 0) o.init_rank = 2;
   require(o.precision == IGA_FP64 || o.precision == IGA_FP32 || o.precision == IGA_BF16, IGA_EINVAL,
           "amen_solve: bad precision");
+  require(kkt->nt == 0 || o.precision == IGA_FP64, IGA_EINVAL,
+          "amen_solve: the time-dependent system is solved in FP64 only");
   Amen a(ctx, kkt, yhat, tol, o);
   return a.run(x0, sol, stats);
 }

@@ -119,33 +119,76 @@ static void upload(iga_ctx* ctx, double* dst, const double* src, size_t n) {
 }  // namespace iga
 
 namespace iga {
-// ||A f - b|| / ||b|| with b = [M yhat; 0; 0]: f and yhat are expanded and the TT-matrices
-// applied to the full tensors mode by mode, all in FP64.
+// ||A f - b|| / ||b|| with the block structure of the KKT handle (b_o = cb[o] M yhat): f and
+// yhat are expanded and the TT-matrices applied to the full tensors mode by mode, all in FP64.
 double kkt_residual_impl(iga_ctx* ctx, const iga_kkt* kkt, const iga_tt* yhat, const iga_btt* f) {
+  require(f->nblk == kkt->nblk, IGA_EINVAL, "kkt_residual: block count differs from the KKT system");
   const long N = (long)f->n[0] * f->n[1] * f->n[2];
-  DBuf full(ctx, 3 * N), yh(ctx, N), r(ctx, 3 * N);
+  const int nb = kkt->nblk;
+  DBuf full(ctx, (size_t)nb * N), yh(ctx, N), Myh(ctx, N), r(ctx, N);
   btt_expand(ctx, f, full.get());
   tt_expand(ctx, yhat->n, yhat->r, yhat->core, yh.get());
-  const double* f0 = full.get();
-  const double* f1 = full.get() + N;
-  const double* f2 = full.get() + 2 * N;
-  double* r0 = r.get();
-  double* r1 = r.get() + N;
-  double* r2 = r.get() + 2 * N;
-  const iga_ttop* M = kkt->M;
-  const iga_ttop* K = kkt->K;
-  // r0 = M f0 + K f2 - M yhat;  r1 = beta M f1 - M f2;  r2 = K f0 - M f1
-  full_apply(ctx, M, yh.get(), r2, 1.0, 0.0);  // b (kept in r2 for its norm)
-  const double nb = norm2_host(ctx, N, r2);
-  full_apply(ctx, M, f0, r0, 1.0, 0.0);
-  k::axpby(ctx->stream, N, -1.0, r2, 1.0, r0);
-  full_apply(ctx, K, f2, r0, 1.0, 1.0);
-  full_apply(ctx, M, f1, r1, kkt->beta, 0.0);
-  full_apply(ctx, M, f2, r1, -1.0, 1.0);
-  full_apply(ctx, K, f0, r2, 1.0, 0.0);
-  full_apply(ctx, M, f1, r2, -1.0, 1.0);
-  const double nr = norm2_host(ctx, 3 * N, r.get());
-  return nb > 0 ? std::sqrt(nr / nb) : std::sqrt(nr);
+  full_apply(ctx, kkt->M, yh.get(), Myh.get(), 1.0, 0.0);
+  double nb2 = 0, nr2 = 0;
+  const double nm = norm2_host(ctx, N, Myh.get());
+  for (int o = 0; o < nb; ++o) {
+    const double cb = kkt->cb[o];
+    nb2 += cb * cb * nm;
+    // r_o = sum_l cM[o][l] M f_l + cK[o][l] K f_l - cb[o] M yhat
+    k::fill(ctx->stream, N, 0.0, r.get());
+    for (int l = 0; l < nb; ++l) {
+      const double cm = kkt->cM[(size_t)o * nb + l], ck = kkt->cK[(size_t)o * nb + l];
+      if (cm != 0.0) full_apply(ctx, kkt->M, full.get() + l * N, r.get(), cm, 1.0);
+      if (ck != 0.0) full_apply(ctx, kkt->K, full.get() + l * N, r.get(), ck, 1.0);
+    }
+    if (cb != 0.0) k::axpby(ctx->stream, N, -cb, Myh.get(), 1.0, r.get());
+    nr2 += norm2_host(ctx, N, r.get());
+  }
+  return nb2 > 0 ? std::sqrt(nr2 / nb2) : std::sqrt(nr2);
+}
+
+// Block tables of the stationary system (Section 4 with time dropped):
+//   [M 0 K; 0 beta M -M; K -M 0] [y; u; lambda] = [M yhat; 0; 0].
+void kkt_blocks_stationary(iga_kkt* k) {
+  k->nblk = 3;
+  k->nt = 0;
+  k->tau = 0;
+  k->cM = {1, 0, 0, 0, k->beta, -1, 0, -1, 0};
+  k->cK = {0, 0, 1, 0, 0, 0, 1, 0, 0};
+  k->cb = {1, 0, 0};
+}
+
+// Block tables of the time-dependent system (eq. KKTSystem): with calM = I (x) M and
+// calK = I (x) tau K + C (x) M, C lower bidiagonal (1, -1),
+//   [tau calM 0 calK^T; 0 tau beta calM -tau calM; calK -tau calM 0] [y; u; lambda]
+//     = [tau calM yhat; 0; 0], the desired state the same at every step.
+void kkt_blocks_parabolic(iga_kkt* k, int nt, double tau) {
+  const int nb = 3 * nt;
+  k->nblk = nb;
+  k->nt = nt;
+  k->tau = tau;
+  k->cM.assign((size_t)nb * nb, 0.0);
+  k->cK.assign((size_t)nb * nb, 0.0);
+  k->cb.assign(nb, 0.0);
+  auto cm = [&](int o, int l) -> double& { return k->cM[(size_t)o * nb + l]; };
+  auto ck = [&](int o, int l) -> double& { return k->cK[(size_t)o * nb + l]; };
+  const int Y = 0, U = nt, L = 2 * nt;
+  for (int t = 0; t < nt; ++t) {
+    // y rows: tau M y_t + (tau K + M) lambda_t - M lambda_{t+1}
+    cm(Y + t, Y + t) = tau;
+    ck(Y + t, L + t) = tau;
+    cm(Y + t, L + t) += 1.0;
+    if (t + 1 < nt) cm(Y + t, L + t + 1) = -1.0;
+    k->cb[Y + t] = tau;
+    // u rows: tau beta M u_t - tau M lambda_t
+    cm(U + t, U + t) = tau * k->beta;
+    cm(U + t, L + t) = -tau;
+    // lambda rows: (tau K + M) y_t - M y_{t-1} - tau M u_t
+    ck(L + t, Y + t) = tau;
+    cm(L + t, Y + t) += 1.0;
+    if (t > 0) cm(L + t, Y + t - 1) = -1.0;
+    cm(L + t, U + t) = -tau;
+  }
 }
 }  // namespace iga
 
@@ -362,13 +405,15 @@ int iga_btt_get_core(iga_ctx* ctx, const iga_btt* x, int d, double* host_out) {
   return guarded([&] {
     require(ctx && x && host_out && d >= 0 && d < 3, IGA_EINVAL, "btt_get_core: bad argument");
     use_device(ctx);
-    const size_t sz = (size_t)(d == x->ell ? 3 : 1) * x->r[d] * x->n[d] * x->r[d + 1];
+    const size_t sz = (size_t)(d == x->ell ? x->nblk : 1) * x->r[d] * x->n[d] * x->r[d + 1];
     IGA_HIP(hipMemcpyAsync(host_out, x->core[d].get(), sz * sizeof(double), hipMemcpyDeviceToHost,
                            ctx->stream));
     IGA_HIP(hipStreamSynchronize(ctx->stream));
     return IGA_OK;
   });
 }
+
+int iga_btt_blocks(const iga_btt* x) { return x ? x->nblk : IGA_EINVAL; }
 
 int iga_btt_to_full(iga_ctx* ctx, const iga_btt* x, double* dev_out) {
   return guarded([&] {
@@ -400,6 +445,7 @@ int iga_kkt_create(iga_ctx* ctx, const iga_ttop* M, const iga_ttop* K, double be
     k->M = M;
     k->K = K;
     k->beta = beta;
+    kkt_blocks_stationary(k.get());
     if (M->has_ref) {
       // Laplace-form reference operator sum_d c_d (Mbar (x) .. Kbar_d .. (x) Mbar), ranks (1,2,2,1)
       const int p = M->p, b = 2 * p + 1;
@@ -465,6 +511,24 @@ int iga_kkt_create(iga_ctx* ctx, const iga_ttop* M, const iga_ttop* K, double be
   });
 }
 
+int iga_kkt_create_parabolic(iga_ctx* ctx, const iga_ttop* M, const iga_ttop* K, double beta, int nt, double tau,
+                             iga_kkt** out) {
+  return guarded([&] {
+    require(out != nullptr, IGA_EINVAL, "kkt_create_parabolic: NULL out");
+    *out = nullptr;
+    require(nt >= 1 && nt <= IGA_MAX_TIME_STEPS, IGA_EINVAL, "kkt_create_parabolic: nt must be 1..64");
+    require(tau > 0.0 && std::isfinite(tau), IGA_EINVAL, "kkt_create_parabolic: tau must be > 0");
+    iga_kkt* k = nullptr;
+    const int rc = iga_kkt_create(ctx, M, K, beta, &k);
+    if (rc != IGA_OK) return rc;
+    kkt_blocks_parabolic(k, nt, tau);
+    *out = k;
+    return IGA_OK;
+  });
+}
+
+int iga_kkt_blocks(const iga_kkt* kkt) { return kkt ? kkt->nblk : IGA_EINVAL; }
+
 void iga_kkt_destroy(iga_kkt* kkt) {
   if (!kkt) return;
   (void)hipSetDevice(kkt->ctx->device);
@@ -475,6 +539,7 @@ void iga_kkt_destroy(iga_kkt* kkt) {
 static void check_btt_matches(const iga_kkt* kkt, const iga_btt* x) {
   for (int d = 0; d < 3; ++d)
     require(x->n[d] == kkt->M->n[d], IGA_EINVAL, "block-TT mode sizes differ from the operator");
+  require(x->nblk == kkt->nblk, IGA_EINVAL, "block-TT block count differs from the KKT system");
 }
 
 int iga_kkt_apply(iga_ctx* ctx, const iga_kkt* kkt, const iga_btt* x, iga_btt** y) {
@@ -557,6 +622,8 @@ int iga_local_matvec_batched(iga_ctx* ctx, int nprob, const iga_local_problem* p
 int iga_objective(iga_ctx* ctx, const iga_kkt* kkt, const iga_tt* yhat, const iga_btt* f, double* J) {
   return guarded([&] {
     require(ctx && J, IGA_EINVAL, "objective: NULL argument");
+    require(!kkt || (kkt->nt == 0 && (!f || f->nblk == 3)), IGA_EINVAL,
+            "objective: stationary systems only");
     use_device(ctx);
     return objective_impl(ctx, kkt, yhat, f, J, nullptr);
   });
@@ -565,6 +632,8 @@ int iga_objective(iga_ctx* ctx, const iga_kkt* kkt, const iga_tt* yhat, const ig
 int iga_grad_yhat(iga_ctx* ctx, const iga_kkt* kkt, const iga_tt* yhat, const iga_btt* f, double* grad) {
   return guarded([&] {
     require(ctx && grad, IGA_EINVAL, "grad_yhat: NULL argument");
+    require(!kkt || (kkt->nt == 0 && (!f || f->nblk == 3)), IGA_EINVAL,
+            "grad_yhat: stationary systems only");
     use_device(ctx);
     return objective_impl(ctx, kkt, yhat, f, nullptr, grad);
   });
@@ -576,6 +645,7 @@ int iga_grad_geometry(iga_ctx* ctx, const iga_geometry* geo, int degree, const i
   return guarded([&] {
     require(ctx && n, IGA_EINVAL, "grad_geometry: NULL argument");
     require(beta > 0.0, IGA_EINVAL, "grad_geometry: beta must be > 0");
+    require(!f || f->nblk == 3, IGA_EINVAL, "grad_geometry: stationary solutions only");
     use_device(ctx);
     return grad_geometry_impl(ctx, geo, degree, n, opts, beta, yhat, f, grad);
   });

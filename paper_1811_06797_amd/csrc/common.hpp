@@ -155,6 +155,7 @@ struct iga_btt {
   int n[3] = {0, 0, 0};
   int r[4] = {1, 0, 0, 1};
   int ell = 0;
+  int nblk = 3;  // components carried by core ell: [nblk][r_ell][n_ell][r_ell+1]
   iga::DBuf core[3];
 };
 
@@ -177,6 +178,14 @@ struct iga_kkt {
   const iga_ttop* M = nullptr;
   const iga_ttop* K = nullptr;
   double beta = 0;
+  // Block structure: block o of A f is sum_l cM[o][l] M f_l + cK[o][l] K f_l and block o of
+  // the right-hand side is cb[o] M yhat. Stationary: 3 blocks (y, u, lambda). Time-dependent
+  // (nt > 0 implicit Euler steps of length tau): 3 nt blocks y_1..y_nt, u_1..u_nt,
+  // lambda_1..lambda_nt.
+  int nblk = 3;
+  int nt = 0;
+  double tau = 0;
+  std::vector<double> cM, cK, cb;  // [nblk][nblk], [nblk][nblk], [nblk]
   // Laplace-form reference TT-matrix (ranks 1,2,2,1) for the local preconditioner
   iga_ttop* Kref = nullptr;
   // univariate generalised eigen-decompositions of (c_d Kbar_d, Mbar_d): V_d [n][n], lambda_d [n]

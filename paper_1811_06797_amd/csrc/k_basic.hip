@@ -293,6 +293,65 @@ __global__ void kkt_combine_kernel(long e, T k02, T m11, T m12, T k20, T m21, co
   }
 }
 
+// y[o] = sum of coef[t] z[src[t]] over the terms t of output block o (blockIdx.y = o).
+__global__ void combine_blocks_kernel(long e, const int* toff, const int* src, const double* coef,
+                                      const double* z, double* y) {
+  const int o = blockIdx.y;
+  const int t0 = toff[o], t1 = toff[o + 1];
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < e; i += (long)gridDim.x * blockDim.x) {
+    double a = 0.0;
+    for (int t = t0; t < t1; ++t) a += coef[t] * z[(long)src[t] * e + i];
+    y[(long)o * e + i] = a;
+  }
+}
+
+// Per spatial mode (a, i, b) of the reference operator (mass -> 1, stiffness -> mu =
+// lamL[a] + lamN[i] + lamR[b]) the time-dependent KKT system couples the nt steps:
+//   tau y + A^T l = f1,  tau beta u - tau l = f2,  A y - tau u = f3,  A = tau mu I + C
+// (C lower bidiagonal 1, -1). Eliminating u and y leaves the SPD tridiagonal system
+//   (A A^T / tau + tau / beta I) l = A f1 / tau - f3 - f2 / beta,
+// solved by forward elimination and back substitution (Thomas); then
+// y = (f1 - A^T l) / tau and u = (f2 + tau l) / (tau beta). v: [3][nt][e] in place; work:
+// [nt][e] elimination factors.
+__global__ void fd_solve_time_kernel(int r0, int n, int r1, int nt, const double* lamL, const double* lamN,
+                                     const double* lamR, double beta, double tau, double* v, double* work) {
+  const long e = (long)r0 * n * r1;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < e;
+       idx += (long)gridDim.x * blockDim.x) {
+    const int b = idx % r1;
+    const int i = (idx / r1) % n;
+    const int a = idx / ((long)r1 * n);
+    const double aa = tau * (lamL[a] + lamN[i] + lamR[b]) + 1.0;  // diagonal of A
+    const double off = -aa / tau;                                   // off-diagonal of the system
+    double* f1 = v + idx;
+    double* f2 = v + (long)nt * e + idx;
+    double* f3 = v + 2L * nt * e + idx;
+    double cprev = 0.0, dprev = 0.0, f1prev = 0.0;
+    for (int t = 0; t < nt; ++t) {
+      const double x1 = f1[t * e], x2 = f2[t * e], x3 = f3[t * e];
+      const double rhs = (aa * x1 - f1prev) / tau - x3 - x2 / beta;
+      const double diag = (aa * aa + (t > 0 ? 1.0 : 0.0)) / tau + tau / beta;
+      const double den = diag - off * cprev;
+      const double cp = off / den, dp = (rhs - off * dprev) / den;
+      work[t * e + idx] = cp;
+      f3[t * e] = dp;
+      cprev = cp;
+      dprev = dp;
+      f1prev = x1;
+    }
+    double lnext = 0.0;
+    for (int t = nt - 1; t >= 0; --t) {
+      const double l = f3[t * e] - work[t * e + idx] * lnext;
+      const double y = (f1[t * e] - (aa * l - lnext)) / tau;
+      const double u = (f2[t * e] + tau * l) / (tau * beta);
+      f1[t * e] = y;
+      f2[t * e] = u;
+      f3[t * e] = l;
+      lnext = l;
+    }
+  }
+}
+
 // Grouped forms for the batched local operator: blockIdx.y selects the item.
 template <typename T>
 __global__ void fill_segments_kernel(const Segment* seg, T* base) {
@@ -426,6 +485,23 @@ __global__ void coldot_kernel(int m, int k, const double* A, long lda, const dou
 void kkt_combine(hipStream_t s, long e, const KktCoef& c, const double* zM, const double* zK, double* y) {
   if (e <= 0) return;
   kkt_combine_kernel<double><<<grid_for(e), 256, 0, s>>>(e, c.k02, c.m11, c.m12, c.k20, c.m21, zM, zK, y);
+  IGA_HIP(hipGetLastError());
+}
+
+void combine_blocks(hipStream_t s, long e, int nblk, const int* toff, const int* src, const double* coef,
+                    const double* z, double* y) {
+  if (e <= 0 || nblk <= 0) return;
+  require(nblk <= 65535, IGA_EINVAL, "combine_blocks: too many blocks");
+  dim3 g((unsigned)std::min<long>((e + 255) / 256, 1024), nblk);
+  combine_blocks_kernel<<<g, 256, 0, s>>>(e, toff, src, coef, z, y);
+  IGA_HIP(hipGetLastError());
+}
+
+void fd_solve_time(hipStream_t s, int r0, int n, int r1, int nt, const double* lamL, const double* lamN,
+                   const double* lamR, double beta, double tau, double* v, double* work) {
+  const long e = (long)r0 * n * r1;
+  if (e <= 0 || nt <= 0) return;
+  fd_solve_time_kernel<<<grid_for(e), 256, 0, s>>>(r0, n, r1, nt, lamL, lamN, lamR, beta, tau, v, work);
   IGA_HIP(hipGetLastError());
 }
 

@@ -157,6 +157,14 @@ struct KktCoef {
 };
 void kkt_combine(hipStream_t s, long e, const KktCoef& c, const double* zM, const double* zK, double* y);
 void kkt_combine_f32(hipStream_t s, long e, const KktCoef& c, const float* zM, const float* zK, float* y);
+// General block combination: y[o][.] = sum_{t in [toff[o], toff[o+1])} coef[t] z[src[t]][.]
+// for o < nblk, blocks of e elements (device tables).
+void combine_blocks(hipStream_t s, long e, int nblk, const int* toff, const int* src, const double* coef,
+                    const double* z, double* y);
+// Per-mode solve of the time-dependent reference KKT system (nt steps of length tau) in
+// place on v [3][nt][r0 n r1]; work: nt r0 n r1 doubles.
+void fd_solve_time(hipStream_t s, int r0, int n, int r1, int nt, const double* lamL, const double* lamN,
+                   const double* lamR, double beta, double tau, double* v, double* work);
 // Grouped helpers of the batched local operator (one launch for all items; blockIdx.y = item).
 struct Segment {
   long off, len;  // base[off .. off + len) = 0

@@ -39,8 +39,8 @@ static double op_flops(const OpView& A, int r0o, int r0, int r1o, int r1, int nc
 
 double local_flops(const LocalOp& L) {
   const double nb = band_nnz(L.n, L.M.p);
-  return op_flops(L.M, L.out0(), L.r0, L.out1(), L.r1, 3, nb) +
-         op_flops(L.K, L.out0(), L.r0, L.out1(), L.r1, 2, nb);
+  return op_flops(L.M, L.out0(), L.r0, L.out1(), L.r1, L.nblk, nb) +
+         op_flops(L.K, L.out0(), L.r0, L.out1(), L.r1, L.kcols(), nb);
 }
 
 // Element-type plumbing of the staged apply: the FP64 and FP32 matrix-core GEMMs.
@@ -149,6 +149,21 @@ void local_matvec(iga_ctx* ctx, const LocalOp& L, const double* x, double* y, Lo
   const long colsz = (long)L.r0 * L.n * L.r1;
   const int r0o = L.out0(), r1o = L.out1();
   const long osz = (long)r0o * L.n * r1o;  // one output column
+  if (L.toff) {
+    // general block structure: M on every block, K on its block ranges, table combination
+    const int nz = L.nblk + L.kcols();
+    w.z.ensure(ctx, (size_t)nz * osz);
+    op_apply<double>(ctx, L.M, L.M.A, L.M.Ar, L.Mblocks, L.PhiL_M, L.PhiR_M, r0o, L.r0, L.r1, r1o, L.nblk, x,
+                     colsz, w.z.get(), osz, w.tM, w.tM2, w.split, w.padM, 0);
+    int pos = L.nblk;
+    for (int j = 0; j < L.nkr; ++j) {
+      op_apply<double>(ctx, L.K, L.K.A, L.K.Ar, L.Kblocks, L.PhiL_K, L.PhiR_K, r0o, L.r0, L.r1, r1o, L.kn[j],
+                       x + L.kb[j] * colsz, colsz, w.z.get() + pos * osz, osz, w.tK, w.tK2, w.split, w.padK, 1);
+      pos += L.kn[j];
+    }
+    k::combine_blocks(ctx->stream, osz, L.nblk, L.toff, L.src, L.tcoef, w.z.get(), y);
+    return;
+  }
   w.z.ensure(ctx, (size_t)5 * osz);
   op_apply<double>(ctx, L.M, L.M.A, L.M.Ar, L.Mblocks, L.PhiL_M, L.PhiR_M, r0o, L.r0, L.r1, r1o, 3, x, colsz, w.z.get(),
                    osz, w.tM, w.tM2, w.split, w.padM, 0);
@@ -160,6 +175,7 @@ void local_matvec(iga_ctx* ctx, const LocalOp& L, const double* x, double* y, Lo
 void local_matvec_f32(iga_ctx* ctx, const LocalOp& L, const float* x, float* y, LocalWork& w, bool bf16) {
   require(L.M.Af && L.K.Af && L.fPhiL_M && L.fPhiR_M && L.fPhiL_K && L.fPhiR_K, IGA_EINVAL,
           "local_matvec_f32: FP32 operands missing");
+  require(L.toff == nullptr, IGA_EINVAL, "local_matvec_f32: the time-dependent system is FP64 only");
   const long colsz = (long)L.r0 * L.n * L.r1;
   const int r0o = L.out0(), r1o = L.out1();
   const long osz = (long)r0o * L.n * r1o;

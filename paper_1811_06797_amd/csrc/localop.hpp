@@ -28,10 +28,20 @@ struct LocalOp {
   const float* fPhiR_M = nullptr;
   const float* fPhiL_K = nullptr;
   const float* fPhiR_K = nullptr;
+  // General block structure (time-dependent system), null for the stationary 3 blocks:
+  // M acts on all nblk blocks, K on the block ranges [kb[j], kb[j] + kn[j]), j < nkr, and
+  // output block o = sum over its terms t of tcoef[t] z[src[t]], z = [M x_0 .. M x_{nblk-1},
+  // K x of the ranges in order] (device tables toff [nblk + 1], src, tcoef).
+  int nblk = 3;
+  int nkr = 0, kb[2] = {0, 0}, kn[2] = {0, 0};
+  const int* toff = nullptr;
+  const int* src = nullptr;
+  const double* tcoef = nullptr;
   int out0() const { return r0o < 0 ? r0 : r0o; }
   int out1() const { return r1o < 0 ? r1 : r1o; }
-  long size() const { return 3L * r0 * n * r1; }
-  long out_size() const { return 3L * out0() * n * out1(); }
+  long size() const { return (long)nblk * r0 * n * r1; }
+  long out_size() const { return (long)nblk * out0() * n * out1(); }
+  int kcols() const { return toff ? kn[0] + kn[1] : 2; }
 };
 
 struct LocalWork {

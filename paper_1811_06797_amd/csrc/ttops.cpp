@@ -160,7 +160,7 @@ void tt_expand(iga_ctx* ctx, const int n[3], const int r[4], const double* const
 
 void btt_expand(iga_ctx* ctx, const iga_btt* x, double* out) {
   const long N = (long)x->n[0] * x->n[1] * x->n[2];
-  for (int l = 0; l < 3; ++l) {
+  for (int l = 0; l < x->nblk; ++l) {
     const double* c[3];
     for (int d = 0; d < 3; ++d) {
       const long sz = (long)x->r[d] * x->n[d] * x->r[d + 1];
@@ -205,18 +205,19 @@ iga_btt* kkt_apply_impl(iga_ctx* ctx, const iga_kkt* kkt, const iga_btt* x) {
   std::unique_ptr<iga_btt> y(new iga_btt());
   y->ctx = ctx;
   y->ell = x->ell;
+  y->nblk = x->nblk;
+  const int nbk = kkt->nblk;
+  require(x->nblk == nbk, IGA_EINVAL, "kkt_apply: block count differs from the KKT system");
   int s[4];
   s[0] = 1; s[3] = 1;
   for (int d = 0; d < 3; ++d) y->n[d] = x->n[d];
   for (int d = 1; d < 3; ++d) s[d] = (M->R[d] + K->R[d]) * x->r[d];
   for (int d = 0; d < 4; ++d) y->r[d] = s[d];
   Scratch& S = scratch_of(ctx);
-  const double cM[3][3] = {{1, 0, 0}, {0, kkt->beta, -1}, {0, -1, 0}};
-  const double cK[3][3] = {{0, 0, 1}, {0, 0, 0}, {1, 0, 0}};
   for (int d = 0; d < 3; ++d) {
     const int n = x->n[d];
     const bool ellc = (d == x->ell);
-    const int nl = ellc ? 3 : 1;
+    const int nl = ellc ? nbk : 1;
     const long ysz = (long)s[d] * n * s[d + 1];
     y->core[d].reset(ctx, nl * ysz);
     k::fill(ctx->stream, nl * ysz, 0.0, y->core[d].get());
@@ -234,8 +235,8 @@ iga_btt* kkt_apply_impl(iga_ctx* ctx, const iga_kkt* kkt, const iga_btt* x) {
         } else {
           // sum_l c[lo][l] A (.) x_l
           bool first = true;
-          for (int l = 0; l < 3; ++l) {
-            const double c = which == 0 ? cM[lo][l] : cK[lo][l];
+          for (int l = 0; l < nbk; ++l) {
+            const double c = (which == 0 ? kkt->cM : kkt->cK)[(size_t)lo * nbk + l];
             if (c == 0.0) continue;
             core_product(ctx, v, x->core[d].get() + l * xsz, x->r[d], x->r[d + 1], S.t3.get(), c,
                          first ? 0.0 : 1.0);

@@ -28,8 +28,8 @@ _NAMES = {EINVAL: "IGA_EINVAL", ENOMEM: "IGA_ENOMEM", EHIP: "IGA_EHIP", EGEOM: "
 EXPORTED = [
     "iga_ctx_create", "iga_ctx_destroy", "iga_assemble_factors", "iga_ttop_create", "iga_ttop_info",
     "iga_ttop_get_core", "iga_ttop_destroy", "iga_tt_create", "iga_tt_wrap", "iga_tt_from_full", "iga_tt_destroy",
-    "iga_btt_create", "iga_btt_info", "iga_btt_get_core", "iga_btt_to_full", "iga_btt_destroy",
-    "iga_kkt_create", "iga_kkt_destroy", "iga_kkt_apply", "iga_kkt_residual", "iga_amen_solve",
+    "iga_btt_create", "iga_btt_info", "iga_btt_blocks", "iga_btt_get_core", "iga_btt_to_full", "iga_btt_destroy",
+    "iga_kkt_create", "iga_kkt_create_parabolic", "iga_kkt_blocks", "iga_kkt_destroy", "iga_kkt_apply", "iga_kkt_residual", "iga_amen_solve",
     "iga_local_matvec", "iga_local_matvec_batched", "iga_local_matvec_flops", "iga_profile_start", "iga_profile_stop", "iga_objective",
     "iga_grad_yhat", "iga_grad_geometry", "iga_last_error",
 ]
@@ -118,6 +118,9 @@ lib.iga_btt_to_full.argtypes = [P, P, PD]
 lib.iga_btt_destroy.argtypes = [P]
 lib.iga_btt_destroy.restype = None
 lib.iga_kkt_create.argtypes = [P, P, P, C.c_double, C.POINTER(P)]
+lib.iga_kkt_create_parabolic.argtypes = [P, P, P, C.c_double, C.c_int, C.c_double, C.POINTER(P)]
+lib.iga_kkt_blocks.argtypes = [P]
+lib.iga_btt_blocks.argtypes = [P]
 lib.iga_kkt_destroy.argtypes = [P]
 lib.iga_kkt_destroy.restype = None
 lib.iga_kkt_apply.argtypes = [P, P, P, C.POINTER(P)]
@@ -250,9 +253,17 @@ def btt_info(x):
     return list(n), list(r), e.value
 
 
+def btt_blocks(x) -> int:
+    """Number of solution blocks: 3 (stationary) or 3 nt (time-dependent)."""
+    nb = lib.iga_btt_blocks(x)
+    if nb < 0:
+        raise IgaError(nb, last_error())
+    return nb
+
+
 def btt_get_core(ctx, x, d):
     n, r, e = btt_info(x)
-    shape = (r[d], n[d], r[d + 1]) if d != e else (3, r[d], n[d], r[d + 1])
+    shape = (r[d], n[d], r[d + 1]) if d != e else (btt_blocks(x), r[d], n[d], r[d + 1])
     out = np.empty(shape)
     _check(lib.iga_btt_get_core(ctx, x, d, _dptr(out)))
     return out
@@ -263,12 +274,13 @@ def btt_get_cores(ctx, x):
 
 
 def btt_to_full(ctx, x, out=None):
-    """Expand into a device tensor [3][n1][n2][n3] (torch, on the context's device)."""
+    """Expand into a device tensor [nblk][n1][n2][n3] (torch, on the context's device)."""
     import torch
     n, _, _ = btt_info(x)
+    nb = btt_blocks(x)
     if out is None:
-        out = torch.empty((3, n[0], n[1], n[2]), dtype=torch.float64, device="cuda")
-    assert out.is_cuda and out.dtype == torch.float64 and out.is_contiguous() and out.numel() == 3 * np.prod(n)
+        out = torch.empty((nb, n[0], n[1], n[2]), dtype=torch.float64, device="cuda")
+    assert out.is_cuda and out.dtype == torch.float64 and out.is_contiguous() and out.numel() == nb * np.prod(n)
     _check(lib.iga_btt_to_full(ctx, x, C.cast(P(out.data_ptr()), PD)))
     return out
 
@@ -281,6 +293,21 @@ def kkt_create(ctx, M, K, beta: float):
     out = P()
     _check(lib.iga_kkt_create(ctx, M, K, float(beta), C.byref(out)))
     return out
+
+
+def kkt_create_parabolic(ctx, M, K, beta: float, nt: int, tau: float):
+    """Time-dependent KKT system (implicit Euler, nt steps of length tau); solutions have
+    3 nt blocks y_1..y_nt, u_1..u_nt, lambda_1..lambda_nt."""
+    out = P()
+    _check(lib.iga_kkt_create_parabolic(ctx, M, K, float(beta), int(nt), float(tau), C.byref(out)))
+    return out
+
+
+def kkt_blocks(k) -> int:
+    nb = lib.iga_kkt_blocks(k)
+    if nb < 0:
+        raise IgaError(nb, last_error())
+    return nb
 
 
 def kkt_destroy(k):
