@@ -21,6 +21,9 @@ Printed JSON line:
   differentiation  times of the reduced cost, its desired-state gradient and its
              control-point gradient at the FP64 solution;
   batching   64 uneven local TT-matvecs, one call per problem versus one batched call;
+  time_dependent  the time-dependent KKT system on the same geometry and desired state
+             with 10 implicit Euler steps (3 x 10 x 64^3 = 7.9 M unknowns), FP64 AMEn to
+             1e-6: solve time, residual, ranks, time parts;
   roofline   the dominant kernel of the local TT-matvec at the microbenchmark shape
              (r, R_M, R_K, n, p) = (32, 10, 60, 64, 3): the banded middle stage of
              the K operator, timed by the library with HIP events on its stream;
@@ -195,6 +198,30 @@ def batching_bench(iga, ctx, torch, nprob=64, seed=100, iters=3):
     return out
 
 
+def time_dependent_bench(iga, ctx, torch, geo, c, Y, nt=10):
+    """The time-dependent system (implicit Euler, nt steps, tau = 1 / nt) on the workload's
+    geometry and desired state, FP64, AMEn tolerance 1e-6: one warm-up solve, one timed."""
+    n, p, beta = c["n"], c["degree"], c["beta"]
+    M, K, _ = iga.assemble_factors(ctx, geo, p, n, weight_tol=c["weight_tol"])
+    kk = iga.kkt_create_parabolic(ctx, M, K, beta, nt, 1.0 / nt)
+    out = {"time_steps": nt, "unknowns": 3 * nt * n ** 3}
+    for i in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sol, st, rc = iga.amen_solve(ctx, kk, Y, 1e-6)
+        t1 = time.perf_counter()
+        iga.btt_destroy(sol)
+    out.update({"solve_time_s": t1 - t0, "status": rc, "kkt_residual": st["residual"],
+                "half_sweeps": st["half_sweeps"], "ranks": st["ranks"], "local_iterations": st["local_iterations"],
+                "t_local_matvec": st["t_local_matvec"], "t_svd": st["t_svd"], "t_precond": st["t_precond"],
+                "local_matvec_gflops": st["local_matvec_flops"] / st["t_local_matvec"] / 1e9
+                if st["t_local_matvec"] else None})
+    iga.kkt_destroy(kk)
+    iga.ttop_destroy(M)
+    iga.ttop_destroy(K)
+    return out
+
+
 def micro_bench(iga, ctx, torch, iters):
     """Local TT-matvec at the microbenchmark shape on seeded N(0,1) inputs; the library times
     the banded stage of each operator with HIP events on its stream."""
@@ -330,6 +357,7 @@ def main():
     gflops = flops / t_mv / 1e9
     mixed = mixed_compare(iga, ctx, torch, geo, c, Y, max(1, min(a.steps, 3)))
     batching = batching_bench(iga, ctx, torch)
+    timedep = time_dependent_bench(iga, ctx, torch, geo, c, Y)
     micro, prob = micro_bench(iga, ctx, torch, a.micro_iters)
     prof = micro["profile"]
     k_ms = prof["ms"][1] / max(prof["launches"][1], 1)
@@ -363,6 +391,7 @@ def main():
         "mixed_vs_fp64": {k: v for k, v in mixed.items() if k != "differentiation"},
         "differentiation": mixed["differentiation"],
         "batching": batching,
+        "time_dependent": timedep,
         "microbench_local_matvec": {k: micro[k] for k in ("shape", "ms", "gflops", "flops", "fp32", "bf16")},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,

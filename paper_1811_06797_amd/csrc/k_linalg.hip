@@ -240,6 +240,8 @@ constexpr int OSB = 16;        // columns per block
 constexpr int OSP = 2 * OSB;   // columns per block pair
 constexpr int OST = 256;       // threads per pair workgroup
 constexpr int OSR = 64;        // rows per LDS tile
+constexpr int OSL = OSP + 4;   // LDS row pitch: the 16 (k, column) fragment addresses of one
+                               // FP64 MFMA step fall in distinct banks
 
 __device__ inline void circle_pair(int t, int round, int nplayers, int& a, int& b) {
   auto player = [&](int pos) { return pos == 0 ? 0 : 1 + (pos - 1 + round) % (nplayers - 1); };
@@ -248,40 +250,56 @@ __device__ inline void circle_pair(int t, int round, int nplayers, int& a, int& 
   if (a > b) { const int x = a; a = b; b = x; }
 }
 
-// One round of the one-sided block Jacobi method, in three launches so that the work over
+// One round of the one-sided block Jacobi method, in four launches so that the work over
 // the m rows spreads across the chip. The round-robin schedule pairs block I with block J;
 // for each pair:
 //   osbj_gram:  partial 32 x 32 Gram matrices of the pair's columns, one per chunk of rows;
-//   osbj_rot:   their sum (fixed order), diagonalised by cyclic Jacobi in LDS by one wave,
-//               giving the rotation W (32 x 32); flags[pair] = 1 if anything rotated;
+//   osbj_sum:   their sum (fixed order);
+//   osbj_rot:   cyclic Jacobi on the summed Gram matrix in LDS, giving the rotation W
+//               (32 x 32); flags[pair] = 1 if anything rotated;
 //   osbj_apply: [B_I B_J] <- [B_I B_J] W and [V_I V_J] <- [V_I V_J] W, chunk by chunk.
+// The Gram and apply products run on the FP64 matrix cores (v_mfma_f64_4x4x4_4b, lane
+// l = 16 lx + 4 lb + ly: A operand at (row 4 r + ly, k lx), B operand at (k lx, column
+// 16 c + 4 lb + ly), result at (row 4 r + lx, column 16 c + 4 lb + ly)).
 __global__ __launch_bounds__(OST) void osbj_gram_kernel(const double* B, int m, long ldb, int nb, int round,
                                                         int chunk, double* P) {
-  __shared__ double T[OSR][OSP + 1];
+  __shared__ double T[OSR][OSL];
   const int tid = threadIdx.x, pair = blockIdx.x, c = blockIdx.y;
   int I, J;
   circle_pair(pair, round, nb, I, J);
   auto col = [&](int q) { return q < OSB ? I * OSB + q : J * OSB + (q - OSB); };
   const int rb = c * chunk, re = min(m, rb + chunk);
-  double acc[4] = {0, 0, 0, 0};
+  // wave w owns Gram rows 8 w .. 8 w + 7 and all 32 columns: G[i][j] = sum_row T[row][i] T[row][j]
+  const int wave = tid / 64, lane = tid % 64;
+  const int lx = lane / 16, lb = (lane / 4) % 4, ly = lane % 4;
+  const int wm0 = 8 * wave;
+  double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
   for (int r0 = rb; r0 < re; r0 += OSR) {
     for (int e = tid; e < OSR * OSP; e += OST) {
       const int rr = e / OSP, q = e % OSP, row = r0 + rr;
       T[rr][q] = row < re ? B[(long)row * ldb + col(q)] : 0.0;
     }
     __syncthreads();
+#pragma unroll 4
+    for (int ks = 0; ks < OSR; ks += 4) {
+      double fa[2], fb[2];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int e = tid + OST * s, i = e / OSP, j = e % OSP;
-      double a = acc[s];
-      for (int rr = 0; rr < OSR; ++rr) a = fma(T[rr][i], T[rr][j], a);
-      acc[s] = a;
+      for (int r = 0; r < 2; ++r) fa[r] = T[ks + lx][wm0 + 4 * r + ly];
+#pragma unroll
+      for (int cc = 0; cc < 2; ++cc) fb[cc] = T[ks + lx][16 * cc + 4 * lb + ly];
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int cc = 0; cc < 2; ++cc)
+          acc[r][cc] = __builtin_amdgcn_mfma_f64_4x4x4f64(fa[r], fb[cc], acc[r][cc], 0, 0, 0);
     }
     __syncthreads();
   }
   double* out = P + ((long)pair * gridDim.y + c) * (OSP * OSP);
 #pragma unroll
-  for (int s = 0; s < 4; ++s) out[tid + OST * s] = acc[s];
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int cc = 0; cc < 2; ++cc) out[(wm0 + 4 * r + lx) * OSP + 16 * cc + 4 * lb + ly] = acc[r][cc];
 }
 
 constexpr int ORT = 256;  // threads per pair in osbj_rot: one per 2 x 2 block of the 32 x 32 Gram matrix
@@ -401,8 +419,8 @@ __global__ __launch_bounds__(ORT) void osbj_rot_kernel(const double* Gsum, doubl
 __global__ __launch_bounds__(OST) void osbj_apply_kernel(double* B, int m, long ldb, double* V, int kv, long ldv,
                                                          int nb, int round, int chunk, int nchunkB,
                                                          const double* Wg, const int* flags) {
-  __shared__ double W[OSP][OSP + 1];
-  __shared__ double T[OSR][OSP + 1];
+  __shared__ double W[OSP][OSL];
+  __shared__ double T[OSR][OSL];
   const int tid = threadIdx.x, pair = blockIdx.x, c = blockIdx.y;
   if (!flags[pair]) return;
   int I, J;
@@ -414,6 +432,10 @@ __global__ __launch_bounds__(OST) void osbj_apply_kernel(double* B, int m, long 
   const int rows = onB ? m : kv;
   const long ld = onB ? ldb : ldv;
   const int rb = (onB ? c : c - nchunkB) * chunk, re = min(rows, rb + chunk);
+  // wave w owns tile rows 16 w .. 16 w + 15 and all 32 columns: X[row][q] = sum_t T[row][t] W[t][q]
+  const int wave = tid / 64, lane = tid % 64;
+  const int lx = lane / 16, lb = (lane / 4) % 4, ly = lane % 4;
+  const int wm0 = 16 * wave;
   __syncthreads();
   for (int r0 = rb; r0 < re; r0 += OSR) {
     for (int e = tid; e < OSR * OSP; e += OST) {
@@ -421,12 +443,26 @@ __global__ __launch_bounds__(OST) void osbj_apply_kernel(double* B, int m, long 
       T[rr][q] = row < re ? X[(long)row * ld + col(q)] : 0.0;
     }
     __syncthreads();
-    for (int e = tid; e < OSR * OSP; e += OST) {
-      const int rr = e / OSP, q = e % OSP, row = r0 + rr;
+    double acc[4][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+#pragma unroll
+    for (int ks = 0; ks < OSP; ks += 4) {
+      double fa[4], fb[2];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) fa[r] = T[wm0 + 4 * r + ly][ks + lx];
+#pragma unroll
+      for (int cc = 0; cc < 2; ++cc) fb[cc] = W[ks + lx][16 * cc + 4 * lb + ly];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int cc = 0; cc < 2; ++cc)
+          acc[r][cc] = __builtin_amdgcn_mfma_f64_4x4x4f64(fa[r], fb[cc], acc[r][cc], 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = r0 + wm0 + 4 * r + lx;
       if (row >= re) continue;
-      double a = 0.0;
-      for (int t = 0; t < OSP; ++t) a = fma(T[rr][t], W[t][q], a);
-      X[(long)row * ld + col(q)] = a;
+#pragma unroll
+      for (int cc = 0; cc < 2; ++cc) X[(long)row * ld + col(16 * cc + 4 * lb + ly)] = acc[r][cc];
     }
     __syncthreads();
   }
