@@ -187,7 +187,7 @@ class Amen {
   void orthonormal_columns(double* A, int m, int k, int kmax, DBuf& Q, int& q, double rel_floor);
   // smallest rank whose truncated core keeps the local residual <= target (see move_right)
   template <class Recon>
-  int residual_rank(int d, int kmin, int kmax, Recon recon);
+  int residual_rank(int d, int kmin, int kmax, const std::vector<double>& sigma, Recon recon);
   double local_res_of(int d, const double* xk);
 
   iga_ctx* ctx_;
@@ -793,21 +793,87 @@ double Amen::local_res_of(int d, const double* xk) {
 
 // Residual-based truncation: the smallest k in [kmin, kmax] such that the rank-k
 // approximation of the solved core has local residual <= max(tol / 2, 1.5 r_full),
-// r_full the residual of the untruncated core (bisection; the residual decreases with k).
+// r_full the residual of the untruncated core (the residual decreases with k; kmax if no
+// k passes). Each test costs a local matvec, so the search starts from a prediction: one
+// probe at the rank where the singular-value tail t(k) = (sum_{j >= k} s_j^2)^(1/2) drops
+// below target * t(0) fits r(k)^2 = r_full^2 + (a t(k))^2, the model's smallest passing
+// rank is tested, and the search gallops away from it in steps 1, 2, 4, .. until the test
+// changes, then bisects the last step.
 template <class Recon>
-int Amen::residual_rank(int d, int kmin, int kmax, Recon recon) {
+int Amen::residual_rank(int d, int kmin, int kmax, const std::vector<double>& sigma, Recon recon) {
   const long N = (long)nb_ * r_[d] * n_[d] * r_[d + 1];
   xk_.ensure(ctx_, N);
   const double full = local_res_of(d, X_[d].get());
   const double target = std::max(0.5 * tol_, 1.5 * full);
-  auto ok = [&](int kk) {
+  std::vector<signed char> known((size_t)kmax + 1, -1);
+  double probe_res = 0.0;
+  auto test = [&](int kk, double* resid) {
+    if (known[kk] >= 0 && !resid) return known[kk] == 1;
     recon(kk, xk_.get());
-    return local_res_of(d, xk_.get()) <= target;
+    const double r = local_res_of(d, xk_.get());
+    if (resid) *resid = r;
+    known[kk] = r <= target ? 1 : 0;
+    return r <= target;
   };
-  int lo = std::max(1, kmin), hi = kmax;
+  auto ok = [&](int kk) { return test(kk, nullptr); };
+  int lo = std::max(1, kmin), hi = kmax;  // the answer lies in [lo, hi]
   if (lo >= hi) return hi;
-  if (!ok(hi)) return hi;
-  if (ok(lo)) return lo;
+  // singular-value tails t(k), k = 0 .. kmax
+  std::vector<double> tail((size_t)kmax + 1, 0.0);
+  {
+    double acc = 0.0;
+    for (int j = (int)sigma.size() - 1; j >= 0; --j) {
+      acc += sigma[j] * sigma[j];
+      if (j <= kmax) tail[j] = std::sqrt(acc);
+    }
+  }
+  int kp = hi;
+  for (int k = lo; k <= hi; ++k)
+    if (tail[k] <= target * tail[0]) { kp = k; break; }
+  test(kp, &probe_res);
+  int guess = kp;
+  if (tail[kp] > 0.0 && probe_res > full) {
+    const double a2 = (probe_res * probe_res - full * full) / (tail[kp] * tail[kp]);
+    const double room = target * target - full * full;
+    guess = hi;
+    if (room > 0.0)
+      for (int k = lo; k <= hi; ++k)
+        if (a2 * tail[k] * tail[k] <= room) { guess = k; break; }
+  }
+  const int g = std::min(std::max(guess, lo), hi);
+  if (ok(g)) {
+    // passes: step down until a rank fails
+    hi = g;
+    int step = 1;
+    while (hi > lo) {
+      const int t = std::max(lo, hi - step);
+      if (ok(t)) {
+        hi = t;
+        step *= 2;
+      } else {
+        lo = t;
+        break;
+      }
+    }
+    if (hi == lo) return hi;
+  } else {
+    // fails: step up until a rank passes
+    lo = g;
+    int step = 1;
+    while (true) {
+      const int t = std::min(hi, lo + step);
+      if (t == hi) {
+        if (t == g || !ok(t)) return hi;
+        break;
+      }
+      if (ok(t)) {
+        hi = t;
+        break;
+      }
+      lo = t;
+      step *= 2;
+    }
+  }
   while (hi - lo > 1) {
     const int mid = (lo + hi) / 2;
     if (ok(mid)) hi = mid; else lo = mid;
@@ -851,7 +917,7 @@ void Amen::move_right(int d) {
       const int perm[4] = {2, 0, 1, 3};
       k::permute4(st_, Fk.get(), dims, perm, out);
     };
-    rt = residual_rank(d, 1, std::min(rmax, std::max(nz, 1)), recon);
+    rt = residual_rank(d, 1, std::min(rmax, std::max(nz, 1)), s.sigma, recon);
   }
   static thread_local char ph[200];
   std::snprintf(ph, sizeof ph, "move_right d=%d r0=%d r1=%d m=%d K3=%d rt=%d rho=%d,%d r2=%d", d, r0, r1, m, K3, rt, rho_[d], rho_[d + 1], r_[d + 2]);
@@ -956,7 +1022,7 @@ void Amen::move_left(int d) {
       // F_k = V_k B_k^T: (nb r0) x (n r1) in the natural [l][a][j][b] layout
       k::gemm_rm(st_, K3, m, kk, s.V.get(), s.p, false, s.B.get(), s.p, true, out, m);
     };
-    rt = residual_rank(d, 1, std::min(rmax, std::max(nz, 1)), recon);
+    rt = residual_rank(d, 1, std::min(rmax, std::max(nz, 1)), s.sigma, recon);
   }
   static thread_local char ph[200];
   std::snprintf(ph, sizeof ph, "move_left d=%d r0=%d r1=%d m=%d K3=%d rt=%d rho=%d,%d rp=%d", d, r0, r1, m, K3, rt, rho_[d], rho_[d + 1], r_[d - 1]);
