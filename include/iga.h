@@ -126,7 +126,9 @@ typedef struct {
   double t_precond;
   double t_krylov_other;
   double t_interfaces;
-  double t_svd;
+  double t_svd;                /* truncation steps: SVD, enrichment, next-core update (the
+                                  local matvecs of the residual-based rank search are in
+                                  t_local_matvec) */
   double t_residual;
   /* mixed form (precision IGA_FP32 or IGA_BF16): local matvecs with low-precision
    * contractions (FP32 or BF16 products, as chosen) inside the refinement's inner solves,
@@ -235,6 +237,22 @@ int iga_kkt_residual(iga_ctx* ctx, const iga_kkt* kkt, const iga_tt* yhat, const
 int iga_amen_solve(iga_ctx* ctx, const iga_kkt* kkt, const iga_tt* yhat, double tol,
                    const iga_amen_opts* opts, const iga_btt* x0, iga_btt** sol,
                    iga_amen_stats* stats);
+
+/* SWITCHED OFF: returns IGA_EINVAL after checking its arguments (a run of 64 problems of
+ * the batching workload through it faulted the GPU; the cause has not been found).
+ * Batching form for whole solves: nprob independent block-AMEn solves, each exactly as
+ * iga_amen_solve(ctx, kkts[i], yhats[i], tols[i], opts, NULL, &sols[i], &stats[i]), run
+ * concurrently by nworkers (1..64) host threads. Each worker owns a stream and a workspace
+ * on ctx's device for the duration of the call (default priority), so the solves' small
+ * launches overlap on the GPU; each solve runs the same kernels in the same order as alone,
+ * so results are those of the sequential calls. Every kkts[i] must live on ctx's device.
+ * status[i] receives each solve's return code; sols[i] its solution (owned by the caller,
+ * in ctx) for every status IGA_OK, IGA_ENOCONV or IGA_ERANK, else NULL. stats may be NULL
+ * (else nprob entries). Returns IGA_OK, or the first failing problem's code when a solve
+ * produced no solution. Memory: up to nworkers solves' workspaces at once. Synchronises. */
+int iga_amen_solve_many(iga_ctx* ctx, int nprob, const iga_kkt* const* kkts, const iga_tt* const* yhats,
+                        const double* tols, const iga_amen_opts* opts, int nworkers, iga_btt** sols,
+                        iga_amen_stats* stats, int* status);
 
 /* The projected local TT-matvec of one block-AMEn step (eq. KKT_red), on raw
  * device buffers: for l = 0..2 and A in {M, K}

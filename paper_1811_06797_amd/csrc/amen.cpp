@@ -886,7 +886,7 @@ void Amen::move_right(int d) {
   const int r0 = r_[d], r1 = r_[d + 1], n = n_[d];
   const int m = r0 * n;
   const long e = (long)r0 * n * r1;
-  const int sid = t_svd_.begin();
+  int sid = t_svd_.begin();
   // residual projections with the solved core
   DBuf zc, rz;
   if (kick_ > 0) {
@@ -917,7 +917,10 @@ void Amen::move_right(int d) {
       const int perm[4] = {2, 0, 1, 3};
       k::permute4(st_, Fk.get(), dims, perm, out);
     };
+    // the search's local matvecs are timed as local matvecs, not as truncation
+    t_svd_.end(sid);
     rt = residual_rank(d, 1, std::min(rmax, std::max(nz, 1)), s.sigma, recon);
+    sid = t_svd_.begin();
   }
   static thread_local char ph[200];
   std::snprintf(ph, sizeof ph, "move_right d=%d r0=%d r1=%d m=%d K3=%d rt=%d rho=%d,%d r2=%d", d, r0, r1, m, K3, rt, rho_[d], rho_[d + 1], r_[d + 2]);
@@ -1001,7 +1004,7 @@ void Amen::move_left(int d) {
   g_phase = "move_left";
   const int r0 = r_[d], r1 = r_[d + 1], n = n_[d];
   const int m = n * r1;
-  const int sid = t_svd_.begin();
+  int sid = t_svd_.begin();
   DBuf zc, rz;
   if (kick_ > 0) {
     zc.reset(ctx_, (long)nb_ * rho_[d] * n * rho_[d + 1]);
@@ -1022,7 +1025,10 @@ void Amen::move_left(int d) {
       // F_k = V_k B_k^T: (nb r0) x (n r1) in the natural [l][a][j][b] layout
       k::gemm_rm(st_, K3, m, kk, s.V.get(), s.p, false, s.B.get(), s.p, true, out, m);
     };
+    // the search's local matvecs are timed as local matvecs, not as truncation
+    t_svd_.end(sid);
     rt = residual_rank(d, 1, std::min(rmax, std::max(nz, 1)), s.sigma, recon);
+    sid = t_svd_.begin();
   }
   static thread_local char ph[200];
   std::snprintf(ph, sizeof ph, "move_left d=%d r0=%d r1=%d m=%d K3=%d rt=%d rho=%d,%d rp=%d", d, r0, r1, m, K3, rt, rho_[d], rho_[d + 1], r_[d - 1]);

@@ -2,6 +2,8 @@
 // of symmetric matrices, Gauss-Jordan inverse, column gathers and block copies.
 #include <algorithm>
 
+#include <mutex>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -513,15 +515,15 @@ int jacobi_lds_max() { return LDS_MAX_K; }
 void jacobi_eig(hipStream_t s, int nmat, int k, double* H, long strideH, double* W, long strideW,
                 double tol, int max_sweeps, int* sweeps_out) {
   require(k >= 1 && k <= 1024, IGA_EINVAL, "jacobi_eig: k out of range");
-  static bool attr_set = false;
-  if (!attr_set) {
+  // once per process (solves may run in several host threads)
+  static std::once_flag attr_once;
+  std::call_once(attr_once, [] {
     IGA_HIP(hipFuncSetAttribute((const void*)jacobi_kernel<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (LDS_MAX_K + 1) * LDS_MAX_K * (int)sizeof(double)));
     IGA_HIP(hipFuncSetAttribute((const void*)jacobi_kernel<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 ((LDS_BOTH_MAX_K + 1) * LDS_BOTH_MAX_K + LDS_BOTH_MAX_K * LDS_BOTH_MAX_K) *
                                     (int)sizeof(double)));
-    attr_set = true;
-  }
+  });
   if (k <= LDS_BOTH_MAX_K) {
     const size_t lds = ((size_t)(k + 1) * k + (size_t)k * k) * sizeof(double);
     jacobi_kernel<2><<<nmat, JT, lds, s>>>(k, H, strideH, W, strideW, tol, max_sweeps, sweeps_out);

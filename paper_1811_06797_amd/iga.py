@@ -30,6 +30,7 @@ EXPORTED = [
     "iga_ttop_get_core", "iga_ttop_destroy", "iga_tt_create", "iga_tt_wrap", "iga_tt_from_full", "iga_tt_destroy",
     "iga_btt_create", "iga_btt_info", "iga_btt_blocks", "iga_btt_get_core", "iga_btt_to_full", "iga_btt_destroy",
     "iga_kkt_create", "iga_kkt_create_parabolic", "iga_kkt_blocks", "iga_kkt_destroy", "iga_kkt_apply", "iga_kkt_residual", "iga_amen_solve",
+    "iga_amen_solve_many",
     "iga_local_matvec", "iga_local_matvec_batched", "iga_local_matvec_flops", "iga_profile_start", "iga_profile_stop", "iga_objective",
     "iga_grad_yhat", "iga_grad_geometry", "iga_last_error",
 ]
@@ -120,6 +121,8 @@ lib.iga_btt_destroy.restype = None
 lib.iga_kkt_create.argtypes = [P, P, P, C.c_double, C.POINTER(P)]
 lib.iga_kkt_create_parabolic.argtypes = [P, P, P, C.c_double, C.c_int, C.c_double, C.POINTER(P)]
 lib.iga_kkt_blocks.argtypes = [P]
+lib.iga_amen_solve_many.argtypes = [P, C.c_int, C.POINTER(P), C.POINTER(P), C.POINTER(C.c_double), C.POINTER(AmenOpts),
+                                    C.c_int, C.POINTER(P), C.c_void_p, C.POINTER(C.c_int)]
 lib.iga_btt_blocks.argtypes = [P]
 lib.iga_kkt_destroy.argtypes = [P]
 lib.iga_kkt_destroy.restype = None
@@ -337,6 +340,31 @@ def amen_solve(ctx, kkt, yhat, tol: float, x0=None, raise_on_noconv: bool = Fals
     if rc != OK and not (rc in (ENOCONV, ERANK) and not raise_on_noconv and sol):
         raise IgaError(rc, last_error())
     return sol, st.as_dict(), rc
+
+
+def amen_solve_many(ctx, kkts, yhats, tols, workers: int = 8, **opts):
+    """Independent solves run concurrently (iga_amen_solve_many). Returns (solution handles,
+    stats dicts, status codes); a handle is None where a solve produced no solution."""
+    n = len(kkts)
+    o = AmenOpts()
+    for k, v in opts.items():
+        setattr(o, k, v)
+    if not isinstance(tols, (list, tuple)):
+        tols = [tols] * n
+    K = (P * n)(*kkts)
+    Y = (P * n)(*yhats)
+    T = (C.c_double * n)(*[float(t) for t in tols])
+    S = (P * n)()
+    st = (AmenStats * n)()
+    rc = (C.c_int * n)()
+    code = lib.iga_amen_solve_many(ctx, n, K, Y, T, C.byref(o), int(workers), S, C.cast(st, C.c_void_p), rc)
+    sols = [P(S[i]) if S[i] else None for i in range(n)]
+    if code != OK:
+        for s_ in sols:
+            if s_ is not None:
+                btt_destroy(s_)
+        raise IgaError(code, last_error())
+    return sols, [st[i].as_dict() for i in range(n)], list(rc)
 
 
 def local_matvec(ctx, r0, n, r1, degree, RM0, RM1, RK0, RK1, PhiL_M, PhiR_M, PhiL_K, PhiR_K, Mcore, Kcore,

@@ -26,7 +26,7 @@ __all__ = [
     "Geometry", "open_uniform_knots", "greville_abscissae", "interior_greville",
     "identity_geometry", "box_geometry", "affine_geometry", "twisted_annulus",
     "perturbed_cube", "yhat_sine", "yhat_fourier", "random_tt", "random_btt",
-    "random_local_problem", "tt_ranks_of", "CONFIGS", "config",
+    "random_local_problem", "tt_ranks_of", "CONFIGS", "config", "batch_problems",
 ]
 
 
@@ -247,6 +247,29 @@ CONFIGS = {
     "c5": dict(name="twisted annulus p=3 n=256", geometry="twisted_annulus", degree=3, n=256, beta=1e-6,
                yhat="fourier", tol=1e-6, weight_tol=1e-10, seed_geo=5, seed_y=6, r_max=40),
 }
+
+
+def batch_problems(count: int = 64, seed0: int = 100, n_choices=(32, 48, 64, 96, 128)):
+    """Independent problems of the batching workload, problem i from seed seed0 + i: n drawn
+    uniformly from n_choices, degree from {2, 3}, log10 beta uniform in [-8, -2], the geometry a
+    perturbed cube (amplitude 0.07: at 0.1 one of the 64 draws folds near a face) or a twisted
+    annulus (coin flip, own seed), a Fourier desired state.
+    Returns a list of (geometry, yhat cores, params)."""
+    out = []
+    for i in range(count):
+        rng = np.random.default_rng(seed0 + i)
+        n = int(rng.choice(n_choices))
+        degree = int(rng.integers(2, 4))
+        beta = float(10.0 ** rng.uniform(-8.0, -2.0))
+        gseed = int(rng.integers(0, 1 << 30))
+        if rng.random() < 0.5:
+            geo, gname = perturbed_cube(seed=gseed, amplitude=0.07), "perturbed_cube"
+        else:
+            geo, gname = twisted_annulus(seed=gseed), "twisted_annulus"
+        y = yhat_fourier(n, degree, seed=gseed + 1)
+        out.append((geo, y, dict(name="batch %d" % i, geometry=gname, degree=degree, n=n, beta=beta,
+                                 seed=seed0 + i)))
+    return out
 
 
 def config(key: str, n: int | None = None):

@@ -160,3 +160,14 @@ def test_matrix_free_box_matches_assembled_rows(mode):
     refK = (K @ f.ravel()).reshape(n, n, n)[0:3, 2:7, 4:6]
     assert np.abs(oM[0] - refM).max() < 1e-14 * np.abs(refM).max() * 10
     assert np.abs(oK[0] - refK).max() < 1e-13 * np.abs(refK).max() * 10
+
+
+def test_batch_workload_geometries_do_not_fold():
+    """Every geometry of the 64-problem batching workload is one-to-one: det grad G > 0 on a
+    grid that reaches within 0.005 of every face (the library refuses folded maps)."""
+    from oracle import geometry
+    g = np.concatenate([np.linspace(0, 1, 41), [0.005, 0.995, 0.0125, 0.9875]])
+    for geo, yc, c in synth.batch_problems(64):
+        G, J = geometry.evaluate(geo, g, g, g)
+        d = np.linalg.det(np.moveaxis(J.reshape(3, 3, -1), -1, 0)) if J.shape[0] == 3 else np.linalg.det(J)
+        assert d.min() > 0, c["name"]
