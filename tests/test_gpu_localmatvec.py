@@ -135,6 +135,47 @@ def test_local_matvec_bf16_benchmark_shape(gpu_ctx):
     assert rel_err(y, _reference_bf16(prob, p, 1e-6)) < 2e-4
 
 
+def _sampled_reference(prob, p, beta, samples):
+    """Outputs y[l][a', i, b'] of the local matvec written out one by one from the definition
+    sum PhiL[al][a'][a] A[al][i][j][be] x[a][j][b] PhiR[be][b'][b] over the band j = i + o - p
+    (the full product is out of reach of the oracle at these sizes)."""
+    x = prob["x"]
+
+    def one(PhiL, core, PhiR, xl, a1, i, b1):
+        n = xl.shape[1]
+        js = [i + o - p for o in range(2 * p + 1) if 0 <= i + o - p < n]
+        os_ = [j - i + p for j in js]
+        t1 = np.einsum("pa,ajb->pjb", PhiL[:, a1, :], xl[:, js, :])
+        t2 = np.einsum("pjq,pjb->qb", core[:, i, os_, :], t1)
+        return np.einsum("qb,qb->", t2, PhiR[:, b1, :])
+
+    out = []
+    for (a1, i, b1) in samples:
+        Mf = [one(prob["PhiL_M"], prob["M"], prob["PhiR_M"], x[l], a1, i, b1) for l in range(3)]
+        Kf = [one(prob["PhiL_K"], prob["K"], prob["PhiR_K"], x[l], a1, i, b1) for l in range(3)]
+        out.append(kkt_rows(Mf, Kf, beta))
+    return np.array(out)  # [sample][row]
+
+
+@pytest.mark.parametrize("shape", [(40, 15, 80, 128, 3), (40, 10, 60, 256, 3)])
+def test_local_matvec_full_size_sampled(gpu_ctx, shape):
+    """The n = 128 and n = 256 benchmark shapes (r, R_M, R_K, n, p): 24 sampled outputs of each
+    of the three rows against the definition, including the first and last rows of the band."""
+    from paper_1811_06797_amd import iga
+    r, RM, RK, n, p = shape
+    prob = synth.random_local_problem(r, RM, RK, n, p, seed=7)
+    rng = np.random.default_rng(11)
+    samples = [(int(rng.integers(r)), int(i), int(rng.integers(r)))
+               for i in [0, 1, 2, n // 2, n - 3, n - 2, n - 1] + list(rng.integers(0, n, 17))]
+    ref = _sampled_reference(prob, p, 1e-6, samples)
+    y = _run(gpu_ctx, prob, r, n, p, RM, RK, 1e-6, iga.FP64)
+    got = np.array([[y[l, a1, i, b1] for l in range(3)] for (a1, i, b1) in samples])
+    assert rel_err(got, ref) < 1e-12
+    y32 = _run(gpu_ctx, prob, r, n, p, RM, RK, 1e-6, iga.FP32)
+    got32 = np.array([[y32[l, a1, i, b1] for l in range(3)] for (a1, i, b1) in samples])
+    assert rel_err(got32, ref) < FP32_TOL
+
+
 def test_local_matvec_flops_formula():
     from paper_1811_06797_amd import iga
     r, RM, RK, n, p = 32, 10, 60, 64, 3
