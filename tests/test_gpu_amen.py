@@ -201,3 +201,40 @@ def test_rank_cap_is_reported(gpu_ctx):
     f, st, rc, res, r = _solve(gpu_ctx, geo, p, n, 1e-6, synth.yhat_fourier(n, p, seed=2), 1e-10, r_max=3,
                                nswp=4)
     assert rc == iga.ERANK and st["converged"] == 0 and max(r[1], r[2]) >= 3
+
+
+def test_trends_in_beta(gpu_ctx):
+    """Section 6: with a smaller control cost beta the solution is harder, and the solver needs
+    at least as much rank and work; the objective grows and the control shrinks as beta grows
+    (the oracle pins the latter on its direct solves)."""
+    from paper_1811_06797_amd import iga
+    geo = synth.twisted_annulus(seed=1)
+    n, p = 16, 3
+    yc = synth.yhat_fourier(n, p, seed=2)
+    M, K, _ = iga.assemble_factors(gpu_ctx, geo, p, n, weight_tol=1e-10)
+    Y = iga.tt_create(gpu_ctx, yc)
+    rows = []
+    try:
+        for beta in (1e-1, 1e-3, 1e-5, 1e-7):
+            kk = iga.kkt_create(gpu_ctx, M, K, beta)
+            sol, st, rc = iga.amen_solve(gpu_ctx, kk, Y, 1e-8)
+            try:
+                assert rc == 0 and st["residual"] < 1e-6
+                J = iga.objective(gpu_ctx, kk, Y, sol)
+                u = iga.btt_to_full(gpu_ctx, sol)[1]
+                rows.append((beta, max(st["ranks"]), st["local_iterations"], J, float(u.norm())))
+            finally:
+                iga.btt_destroy(sol)
+                iga.kkt_destroy(kk)
+    finally:
+        iga.tt_destroy(Y)
+        iga.ttop_destroy(M)
+        iga.ttop_destroy(K)
+    print(rows, flush=True)
+    ranks = [r[1] for r in rows]
+    its = [r[2] for r in rows]
+    Js = [r[3] for r in rows]
+    us = [r[4] for r in rows]
+    assert ranks[-1] >= ranks[0] and its[-1] >= its[0]
+    assert all(a > b for a, b in zip(Js, Js[1:]))   # beta decreasing: J decreases
+    assert all(a < b for a, b in zip(us, us[1:]))   # beta decreasing: control grows
