@@ -88,7 +88,7 @@ def traffic_from_profile():
 
 
 def mixed_compare(iga, ctx, torch, geo, c, Y, steps):
-    """The c2 solve in the mixed forms (FP32 local contractions or BF16 products, FP64
+    """The workload's solve in the mixed forms (FP32 local contractions or BF16 products, FP64
     refinement) and in FP64 from the same assembled operators: solve times, residuals, state
     differences."""
     n, p, beta = c["n"], c["degree"], c["beta"]
@@ -320,7 +320,7 @@ def main():
     torch.cuda.init()
     stream = torch.cuda.current_stream()
     ctx = iga.ctx_create(0, stream.cuda_stream)
-    geo, yc, c = synth.config("c2")
+    geo, yc, c = synth.config("annulus_n64")
     n, p, beta = c["n"], c["degree"], c["beta"]
     Y = iga.tt_create(ctx, yc)
     torch.cuda.synchronize()

@@ -238,13 +238,13 @@ def tt_ranks_of(cores):
 
 # The five workloads the method is exercised on (sizes, degrees, regularisation).
 CONFIGS = {
-    "c1": dict(name="identity cube p=2 n=16", geometry="identity", degree=2, n=16, beta=1e-4,
+    "cube_n16": dict(name="identity cube p=2 n=16", geometry="identity", degree=2, n=16, beta=1e-4,
                yhat="sine", tol=1e-8, weight_tol=1e-10, seed_geo=0, seed_y=0),
-    "c2": dict(name="twisted annulus p=3 n=64", geometry="twisted_annulus", degree=3, n=64, beta=1e-6,
+    "annulus_n64": dict(name="twisted annulus p=3 n=64", geometry="twisted_annulus", degree=3, n=64, beta=1e-6,
                yhat="fourier", tol=1e-7, weight_tol=1e-10, seed_geo=1, seed_y=2),
-    "c3": dict(name="perturbed cube p=3 n=128", geometry="perturbed_cube", degree=3, n=128, beta=1e-6,
+    "perturbed_cube_n128": dict(name="perturbed cube p=3 n=128", geometry="perturbed_cube", degree=3, n=128, beta=1e-6,
                yhat="fourier", tol=1e-6, weight_tol=1e-6, seed_geo=3, seed_y=4),
-    "c5": dict(name="twisted annulus p=3 n=256", geometry="twisted_annulus", degree=3, n=256, beta=1e-6,
+    "annulus_n256": dict(name="twisted annulus p=3 n=256", geometry="twisted_annulus", degree=3, n=256, beta=1e-6,
                yhat="fourier", tol=1e-6, weight_tol=1e-10, seed_geo=5, seed_y=6, r_max=40),
 }
 

@@ -57,7 +57,7 @@ def test_tiny_full_rank_equals_direct_solve(gpu_ctx):
 
 def test_identity_cube_n16(gpu_ctx):
     """Unit cube, p = 2, n = 16 (4096 dofs), beta = 1e-4, yhat = prod sin, tol 1e-8."""
-    geo, yc, c = synth.config("c1")
+    geo, yc, c = synth.config("cube_n16")
     f, st, rc, res, r = _solve(gpu_ctx, geo, c["degree"], c["n"], c["beta"], yc, c["tol"],
                                weight_tol=c["weight_tol"])
     print("stats", st, flush=True)
@@ -99,7 +99,7 @@ def test_twisted_annulus_full_size_n64(gpu_ctx):
     the residual of the FP64 exact KKT apply is <= 1e-6, and the oracle's element-by-element
     residual on sampled boxes agrees with the library's."""
     from paper_1811_06797_amd import iga
-    geo, yc, c = synth.config("c2")
+    geo, yc, c = synth.config("annulus_n64")
     n, p, beta = c["n"], c["degree"], c["beta"]
     f, st, rc, res, r = _solve(gpu_ctx, geo, p, n, beta, yc, c["tol"], weight_tol=c["weight_tol"])
     print("stats", st, flush=True)
@@ -121,7 +121,7 @@ def test_twisted_annulus_full_size_n128(gpu_ctx):
     small against the right-hand side there. (The exact product A f in block-TT form has ranks
     (R_M + R_K) r and does not fit in memory at this size, so the residual is the check.)"""
     from paper_1811_06797_amd import iga
-    geo, yc, c = synth.config("c2", n=128)
+    geo, yc, c = synth.config("annulus_n64", n=128)
     n, p, beta = c["n"], c["degree"], c["beta"]
     f, st, rc, res, r = _solve(gpu_ctx, geo, p, n, beta, yc, 1e-6, weight_tol=c["weight_tol"])
     print("stats", st, flush=True)
@@ -152,7 +152,7 @@ def test_mixed_precision_identity_cube_n16(gpu_ctx, prec):
     residual and the state error against the oracle's direct solve meet the FP64 bars
     (1e-6, 1e-5)."""
     from paper_1811_06797_amd import iga
-    geo, yc, c = synth.config("c1")
+    geo, yc, c = synth.config("cube_n16")
     f, st, rc, res, r = _solve(gpu_ctx, geo, c["degree"], c["n"], c["beta"], yc, c["tol"],
                                weight_tol=c["weight_tol"], precision=getattr(iga, prec))
     print("stats", st, flush=True)
@@ -178,10 +178,10 @@ def test_mixed_precision_twisted_annulus_small(gpu_ctx, beta, prec):
 
 
 def test_mixed_precision_matches_fp64_n64(gpu_ctx):
-    """c2 (n = 64) in the three forms: the mixed forms (FP32 and BF16 products) reach the same
+    """Twisted annulus, n = 64, in the three forms: the mixed forms (FP32 and BF16 products) reach the same
     residual bar and their states differ from the FP64 GPU form's by <= 1e-5 relative."""
     from paper_1811_06797_amd import iga
-    geo, yc, c = synth.config("c2")
+    geo, yc, c = synth.config("annulus_n64")
     n, p, beta = c["n"], c["degree"], c["beta"]
     f64, st64, rc64, res64, _ = _solve(gpu_ctx, geo, p, n, beta, yc, c["tol"], weight_tol=c["weight_tol"])
     assert rc64 == 0 and res64 < 1e-6

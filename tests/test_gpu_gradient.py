@@ -88,7 +88,7 @@ def test_geometry_gradient_matches_central_differences(gpu_ctx, small_case):
 def test_geometry_gradient_n16_identity_cube(gpu_ctx):
     """c1 geometry (unit cube, trilinear control net), p = 2, n = 16: one random direction of
     control-point motion against the oracle's central difference."""
-    geo, yc, c = synth.config("c1")
+    geo, yc, c = synth.config("cube_n16")
     p, n, beta = c["degree"], c["n"], c["beta"]
     J, gy, gC = _gpu(gpu_ctx, geo, p, n, beta, yc, tol=1e-10)
     yh = tt.tt_full(yc)
