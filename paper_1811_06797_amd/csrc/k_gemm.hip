@@ -31,13 +31,20 @@ constexpr int NTHR = 256;
 // Source of the zeros that pad partial tiles.
 __device__ const double kZero[1] = {0.0};
 
+// Tile loads go through global (address space 1) pointers. Through a generic pointer the
+// select against kZero compiles to flat loads, which count in the LDS counter as well, so
+// every wait for an LDS fragment read would also wait for the tile loads still in flight.
+__device__ __forceinline__ double gload(const double* p) {
+  return *(const __attribute__((address_space(1))) double*)p;
+}
+
 // Tile of the wide variant used for M <= 64 with many column tiles (the banded stage of the
 // local matvec): 64 x (32 WN) outputs, K step BK, NBUF LDS buffers.
 #ifndef IGA_WIDE_WN
 #define IGA_WIDE_WN 4
 #endif
 #ifndef IGA_WIDE_BK
-#define IGA_WIDE_BK 16
+#define IGA_WIDE_BK 12
 #endif
 #ifndef IGA_WIDE_NBUF
 #define IGA_WIDE_NBUF 2
@@ -149,7 +156,7 @@ __device__ __forceinline__ void gemm2_tile(const G2Args& g, int bx, int by, int 
 #pragma unroll
     for (int s = 0; s < LA; ++s) {
       const bool ok = a_ok[s] && a_kk[s] < klim;
-      ra[s] = *(ok ? A + oa[s] : kZero);
+      ra[s] = gload(ok ? A + oa[s] : kZero);
       if constexpr (K1) {
         oa[s] += dA;  // single-level K: constant stride
       } else {
@@ -162,7 +169,7 @@ __device__ __forceinline__ void gemm2_tile(const G2Args& g, int bx, int by, int 
 #pragma unroll
     for (int s = 0; s < LB; ++s) {
       const bool ok = b_ok[s] && b_kk[s] < klim;
-      rb[s] = *(ok ? B + ob[s] : kZero);
+      rb[s] = gload(ok ? B + ob[s] : kZero);
       if constexpr (K1) {
         ob[s] += dB;
       } else {
@@ -209,22 +216,25 @@ __device__ __forceinline__ void gemm2_tile(const G2Args& g, int bx, int by, int 
     // two K tiles of global loads in flight: register sets 0 and 1 alternate, LDS buffers
     // 0 and 1 alternate; tile t is in LDS buffer t % 2 when it is multiplied
     static_assert(NBUF == 2, "prefetch depth 2 needs two LDS buffers");
+    // The loop body has no branch around its loads and stores: a tile past the end reads
+    // only the zero word, and storing it is harmless, since the buffer it goes to is not read
+    // in that phase. With such branches the compiler's wait counting merges paths on which
+    // the older register set is still in flight, and then waits for every load in flight
+    // before it issues the next tile's loads.
     double ra1[LA], rb1[LB];
-    if (nkt > 0) {
-      load_tile(kbeg, ra0, rb0);
-      store_tile(0, ra0, rb0);
-    }
-    if (nkt > 1) load_tile(kbeg + BK, ra1, rb1);
+    load_tile(kbeg, ra0, rb0);
+    store_tile(0, ra0, rb0);
+    load_tile(kbeg + BK, ra1, rb1);
     __syncthreads();
     for (int t = 0; t < nkt; t += 2) {
-      if (t + 2 < nkt) load_tile(kbeg + (t + 2) * BK, ra0, rb0);
+      load_tile(kbeg + (t + 2) * BK, ra0, rb0);
       compute(0);
-      if (t + 1 < nkt) store_tile(1, ra1, rb1);
+      store_tile(1, ra1, rb1);  // tile t + 1; buffer 1 was last read before the previous barrier
       __syncthreads();
       if (t + 1 >= nkt) break;
-      if (t + 3 < nkt) load_tile(kbeg + (t + 3) * BK, ra1, rb1);
+      load_tile(kbeg + (t + 3) * BK, ra1, rb1);
       compute(1);
-      if (t + 2 < nkt) store_tile(0, ra0, rb0);
+      store_tile(0, ra0, rb0);  // tile t + 2
       __syncthreads();
     }
   } else {
@@ -235,7 +245,7 @@ __device__ __forceinline__ void gemm2_tile(const G2Args& g, int bx, int by, int 
     __syncthreads();
     for (int t = 0; t < nkt; ++t) {
       const int cur = NBUF == 2 ? (t & 1) : 0;
-      if (t + 1 < nkt) load_tile(kbeg + (t + 1) * BK, ra0, rb0);
+      load_tile(kbeg + (t + 1) * BK, ra0, rb0);  // past the end: zeros, never stored
       compute(cur);
       if (NBUF == 1) __syncthreads();  // single buffer: every wave is done reading it
       if (t + 1 < nkt) store_tile(NBUF == 2 ? (cur ^ 1) : 0, ra0, rb0);
@@ -298,13 +308,15 @@ __global__ __launch_bounds__(NTHR) void gemm2_grouped_kernel(const G2Args* gs, c
   constexpr int BM = 4 * WM * WAVES_M, BN = 16 * WN * WAVES_N;
   __shared__ TileLds<BM, BN, BK, NBUF> L;
   for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    // the prefix sums are read through a global pointer (global, not flat, loads)
+    const __attribute__((address_space(1))) int* pre = (const __attribute__((address_space(1))) int*)prefix;
     int lo = 0, hi = ngemm;
     while (hi - lo > 1) {
       const int mid = (lo + hi) / 2;
-      if (prefix[mid] <= t) lo = mid; else hi = mid;
+      if (pre[mid] <= t) lo = mid; else hi = mid;
     }
     const G2Args g = gs[lo];
-    const int local = t - prefix[lo];
+    const int local = t - pre[lo];
     const int gx = (g.N + BN - 1) / BN, gy = (g.M + BM - 1) / BM;
     __syncthreads();  // the previous tile is done with the LDS buffers
     gemm2_tile<WM, WN, WAVES_M, WAVES_N, BK, NBUF, PF>(g, local % gx, (local / gx) % gy, local / (gx * gy), L);
@@ -438,7 +450,7 @@ void gemm2(hipStream_t s, const Gemm2& d, double* work, size_t work_len) {
   variant_tile(variant, BM, BN);
   const long tiles = (long)((d.M + BM - 1) / BM) * ((d.N + BN - 1) / BN) * nb;
   // split K when the tiles cannot fill the chip and the contraction is long
-  constexpr int KALIGN = 32;  // split-K chunks are whole K tiles of every variant
+  constexpr int KALIGN = 48;  // split-K chunks are whole K tiles of every variant (12 or 16 deep)
   if (work && tiles < 256 && d.K >= 4 * KALIGN) {
     int ks = (int)std::min<long>((512 + tiles - 1) / tiles, d.K / (2 * KALIGN));
     while (ks > 1 && (size_t)ks * nb * d.M * d.N > work_len) --ks;
