@@ -280,6 +280,46 @@ def micro_bench(iga, ctx, torch, iters):
     return out, prob
 
 
+# microbenchmark shapes (r, R_M, R_K, n, p): the three workload shapes, then a sweep over r at
+# the first one's operator ranks
+SHAPES = [(32, 10, 60, 64, 3), (40, 15, 80, 128, 3), (40, 10, 60, 256, 3)] + \
+         [(r, 10, 60, 64, 3) for r in (16, 24, 40, 64)]
+
+
+def shapes_bench(iga, ctx, torch, warmup=10, calls=50):
+    """FP64 local TT-matvec on seeded N(0,1) operands at each shape: median of per-call HIP
+    event times after warm-up, algorithmic GFLOP/s, and the banded K stage's TF/s from the
+    library's event profile of the same calls."""
+    import numpy as np
+    import synth
+    out = []
+    stream = torch.cuda.current_stream()
+    for (r, RM, RK, n, p) in SHAPES:
+        prob = synth.random_local_problem(r, RM, RK, n, p, seed=1)
+        dev = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda() for k, v in prob.items()}
+        y = torch.empty_like(dev["x"])
+        args = (ctx, r, n, r, p, RM, RM, RK, RK, dev["PhiL_M"], dev["PhiR_M"], dev["PhiL_K"], dev["PhiR_K"],
+                dev["M"], dev["K"], 1e-6, dev["x"], y)
+        for _ in range(warmup):
+            iga.local_matvec(*args)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(calls)]
+        torch.cuda.synchronize()
+        iga.profile_start(ctx)
+        for e0, e1 in ev:
+            e0.record(stream)
+            iga.local_matvec(*args)
+            e1.record(stream)
+        pr = iga.profile_stop(ctx)
+        torch.cuda.synchronize()
+        ms = float(np.median([e0.elapsed_time(e1) for e0, e1 in ev]))
+        flops = iga.local_matvec_flops(r, n, r, p, RM, RM, RK, RK)
+        out.append({"shape": {"r": r, "RM": RM, "RK": RK, "n": n, "p": p}, "median_ms": ms,
+                    "gflops": flops / ms / 1e6,
+                    "band_K_tflops": pr["flops"][1] / (pr["ms"][1] * 1e-3) / 1e12 if pr["ms"][1] else None})
+        del dev, y
+    return out
+
+
 def cpu_baseline(prob, budget_s=12.0, max_calls=400):
     """The oracle's local projected matvec (numpy FP64 einsum stages) at the microbenchmark
     shape, timed on the host cores."""
@@ -364,6 +404,8 @@ def main():
     batching = batching_bench(iga, ctx, torch)
     timedep = time_dependent_bench(iga, ctx, torch, geo, c, Y)
     micro, prob = micro_bench(iga, ctx, torch, a.micro_iters)
+    shapes = shapes_bench(iga, ctx, torch)
+    peaks = iga.measure_peaks(ctx)
     prof = micro["profile"]
     k_ms = prof["ms"][1] / max(prof["launches"][1], 1)
     k_flops = prof["flops"][1] / max(prof["launches"][1], 1)
@@ -398,8 +440,12 @@ def main():
         "batching": batching,
         "time_dependent": timedep,
         "microbench_local_matvec": {k: micro[k] for k in ("shape", "ms", "gflops", "flops", "fp32", "bf16")},
+        "microbench_shapes": shapes,
+        "measured_peaks": peaks,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
+                     "peak_measured": peaks["mfma_f64_4x4x4_tflops"],
+                     "frac_of_measured": achieved / peaks["mfma_f64_4x4x4_tflops"],
                      "kernel": ROOFLINE_KERNEL + ": banded middle stage of the K operator in the "
                                "local TT-matvec at (r, R_M, R_K, n, p) = (32, 10, 60, 64, 3)",
                      "flops_per_launch": k_flops, "ms_per_launch": k_ms, "launches": prof["launches"][1]},

@@ -338,6 +338,18 @@ typedef struct {
 int iga_profile_start(iga_ctx* ctx);
 int iga_profile_stop(iga_ctx* ctx, iga_profile* out);
 
+/* Measured ceilings of the device for the roofline of the local TT-matvec (Section 5's
+ * contractions run on the matrix cores; their operands stream from HBM). Runs six short
+ * project-written probe kernels on the context stream and writes to out[6] (host memory,
+ * caller-owned): TFLOP/s of v_mfma_f64_4x4x4_4b (the instruction of the FP64 contractions),
+ * of v_mfma_f64_16x16x4, of v_mfma_f32_16x16x4 (FP32 form) and of v_mfma_f32_16x16x32_bf16
+ * (BF16 form), each with 8 independent accumulators per wave and 8 workgroups per CU; then
+ * GB/s of a device copy (bytes read plus written) and of a device read, over 512 MiB
+ * buffers. Best of three timed launches each. Temporarily allocates 1 GiB of device memory
+ * (IGA_ENOMEM if that fails) and about 5 MB from the context pool. Synchronises; takes about
+ * 0.1 s. */
+int iga_measure_peaks(iga_ctx* ctx, double* out);
+
 const char* iga_last_error(void);
 
 #ifdef __cplusplus

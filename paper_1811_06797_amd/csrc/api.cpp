@@ -711,6 +711,16 @@ int iga_profile_stop(iga_ctx* ctx, iga_profile* out) {
   });
 }
 
+int iga_measure_peaks(iga_ctx* ctx, double* out) {
+  return guarded([&] {
+    require(ctx && out, IGA_EINVAL, "measure_peaks: NULL argument");
+    use_device(ctx);
+    IGA_HIP(hipStreamSynchronize(ctx->stream));
+    k::measure_peaks(ctx, out);
+    return IGA_OK;
+  });
+}
+
 double iga_local_matvec_flops(int r0, int n, int r1, int degree, int RM0, int RM1, int RK0, int RK1) {
   return local_matvec_flops(r0, n, r1, degree, RM0, RM1, RK0, RK1);
 }

@@ -268,3 +268,12 @@ void factor_quadrature(hipStream_t s, int S, int n, int p, int nel, int nq, cons
 
 }  // namespace k
 }  // namespace iga
+
+struct iga_ctx;
+namespace iga {
+namespace k {
+// Measured device ceilings (k_probe.hip): out[0..3] TFLOP/s of the FP64 4x4x4, FP64 16x16x4,
+// FP32 16x16x4 and BF16 16x16x32 MFMA instructions; out[4], out[5] GB/s of a copy and a read.
+void measure_peaks(iga_ctx* ctx, double* out);
+}  // namespace k
+}  // namespace iga

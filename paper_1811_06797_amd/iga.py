@@ -31,7 +31,8 @@ EXPORTED = [
     "iga_btt_create", "iga_btt_info", "iga_btt_blocks", "iga_btt_get_core", "iga_btt_to_full", "iga_btt_destroy",
     "iga_kkt_create", "iga_kkt_create_parabolic", "iga_kkt_blocks", "iga_kkt_destroy", "iga_kkt_apply", "iga_kkt_residual", "iga_amen_solve",
     "iga_amen_solve_many",
-    "iga_local_matvec", "iga_local_matvec_batched", "iga_local_matvec_flops", "iga_profile_start", "iga_profile_stop", "iga_objective",
+    "iga_local_matvec", "iga_local_matvec_batched", "iga_local_matvec_flops", "iga_profile_start", "iga_profile_stop",
+    "iga_measure_peaks", "iga_objective",
     "iga_grad_yhat", "iga_grad_geometry", "iga_last_error",
 ]
 
@@ -141,6 +142,7 @@ lib.iga_grad_geometry.argtypes = [P, C.POINTER(Geometry), C.c_int, I3, C.POINTER
                                   PD]
 lib.iga_profile_start.argtypes = [P]
 lib.iga_profile_stop.argtypes = [P, C.POINTER(Profile)]
+lib.iga_measure_peaks.argtypes = [P, PD]
 
 
 def last_error() -> str:
@@ -391,6 +393,17 @@ def profile_stop(ctx) -> dict:
     out = Profile()
     _check(lib.iga_profile_stop(ctx, C.byref(out)))
     return out.as_dict()
+
+
+PEAK_KEYS = ("mfma_f64_4x4x4_tflops", "mfma_f64_16x16x4_tflops", "mfma_f32_16x16x4_tflops",
+             "mfma_bf16_16x16x32_tflops", "hbm_copy_gbps", "hbm_read_gbps")
+
+
+def measure_peaks(ctx) -> dict:
+    """Measured device ceilings from the library's probe kernels (iga_measure_peaks)."""
+    out = (C.c_double * 6)()
+    _check(lib.iga_measure_peaks(ctx, out))
+    return dict(zip(PEAK_KEYS, list(out)))
 
 
 def objective(ctx, kkt, yhat, f) -> float:
