@@ -63,6 +63,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--micro-iters", type=int, default=20)
+    ap.add_argument("--solve-only", action="store_true",
+                    help="one step (assembly and solve) of the workload and its statistics, for tracing")
     return ap.parse_args()
 
 
@@ -387,6 +389,15 @@ def main():
         iga.ttop_destroy(M)
         iga.ttop_destroy(K)
         return st
+
+    if a.solve_only:
+        st = step()
+        print(json.dumps({k: st[k] for k in ("assembly_s", "solve_wall_s", "residual", "ranks", "half_sweeps",
+                                             "local_iterations", "local_matvecs", "t_local_matvec", "t_svd",
+                                             "t_precond", "op_ranks")}), flush=True)
+        iga.tt_destroy(Y)
+        iga.ctx_destroy(ctx)
+        return
 
     for _ in range(a.warmup):
         step()

@@ -123,12 +123,14 @@ class Amen {
     lowp_ = o.precision == IGA_FP32 || o.precision == IGA_BF16;
     bf16_ = o.precision == IGA_BF16;
     // dense cores re-laid as [n][2p+1][R0][R1] once per solve: the banded stage of the
-    // local matvec then contracts over one (R0, 2p+1) index instead of two nested ones
+    // local matvec then contracts over one (R0, 2p+1) index instead of two nested ones.
+    // Block-structured cores with few rank pairs are re-laid too, zeros included: for them
+    // one product over the whole core costs less than one small launch per block.
     for (int op = 0; op < 2; ++op)
       for (int d = 0; d < 3; ++d) {
         const OpCore& c = ops_[op]->core[d];
         const bool dense = c.blocks.size() == 1 && c.blocks[0].na == c.R0 && c.blocks[0].nb == c.R1;
-        if (!dense) continue;
+        if (!dense && (long)c.R0 * c.R1 > kDenseRankPairs) continue;
         const int b = 2 * ops_[op]->p + 1;
         const int dims[4] = {c.R0, c.n, b, c.R1}, perm[4] = {1, 2, 0, 3};
         rcore_[op][d].reset(ctx, (long)c.R0 * c.n * b * c.R1);

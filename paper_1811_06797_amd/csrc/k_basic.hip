@@ -293,6 +293,21 @@ __global__ void kkt_combine_kernel(long e, T k02, T m11, T m12, T k20, T m21, co
   }
 }
 
+// Banded stage of a rank-1 operator core (one left and one right rank): row i of y is the
+// band combination y[i][c] = sum_{o < b} A[i][o] x[i + o][c] of the b rows of x around it,
+// o in increasing order (blockIdx.y = i). Memory-bound: each x row is read by b output rows.
+template <typename T>
+__global__ __launch_bounds__(256) void band_rank1_kernel(int b, long ncols, const T* A, const T* x, long ldx, T* y) {
+  const int i = blockIdx.y;
+  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncols) return;
+  const T* a = A + (long)i * b;
+  const T* xc = x + (long)i * ldx + c;
+  T acc = a[0] * xc[0];
+  for (int o = 1; o < b; ++o) acc += a[o] * xc[(long)o * ldx];
+  y[(long)i * ncols + c] = acc;
+}
+
 // y[o] = sum of coef[t] z[src[t]] over the terms t of output block o (blockIdx.y = o).
 __global__ void combine_blocks_kernel(long e, const int* toff, const int* src, const double* coef,
                                       const double* z, double* y) {
@@ -560,6 +575,23 @@ void symmetrize(hipStream_t s, int nmat, int k, double* H, long stride) {
   dim3 grid((unsigned)std::max<long>(1, std::min<long>(((long)k * k + 255) / 256, 1024)), nmat);
   symmetrize_kernel<<<grid, 256, 0, s>>>(k, H, stride);
   IGA_HIP(hipGetLastError());
+}
+
+template <typename T>
+static void band_rank1_launch(hipStream_t s, int n, int b, long ncols, const T* A, const T* x, long ldx, T* y) {
+  if (n <= 0 || ncols <= 0) return;
+  require(n <= 65535 && b >= 1, IGA_EINVAL, "band_rank1: bad sizes");
+  dim3 grid((unsigned)((ncols + 255) / 256), (unsigned)n);
+  band_rank1_kernel<T><<<grid, 256, 0, s>>>(b, ncols, A, x, ldx, y);
+  IGA_HIP(hipGetLastError());
+}
+
+void band_rank1(hipStream_t s, int n, int b, long ncols, const double* A, const double* x, long ldx, double* y) {
+  band_rank1_launch<double>(s, n, b, ncols, A, x, ldx, y);
+}
+
+void band_rank1_f32(hipStream_t s, int n, int b, long ncols, const float* A, const float* x, long ldx, float* y) {
+  band_rank1_launch<float>(s, n, b, ncols, A, x, ldx, y);
 }
 
 void kkt_combine_f32(hipStream_t s, long e, const KktCoef& c, const float* zM, const float* zK, float* y) {

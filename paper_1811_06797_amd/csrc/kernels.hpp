@@ -157,6 +157,10 @@ struct KktCoef {
 };
 void kkt_combine(hipStream_t s, long e, const KktCoef& c, const double* zM, const double* zK, double* y);
 void kkt_combine_f32(hipStream_t s, long e, const KktCoef& c, const float* zM, const float* zK, float* y);
+// Banded stage of a rank-1 operator core: y[i][c] = sum_{o < b} A[i][o] x[(i + o) ldx + c],
+// i < n, c < ncols, y rows of ncols (FP64 and FP32 forms).
+void band_rank1(hipStream_t s, int n, int b, long ncols, const double* A, const double* x, long ldx, double* y);
+void band_rank1_f32(hipStream_t s, int n, int b, long ncols, const float* A, const float* x, long ldx, float* y);
 // General block combination: y[o][.] = sum_{t in [toff[o], toff[o+1])} coef[t] z[src[t]][.]
 // for o < nblk, blocks of e elements (device tables).
 void combine_blocks(hipStream_t s, long e, int nblk, const int* toff, const int* src, const double* coef,

@@ -49,6 +49,9 @@ template <> struct Prec<double> {
   using G = k::Gemm2;
   static void gemm(hipStream_t s, const G& g, double* w, size_t n, bool) { k::gemm2(s, g, w, n); }
   static void zero(hipStream_t s, long n, double* y) { k::fill(s, n, 0.0, y); }
+  static void band1(hipStream_t s, int n, int b, long nc, const double* A, const double* x, long ldx, double* y) {
+    k::band_rank1(s, n, b, nc, A, x, ldx, y);
+  }
   static constexpr int prof_base = 0;
 };
 template <> struct Prec<float> {
@@ -61,6 +64,9 @@ template <> struct Prec<float> {
       k::gemm2_f32(s, g, w, n);
   }
   static void zero(hipStream_t s, long n, float* y) { k::fill_f32(s, n, 0.0f, y); }
+  static void band1(hipStream_t s, int n, int b, long nc, const float* A, const float* x, long ldx, float* y) {
+    k::band_rank1_f32(s, n, b, nc, A, x, ldx, y);
+  }
   static constexpr int prof_base = 2;
 };
 
@@ -104,7 +110,14 @@ static void op_apply(iga_ctx* ctx, const OpView& A, const T* core, const T* rela
     IGA_HIP(hipEventRecord(pa, st));
   }
   const bool dense = blocks.size() == 1 && blocks[0].na == R0 && blocks[0].nb == R1;
-  if (dense && relaid) {
+  // a re-laid core: dense, or block-structured with few rank pairs (zeros included)
+  const bool whole = relaid && (dense || (long)R0 * R1 <= kDenseRankPairs);
+  if (whole && R0 == 1 && R1 == 1 && !bf16) {
+    // a rank-1 core (the mass operator of a separable weight): a one-row GEMM would use one
+    // sixteenth of a matrix-core tile, so the band combination of t1's slices runs as a
+    // memory-bound stencil; the relaid core is [i][o]
+    Prec<T>::band1(st, n, b, S1, relaid, t1.get(), SJ, t2.get());
+  } else if (whole) {
     // core [i][o][d][g]: for row i the contraction index k = o R0 + d has constant strides
     // (R1 in the core, S1 in t1, whose slice i + o starts at (i + o) SJ = i SJ + o R0 S1)
     G g2;

@@ -13,6 +13,10 @@
 
 namespace iga {
 
+// A block-structured operator core with at most this many rank pairs R0 R1 is contracted as one
+// dense product over its re-laid form (zeros included) in the banded stage, not block by block.
+constexpr long kDenseRankPairs = 1024;
+
 struct LocalOp {
   OpView M, K;
   std::vector<RankBlock> Mblocks, Kblocks;  // nonzero rank blocks of the two cores

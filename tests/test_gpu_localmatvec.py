@@ -32,7 +32,8 @@ def _run(gpu_ctx, prob, r, n, p, RM, RK, beta, precision, rr=None):
 
 
 @pytest.mark.parametrize("r,RM,RK,n,p,rr", [(3, 1, 2, 5, 1, None), (5, 2, 3, 9, 2, None), (7, 3, 5, 13, 3, 4),
-                                             (1, 1, 3, 6, 2, 4), (17, 2, 9, 23, 3, None)])
+                                             (1, 1, 3, 6, 2, 4), (17, 2, 9, 23, 3, None),
+                                             (24, 1, 1, 40, 3, 30)])
 def test_local_matvec_matches_oracle(gpu_ctx, r, RM, RK, n, p, rr):
     from paper_1811_06797_amd import iga
     prob = synth.random_local_problem(r, RM, RK, n, p, seed=r + n, r_right=rr)
