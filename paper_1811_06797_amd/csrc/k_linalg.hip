@@ -40,6 +40,7 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(int k, double* Hs, long sH, 
     for (int e = tid; e < k * k; e += nt) H[(e / k) * ld + e % k] = Hg[e];
   for (int e = tid; e < k * k; e += nt) WT[e] = (e / k == e % k) ? 1.0 : 0.0;
   __shared__ double cs[JT / 2], sn[JT / 2], dp[JT / 2], dq[JT / 2];
+  __shared__ int pp[JT / 2], qq[JT / 2];  // this round's pairs, found once by their rotation's thread
   __shared__ int rotated;
   __shared__ double trace;
   __syncthreads();
@@ -84,6 +85,7 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(int k, double* Hs, long sH, 
           }
         }
         cs[t] = c; sn[t] = s; dp[t] = np; dq[t] = nq;
+        pp[t] = p; qq[t] = q;
       }
       __syncthreads();
       // H by 2 x 2 blocks
@@ -91,9 +93,7 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(int k, double* Hs, long sH, 
         const int t1 = blk / npair, t2 = blk - t1 * npair;
         const double s1 = sn[t1], s2 = sn[t2];
         if (s1 == 0.0 && s2 == 0.0) continue;
-        int p1, q1, p2, q2;
-        pair_of(t1, round, p1, q1);
-        pair_of(t2, round, p2, q2);
+        const int p1 = pp[t1], q1 = qq[t1], p2 = pp[t2], q2 = qq[t2];
         if (t1 == t2) {
           H[p1 * ld + p1] = dp[t1];
           H[q1 * ld + q1] = dq[t1];
@@ -120,8 +120,7 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(int k, double* Hs, long sH, 
         const double s = sn[t];
         if (s == 0.0) continue;
         const double c = cs[t];
-        int p, q;
-        pair_of(t, round, p, q);
+        const int p = pp[t], q = qq[t];
         const double wp = WT[p * k + j], wq = WT[q * k + j];
         WT[p * k + j] = c * wp - s * wq;
         WT[q * k + j] = s * wp + c * wq;
@@ -514,7 +513,8 @@ int jacobi_lds_max() { return LDS_MAX_K; }
 
 void jacobi_eig(hipStream_t s, int nmat, int k, double* H, long strideH, double* W, long strideW,
                 double tol, int max_sweeps, int* sweeps_out) {
-  require(k >= 1 && k <= 1024, IGA_EINVAL, "jacobi_eig: k out of range");
+  // one rotation per thread pair slot: the per-round tables hold JT / 2 pairs
+  require(k >= 1 && k <= JT, IGA_EINVAL, "jacobi_eig: k out of range");
   // once per process (solves may run in several host threads)
   static std::once_flag attr_once;
   std::call_once(attr_once, [] {

@@ -226,7 +226,7 @@ void geometry_adjoint(hipStream_t s, const int np[3], const int ncp[3], const do
                       const double* const Bd[3], const double* ctrl, const double* H, double* T);
 
 // Symmetric Jacobi eigen-decomposition, one workgroup per matrix, nmat matrices of size k
-// (k <= 1024): H (in: symmetric, out: diagonal holds the eigenvalues), WT (out: row i is
+// (k <= 512): H (in: symmetric, out: diagonal holds the eigenvalues), WT (out: row i is
 // the i-th eigenvector, H_in = WT^T diag WT). Rotations are skipped when
 // |h_pq| <= max(tol * sqrt(|h_pp h_qq|), 1e-30 trace). sweeps_out[mat] (nullable) counts
 // the sweeps that rotated anything (0: H was already diagonal to that tolerance).
