@@ -144,6 +144,10 @@ class Amen {
           const long sz = (long)c.R0 * c.n * (2 * ops_[op]->p + 1) * c.R1;
           fcore_[op][d].reset(ctx, sz);
           k::to_f32(st_, sz, c.data.get(), fcore_[op][d].get());
+          if (rcore_[op][d].get()) {
+            frcore_[op][d].reset(ctx, sz);
+            k::to_f32(st_, sz, rcore_[op][d].get(), frcore_[op][d].get());
+          }
         }
     }
   }
@@ -237,6 +241,7 @@ class Amen {
   bool lowp_ = false, lp_inner_ = false;
   bool bf16_ = false;  // inner products on BF16 matrix cores instead of FP32
   FBuf fcore_[2][3], fPL_[2], fPR_[2], fx_, fy_;
+  FBuf frcore_[2][3];  // FP32 copies of the re-laid cores
   DBuf rcore_[2][3];  // re-laid dense cores (null for block-structured ones)
   void lowp_operands(int d, LocalOp& L);
   int refine_solve(int d, const LocalOp& L, double bn, double ltol, double res0);
@@ -501,6 +506,8 @@ void Amen::lowp_operands(int d, LocalOp& L) {
   L.fPhiL_K = fPL_[1].get(); L.fPhiR_K = fPR_[1].get();
   L.M.Af = fcore_[0][d].get();
   L.K.Af = fcore_[1][d].get();
+  L.M.Arf = frcore_[0][d].get();
+  L.K.Arf = frcore_[1][d].get();
 }
 
 // Mixed-precision local solve by iterative refinement: the FP64 residual r = b - A x (in

@@ -193,9 +193,9 @@ void local_matvec_f32(iga_ctx* ctx, const LocalOp& L, const float* x, float* y, 
   const int r0o = L.out0(), r1o = L.out1();
   const long osz = (long)r0o * L.n * r1o;
   w.fz.ensure(ctx, (size_t)5 * osz);
-  op_apply<float>(ctx, L.M, L.M.Af, (const float*)nullptr, L.Mblocks, L.fPhiL_M, L.fPhiR_M, r0o, L.r0, L.r1, r1o, 3, x, colsz,
+  op_apply<float>(ctx, L.M, L.M.Af, L.M.Arf, L.Mblocks, L.fPhiL_M, L.fPhiR_M, r0o, L.r0, L.r1, r1o, 3, x, colsz,
                   w.fz.get(), osz, w.ftM, w.ftM2, w.fsplit, w.fpadM, 0, bf16);
-  op_apply<float>(ctx, L.K, L.K.Af, (const float*)nullptr, L.Kblocks, L.fPhiL_K, L.fPhiR_K, r0o, L.r0, L.r1, r1o, 2, x, 2 * colsz,
+  op_apply<float>(ctx, L.K, L.K.Af, L.K.Arf, L.Kblocks, L.fPhiL_K, L.fPhiR_K, r0o, L.r0, L.r1, r1o, 2, x, 2 * colsz,
                   w.fz.get() + 3 * osz, osz, w.ftK, w.ftK2, w.fsplit, w.fpadK, 1, bf16);
   k::kkt_combine_f32(ctx->stream, osz, L.coef, w.fz.get(), w.fz.get() + 3 * osz, y);
 }

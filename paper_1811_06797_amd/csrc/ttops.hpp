@@ -14,6 +14,7 @@ struct OpView {
   const double* A = nullptr;
   const float* Af = nullptr;  // FP32 copy (mixed-precision form), may be null
   const double* Ar = nullptr; // the core re-laid as [n][2p+1][R0][R1] (dense cores), may be null
+  const float* Arf = nullptr; // FP32 copy of Ar (mixed-precision form), may be null
   const int* lo_R1 = nullptr;  // for output right rank g: contract left ranks [lo, hi)
   const int* hi_R1 = nullptr;
   const int* lo_R0 = nullptr;  // for output left rank g: contract right ranks [lo, hi)
