@@ -961,8 +961,10 @@ void Amen::move_right(int d) {
     const int dims[4] = {nb_, r0, n, rho_[d + 1]};
     const int perm[4] = {1, 2, 0, 3};
     k::permute4(st_, rz.get(), dims, perm, Rz.get());
+    // T = U^T Rz has few output tiles and a contraction over all m rows: split it
+    DBuf W(ctx_, (size_t)64 * rt * kz);
     for (int pass = 0; pass < 2; ++pass) {
-      k::gemm_rm(st_, rt, kz, m, U.get(), rt, true, Rz.get(), kz, false, T.get(), kz);
+      k::gemm_rm(st_, rt, kz, m, U.get(), rt, true, Rz.get(), kz, false, T.get(), kz, 1.0, 0.0, W.get(), W.size());
       k::gemm_rm(st_, m, kz, rt, U.get(), rt, false, T.get(), kz, false, Rz.get(), kz, -1.0, 1.0);
     }
     orthonormal_columns(Rz.get(), m, kz, std::min(kick_, m - rt), Qz, q, 1e-12);
@@ -1065,8 +1067,10 @@ void Amen::move_left(int d) {
     DBuf Rz(ctx_, (size_t)m * kz), T(ctx_, (size_t)rt * kz);
     // rz [nb][z0][n][r1] viewed as (nb z0) x (n r1); transpose to (n r1) x (nb z0)
     k::copy2d(st_, m, kz, rz.get(), 1, m, Rz.get(), kz);
+    // T = U^T Rz has few output tiles and a contraction over all m rows: split it
+    DBuf W(ctx_, (size_t)64 * rt * kz);
     for (int pass = 0; pass < 2; ++pass) {
-      k::gemm_rm(st_, rt, kz, m, U.get(), rt, true, Rz.get(), kz, false, T.get(), kz);
+      k::gemm_rm(st_, rt, kz, m, U.get(), rt, true, Rz.get(), kz, false, T.get(), kz, 1.0, 0.0, W.get(), W.size());
       k::gemm_rm(st_, m, kz, rt, U.get(), rt, false, T.get(), kz, false, Rz.get(), kz, -1.0, 1.0);
     }
     orthonormal_columns(Rz.get(), m, kz, std::min(kick_, m - rt), Qz, q, 1e-12);

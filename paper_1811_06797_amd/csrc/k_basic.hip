@@ -641,7 +641,7 @@ void coldots(hipStream_t s, int m, int k, const double* A, long lda, const doubl
 
 // FP64 products run on the matrix cores: the (ko, k) contraction index is the two-level K
 // of gemm2 (outer stride s*ko, inner stride s*k).
-void gemm(hipStream_t s, const Gemm& g) {
+void gemm(hipStream_t s, const Gemm& g, double* work, size_t work_len) {
   if (g.M <= 0 || g.N <= 0) return;
   Gemm2 d;
   d.M = g.M; d.N = g.N; d.K = g.K * g.Kout; d.K2 = std::max(g.K, 1);
@@ -657,19 +657,20 @@ void gemm(hipStream_t s, const Gemm& g) {
     launch_gemm<double>(s, g);
     return;
   }
-  gemm2(s, d);
+  gemm2(s, d, work, work_len);
 }
 void gemm_f32(hipStream_t s, const GemmF& g) { launch_gemm<float>(s, g); }
 
 void gemm_rm(hipStream_t s, int M, int N, int K, const double* A, long lda, bool tA,
-             const double* B, long ldb, bool tB, double* C, long ldc, double alpha, double beta) {
+             const double* B, long ldb, bool tB, double* C, long ldc, double alpha, double beta,
+             double* work, size_t work_len) {
   Gemm g;
   g.M = M; g.N = N; g.K = K;
   g.A = A; g.sAm = tA ? 1 : lda; g.sAk = tA ? lda : 1;
   g.B = B; g.sBk = tB ? 1 : ldb; g.sBn = tB ? ldb : 1;
   g.C = C; g.sCm = ldc; g.sCn = 1;
   g.alpha = alpha; g.beta = beta;
-  gemm(s, g);
+  gemm(s, g, work, work_len);
 }
 
 void band(hipStream_t s, const Band& b) { launch_band<double>(s, b, b.alpha, b.beta); }

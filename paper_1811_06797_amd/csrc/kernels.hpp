@@ -20,7 +20,9 @@ struct Gemm {
   long sAb1 = 0, sAb2 = 0, sBb1 = 0, sBb2 = 0, sCb1 = 0, sCb2 = 0;
   double alpha = 1.0, beta = 0.0;
 };
-void gemm(hipStream_t s, const Gemm& g);
+// work (nullable, work_len doubles): split-K partials, so that a product with few output tiles
+// and a long contraction spreads over the chip
+void gemm(hipStream_t s, const Gemm& g, double* work = nullptr, size_t work_len = 0);
 
 // FP64 MFMA GEMM with two-level index maps (k_gemm.hip): every index x of m, n, k is split
 // as x = x1 * X2 + x2 (X2 = inner extent; the default 1 << 30 makes it single-level with
@@ -81,7 +83,7 @@ void gemm2f_grouped(hipStream_t s, int variant, const void* dev_desc, const int*
 // Row-major convenience: C (MxN, ldc) = alpha op(A) op(B) + beta C, op = transpose if t*.
 void gemm_rm(hipStream_t s, int M, int N, int K, const double* A, long lda, bool tA,
              const double* B, long ldb, bool tB, double* C, long ldc, double alpha = 1.0,
-             double beta = 0.0);
+             double beta = 0.0, double* work = nullptr, size_t work_len = 0);
 
 // Banded rank contraction of a TT-matrix core with a 4-way tensor:
 //   out[g][m][i][c] = alpha * sum_{d in [lo[g],hi[g])} sum_o A(d,i,o,g) in[d][m][i+o-p][c] + beta*out
