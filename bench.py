@@ -69,8 +69,8 @@ def parse():
 
 
 # the dominant kernel of the local matvec at the microbenchmark shape (64 x 128 tile, four waves,
-# K tile 12, two LDS buffers, two K tiles of loads in flight, single-level K)
-ROOFLINE_KERNEL = "gemm2_kernel<8, 4, 2, 2, 12, 2, 2, true>"
+# K tile 16, operands loaded straight into three LDS buffers)
+ROOFLINE_KERNEL = "gemm2_dma_kernel"
 
 
 def kernel_source_hash() -> str:

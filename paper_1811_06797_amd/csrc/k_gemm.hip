@@ -56,6 +56,10 @@ __device__ __forceinline__ double gload(const double* p) {
 #ifndef IGA_PREFETCH
 #define IGA_PREFETCH 1
 #endif
+// the wide variant's products that qualify use the LDS-direct kernel (0: never)
+#ifndef IGA_DMA
+#define IGA_DMA 1
+#endif
 
 struct G2Args {
   int M, N, K, M2, N2, K2;
@@ -299,6 +303,164 @@ __global__ __launch_bounds__(NTHR) void gemm2_kernel(G2Args g) {
   gemm2_tile<WM, WN, WAVES_M, WAVES_N, BK, NBUF, PF, K1>(g, tile % gx, (tile / gx) % gy, tile / (gx * gy), L);
 }
 
+// ---- Wide tile with LDS-direct operand loads ----
+// The 64 x 128 tile of the wide variant (four waves of 32 x 64, K tile 16), whose operand tiles
+// go from global memory straight into LDS (global_load_lds_dwordx4: each lane moves 16 bytes to
+// the next 16 bytes of the wave's LDS window), without a register copy and an LDS store. Three
+// LDS buffers hold tiles t, t + 1 and t + 2. For conflict-free fragment reads the 16-byte chunks
+// of odd k rows are permuted: A rows pair up in one 1 KB window (row 2j + 1 at +512 B, chunk
+// index XOR 4); B rows are 1 KB each (odd rows: chunk index XOR 8). Requirements (checked on
+// the host): single-level indices, unit stride along M in A and along N in B, even M, N,
+// strides and 16-byte aligned bases. Partial tiles read a 16-byte zero block.
+__device__ const double kZero2[2] __attribute__((aligned(16))) = {0.0, 0.0};
+constexpr int DBK = 16, DBM = 64, DBN = 128;
+constexpr int DWM = 8, DWN = 4;  // 4-row and 16-column fragment groups per wave
+
+__global__ __launch_bounds__(NTHR) void gemm2_dma_kernel(G2Args g) {
+  __shared__ __attribute__((aligned(16))) double A0[DBK * DBM], A1[DBK * DBM], A2[DBK * DBM];
+  __shared__ __attribute__((aligned(16))) double B0[DBK * DBN], B1[DBK * DBN], B2[DBK * DBN];
+  typedef __attribute__((address_space(3))) void* lds_ptr;
+  typedef const __attribute__((address_space(1))) void* glb_ptr;
+  const int gx = gridDim.x, gy = gridDim.y;
+  const int total = gx * gy * gridDim.z;
+  const int lin = (blockIdx.z * gy + blockIdx.y) * gx + blockIdx.x;
+  const int xcd = lin % 8, q = lin / 8, base = total / 8, rem = total % 8;
+  const int tile = (xcd < rem ? xcd * (base + 1) : rem * (base + 1) + (xcd - rem) * base) + q;
+  const int bx = tile % gx, by = (tile / gx) % gy, bz = tile / (gx * gy);
+  const int split = bz / g.nbatch, bb = bz - split * g.nbatch;
+  const int b1 = bb / g.nb2, b2 = bb - b1 * g.nb2;
+  const double* A = g.A + b1 * g.sAb1 + b2 * g.sAb2;
+  const double* B = g.B + b1 * g.sBb1 + b2 * g.sBb2;
+  const int m0 = by * DBM, n0 = bx * DBN;
+  const int kbeg = split * g.kchunk;
+  const int kend = min(g.K, kbeg + g.kchunk);
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  // this lane's 16-byte chunks: A row pairs 2 wave, 2 wave + 1; B rows 4 wave .. 4 wave + 3
+  int oa[2], ob[4], arow[2];
+  bool mok[2], nok[4];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int hi = lane >> 5;
+    arow[u] = 2 * (2 * wave + u) + hi;
+    const int m = m0 + 2 * ((lane & 31) ^ (4 * hi));
+    mok[u] = m < g.M;
+    oa[u] = (mok[u] ? m : 0) + (kbeg + arow[u]) * (int)g.sAk2;
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int r = 4 * wave + u;
+    const int n = n0 + 2 * (lane ^ (8 * (r & 1)));
+    nok[u] = n < g.N;
+    ob[u] = (nok[u] ? n : 0) + (kbeg + r) * (int)g.sBk2;
+  }
+  const int dA = DBK * (int)g.sAk2, dB = DBK * (int)g.sBk2;
+  auto issue = [&](int kt, double* As, double* Bs) {
+    const int klim = kend - kt;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const double* src = (mok[u] && arow[u] < klim) ? A + oa[u] : kZero2;
+      __builtin_amdgcn_global_load_lds((glb_ptr)src, (lds_ptr)(As + (2 * wave + u) * 128), 16, 0, 0);
+      oa[u] += dA;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double* src = (nok[u] && 4 * wave + u < klim) ? B + ob[u] : kZero2;
+      __builtin_amdgcn_global_load_lds((glb_ptr)src, (lds_ptr)(Bs + (4 * wave + u) * 128), 16, 0, 0);
+      ob[u] += dB;
+    }
+  };
+  const int wm0 = (wave / 2) * (4 * DWM), wn0 = (wave % 2) * (16 * DWN);
+  const int lx = lane / 16, lb = (lane / 4) % 4, ly = lane % 4;
+  // element (k, m) of an A buffer sits at (k / 2) 128 + (k % 2) 64 + 2 ((m / 2) ^ 4 (k % 2)) + m % 2;
+  // element (k, n) of a B buffer at k 128 + 2 ((n / 2) ^ 8 (k % 2)) + n % 2
+  int offA[DWM], offB[DWN];
+#pragma unroll
+  for (int r = 0; r < DWM; ++r) offA[r] = (lx >> 1) * 128 + (lx & 1) * 64 + wm0 + ly + ((4 * r) ^ (8 * (lx & 1)));
+#pragma unroll
+  for (int c = 0; c < DWN; ++c) offB[c] = lx * 128 + wn0 + 4 * lb + ly + ((16 * c) ^ (16 * (lx & 1)));
+  double acc[DWM][DWN];
+#pragma unroll
+  for (int i = 0; i < DWM; ++i)
+#pragma unroll
+    for (int j = 0; j < DWN; ++j) acc[i][j] = 0.0;
+  auto compute = [&](const double* As, const double* Bs) {
+    double fa[2][DWM], fb[2][DWN];
+#pragma unroll
+    for (int r = 0; r < DWM; ++r) fa[0][r] = As[offA[r]];
+#pragma unroll
+    for (int c = 0; c < DWN; ++c) fb[0][c] = Bs[offB[c]];
+#pragma unroll
+    for (int ks = 0; ks < DBK; ks += 4) {
+      const int h = (ks / 4) & 1;
+      if (ks + 4 < DBK) {
+#pragma unroll
+        for (int r = 0; r < DWM; ++r) fa[h ^ 1][r] = As[offA[r] + (ks + 4) * 64];
+#pragma unroll
+        for (int c = 0; c < DWN; ++c) fb[h ^ 1][c] = Bs[offB[c] + (ks + 4) * 128];
+      }
+#pragma unroll
+      for (int r = 0; r < DWM; ++r)
+#pragma unroll
+        for (int c = 0; c < DWN; ++c)
+          acc[r][c] = __builtin_amdgcn_mfma_f64_4x4x4f64(fa[h][r], fb[h][c], acc[r][c], 0, 0, 0);
+    }
+  };
+  // Step t: wait for this wave's loads of tile t (those of tile t + 1, six per wave, may stay
+  // in flight), then a barrier: every wave's tile t is in LDS and every wave is done with tile
+  // t - 1, whose buffer then receives tile t + 2.
+  auto step = [&](int t, const double* As, const double* Bs, double* An, double* Bn) {
+    __builtin_amdgcn_s_waitcnt(0x0F76);  // vmcnt(6); expcnt and lgkmcnt unconstrained
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    issue(kbeg + (t + 2) * DBK, An, Bn);  // past the end: the zero block, never read
+    compute(As, Bs);
+  };
+  const int nkt = (kend - kbeg + DBK - 1) / DBK;
+  issue(kbeg, A0, B0);
+  issue(kbeg + DBK, A1, B1);
+  for (int t = 0; t < nkt; t += 3) {
+    step(t, A0, B0, A2, B2);
+    if (t + 1 >= nkt) break;
+    step(t + 1, A1, B1, A0, B0);
+    if (t + 2 >= nkt) break;
+    step(t + 2, A2, B2, A1, B1);
+  }
+  // drain the loads still in flight (tiles past the end) before the workgroup's LDS is released
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+  // acc[r][c] at this lane is C[wm0 + 4r + lx][wn0 + 16c + 4lb + ly]
+  if (g.ksplit > 1) {
+    double* W = g.work + ((long)split * g.nbatch + bb) * (long)g.M * g.N;
+#pragma unroll
+    for (int r = 0; r < DWM; ++r) {
+      const int m = m0 + wm0 + r * 4 + lx;
+      if (m >= g.M) continue;
+#pragma unroll
+      for (int c = 0; c < DWN; ++c) {
+        const int n = n0 + wn0 + c * 16 + lb * 4 + ly;
+        if (n < g.N) W[(long)m * g.N + n] = acc[r][c];
+      }
+    }
+    return;
+  }
+  double* C = g.C + b1 * g.sCb1 + b2 * g.sCb2;
+#pragma unroll
+  for (int r = 0; r < DWM; ++r) {
+    const int m = m0 + wm0 + r * 4 + lx;
+    if (m >= g.M) continue;
+    const long crow = off2(m, g.M2, g.sCm1, g.sCm2);
+#pragma unroll
+    for (int c = 0; c < DWN; ++c) {
+      const int n = n0 + wn0 + c * 16 + lb * 4 + ly;
+      if (n >= g.N) continue;
+      double* p = C + crow + off2(n, g.N2, g.sCn1, g.sCn2);
+      double v = g.alpha * acc[r][c];
+      if (g.beta != 0.0) v += g.beta * *p;
+      *p = v;
+    }
+  }
+}
+
 // Many independent products in one persistent launch: workgroup w takes the tiles
 // w, w + gridDim.x, ... of the concatenated tile lists (product i owns the tiles
 // [prefix[i], prefix[i + 1])), so every workgroup ends after at most ceil(total / grid) tiles.
@@ -440,6 +602,16 @@ void gemm2_grouped(hipStream_t s, int variant, const void* dev_desc, const int* 
   IGA_HIP(hipGetLastError());
 }
 
+// The LDS-direct wide tile moves 16-byte chunks of two consecutive M (or N) elements: single-
+// level indices, unit strides along M in A and N in B, even extents and strides, and 16-byte
+// aligned operand bases.
+static bool dma_eligible(const Gemm2& d) {
+  auto even = [](long v) { return v % 2 == 0; };
+  return d.K2 >= d.K && d.M2 >= d.M && d.N2 >= d.N && d.sAm2 == 1 && d.sBn2 == 1 && even(d.M) && even(d.N) &&
+         even(d.sAk2) && even(d.sBk2) && even(d.sAb1) && even(d.sAb2) && even(d.sBb1) && even(d.sBb2) &&
+         reinterpret_cast<uintptr_t>(d.A) % 16 == 0 && reinterpret_cast<uintptr_t>(d.B) % 16 == 0;
+}
+
 void gemm2(hipStream_t s, const Gemm2& d, double* work, size_t work_len) {
   if (d.M <= 0 || d.N <= 0 || d.nb1 <= 0 || d.nb2 <= 0) return;
   G2Args a = make_args(d);
@@ -462,6 +634,11 @@ void gemm2(hipStream_t s, const Gemm2& d, double* work, size_t work_len) {
     }
   }
   require((long)nb * a.ksplit <= 65535, IGA_EINVAL, "gemm2: batch too large");
+  if (IGA_DMA && variant == 4 && IGA_WIDE_WN == 4 && dma_eligible(d)) {
+    dim3 grid((a.N + DBN - 1) / DBN, (a.M + DBM - 1) / DBM, (unsigned)(nb * a.ksplit));
+    require((long)grid.x * grid.y * grid.z < (1L << 31), IGA_EINVAL, "gemm2: grid too large");
+    gemm2_dma_kernel<<<grid, NTHR, 0, s>>>(a);
+  } else {
   switch (variant) {
     case 2: launch<4, 4, 1, 4, 16, 2, IGA_PREFETCH>(s, a, (int)nb); break;
     case 1: launch<8, 2, 1, 4, 16, 2, IGA_PREFETCH>(s, a, (int)nb); break;
@@ -469,6 +646,7 @@ void gemm2(hipStream_t s, const Gemm2& d, double* work, size_t work_len) {
     case 4: launch<8, IGA_WIDE_WN, 2, 2, IGA_WIDE_BK, IGA_WIDE_NBUF, IGA_WIDE_PREFETCH>(s, a, (int)nb); break;
     case 5: launch<10, 2, 2, 2, 16, 2, IGA_PREFETCH>(s, a, (int)nb); break;
     default: launch<8, 2, 2, 2, 16, 2, IGA_PREFETCH>(s, a, (int)nb); break;
+  }
   }
   IGA_HIP(hipGetLastError());
   if (a.ksplit > 1) {
