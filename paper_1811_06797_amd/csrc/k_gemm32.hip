@@ -24,6 +24,10 @@ namespace k {
 namespace {
 
 constexpr int NT = 256, BKF = 16, BKH = 32;
+// FP32 wide-tile products that qualify use the LDS-direct kernel (0: never)
+#ifndef IGA_DMA_F32
+#define IGA_DMA_F32 1
+#endif
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef short s8 __attribute__((ext_vector_type(8)));
@@ -254,6 +258,156 @@ __global__ __launch_bounds__(NT) void gemm2f_kernel(G2FArgs g) {
   gemm2f_tile<WM, WN, WAVES_M, WAVES_N, BF>(g, tile % gx, (tile / gx) % gy, tile / (gx * gy), L);
 }
 
+// FP32 wide tile (64 x 128, four waves of 32 x 64, K tile 16) with LDS-direct operand loads:
+// each global_load_lds_dwordx4 moves four floats per lane into the next 16 bytes of the wave's
+// LDS window, three LDS buffers hold tiles t, t + 1 and t + 2. A windows hold four K rows of 64
+// floats, B windows two K rows of 128; in K row k the 16-byte chunk c sits at position
+// c ^ 4 (k % 4), so that the four rows a fragment read touches fall into disjoint banks.
+// Requirements (checked on the host): single-level indices, unit strides along M in A and N in
+// B, M, N and the strides multiples of 4, 16-byte aligned bases. Partial tiles read zeros.
+__device__ const float kZeroF4[4] __attribute__((aligned(16))) = {0.0f, 0.0f, 0.0f, 0.0f};
+constexpr int FDM = 64, FDN = 128;
+
+__global__ __launch_bounds__(NT) void gemm2f_dma_kernel(G2FArgs g) {
+  __shared__ __attribute__((aligned(16))) float A0[BKF * FDM], A1[BKF * FDM], A2[BKF * FDM];
+  __shared__ __attribute__((aligned(16))) float B0[BKF * FDN], B1[BKF * FDN], B2[BKF * FDN];
+  typedef __attribute__((address_space(3))) void* lds_ptr;
+  typedef const __attribute__((address_space(1))) void* glb_ptr;
+  const int gx = gridDim.x, gy = gridDim.y;
+  const int total = gx * gy * gridDim.z;
+  const int lin = (blockIdx.z * gy + blockIdx.y) * gx + blockIdx.x;
+  const int xcd = lin % 8, q8 = lin / 8, base = total / 8, rem = total % 8;
+  const int tile = (xcd < rem ? xcd * (base + 1) : rem * (base + 1) + (xcd - rem) * base) + q8;
+  const int bx = tile % gx, by = (tile / gx) % gy, bz = tile / (gx * gy);
+  const int split = bz / g.nbatch, bb = bz - split * g.nbatch;
+  const int b1 = bb / g.nb2, b2 = bb - b1 * g.nb2;
+  const float* A = g.A + b1 * g.sAb1 + b2 * g.sAb2;
+  const float* B = g.B + b1 * g.sBb1 + b2 * g.sBb2;
+  const int m0 = by * FDM, n0 = bx * FDN;
+  const int kbeg = split * g.kchunk;
+  const int kend = min(g.K, kbeg + g.kchunk);
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  // this lane's chunks: A window = wave (K rows 4 wave .. 4 wave + 3), B windows 2 wave, 2 wave + 1
+  int oa, ob[2], brow[2];
+  bool mok, nok[2];
+  const int arow = 4 * wave + (lane >> 4);
+  {
+    const int m = m0 + 4 * ((lane & 15) ^ (4 * (lane >> 4)));
+    mok = m < g.M;
+    oa = (mok ? m : 0) + (kbeg + arow) * (int)g.sAk2;
+  }
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int i = 2 * wave + u;
+    brow[u] = 2 * i + (lane >> 5);
+    const int n = n0 + 4 * ((lane & 31) ^ (4 * (brow[u] & 3)));
+    nok[u] = n < g.N;
+    ob[u] = (nok[u] ? n : 0) + (kbeg + brow[u]) * (int)g.sBk2;
+  }
+  const int dA = BKF * (int)g.sAk2, dB = BKF * (int)g.sBk2;
+  auto issue = [&](int kt, float* As, float* Bs) {
+    const int klim = kend - kt;
+    {
+      const float* src = (mok && arow < klim) ? A + oa : kZeroF4;
+      __builtin_amdgcn_global_load_lds((glb_ptr)src, (lds_ptr)(As + wave * 256), 16, 0, 0);
+      oa += dA;
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const float* src = (nok[u] && brow[u] < klim) ? B + ob[u] : kZeroF4;
+      __builtin_amdgcn_global_load_lds((glb_ptr)src, (lds_ptr)(Bs + (2 * wave + u) * 256), 16, 0, 0);
+      ob[u] += dB;
+    }
+  };
+  constexpr int WM = 2, WN = 4;
+  const int wm0 = (wave / 2) * (16 * WM), wn0 = (wave % 2) * (16 * WN);
+  const int lq = lane / 16, lt = lane % 16;
+  // element (k, m) of an A buffer: (k / 4) 256 + (k % 4) 64 + 4 ((m / 4) ^ 4 (k % 4)) + m % 4;
+  // element (k, n) of a B buffer: (k / 2) 256 + (k % 2) 128 + 4 ((n / 4) ^ 4 (k % 4)) + n % 4
+  int offA[WM], offB[WN];
+#pragma unroll
+  for (int r = 0; r < WM; ++r) offA[r] = lq * 64 + 4 * (((wm0 >> 2) + 4 * r + (lt >> 2)) ^ (4 * lq)) + (lt & 3);
+#pragma unroll
+  for (int c = 0; c < WN; ++c)
+    offB[c] = (lq >> 1) * 256 + (lq & 1) * 128 + 4 * (((wn0 >> 2) + 4 * c + (lt >> 2)) ^ (4 * lq)) + (lt & 3);
+  f4 acc[WM][WN];
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j) acc[i][j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+  auto compute = [&](const float* As, const float* Bs) {
+#pragma unroll
+    for (int ks = 0; ks < BKF; ks += 4) {
+      float fa[WM], fb[WN];
+#pragma unroll
+      for (int r = 0; r < WM; ++r) fa[r] = As[offA[r] + ks * 64];
+#pragma unroll
+      for (int c = 0; c < WN; ++c) fb[c] = Bs[offB[c] + ks * 128];
+#pragma unroll
+      for (int r = 0; r < WM; ++r)
+#pragma unroll
+        for (int c = 0; c < WN; ++c)
+          acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[r], fb[c], acc[r][c], 0, 0, 0);
+    }
+  };
+  // as in gemm2_dma_kernel: wait for this wave's loads of tile t (three per wave for tile t + 1
+  // may stay in flight), barrier, issue tile t + 2 into the buffer of tile t - 1, multiply tile t
+  auto step = [&](int t, const float* As, const float* Bs, float* An, float* Bn) {
+    __builtin_amdgcn_s_waitcnt(0x0F73);  // vmcnt(3); expcnt and lgkmcnt unconstrained
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    issue(kbeg + (t + 2) * BKF, An, Bn);
+    compute(As, Bs);
+  };
+  const int nkt = (kend - kbeg + BKF - 1) / BKF;
+  issue(kbeg, A0, B0);
+  issue(kbeg + BKF, A1, B1);
+  for (int t = 0; t < nkt; t += 3) {
+    step(t, A0, B0, A2, B2);
+    if (t + 1 >= nkt) break;
+    step(t + 1, A1, B1, A0, B0);
+    if (t + 2 >= nkt) break;
+    step(t + 2, A2, B2, A1, B1);
+  }
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): no load may land after the workgroup ends
+  // acc[r][c][v] at this lane is C[wm0 + 16 r + 4 lq + v][wn0 + 16 c + lt]
+  if (g.ksplit > 1) {
+    float* W = g.work + ((long)split * g.nbatch + bb) * (long)g.M * g.N;
+#pragma unroll
+    for (int r = 0; r < WM; ++r)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = m0 + wm0 + 16 * r + 4 * lq + v;
+        if (m >= g.M) continue;
+#pragma unroll
+        for (int c = 0; c < WN; ++c) {
+          const int n = n0 + wn0 + 16 * c + lt;
+          if (n < g.N) W[(long)m * g.N + n] = acc[r][c][v];
+        }
+      }
+    return;
+  }
+  float* C = g.C + b1 * g.sCb1 + b2 * g.sCb2;
+#pragma unroll
+  for (int r = 0; r < WM; ++r)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int m = m0 + wm0 + 16 * r + 4 * lq + v;
+      if (m >= g.M) continue;
+      const long crow = off2f(m, g.M2, g.sCm1, g.sCm2);
+#pragma unroll
+      for (int c = 0; c < WN; ++c) {
+        const int n = n0 + wn0 + 16 * c + lt;
+        if (n >= g.N) continue;
+        float* p = C + crow + off2f(n, g.N2, g.sCn1, g.sCn2);
+        float val = g.alpha * acc[r][c][v];
+        if (g.beta != 0.0f) val += g.beta * *p;
+        *p = val;
+      }
+    }
+}
+
 // Persistent grouped form (see gemm2_grouped_kernel).
 template <int WM, int WN, int WAVES_M, int WAVES_N>
 __global__ __launch_bounds__(NT) void gemm2f_grouped_kernel(const G2FArgs* gs, const int* prefix, int ngemm,
@@ -375,6 +529,16 @@ void gemm2f_grouped(hipStream_t s, int variant, const void* dev_desc, const int*
   IGA_HIP(hipGetLastError());
 }
 
+// The FP32 LDS-direct tile moves chunks of four consecutive M (or N) elements: single-level
+// indices, unit strides along M in A and N in B, extents and strides multiples of 4, 16-byte
+// aligned operand bases.
+static bool dma_eligible_f(const Gemm2F& d) {
+  auto q4 = [](long v) { return v % 4 == 0; };
+  return d.K2 >= d.K && d.M2 >= d.M && d.N2 >= d.N && d.sAm2 == 1 && d.sBn2 == 1 && q4(d.M) && q4(d.N) &&
+         q4(d.sAk2) && q4(d.sBk2) && q4(d.sAb1) && q4(d.sAb2) && q4(d.sBb1) && q4(d.sBb2) &&
+         reinterpret_cast<uintptr_t>(d.A) % 16 == 0 && reinterpret_cast<uintptr_t>(d.B) % 16 == 0;
+}
+
 static void gemm2_fstore(hipStream_t s, const Gemm2F& d, float* work, size_t work_len, bool bf16) {
   if (d.M <= 0 || d.N <= 0 || d.nb1 <= 0 || d.nb2 <= 0) return;
   G2FArgs a = make_args_f(d);
@@ -394,12 +558,18 @@ static void gemm2_fstore(hipStream_t s, const Gemm2F& d, float* work, size_t wor
     }
   }
   require((long)nb * a.ksplit <= 65535, IGA_EINVAL, "gemm2_f32: batch too large");
+  if (IGA_DMA_F32 && !bf16 && variant == 4 && dma_eligible_f(d)) {
+    dim3 grid((a.N + FDN - 1) / FDN, (a.M + FDM - 1) / FDM, (unsigned)(nb * a.ksplit));
+    require((long)grid.x * grid.y * grid.z < (1L << 31), IGA_EINVAL, "gemm2_f32: grid too large");
+    gemm2f_dma_kernel<<<grid, NT, 0, s>>>(a);
+  } else {
   switch (variant) {
     case 2: launchf<1, 4, 1, 4>(s, a, (int)nb, bf16); break;
     case 1: launchf<2, 2, 1, 4>(s, a, (int)nb, bf16); break;
     case 3: launchf<2, 2, 4, 1>(s, a, (int)nb, bf16); break;
     case 4: launchf<2, 4, 2, 2>(s, a, (int)nb, bf16); break;
     default: launchf<2, 2, 2, 2>(s, a, (int)nb, bf16); break;
+  }
   }
   IGA_HIP(hipGetLastError());
   if (a.ksplit > 1) {

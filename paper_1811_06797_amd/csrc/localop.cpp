@@ -209,6 +209,7 @@ struct RawCache {
   LocalWork w;
   FBuf fPhi[4], fM, fK, fx, fy;
   DBuf rM, rK;  // cores re-laid for the banded stage
+  FBuf frM, frK;  // their FP32 copies (mixed-precision forms)
 };
 std::unordered_map<iga_ctx*, std::unique_ptr<RawCache>> g_raw;
 RawCache& raw_cache(iga_ctx* ctx) {
@@ -288,6 +289,17 @@ void local_matvec_impl(iga_ctx* ctx, int r0, int n, int r1, int p, int RM0, int 
   k::to_f32(st, kz, Kcore, C.fK.get());
   k::to_f32(st, xz, x, C.fx.get());
   L.M.Af = C.fM.get(); L.K.Af = C.fK.get();
+  {
+    // re-laid cores, as in the FP64 form, converted to FP32
+    const int dimsM[4] = {RM0, n, b, RM1}, dimsK[4] = {RK0, n, b, RK1}, perm[4] = {1, 2, 0, 3};
+    C.rM.ensure(ctx, mz); C.rK.ensure(ctx, kz);
+    C.frM.ensure(ctx, mz); C.frK.ensure(ctx, kz);
+    k::permute4(st, Mcore, dimsM, perm, C.rM.get());
+    k::permute4(st, Kcore, dimsK, perm, C.rK.get());
+    k::to_f32(st, mz, C.rM.get(), C.frM.get());
+    k::to_f32(st, kz, C.rK.get(), C.frK.get());
+    L.M.Arf = C.frM.get(); L.K.Arf = C.frK.get();
+  }
   L.fPhiL_M = C.fPhi[0].get(); L.fPhiR_M = C.fPhi[1].get();
   L.fPhiL_K = C.fPhi[2].get(); L.fPhiR_K = C.fPhi[3].get();
   local_matvec_f32(ctx, L, C.fx.get(), C.fy.get(), C.w, precision == IGA_BF16);

@@ -33,7 +33,12 @@ def _run(gpu_ctx, prob, r, n, p, RM, RK, beta, precision, rr=None):
 
 @pytest.mark.parametrize("r,RM,RK,n,p,rr", [(3, 1, 2, 5, 1, None), (5, 2, 3, 9, 2, None), (7, 3, 5, 13, 3, 4),
                                              (1, 1, 3, 6, 2, 4), (17, 2, 9, 23, 3, None),
-                                             (24, 1, 1, 40, 3, 30)])
+                                             (24, 1, 1, 40, 3, 30),
+                                             # banded K stage on the LDS-direct wide tile: N = 2 r^2 = 2178
+                                             # is 17 column tiles and a ragged one, M = 50 a partial tile,
+                                             # K = 350 a partial K tile; odd R_K = 51 takes the
+                                             # register-staged kernel instead
+                                             (33, 4, 50, 32, 3, None), (33, 4, 51, 32, 3, None)])
 def test_local_matvec_matches_oracle(gpu_ctx, r, RM, RK, n, p, rr):
     from paper_1811_06797_amd import iga
     prob = synth.random_local_problem(r, RM, RK, n, p, seed=r + n, r_right=rr)
@@ -49,7 +54,12 @@ FP32_TOL = 5e-5
 
 
 @pytest.mark.parametrize("r,RM,RK,n,p,rr", [(3, 1, 2, 5, 1, None), (5, 2, 3, 9, 2, None), (7, 3, 5, 13, 3, 4),
-                                             (1, 1, 3, 6, 2, 4), (17, 2, 9, 23, 3, None)])
+                                             (1, 1, 3, 6, 2, 4), (17, 2, 9, 23, 3, None),
+                                             # banded K stage on the FP32 LDS-direct wide tile (N = 2312:
+                                             # a ragged column tile, M = 52 and K = 364 partial tiles);
+                                             # R_K = 50 is not a multiple of 4 and takes the
+                                             # register-staged kernel
+                                             (34, 4, 52, 32, 3, None), (34, 4, 50, 32, 3, None)])
 def test_local_matvec_fp32_matches_oracle(gpu_ctx, r, RM, RK, n, p, rr):
     from paper_1811_06797_amd import iga
     prob = synth.random_local_problem(r, RM, RK, n, p, seed=r + n, r_right=rr)
