@@ -621,10 +621,11 @@ void gemm2(hipStream_t s, const Gemm2& d, double* work, size_t work_len) {
   int BM, BN;
   variant_tile(variant, BM, BN);
   const long tiles = (long)((d.M + BM - 1) / BM) * ((d.N + BN - 1) / BN) * nb;
-  // split K when the tiles cannot fill the chip and the contraction is long
+  // split K when the tiles cannot fill the chip (about four workgroups per CU) and the
+  // contraction is long
   constexpr int KALIGN = 48;  // split-K chunks are whole K tiles of every variant (12 or 16 deep)
-  if (work && tiles < 256 && d.K >= 4 * KALIGN) {
-    int ks = (int)std::min<long>((512 + tiles - 1) / tiles, d.K / (2 * KALIGN));
+  if (work && tiles < 512 && d.K >= 4 * KALIGN) {
+    int ks = (int)std::min<long>((1024 + tiles - 1) / tiles, d.K / (2 * KALIGN));
     while (ks > 1 && (size_t)ks * nb * d.M * d.N > work_len) --ks;
     if (ks > 1) {
       a.ksplit = ks;
