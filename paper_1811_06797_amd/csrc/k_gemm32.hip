@@ -547,8 +547,9 @@ static void gemm2_fstore(hipStream_t s, const Gemm2F& d, float* work, size_t wor
   int BM, BN;
   variant_tile_f(variant, BM, BN);
   const long tiles = (long)((d.M + BM - 1) / BM) * ((d.N + BN - 1) / BN) * nb;
-  if (work && tiles < 256 && d.K >= 4 * 32) {
-    int ks = (int)std::min<long>((512 + tiles - 1) / tiles, d.K / 64);
+  // split K when the tiles cannot fill the chip (about four workgroups per CU)
+  if (work && tiles < 512 && d.K >= 4 * 32) {
+    int ks = (int)std::min<long>((1024 + tiles - 1) / tiles, d.K / 64);
     while (ks > 1 && (size_t)ks * nb * d.M * d.N > work_len) --ks;
     if (ks > 1) {
       const int bk = bf16 ? BKH : BKF;
