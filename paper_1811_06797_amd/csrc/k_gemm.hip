@@ -9,10 +9,12 @@
 // independent 4x4x4 blocks per instruction, 512 flops): per K-step of 4 it reads WM A
 // fragments (one per 4-row block, shared by the instruction's four blocks) and WN B
 // fragments (four 4-column blocks each) from LDS and issues WM * WN MFMAs. Four waves
-// form the workgroup tile; K is staged through LDS 16 deep with register double
-// buffering. Tile variants serve tall, square and skinny outputs; when the output has too
-// few tiles to fill the chip the K range is split and the partial products are summed in
-// a fixed order by a second kernel (deterministic).
+// form the workgroup tile; K is staged through LDS 16 deep (12 for the wide variant) with
+// register double buffering. Tile variants serve tall, square and skinny outputs; the wide
+// variant's products that qualify load their operand tiles straight into LDS instead
+// (gemm2_dma_kernel). When the output has too few tiles to fill the chip the K range is
+// split and the partial products are summed in a fixed order by a second kernel
+// (deterministic).
 //
 // Operand lane layout of v_mfma_f64_4x4x4 (lane = 16x + 4b + y, b = block):
 //   A_b[i][k] in lane 16k + 4b + i;  B_b[k][j] in lane 16k + 4b + j;  C_b[i][j] in lane 16i + 4b + j.

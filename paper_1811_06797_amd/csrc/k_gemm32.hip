@@ -12,7 +12,8 @@
 //    operand is one 16-byte LDS read.
 // Each wave owns a (16 WM) x (16 WN) block of C; four waves form the workgroup tile; K is
 // staged through LDS (16 deep in FP32, 32 in BF16), double-buffered, with the next tile's
-// global loads in flight during the current tile's products.
+// global loads in flight during the current tile's products. FP32 products of the wide tile
+// that qualify load their operands straight into LDS instead (gemm2f_dma_kernel).
 #include <algorithm>
 #include <cstring>
 
