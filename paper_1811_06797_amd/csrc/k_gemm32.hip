@@ -409,6 +409,179 @@ __global__ __launch_bounds__(NT) void gemm2f_dma_kernel(G2FArgs g) {
     }
 }
 
+// BF16-product form of the LDS-direct wide tile (64 x 128, four waves of 32 x 64, K tile 32):
+// FP32 operand tiles go straight into LDS as in gemm2f_dma_kernel, and each fragment read
+// rounds its eight floats to bfloat16 (nearest, ties to even: v_cvt_pk_bf16_f32) for
+// v_mfma_f32_16x16x32_bf16, whose lane 16 q + t takes K rows 8 q .. 8 q + 7 of row (column)
+// t. A windows hold four K rows of 64 floats, B windows two K rows of 128; in K row k the
+// 16-byte chunk c sits at position c ^ 4 ((k % 4) ^ (k / 8 % 4)), so that the four lane
+// groups q of one read, which share k % 4, still fall into disjoint banks.
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef __bf16 b2v __attribute__((ext_vector_type(2)));
+typedef unsigned u4v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned cvt_bf16x2(float x, float y) {
+  const b2v v = __builtin_convertvector((f2v){x, y}, b2v);
+  return __builtin_bit_cast(unsigned, v);
+}
+
+__global__ __launch_bounds__(NT) void gemm2b_dma_kernel(G2FArgs g) {
+  __shared__ __attribute__((aligned(16))) float A0[BKH * FDM], A1[BKH * FDM], A2[BKH * FDM];
+  __shared__ __attribute__((aligned(16))) float B0[BKH * FDN], B1[BKH * FDN], B2[BKH * FDN];
+  typedef __attribute__((address_space(3))) void* lds_ptr;
+  typedef const __attribute__((address_space(1))) void* glb_ptr;
+  const int gx = gridDim.x, gy = gridDim.y;
+  const int total = gx * gy * gridDim.z;
+  const int lin = (blockIdx.z * gy + blockIdx.y) * gx + blockIdx.x;
+  const int xcd = lin % 8, q8 = lin / 8, base = total / 8, rem = total % 8;
+  const int tile = (xcd < rem ? xcd * (base + 1) : rem * (base + 1) + (xcd - rem) * base) + q8;
+  const int bx = tile % gx, by = (tile / gx) % gy, bz = tile / (gx * gy);
+  const int split = bz / g.nbatch, bb = bz - split * g.nbatch;
+  const int b1 = bb / g.nb2, b2 = bb - b1 * g.nb2;
+  const float* A = g.A + b1 * g.sAb1 + b2 * g.sAb2;
+  const float* B = g.B + b1 * g.sBb1 + b2 * g.sBb2;
+  const int m0 = by * FDM, n0 = bx * FDN;
+  const int kbeg = split * g.kchunk;
+  const int kend = min(g.K, kbeg + g.kchunk);
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  auto swz = [](int k) { return 4 * ((k & 3) ^ ((k >> 3) & 3)); };
+  // this lane's chunks: A windows 2 wave, 2 wave + 1 (K rows 4 j .. 4 j + 3), B windows
+  // 4 wave .. 4 wave + 3 (K rows 2 j, 2 j + 1)
+  int oa[2], ob[4], arow[2], brow[4];
+  bool mok[2], nok[4];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int j = 2 * wave + u;
+    arow[u] = 4 * j + (lane >> 4);
+    const int m = m0 + 4 * ((lane & 15) ^ swz(arow[u]));
+    mok[u] = m < g.M;
+    oa[u] = (mok[u] ? m : 0) + (kbeg + arow[u]) * (int)g.sAk2;
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int j = 4 * wave + u;
+    brow[u] = 2 * j + (lane >> 5);
+    const int n = n0 + 4 * ((lane & 31) ^ swz(brow[u]));
+    nok[u] = n < g.N;
+    ob[u] = (nok[u] ? n : 0) + (kbeg + brow[u]) * (int)g.sBk2;
+  }
+  const int dA = BKH * (int)g.sAk2, dB = BKH * (int)g.sBk2;
+  auto issue = [&](int kt, float* As, float* Bs) {
+    const int klim = kend - kt;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const float* src = (mok[u] && arow[u] < klim) ? A + oa[u] : kZeroF4;
+      __builtin_amdgcn_global_load_lds((glb_ptr)src, (lds_ptr)(As + (2 * wave + u) * 256), 16, 0, 0);
+      oa[u] += dA;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const float* src = (nok[u] && brow[u] < klim) ? B + ob[u] : kZeroF4;
+      __builtin_amdgcn_global_load_lds((glb_ptr)src, (lds_ptr)(Bs + (4 * wave + u) * 256), 16, 0, 0);
+      ob[u] += dB;
+    }
+  };
+  constexpr int WM = 2, WN = 4;
+  const int wm0 = (wave / 2) * (16 * WM), wn0 = (wave % 2) * (16 * WN);
+  const int q = lane / 16, t = lane % 16;
+  // element (k, m) of an A buffer: (k / 4) 256 + (k % 4) 64 + 4 ((m / 4) ^ swz(k)) + m % 4;
+  // element (k, n) of a B buffer: (k / 2) 256 + (k % 2) 128 + 4 ((n / 4) ^ swz(k)) + n % 4.
+  // For k = 8 q + e the rows e and e + 4 lie 256 (A) or 512 (B) floats apart.
+  int offA[WM][4], offB[WN][4];
+#pragma unroll
+  for (int r = 0; r < WM; ++r)
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      offA[r][e] = 2 * q * 256 + e * 64 + 4 * (((wm0 >> 2) + 4 * r + (t >> 2)) ^ (4 * (e ^ q))) + (t & 3);
+#pragma unroll
+  for (int c = 0; c < WN; ++c)
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      offB[c][e] = (4 * q + (e >> 1)) * 256 + (e & 1) * 128 + 4 * (((wn0 >> 2) + 4 * c + (t >> 2)) ^ (4 * (e ^ q))) +
+                   (t & 3);
+  f4 acc[WM][WN];
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j) acc[i][j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+  auto frag = [&](const float* X, const int (&off)[4], int step) {
+    float v[8];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      v[e] = X[off[e]];
+      v[e + 4] = X[off[e] + step];
+    }
+    const u4v w = {cvt_bf16x2(v[0], v[1]), cvt_bf16x2(v[2], v[3]), cvt_bf16x2(v[4], v[5]), cvt_bf16x2(v[6], v[7])};
+    return __builtin_bit_cast(s8, w);
+  };
+  auto compute = [&](const float* As, const float* Bs) {
+    s8 fa[WM], fb[WN];
+#pragma unroll
+    for (int r = 0; r < WM; ++r) fa[r] = frag(As, offA[r], 256);
+#pragma unroll
+    for (int c = 0; c < WN; ++c) fb[c] = frag(Bs, offB[c], 512);
+#pragma unroll
+    for (int r = 0; r < WM; ++r)
+#pragma unroll
+      for (int c = 0; c < WN; ++c)
+        acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[r], fb[c], acc[r][c], 0, 0, 0);
+  };
+  auto step = [&](int tt, const float* As, const float* Bs, float* An, float* Bn) {
+    __builtin_amdgcn_s_waitcnt(0x0F76);  // vmcnt(6): this wave's loads of the next tile may stay in flight
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    issue(kbeg + (tt + 2) * BKH, An, Bn);
+    compute(As, Bs);
+  };
+  const int nkt = (kend - kbeg + BKH - 1) / BKH;
+  issue(kbeg, A0, B0);
+  issue(kbeg + BKH, A1, B1);
+  for (int tt = 0; tt < nkt; tt += 3) {
+    step(tt, A0, B0, A2, B2);
+    if (tt + 1 >= nkt) break;
+    step(tt + 1, A1, B1, A0, B0);
+    if (tt + 2 >= nkt) break;
+    step(tt + 2, A2, B2, A1, B1);
+  }
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+  // acc[r][c][v] at this lane is C[wm0 + 16 r + 4 q + v][wn0 + 16 c + t]
+  if (g.ksplit > 1) {
+    float* W = g.work + ((long)split * g.nbatch + bb) * (long)g.M * g.N;
+#pragma unroll
+    for (int r = 0; r < WM; ++r)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = m0 + wm0 + 16 * r + 4 * q + v;
+        if (m >= g.M) continue;
+#pragma unroll
+        for (int c = 0; c < WN; ++c) {
+          const int n = n0 + wn0 + 16 * c + t;
+          if (n < g.N) W[(long)m * g.N + n] = acc[r][c][v];
+        }
+      }
+    return;
+  }
+  float* C = g.C + b1 * g.sCb1 + b2 * g.sCb2;
+#pragma unroll
+  for (int r = 0; r < WM; ++r)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int m = m0 + wm0 + 16 * r + 4 * q + v;
+      if (m >= g.M) continue;
+      const long crow = off2f(m, g.M2, g.sCm1, g.sCm2);
+#pragma unroll
+      for (int c = 0; c < WN; ++c) {
+        const int n = n0 + wn0 + 16 * c + t;
+        if (n >= g.N) continue;
+        float* p = C + crow + off2f(n, g.N2, g.sCn1, g.sCn2);
+        float val = g.alpha * acc[r][c][v];
+        if (g.beta != 0.0f) val += g.beta * *p;
+        *p = val;
+      }
+    }
+}
+
 // Persistent grouped form (see gemm2_grouped_kernel).
 template <int WM, int WN, int WAVES_M, int WAVES_N>
 __global__ __launch_bounds__(NT) void gemm2f_grouped_kernel(const G2FArgs* gs, const int* prefix, int ngemm,
@@ -560,10 +733,13 @@ static void gemm2_fstore(hipStream_t s, const Gemm2F& d, float* work, size_t wor
     }
   }
   require((long)nb * a.ksplit <= 65535, IGA_EINVAL, "gemm2_f32: batch too large");
-  if (IGA_DMA_F32 && !bf16 && variant == 4 && dma_eligible_f(d)) {
+  if (IGA_DMA_F32 && variant == 4 && dma_eligible_f(d)) {
     dim3 grid((a.N + FDN - 1) / FDN, (a.M + FDM - 1) / FDM, (unsigned)(nb * a.ksplit));
     require((long)grid.x * grid.y * grid.z < (1L << 31), IGA_EINVAL, "gemm2_f32: grid too large");
-    gemm2f_dma_kernel<<<grid, NT, 0, s>>>(a);
+    if (bf16)
+      gemm2b_dma_kernel<<<grid, NT, 0, s>>>(a);
+    else
+      gemm2f_dma_kernel<<<grid, NT, 0, s>>>(a);
   } else {
   switch (variant) {
     case 2: launchf<1, 4, 1, 4>(s, a, (int)nb, bf16); break;
