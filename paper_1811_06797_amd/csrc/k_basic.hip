@@ -308,6 +308,33 @@ __global__ __launch_bounds__(256) void band_rank1_kernel(int b, long ncols, cons
   y[(long)i * ncols + c] = acc;
 }
 
+// Banded stage of an operator core with few right ranks (R1 <= 16): for row i (blockIdx.y)
+// and column c, y[i][g][c] = sum_{o < b, d < R0} A[i][o][d][g] x[(i + o) ldx + d ldd + c] for
+// g < R1, with A the core re-laid as [n][b][R0][R1]. The coefficients are the same for the
+// whole workgroup, so they are read as scalars; each thread keeps its column's R1 sums.
+template <typename T, int R1>
+__global__ __launch_bounds__(256) void band_small_kernel(int b, int R0, long ncols, const T* A, const T* x, long ldx,
+                                                         long ldd, T* y) {
+  constexpr int GM = R1;
+  const int i = blockIdx.y;
+  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncols) return;
+  T acc[GM];
+#pragma unroll
+  for (int g = 0; g < GM; ++g) acc[g] = T(0);
+  const T* a = A + (long)i * b * R0 * R1;
+  for (int o = 0; o < b; ++o) {
+    const T* xo = x + (long)(i + o) * ldx + c;
+    for (int d = 0; d < R0; ++d, a += R1) {
+      const T v = xo[(long)d * ldd];
+#pragma unroll
+      for (int g = 0; g < GM; ++g) acc[g] += a[g] * v;
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < GM; ++g) y[((long)i * R1 + g) * ncols + c] = acc[g];
+}
+
 // y[o] = sum of coef[t] z[src[t]] over the terms t of output block o (blockIdx.y = o).
 __global__ void combine_blocks_kernel(long e, const int* toff, const int* src, const double* coef,
                                       const double* z, double* y) {
@@ -584,6 +611,33 @@ static void band_rank1_launch(hipStream_t s, int n, int b, long ncols, const T* 
   dim3 grid((unsigned)((ncols + 255) / 256), (unsigned)n);
   band_rank1_kernel<T><<<grid, 256, 0, s>>>(b, ncols, A, x, ldx, y);
   IGA_HIP(hipGetLastError());
+}
+
+template <typename T>
+static void band_small_launch(hipStream_t s, int n, int b, int R0, int R1, long ncols, const T* A, const T* x,
+                              long ldx, long ldd, T* y) {
+  if (n <= 0 || ncols <= 0) return;
+  require(n <= 65535 && b >= 1 && R0 >= 1 && R1 >= 1 && R1 <= 16, IGA_EINVAL, "band_small: bad sizes");
+  dim3 grid((unsigned)((ncols + 255) / 256), (unsigned)n);
+  switch (R1) {
+#define IGA_BAND_SMALL(r) \
+  case r: band_small_kernel<T, r><<<grid, 256, 0, s>>>(b, R0, ncols, A, x, ldx, ldd, y); break;
+    IGA_BAND_SMALL(1) IGA_BAND_SMALL(2) IGA_BAND_SMALL(3) IGA_BAND_SMALL(4) IGA_BAND_SMALL(5) IGA_BAND_SMALL(6)
+    IGA_BAND_SMALL(7) IGA_BAND_SMALL(8) IGA_BAND_SMALL(9) IGA_BAND_SMALL(10) IGA_BAND_SMALL(11) IGA_BAND_SMALL(12)
+    IGA_BAND_SMALL(13) IGA_BAND_SMALL(14) IGA_BAND_SMALL(15) IGA_BAND_SMALL(16)
+#undef IGA_BAND_SMALL
+  }
+  IGA_HIP(hipGetLastError());
+}
+
+void band_small(hipStream_t s, int n, int b, int R0, int R1, long ncols, const double* A, const double* x, long ldx,
+                long ldd, double* y) {
+  band_small_launch<double>(s, n, b, R0, R1, ncols, A, x, ldx, ldd, y);
+}
+
+void band_small_f32(hipStream_t s, int n, int b, int R0, int R1, long ncols, const float* A, const float* x, long ldx,
+                    long ldd, float* y) {
+  band_small_launch<float>(s, n, b, R0, R1, ncols, A, x, ldx, ldd, y);
 }
 
 void band_rank1(hipStream_t s, int n, int b, long ncols, const double* A, const double* x, long ldx, double* y) {

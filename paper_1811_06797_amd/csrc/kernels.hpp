@@ -163,6 +163,12 @@ void kkt_combine_f32(hipStream_t s, long e, const KktCoef& c, const float* zM, c
 // i < n, c < ncols, y rows of ncols (FP64 and FP32 forms).
 void band_rank1(hipStream_t s, int n, int b, long ncols, const double* A, const double* x, long ldx, double* y);
 void band_rank1_f32(hipStream_t s, int n, int b, long ncols, const float* A, const float* x, long ldx, float* y);
+// Banded stage of a core with R1 <= 16 right ranks: y[i][g][c] = sum_{o < b, d < R0}
+// A[i][o][d][g] x[(i + o) ldx + d ldd + c], A re-laid [n][b][R0][R1], y [n][R1][ncols].
+void band_small(hipStream_t s, int n, int b, int R0, int R1, long ncols, const double* A, const double* x, long ldx,
+                long ldd, double* y);
+void band_small_f32(hipStream_t s, int n, int b, int R0, int R1, long ncols, const float* A, const float* x, long ldx,
+                    long ldd, float* y);
 // General block combination: y[o][.] = sum_{t in [toff[o], toff[o+1])} coef[t] z[src[t]][.]
 // for o < nblk, blocks of e elements (device tables).
 void combine_blocks(hipStream_t s, long e, int nblk, const int* toff, const int* src, const double* coef,

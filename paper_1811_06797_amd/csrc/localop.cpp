@@ -52,6 +52,10 @@ template <> struct Prec<double> {
   static void band1(hipStream_t s, int n, int b, long nc, const double* A, const double* x, long ldx, double* y) {
     k::band_rank1(s, n, b, nc, A, x, ldx, y);
   }
+  static void bandsm(hipStream_t s, int n, int b, int R0, int R1, long nc, const double* A, const double* x, long ldx,
+                     long ldd, double* y) {
+    k::band_small(s, n, b, R0, R1, nc, A, x, ldx, ldd, y);
+  }
   static constexpr int prof_base = 0;
 };
 template <> struct Prec<float> {
@@ -66,6 +70,10 @@ template <> struct Prec<float> {
   static void zero(hipStream_t s, long n, float* y) { k::fill_f32(s, n, 0.0f, y); }
   static void band1(hipStream_t s, int n, int b, long nc, const float* A, const float* x, long ldx, float* y) {
     k::band_rank1_f32(s, n, b, nc, A, x, ldx, y);
+  }
+  static void bandsm(hipStream_t s, int n, int b, int R0, int R1, long nc, const float* A, const float* x, long ldx,
+                     long ldd, float* y) {
+    k::band_small_f32(s, n, b, R0, R1, nc, A, x, ldx, ldd, y);
   }
   static constexpr int prof_base = 2;
 };
@@ -117,6 +125,10 @@ static void op_apply(iga_ctx* ctx, const OpView& A, const T* core, const T* rela
     // sixteenth of a matrix-core tile, so the band combination of t1's slices runs as a
     // memory-bound stencil; the relaid core is [i][o]
     Prec<T>::band1(st, n, b, S1, relaid, t1.get(), SJ, t2.get());
+  } else if (whole && R1 <= kSmallR1 && !bf16) {
+    // few right ranks: a 16-row matrix-core tile would be mostly padding and its launch
+    // overheads dominate, so the band sums run on the vector units
+    Prec<T>::bandsm(st, n, b, R0, R1, S1, relaid, t1.get(), SJ, S1, t2.get());
   } else if (whole) {
     // core [i][o][d][g]: for row i the contraction index k = o R0 + d has constant strides
     // (R1 in the core, S1 in t1, whose slice i + o starts at (i + o) SJ = i SJ + o R0 S1)

@@ -16,6 +16,8 @@ namespace iga {
 // A block-structured operator core with at most this many rank pairs R0 R1 is contracted as one
 // dense product over its re-laid form (zeros included) in the banded stage, not block by block.
 constexpr long kDenseRankPairs = 1024;
+// Re-laid cores with at most this many right ranks take the vector-unit banded stage.
+constexpr int kSmallR1 = 16;
 
 struct LocalOp {
   OpView M, K;
