@@ -310,29 +310,52 @@ __global__ __launch_bounds__(256) void band_rank1_kernel(int b, long ncols, cons
 
 // Banded stage of an operator core with few right ranks (R1 <= 16): for row i (blockIdx.y)
 // and column c, y[i][g][c] = sum_{o < b, d < R0} A[i][o][d][g] x[(i + o) ldx + d ldd + c] for
-// g < R1, with A the core re-laid as [n][b][R0][R1]. The coefficients are the same for the
-// whole workgroup, so they are read as scalars; each thread keeps its column's R1 sums.
+// g < R1, with A the core re-laid as [n][b][R0][R1]. A workgroup covers 64 columns; its
+// BAND_WAVES waves split the rank index d (wave w takes d = w, w + BAND_WAVES, ...), so the
+// chain of dependent loads per thread is b * R0 / BAND_WAVES long, and the partial sums are
+// added in LDS in the fixed wave order. The coefficients are the same for a whole wave and are
+// read as scalars.
+constexpr int BAND_WAVES = 4;
+
 template <typename T, int R1>
-__global__ __launch_bounds__(256) void band_small_kernel(int b, int R0, long ncols, const T* A, const T* x, long ldx,
-                                                         long ldd, T* y) {
-  constexpr int GM = R1;
+__global__ __launch_bounds__(64 * BAND_WAVES) void band_small_kernel(int b, int R0, long ncols, const T* A,
+                                                                     const T* x, long ldx, long ldd, T* y) {
+  __shared__ T red[(BAND_WAVES - 1) * R1 * 64];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int i = blockIdx.y;
-  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncols) return;
-  T acc[GM];
+  const long c = (long)blockIdx.x * 64 + lane;
+  const bool live = c < ncols;
+  T acc[R1];
 #pragma unroll
-  for (int g = 0; g < GM; ++g) acc[g] = T(0);
-  const T* a = A + (long)i * b * R0 * R1;
-  for (int o = 0; o < b; ++o) {
-    const T* xo = x + (long)(i + o) * ldx + c;
-    for (int d = 0; d < R0; ++d, a += R1) {
-      const T v = xo[(long)d * ldd];
+  for (int g = 0; g < R1; ++g) acc[g] = T(0);
+  if (live) {
+    const T* ai = A + (long)i * b * R0 * R1;
+    for (int o = 0; o < b; ++o) {
+      const T* xo = x + (long)(i + o) * ldx + c;
+      const T* ao = ai + (long)o * R0 * R1;
+#pragma unroll 4
+      for (int d = w; d < R0; d += BAND_WAVES) {
+        const T v = xo[(long)d * ldd];
 #pragma unroll
-      for (int g = 0; g < GM; ++g) acc[g] += a[g] * v;
+        for (int g = 0; g < R1; ++g) acc[g] += ao[d * R1 + g] * v;
+      }
     }
   }
+  if (w > 0) {
 #pragma unroll
-  for (int g = 0; g < GM; ++g) y[((long)i * R1 + g) * ncols + c] = acc[g];
+    for (int g = 0; g < R1; ++g) red[((w - 1) * R1 + g) * 64 + lane] = acc[g];
+  }
+  __syncthreads();
+  if (w == 0 && live) {
+#pragma unroll
+    for (int g = 0; g < R1; ++g) {
+      T s = acc[g];
+#pragma unroll
+      for (int v = 0; v < BAND_WAVES - 1; ++v) s += red[(v * R1 + g) * 64 + lane];
+      y[((long)i * R1 + g) * ncols + c] = s;
+    }
+  }
 }
 
 // y[o] = sum of coef[t] z[src[t]] over the terms t of output block o (blockIdx.y = o).
@@ -618,10 +641,11 @@ static void band_small_launch(hipStream_t s, int n, int b, int R0, int R1, long 
                               long ldx, long ldd, T* y) {
   if (n <= 0 || ncols <= 0) return;
   require(n <= 65535 && b >= 1 && R0 >= 1 && R1 >= 1 && R1 <= 16, IGA_EINVAL, "band_small: bad sizes");
-  dim3 grid((unsigned)((ncols + 255) / 256), (unsigned)n);
+  require((ncols + 63) / 64 <= 0x7fffffffL, IGA_EINVAL, "band_small: too many columns");
+  dim3 grid((unsigned)((ncols + 63) / 64), (unsigned)n);
   switch (R1) {
 #define IGA_BAND_SMALL(r) \
-  case r: band_small_kernel<T, r><<<grid, 256, 0, s>>>(b, R0, ncols, A, x, ldx, ldd, y); break;
+  case r: band_small_kernel<T, r><<<grid, 64 * BAND_WAVES, 0, s>>>(b, R0, ncols, A, x, ldx, ldd, y); break;
     IGA_BAND_SMALL(1) IGA_BAND_SMALL(2) IGA_BAND_SMALL(3) IGA_BAND_SMALL(4) IGA_BAND_SMALL(5) IGA_BAND_SMALL(6)
     IGA_BAND_SMALL(7) IGA_BAND_SMALL(8) IGA_BAND_SMALL(9) IGA_BAND_SMALL(10) IGA_BAND_SMALL(11) IGA_BAND_SMALL(12)
     IGA_BAND_SMALL(13) IGA_BAND_SMALL(14) IGA_BAND_SMALL(15) IGA_BAND_SMALL(16)
