@@ -53,5 +53,56 @@ def objective(M, y, u, yhat, beta):
 
 
 def residual(M, K, beta, yhat, f):
+    """||A f - b||_2 / ||b||_2 with A f from kkt_apply and b = [M yhat; 0; 0]."""
     b = kkt_rhs(M, yhat)
     return np.linalg.norm(kkt_apply(M, K, beta, f) - b) / np.linalg.norm(b)
+
+
+def solve_reduced(M, K, beta, yhat, rtol: float = 1e-13, maxiter: int = 200):
+    """The KKT solution through the reduced equation for the state alone.
+
+    Rows 2 and 3 of the KKT system give lambda = beta u and u = M^-1 K y; row 1 then becomes
+        (M + beta K M^-1 K) y = M yhat,
+    a symmetric positive definite system (M SPD, K symmetric). It is solved by preconditioned
+    conjugate gradients, M^-1 applied through a sparse LU of M. The preconditioner is
+        P = (M + g K) M^-1 (M + g K),  g = sqrt(beta),
+    applied as P^-1 = (M + g K)^-1 M (M + g K)^-1 through a sparse LU of M + g K (SPD once the
+    boundary functions are omitted). In the basis of the generalised eigenvectors of (K, M)
+    (eigenvalues mu >= 0) the reduced matrix is diag(1 + beta mu^2) and P is diag((1 + g mu)^2),
+    so the preconditioned spectrum lies in [1/2, 1] and CG converges at a rate of about 0.17
+    per step whatever the mesh and beta. Stops when ||r|| <= rtol ||M yhat||.
+    Returns (y, u, lambda, iterations).
+    """
+    M = sps.csc_matrix(M)
+    K = sps.csc_matrix(K)
+    g = np.sqrt(beta)
+    luM = spla.splu(M)
+    luP = spla.splu(sps.csc_matrix(M + g * K))
+
+    def S(v):
+        return M @ v + beta * (K @ luM.solve(K @ v))
+
+    def Pinv(v):
+        return luP.solve(M @ luP.solve(v))
+
+    b = M @ np.asarray(yhat, dtype=np.float64).ravel()
+    bn = np.linalg.norm(b)
+    y = np.zeros_like(b)
+    r = b.copy()
+    z = Pinv(r)
+    d = z.copy()
+    rz = r @ z
+    its = 0
+    while its < maxiter and np.linalg.norm(r) > rtol * bn:
+        Sd = S(d)
+        a = rz / (d @ Sd)
+        y += a * d
+        r -= a * Sd
+        z = Pinv(r)
+        rz_new = r @ z
+        d = z + (rz_new / rz) * d
+        rz = rz_new
+        its += 1
+    u = luM.solve(K @ y)
+    lam = beta * u
+    return y, u, lam, its

@@ -126,25 +126,20 @@ def projected(Afull, F):
 def local_apply(PhiL, A_dense, PhiR, x):
     """y[a',i,b'] = sum PhiL[al,a',a] A[al,i,j,be] x[a,j,b] PhiR[be,b',b] (the local projected matvec).
 
-    Contracted one index group at a time: trial rank a, then (al, j), then (be, b).
+    One contraction over (al, a, j, be, b), written as the definition of eq. KKT_red's reduced
+    operator applied to a core; numpy picks the order of the pairwise products.
     """
-    t1 = np.einsum("pxa,ajb->pxjb", PhiL, x, optimize=True)
-    t2 = np.einsum("pijq,pxjb->qxib", A_dense, t1, optimize=True)
-    return np.einsum("qxib,qyb->xiy", t2, PhiR, optimize=True)
+    return np.einsum("pxa,pijq,ajb,qyb->xiy", PhiL, A_dense, x, PhiR, optimize=True)
 
 
 def interface_left(PhiL, U, A_dense, V):
-    """Phi'[be,b',b] = sum U[a',i,b'] PhiL[al,a',a] A[al,i,j,be] V[a,j,b]."""
-    t1 = np.einsum("pxa,ajb->pxjb", PhiL, V, optimize=True)
-    t2 = np.einsum("pijq,pxjb->qxib", A_dense, t1, optimize=True)
-    return np.einsum("xiy,qxib->qyb", U, t2, optimize=True)
+    """Phi'[be,b',b] = sum U[a',i,b'] PhiL[al,a',a] A[al,i,j,be] V[a,j,b] (one contraction)."""
+    return np.einsum("xiy,pxa,pijq,ajb->qyb", U, PhiL, A_dense, V, optimize=True)
 
 
 def interface_right(PhiR, U, A_dense, V):
-    """Phi'[al,a',a] = sum U[a',i,b'] PhiR[be,b',b] A[al,i,j,be] V[a,j,b]."""
-    s1 = np.einsum("ajb,qyb->qajy", V, PhiR, optimize=True)
-    s2 = np.einsum("pijq,qajy->paiy", A_dense, s1, optimize=True)
-    return np.einsum("xiy,paiy->pxa", U, s2, optimize=True)
+    """Phi'[al,a',a] = sum U[a',i,b'] PhiR[be,b',b] A[al,i,j,be] V[a,j,b] (one contraction)."""
+    return np.einsum("xiy,qyb,pijq,ajb->pxa", U, PhiR, A_dense, V, optimize=True)
 
 
 def interfaces_from_cores(X, A_dense_cores, Y, d: int):

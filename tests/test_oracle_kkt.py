@@ -88,3 +88,68 @@ def test_reduced_cost_gradient_envelope():
         Jp = kkt.objective(M, *kkt.solve_direct(M, K, beta, yh + e)[:2], yh + e, beta)
         Jm = kkt.objective(M, *kkt.solve_direct(M, K, beta, yh - e)[:2], yh - e, beta)
         assert abs((Jp - Jm) / (2 * h) - g[idx]) < 1e-6 * max(1.0, abs(g[idx]))
+
+
+def _small_system(n=5, p=2, seed=1, beta=1e-3):
+    geo = synth.twisted_annulus(seed=seed)
+    M, K = assembly.assemble(geo, n, p)
+    return M, K, beta
+
+
+def test_kkt_apply_is_the_kkt_matrix_product():
+    """kkt_apply(f) equals the assembled block matrix (pinned by the optimality conditions above)
+    times f, block row by block row, on random vectors (Sec. 4, eq. KKTSystem)."""
+    M, K, beta = _small_system()
+    A = kkt.kkt_matrix(M, K, beta)
+    rng = np.random.default_rng(5)
+    for _ in range(3):
+        f = rng.standard_normal(A.shape[0])
+        ref = A @ f
+        got = kkt.kkt_apply(M, K, beta, f)
+        assert np.linalg.norm(got - ref) <= 1e-14 * np.linalg.norm(ref)
+    # each block row separately: a unit vector in one component excites the columns of that block
+    N = M.shape[0]
+    for comp in range(3):
+        f = np.zeros(3 * N)
+        f[comp * N: (comp + 1) * N] = rng.standard_normal(N)
+        assert np.linalg.norm(kkt.kkt_apply(M, K, beta, f) - A @ f) <= 1e-14 * np.linalg.norm(A @ f)
+
+
+def test_kkt_apply_maps_the_optimum_to_the_rhs_and_residual_is_its_defect():
+    """At the direct solution A f = b, so the relative residual vanishes to rounding; for a
+    perturbed f the residual equals ||A (f + e) - b|| / ||b|| with the assembled block matrix."""
+    M, K, beta = _small_system(beta=1e-2)
+    rng = np.random.default_rng(6)
+    yh = rng.standard_normal(M.shape[0])
+    y, u, lam = kkt.solve_direct(M, K, beta, yh)
+    f = np.concatenate([y, u, lam])
+    assert kkt.residual(M, K, beta, yh, f) < 1e-12
+    b = kkt.kkt_rhs(M, yh)
+    assert np.linalg.norm(kkt.kkt_apply(M, K, beta, f) - b) < 1e-12 * np.linalg.norm(b)
+    e = 1e-3 * rng.standard_normal(f.shape)
+    A = kkt.kkt_matrix(M, K, beta)
+    ref = np.linalg.norm(A @ (f + e) - b) / np.linalg.norm(b)
+    assert abs(kkt.residual(M, K, beta, yh, f + e) - ref) <= 1e-12 * ref
+
+
+@pytest.mark.parametrize("beta", [1e-2, 1e-6])
+@pytest.mark.parametrize("n,p", [(6, 2), (8, 3)])
+def test_reduced_solve_matches_direct_solve(n, p, beta):
+    """The reduced state equation (M + beta K M^-1 K) y = M yhat, with u = M^-1 K y and lambda =
+    beta u from the second and third KKT rows, gives the (y, u, lambda) of a dense LAPACK solve of
+    the whole KKT matrix. At beta = 1e-6 the KKT matrix has a condition number near 1e12, so
+    forward errors of ~1e-11 separate two backward-stable solves; the bar is 1e-9, and both
+    solutions must leave KKT residuals at rounding level."""
+    geo = synth.twisted_annulus(seed=1)
+    M, K = assembly.assemble(geo, n, p, mode="interp")
+    yh = np.einsum("i,j,k->ijk", *[c[0, :, 0] for c in synth.yhat_sine(n, p)]).ravel()
+    yr, ur, lr, its = kkt.solve_reduced(M, K, beta, yh)
+    A = kkt.kkt_matrix(M, K, beta).toarray()
+    yd, ud, ld = np.linalg.solve(A, kkt.kkt_rhs(M, yh)).reshape(3, -1)
+    assert its <= 40
+    for a, b in ((yr, yd), (ur, ud), (lr, ld)):
+        assert np.linalg.norm(a - b) <= 1e-9 * np.linalg.norm(b)
+    assert kkt.residual(M, K, beta, yh, np.concatenate([yr, ur, lr])) < 1e-12
+    # the sparse LU of the whole system agrees to within its own conditioning
+    ys, us, ls = kkt.solve_direct(M, K, beta, yh)
+    assert np.linalg.norm(ys - yr) <= 1e-7 * np.linalg.norm(yr)

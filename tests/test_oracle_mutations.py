@@ -33,7 +33,12 @@ def test_pins_pass_without_a_planted_mistake():
                       lambda: t_basis.test_basis_matches_scipy(3, 9),
                       lambda: t_basis.test_univariate_factors_cardinal_closed_form(3, 20),
                       t_asm.test_affine_map_closed_form,
-                      t_par.test_state_is_the_implicit_euler_march_of_its_control)
+                      t_par.test_state_is_the_implicit_euler_march_of_its_control,
+                      t_kkt.test_kkt_apply_is_the_kkt_matrix_product,
+                      t_kkt.test_kkt_apply_maps_the_optimum_to_the_rhs_and_residual_is_its_defect,
+                      lambda: t_kkt.test_reduced_solve_matches_direct_solve(6, 2, 1e-2),
+                      lambda: t_tt.test_btt_full_is_the_frame_times_the_component_slice(0),
+                      t_tt.test_btt_full_of_rank_one_cores_is_an_outer_product_per_component)
 
 
 def test_wrong_sign_of_the_control_coupling(monkeypatch):
@@ -120,3 +125,52 @@ def test_interface_mistakes_in_the_left_update(monkeypatch, mistake):
     monkeypatch.setattr(tt, "interface_left", interface_left)
     assert caught(lambda: t_tt.test_local_apply_is_projected_operator(1),
                   lambda: t_tt.test_local_apply_is_projected_operator(2))
+
+
+def test_wrong_sign_in_the_second_row_of_the_kkt_apply(monkeypatch):
+    # beta M u + M lambda instead of beta M u - M lambda in the matrix-free apply (eq. KKTSystem)
+    def apply(M, K, beta, f):
+        y, u, lam = np.asarray(f).reshape(3, -1)
+        return np.concatenate([M @ y + K.T @ lam, beta * (M @ u) + M @ lam, K @ y - M @ u])
+    monkeypatch.setattr(kkt, "kkt_apply", apply)
+    assert caught(t_kkt.test_kkt_apply_is_the_kkt_matrix_product)
+    assert caught(t_kkt.test_kkt_apply_maps_the_optimum_to_the_rhs_and_residual_is_its_defect)
+
+
+def test_residual_against_a_rhs_without_the_mass_matrix(monkeypatch):
+    def residual(M, K, beta, yhat, f):
+        y = np.asarray(yhat).ravel()
+        b = np.concatenate([y, 0 * y, 0 * y])
+        return np.linalg.norm(kkt.kkt_apply(M, K, beta, f) - b) / np.linalg.norm(b)
+    monkeypatch.setattr(kkt, "residual", residual)
+    assert caught(t_kkt.test_kkt_apply_maps_the_optimum_to_the_rhs_and_residual_is_its_defect)
+
+
+@pytest.mark.parametrize("mistake", ["neighbour_slice", "first_slice"])
+def test_wrong_component_slice_in_the_block_tt(monkeypatch, mistake):
+    # component l read from the wrong slice of the core that carries the component index (eq. btt)
+    def btt_full(cores, ell_core):
+        out = []
+        for l in range(3):
+            j = (l + 1) % 3 if mistake == "neighbour_slice" else 0
+            cs = [c if d != ell_core else c[j] for d, c in enumerate(cores)]
+            out.append(tt.tt_full(cs))
+        return np.stack(out)
+    monkeypatch.setattr(tt, "btt_full", btt_full)
+    assert caught(lambda: t_tt.test_btt_full_is_the_frame_times_the_component_slice(0),
+                  t_tt.test_btt_full_of_rank_one_cores_is_an_outer_product_per_component)
+
+
+@pytest.mark.parametrize("mistake", ["multiplier_without_beta", "reduced_matrix_without_beta"])
+def test_mistakes_in_the_reduced_solve(monkeypatch, mistake):
+    # lambda = u instead of beta u, or M + K M^-1 K instead of M + beta K M^-1 K
+    true_solve = kkt.solve_reduced
+
+    def solve_reduced(M, K, beta, yhat, rtol=1e-13, maxiter=200):
+        if mistake == "multiplier_without_beta":
+            y, u, lam, its = true_solve(M, K, beta, yhat, rtol, maxiter)
+            return y, u, u, its
+        y, u, lam, its = true_solve(M, K, 1.0, yhat, rtol, maxiter)
+        return y, u, beta * u, its
+    monkeypatch.setattr(kkt, "solve_reduced", solve_reduced)
+    assert caught(lambda: t_kkt.test_reduced_solve_matches_direct_solve(6, 2, 1e-2))

@@ -85,3 +85,30 @@ def test_local_apply_is_projected_operator(d):
     F = tt.frame(X, d)
     ref = F.T @ (tt.ttm_full(A) @ (F @ x.ravel()))
     assert np.allclose(y.ravel(), ref, atol=1e-12 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("ell", [0, 1, 2])
+def test_btt_full_is_the_frame_times_the_component_slice(ell):
+    """Component l of a block-TT is F_{!=ell} vec(F_ell(l)) (eqs. btt and ttlin): the frame of
+    the plain cores times slice l of the core that carries the component index."""
+    rng = np.random.default_rng(7)
+    ns, r = [4, 3, 5], [1, 2, 3, 1]
+    cores = [rng.standard_normal((r[d], ns[d], r[d + 1])) for d in range(3)]
+    cores[ell] = rng.standard_normal((3, r[ell], ns[ell], r[ell + 1]))
+    full = tt.btt_full(cores, ell)
+    assert full.shape == (3, *ns)
+    for l in range(3):
+        plain = [c if d != ell else c[l] for d, c in enumerate(cores)]
+        F = tt.frame(plain, ell)
+        assert np.allclose(full[l].ravel(), F @ cores[ell][l].ravel(), atol=1e-13)
+
+
+def test_btt_full_of_rank_one_cores_is_an_outer_product_per_component():
+    rng = np.random.default_rng(8)
+    a = rng.standard_normal(4)
+    b3 = rng.standard_normal((3, 5))
+    c = rng.standard_normal(2)
+    cores = [a.reshape(1, 4, 1), b3.reshape(3, 1, 5, 1), c.reshape(1, 2, 1)]
+    full = tt.btt_full(cores, 1)
+    for l in range(3):
+        assert np.allclose(full[l], np.einsum("i,j,k->ijk", a, b3[l], c), atol=1e-15)
