@@ -48,6 +48,8 @@ extern "C" {
 #define IGA_EGEOM (-4)   /* det grad G <= 0 at an interpolation point: the map folds */
 #define IGA_ENOCONV (-5) /* block AMEn stopped at nswp sweeps above tolerance */
 #define IGA_ERANK (-6)   /* block AMEn stopped above tolerance with a solution rank at r_max */
+#define IGA_ENUM (-7)    /* a non-finite value (NaN or Inf) arose: in an input, or in a local
+                          residual or Krylov norm of block AMEn; no solution is returned */
 
 #define IGA_FP64 0
 #define IGA_FP32 1
@@ -232,6 +234,8 @@ int iga_kkt_residual(iga_ctx* ctx, const iga_kkt* kkt, const iga_tt* yhat, const
  * component index by a truncated SVD (eqs. svd1, svd2). Stops when every local
  * residual of a half-sweep is <= tol (relative) or after nswp half-sweeps
  * (IGA_ENOCONV, or IGA_ERANK when a solution rank is at r_max; *sol is still returned).
+ * A local residual or Krylov norm that is not finite (an iterate or input holding NaN or
+ * Inf) ends the solve with IGA_ENUM and no solution.
  * x0 (nullable) is the initial guess.
  * stats (nullable) receives the statistics above. */
 int iga_amen_solve(iga_ctx* ctx, const iga_kkt* kkt, const iga_tt* yhat, double tol,

@@ -535,6 +535,7 @@ int Amen::refine_solve(int d, const LocalOp& L, double bn, double ltol, double r
     matvec(L, X_[d].get(), r.get());
     k::axpby(st_, N, 1.0, bl_.get(), -1.0, r.get());
     res = std::sqrt(norm2_host(ctx_, N, r.get())) / bn;
+    require(std::isfinite(res), IGA_ENUM, "amen_solve: non-finite residual in the mixed-precision refinement");
     ++n_refine_;
   }
   return its;
@@ -671,6 +672,7 @@ int Amen::fgmres(const LocalOp& L, const double* b, double* x, double bnorm, dou
     matvec(L, x, V);
     k::axpby(st_, N, 1.0, b, -1.0, V);
     const double beta0 = std::sqrt(norm2_host(ctx_, N, V));
+    require(std::isfinite(beta0), IGA_ENUM, "amen_solve: non-finite residual norm in the local Krylov solve");
     if (beta0 <= abstol || !(beta0 > 0)) break;
     k::scale(st_, N, 1.0 / beta0, V);
     std::fill(gv.begin(), gv.end(), 0.0);
@@ -745,11 +747,14 @@ double Amen::solve_local(int d) {
   tmp_.ensure(ctx_, N);
   rhs_local(d, FX, FX, bl_.get());
   double bn = std::sqrt(norm2_host(ctx_, N, bl_.get()));
+  require(std::isfinite(bn), IGA_ENUM, "amen_solve: non-finite local right-hand side");
   if (!(bn > 0)) bn = 1.0;
   bnorm_ = bn;
   matvec(L, X_[d].get(), tmp_.get());
   k::axpby(st_, N, 1.0, bl_.get(), -1.0, tmp_.get());
   const double res = std::sqrt(norm2_host(ctx_, N, tmp_.get())) / bn;
+  // a NaN compares false with every tolerance, so it would pass for convergence
+  require(std::isfinite(res), IGA_ENUM, "amen_solve: non-finite local residual (the iterate holds NaN or Inf)");
   ++n_solves_;
   const double ltol = o_.local_tol;
   if (res > ltol) {
@@ -813,6 +818,7 @@ int Amen::residual_rank(int d, int kmin, int kmax, const std::vector<double>& si
   const long N = (long)nb_ * r_[d] * n_[d] * r_[d + 1];
   xk_.ensure(ctx_, N);
   const double full = local_res_of(d, X_[d].get());
+  require(std::isfinite(full), IGA_ENUM, "amen_solve: non-finite local residual in the truncation");
   const double target = std::max(0.5 * tol_, 1.5 * full);
   std::vector<signed char> known((size_t)kmax + 1, -1);
   double probe_res = 0.0;
@@ -1220,7 +1226,7 @@ int Amen::run(const iga_btt* x0, iga_btt** sol, iga_amen_stats* stats) {
     for (int s = 0; s < 3; ++s) {
       const int d = fwd ? s : 2 - s;
       const double res = solve_local(d);
-      max_res_ = std::max(max_res_, res);
+      max_res_ = std::isnan(res) ? res : std::max(max_res_, res);
       if (fwd && d < 2) move_right(d);
       if (!fwd && d > 0) move_left(d);
     }

@@ -295,6 +295,8 @@ void svd(iga_ctx* ctx, const double* A, int m, int k, long lda, bool trans, Svd&
     IGA_HIP(hipStreamSynchronize(st));
   }
   const double fro2 = norm2_host(ctx, (long)m * kp, B.get());
+  // NaN or Inf would also break the ordering of the singular values below
+  require(std::isfinite(fro2), IGA_ENUM, "svd: the matrix holds a non-finite entry");
   const double floor_col = 1e-28 * fro2;
   const double tol = 4e-16 * std::max(1.0, std::sqrt((double)m));
   const int npair = nb / 2, nround = nb - 1;

@@ -20,10 +20,10 @@ if not os.path.exists(LIB_PATH):
                       "(or __graft_entry__.build())")
 lib = C.CDLL(LIB_PATH)
 
-OK, EINVAL, ENOMEM, EHIP, EGEOM, ENOCONV, ERANK = 0, -1, -2, -3, -4, -5, -6
+OK, EINVAL, ENOMEM, EHIP, EGEOM, ENOCONV, ERANK, ENUM = 0, -1, -2, -3, -4, -5, -6, -7
 FP64, FP32, BF16 = 0, 1, 2
 _NAMES = {EINVAL: "IGA_EINVAL", ENOMEM: "IGA_ENOMEM", EHIP: "IGA_EHIP", EGEOM: "IGA_EGEOM",
-          ENOCONV: "IGA_ENOCONV", ERANK: "IGA_ERANK"}
+          ENOCONV: "IGA_ENOCONV", ERANK: "IGA_ERANK", ENUM: "IGA_ENUM"}
 
 EXPORTED = [
     "iga_ctx_create", "iga_ctx_destroy", "iga_assemble_factors", "iga_ttop_create", "iga_ttop_info",

@@ -57,6 +57,10 @@ def test_c2_shape_flop_figures():
 
 def test_traffic_figure_only_for_matching_kernel_sources(monkeypatch):
     import bench
+    if not os.path.exists(bench.TRAFFIC_FILE):
+        # no counter summary for the roofline kernel: the line reports traffic as null
+        assert bench.traffic_from_profile() is None
+        return
     txt = open(bench.TRAFFIC_FILE).read()
     recorded = re.search(r"^source_hash:\s*(\S+)", txt, re.M).group(1)
     traffic = float(re.search(r"^traffic_bytes_per_launch:\s*(\S+)", txt, re.M).group(1))
