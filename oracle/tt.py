@@ -123,23 +123,35 @@ def projected(Afull, F):
     return F.T @ (Afull @ F)
 
 
+# The three contractions below are each one einsum of their definition. The order of the
+# pairwise products is given explicitly ("einsum_path" lists, operands numbered as passed,
+# each product appended to the end of the list): numpy's automatic choice under its default
+# memory limit can fall back to a single naive loop over all eight indices, which takes
+# minutes at ranks of a few tens.
+
+
 def local_apply(PhiL, A_dense, PhiR, x):
     """y[a',i,b'] = sum PhiL[al,a',a] A[al,i,j,be] x[a,j,b] PhiR[be,b',b] (the local projected matvec).
 
     One contraction over (al, a, j, be, b), written as the definition of eq. KKT_red's reduced
-    operator applied to a core; numpy picks the order of the pairwise products.
+    operator applied to a core; evaluated as (PhiL x), then A, then PhiR.
     """
-    return np.einsum("pxa,pijq,ajb,qyb->xiy", PhiL, A_dense, x, PhiR, optimize=True)
+    return np.einsum("pxa,pijq,ajb,qyb->xiy", PhiL, A_dense, x, PhiR,
+                     optimize=["einsum_path", (0, 2), (0, 2), (0, 1)])
 
 
 def interface_left(PhiL, U, A_dense, V):
-    """Phi'[be,b',b] = sum U[a',i,b'] PhiL[al,a',a] A[al,i,j,be] V[a,j,b] (one contraction)."""
-    return np.einsum("xiy,pxa,pijq,ajb->qyb", U, PhiL, A_dense, V, optimize=True)
+    """Phi'[be,b',b] = sum U[a',i,b'] PhiL[al,a',a] A[al,i,j,be] V[a,j,b] (one contraction;
+    evaluated as (PhiL V), then A, then U)."""
+    return np.einsum("xiy,pxa,pijq,ajb->qyb", U, PhiL, A_dense, V,
+                     optimize=["einsum_path", (1, 3), (1, 2), (0, 1)])
 
 
 def interface_right(PhiR, U, A_dense, V):
-    """Phi'[al,a',a] = sum U[a',i,b'] PhiR[be,b',b] A[al,i,j,be] V[a,j,b] (one contraction)."""
-    return np.einsum("xiy,qyb,pijq,ajb->pxa", U, PhiR, A_dense, V, optimize=True)
+    """Phi'[al,a',a] = sum U[a',i,b'] PhiR[be,b',b] A[al,i,j,be] V[a,j,b] (one contraction;
+    evaluated as (V PhiR), then A, then U)."""
+    return np.einsum("xiy,qyb,pijq,ajb->pxa", U, PhiR, A_dense, V,
+                     optimize=["einsum_path", (1, 3), (1, 2), (0, 1)])
 
 
 def interfaces_from_cores(X, A_dense_cores, Y, d: int):
