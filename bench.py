@@ -20,8 +20,10 @@ Printed JSON line:
              FP64, from one assembly: solve times, statuses, residuals, state differences
              against the FP64 form, speedups (null for a form whose solve is invalid);
   annulus_n64  the twisted-annulus workload at n = 64 (FP64, tol 1e-7): one step's times;
-  differentiation  times of the reduced cost, its desired-state gradient and its
-             control-point gradient at the FP64 solution of the workload;
+  annulus_n256  the twisted annulus at n = 256 (16.7 M dofs per field, tol 1e-6): the solve
+             with ranks capped at 40 (stops above tolerance with IGA_ERANK), the uncapped
+             solve, and the times of the reduced cost, its desired-state gradient and its
+             control-point gradient at the uncapped solution (differentiation form);
   batching   64 uneven local TT-matvecs, one call per problem versus one batched call;
   time_dependent  the time-dependent KKT system on the annulus geometry and desired state
              with 10 implicit Euler steps (3 x 10 x 64^3 = 7.9 M unknowns), FP64 AMEn to
@@ -138,6 +140,9 @@ def mixed_compare(iga, ctx, torch, geo, c, Y, steps):
              "status": rcs, "converged": [x["converged"] for x in sts],
              "valid": all(solve_ok(r_, x) for r_, x in zip(rcs, sts)),
              "half_sweeps": last["half_sweeps"], "ranks": last["ranks"], "local_iterations": last["local_iterations"]}
+        for part in ("t_local_matvec", "t_local_matvec_fp32", "t_interfaces", "t_svd", "t_precond", "t_krylov_other",
+                     "t_residual"):
+            d[part] = sum(x[part] for x in sts) / len(sts)
         if prec != iga.FP64:
             d["refinements"] = last["refinements"]
             d["local_matvecs_fp32"] = last["local_matvecs_fp32"]
@@ -146,9 +151,49 @@ def mixed_compare(iga, ctx, torch, geo, c, Y, steps):
         d["local_matvec_gflops_fp64"] = (sum(x["local_matvec_flops"] for x in sts)
                                          / sum(x["t_local_matvec"] for x in sts) / 1e9)
         out[name] = d
-    # differentiation form on the FP64 solution of the same operators
+    import numpy as np
+    y64 = fulls["fp64"]
+    for name in ("mixed", "mixed_bf16"):
+        yl = fulls[name]
+        out[name]["state_rel_diff_vs_fp64"] = float(np.linalg.norm(yl - y64) / np.linalg.norm(y64))
+        both = out[name]["valid"] and out["fp64"]["valid"]
+        out[name]["speedup_vs_fp64"] = out["fp64"]["solve_time_s"] / out[name]["solve_time_s"] if both else None
+    iga.kkt_destroy(kk)
+    iga.ttop_destroy(M)
+    iga.ttop_destroy(K)
+    return out
+
+
+def n256_leg(iga, ctx, torch):
+    """The differentiation form's workload: twisted annulus, degree 3, n = 256 (16.7 M dofs per
+    field), beta = 1e-6, tol 1e-6. With the ranks capped at 40 the solve stops above tolerance
+    (IGA_ERANK; residual reached and ranks reported); uncapped it converges, and on that solution
+    the reduced cost, its desired-state gradient and its control-point gradient are timed."""
+    import numpy as np
+    import synth
+    geo, yc, c = synth.config("annulus_n256")
+    n, p, beta = c["n"], c["degree"], c["beta"]
+    Y = iga.tt_create(ctx, yc)
+    M, K, _ = iga.assemble_factors(ctx, geo, p, n, weight_tol=c["weight_tol"])
+    kk = iga.kkt_create(ctx, M, K, beta)
+    out = {"config": c["name"] + ", beta %g, weight tol %g, tol %g" % (beta, c["weight_tol"], c["tol"])}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sol, st, rc = iga.amen_solve(ctx, kk, Y, c["tol"], r_max=c["r_max"])
+    out["capped"] = {"r_max": c["r_max"], "status": rc, "solve_time_s": time.perf_counter() - t0,
+                     "kkt_residual": st["residual"], "max_local_residual": st["max_local_residual"],
+                     "ranks": st["ranks"], "half_sweeps": st["half_sweeps"]}
+    iga.btt_destroy(sol)
+    sol, st, rc = iga.amen_solve(ctx, kk, Y, c["tol"])  # warm-up
+    iga.btt_destroy(sol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     sol, st, rc = iga.amen_solve(ctx, kk, Y, c["tol"])
-    grads = {"solve_status": rc, "kkt_residual": st["residual"]}
+    out["uncapped"] = {"status": rc, "valid": solve_ok(rc, st), "solve_time_s": time.perf_counter() - t0,
+                       "kkt_residual": st["residual"], "ranks": st["ranks"], "half_sweeps": st["half_sweeps"],
+                       "t_local_matvec": st["t_local_matvec"], "t_svd": st["t_svd"], "t_precond": st["t_precond"],
+                       "t_interfaces": st["t_interfaces"], "t_residual": st["t_residual"]}
+    grads = {}
     for name, fn in (("objective", lambda: iga.objective(ctx, kk, Y, sol)),
                      ("grad_yhat", lambda: iga.grad_yhat(ctx, kk, Y, sol, (n, n, n))),
                      ("grad_geometry", lambda: iga.grad_geometry(ctx, geo, p, n, beta, Y, sol))):
@@ -161,20 +206,13 @@ def mixed_compare(iga, ctx, torch, geo, c, Y, steps):
         if name == "objective":
             grads["objective"] = val
         if name == "grad_geometry":
-            import numpy as _np
-            grads["grad_geometry_norm"] = float(_np.linalg.norm(val))
-    iga.btt_destroy(sol)
+            grads["grad_geometry_norm"] = float(np.linalg.norm(val))
     out["differentiation"] = grads
-    import numpy as np
-    y64 = fulls["fp64"]
-    for name in ("mixed", "mixed_bf16"):
-        yl = fulls[name]
-        out[name]["state_rel_diff_vs_fp64"] = float(np.linalg.norm(yl - y64) / np.linalg.norm(y64))
-        both = out[name]["valid"] and out["fp64"]["valid"]
-        out[name]["speedup_vs_fp64"] = out["fp64"]["solve_time_s"] / out[name]["solve_time_s"] if both else None
+    iga.btt_destroy(sol)
     iga.kkt_destroy(kk)
     iga.ttop_destroy(M)
     iga.ttop_destroy(K)
+    iga.tt_destroy(Y)
     return out
 
 
@@ -393,7 +431,7 @@ def run_step(iga, ctx, torch, geo, c, Y, precision=None):
     st["rc"] = rc
     st["valid"] = solve_ok(rc, st)
     st["op_ranks"] = [iga.ttop_info(M)[1], iga.ttop_info(K)[1]]
-    st["weight_ranks"] = ranks
+    st["weight_ranks"] = [[int(v) for v in row] for row in ranks]
     iga.btt_destroy(sol)
     iga.kkt_destroy(kk)
     iga.ttop_destroy(M)
@@ -462,6 +500,7 @@ def main():
                  "solve_time_s": s2["solve_wall_s"], "status": s2["rc"], "valid": s2["valid"],
                  "kkt_residual": s2["residual"], "ranks": s2["ranks"], "half_sweeps": s2["half_sweeps"],
                  "local_matvec_gflops": s2["local_matvec_flops"] / s2["t_local_matvec"] / 1e9}
+    n256 = n256_leg(iga, ctx, torch)
     batching = batching_bench(iga, ctx, torch)
     timedep = time_dependent_bench(iga, ctx, torch, geo2, c2, Y2)
     iga.tt_destroy(Y2)
@@ -510,8 +549,8 @@ def main():
                                 "tflops": band_flops / (band_ms * 1e-3) / 1e12 if band_ms else None,
                                 "frac_of_fp64_peak": band_flops / (band_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS
                                 if band_ms else None},
-        "mixed_vs_fp64": {k: v for k, v in mixed.items() if k != "differentiation"},
-        "differentiation": mixed["differentiation"],
+        "mixed_vs_fp64": mixed,
+        "annulus_n256": n256,
         "annulus_n64": secondary,
         "batching": batching,
         "time_dependent": timedep,

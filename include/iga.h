@@ -113,6 +113,7 @@ typedef struct {
 } iga_amen_opts;
 
 /* Statistics of a solve; times in seconds from HIP events on the context stream. */
+#define IGA_MAX_HISTORY 64
 typedef struct {
   int half_sweeps;
   int converged;
@@ -140,6 +141,13 @@ typedef struct {
   double local_matvec_flops_fp32;
   double t_local_matvec_fp32;
   long long refinements;
+  /* per half-sweep h < min(half_sweeps, IGA_MAX_HISTORY) (the quantities Section 6 reports):
+   * the largest local residual of the half-sweep (measured before each local solve), the
+   * solution ranks r_1, r_2 after it, and the number of stored solution entries
+   * (sum_d r_{d-1} n_d r_d, the core holding the components counted nblk times) */
+  double history_max_local_residual[IGA_MAX_HISTORY];
+  int history_ranks[IGA_MAX_HISTORY][2];
+  long long history_storage[IGA_MAX_HISTORY];
 } iga_amen_stats;
 
 /* Context on GPU `device`; hip_stream is a hipStream_t (NULL: the default stream). */

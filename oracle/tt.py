@@ -100,6 +100,31 @@ def tt_svd(A, eps: float):
     return cores
 
 
+def tt_svd_ranks(A, ranks):
+    """TT-SVD with prescribed ranks (r_1, .., r_{D-1}): the sequential SVDs of the unfoldings of
+    tt_svd, each kept to the given rank instead of a tolerance. With the ranks tt_svd chose at a
+    tolerance it returns the same tensor; used to rebuild a truncation whose ranks are known."""
+    A = np.asarray(A, dtype=np.float64)
+    shape = A.shape
+    D = len(shape)
+    if len(ranks) != D - 1:
+        raise ValueError("need D - 1 ranks")
+    cores = []
+    r = 1
+    C = A.copy()
+    for d in range(D - 1):
+        C = C.reshape(r * shape[d], -1)
+        U, s, Vt = np.linalg.svd(C, full_matrices=False)
+        rk = int(ranks[d])
+        if not 1 <= rk <= len(s):
+            raise ValueError("rank %d out of range at unfolding %d" % (rk, d))
+        cores.append(U[:, :rk].reshape(r, shape[d], rk))
+        C = s[:rk, None] * Vt[:rk]
+        r = rk
+    cores.append(C.reshape(r, shape[-1], 1))
+    return cores
+
+
 def frame(cores, d: int):
     """Frame matrix F_{!=d} (eq. frame): shape (prod n, r_{d-1} n_d r_d).
 

@@ -19,6 +19,7 @@
 #include "assemble.hpp"
 #include "common.hpp"
 #include "kernels.hpp"
+#include "localop.hpp"
 #include "ttops.hpp"
 
 namespace iga {
@@ -91,8 +92,9 @@ int objective_impl(iga_ctx* ctx, const iga_kkt* kkt, const iga_tt* Y, const iga_
   tt_expand(ctx, Y->n, Y->r, yc, yh.get());
   // e = y - yhat in place of yhat
   k::axpby(st, N, 1.0, F.get(), -1.0, yh.get());
-  full_apply(ctx, kkt->M, yh.get(), Me.get(), 1.0, 0.0);
-  full_apply(ctx, kkt->M, F.get() + N, Mu.get(), 1.0, 0.0);
+  FullWork fw;
+  full_apply_mc(ctx, kkt->M, yh.get(), Me.get(), 1.0, 0.0, fw);
+  full_apply_mc(ctx, kkt->M, F.get() + N, Mu.get(), 1.0, 0.0, fw);
   if (J) *J = 0.5 * dot_host(ctx, N, yh.get(), Me.get()) + 0.5 * kkt->beta * dot_host(ctx, N, F.get() + N, Mu.get());
   if (grad) {
     IGA_HIP(hipMemcpyAsync(grad, Me.get(), N * sizeof(double), hipMemcpyDeviceToDevice, st));

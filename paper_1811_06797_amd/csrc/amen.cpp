@@ -126,15 +126,19 @@ class Amen {
     // local matvec then contracts over one (R0, 2p+1) index instead of two nested ones.
     // Block-structured cores with few rank pairs are re-laid too, zeros included: for them
     // one product over the whole core costs less than one small launch per block.
-    for (int op = 0; op < 2; ++op)
+    // The interface updates contract the same cores, the right ones with the rank roles
+    // swapped ([n][2p+1][R1][R0]); the reference operator of the preconditioner is re-laid too.
+    for (int op = 0; op < 3; ++op)
       for (int d = 0; d < 3; ++d) {
         const OpCore& c = ops_[op]->core[d];
         const bool dense = c.blocks.size() == 1 && c.blocks[0].na == c.R0 && c.blocks[0].nb == c.R1;
         if (!dense && (long)c.R0 * c.R1 > kDenseRankPairs) continue;
         const int b = 2 * ops_[op]->p + 1;
-        const int dims[4] = {c.R0, c.n, b, c.R1}, perm[4] = {1, 2, 0, 3};
+        const int dims[4] = {c.R0, c.n, b, c.R1}, perm[4] = {1, 2, 0, 3}, permT[4] = {1, 2, 3, 0};
         rcore_[op][d].reset(ctx, (long)c.R0 * c.n * b * c.R1);
         k::permute4(st_, c.data.get(), dims, perm, rcore_[op][d].get());
+        rcoreT_[op][d].reset(ctx, (long)c.R0 * c.n * b * c.R1);
+        k::permute4(st_, c.data.get(), dims, permT, rcoreT_[op][d].get());
       }
     if (lowp_) {
       // FP32 copies of the operator cores, fixed for the whole solve
@@ -242,7 +246,24 @@ class Amen {
   bool bf16_ = false;  // inner products on BF16 matrix cores instead of FP32
   FBuf fcore_[2][3], fPL_[2], fPR_[2], fx_, fy_;
   FBuf frcore_[2][3];  // FP32 copies of the re-laid cores
-  DBuf rcore_[2][3];  // re-laid dense cores (null for block-structured ones)
+  DBuf rcore_[3][3];   // re-laid cores [n][2p+1][R0][R1] (null for block-structured ones)
+  DBuf rcoreT_[3][3];  // the same with the rank roles swapped, [n][2p+1][R1][R0]
+  IfaceWork iw_;       // workspace of the interface updates and the right-hand-side projections
+  OpView viewr(int op, int d) const {
+    OpView v = view(op, d);
+    v.Ar = rcore_[op][d].get();
+    return v;
+  }
+  const std::vector<RankBlock>& blocks_of(int op, int d) const { return ops_[op]->core[d].blocks; }
+  void ileft(int op, int d, const double* Phi, const double* U, const double* V, int ru0, int ru1, int rv0, int rv1,
+             double* out) {
+    interface_left_mc(ctx_, viewr(op, d), blocks_of(op, d), Phi, U, V, ru0, ru1, rv0, rv1, out, iw_);
+  }
+  void iright(int op, int d, const double* Phi, const double* U, const double* V, int ru0, int ru1, int rv0,
+              int rv1, double* out) {
+    interface_right_mc(ctx_, view(op, d), rcoreT_[op][d].get(), blocks_of(op, d), Phi, U, V, ru0, ru1, rv0, rv1,
+                       out, iw_);
+  }
   void lowp_operands(int d, LocalOp& L);
   int refine_solve(int d, const LocalOp& L, double bn, double ltol, double res0);
   // statistics
@@ -250,6 +271,9 @@ class Amen {
   long long n_solves_ = 0, n_iters_ = 0, n_mv_ = 0, n_mv32_ = 0, n_refine_ = 0;
   double flops_ = 0, flops32_ = 0;
   double max_res_ = 0;
+  double hist_res_[IGA_MAX_HISTORY] = {};
+  int hist_r_[IGA_MAX_HISTORY][2] = {};
+  long long hist_st_[IGA_MAX_HISTORY] = {};
   double bnorm_ = 1.0;  // norm of the local right-hand side of the last solve
   DBuf xk_;
 };
@@ -323,22 +347,18 @@ void Amen::update_right(int d) {
   const int r0 = r_[d], r1 = r_[d + 1];
   for (int op = 0; op < 3; ++op) {
     PR_[op][d - 1].reset(ctx_, (size_t)R(op, d) * r0 * r0);
-    interface_right(ctx_, view(op, d), PR_[op][d].get(), X_[d].get(), X_[d].get(), r0, r1, r0, r1,
-                    PR_[op][d - 1].get());
+    iright(op, d, PR_[op][d].get(), X_[d].get(), X_[d].get(), r0, r1, r0, r1, PR_[op][d - 1].get());
   }
   YR_[d - 1].reset(ctx_, (size_t)R(0, d) * r0 * ry_[d]);
-  interface_right(ctx_, view(0, d), YR_[d].get(), X_[d].get(), Ycore(d), r0, r1, ry_[d], ry_[d + 1],
-                  YR_[d - 1].get());
+  iright(0, d, YR_[d].get(), X_[d].get(), Ycore(d), r0, r1, ry_[d], ry_[d + 1], YR_[d - 1].get());
   if (kick_ > 0) {
     const int z0 = rho_[d], z1 = rho_[d + 1];
     for (int a = 0; a < 2; ++a) {
       ZR_[a][d - 1].reset(ctx_, (size_t)R(a, d) * z0 * r0);
-      interface_right(ctx_, view(a, d), ZR_[a][d].get(), Z_[d].get(), X_[d].get(), z0, z1, r0, r1,
-                      ZR_[a][d - 1].get());
+      iright(a, d, ZR_[a][d].get(), Z_[d].get(), X_[d].get(), z0, z1, r0, r1, ZR_[a][d - 1].get());
     }
     ZYR_[d - 1].reset(ctx_, (size_t)R(0, d) * z0 * ry_[d]);
-    interface_right(ctx_, view(0, d), ZYR_[d].get(), Z_[d].get(), Ycore(d), z0, z1, ry_[d], ry_[d + 1],
-                    ZYR_[d - 1].get());
+    iright(0, d, ZYR_[d].get(), Z_[d].get(), Ycore(d), z0, z1, ry_[d], ry_[d + 1], ZYR_[d - 1].get());
   }
   t_if_.end(id);
 }
@@ -351,22 +371,18 @@ void Amen::update_left(int d) {
   const int r0 = r_[d], r1 = r_[d + 1];
   for (int op = 0; op < 3; ++op) {
     PL_[op][d + 1].reset(ctx_, (size_t)R(op, d + 1) * r1 * r1);
-    interface_left(ctx_, view(op, d), PL_[op][d].get(), X_[d].get(), X_[d].get(), r0, r1, r0, r1,
-                   PL_[op][d + 1].get());
+    ileft(op, d, PL_[op][d].get(), X_[d].get(), X_[d].get(), r0, r1, r0, r1, PL_[op][d + 1].get());
   }
   YL_[d + 1].reset(ctx_, (size_t)R(0, d + 1) * r1 * ry_[d + 1]);
-  interface_left(ctx_, view(0, d), YL_[d].get(), X_[d].get(), Ycore(d), r0, r1, ry_[d], ry_[d + 1],
-                 YL_[d + 1].get());
+  ileft(0, d, YL_[d].get(), X_[d].get(), Ycore(d), r0, r1, ry_[d], ry_[d + 1], YL_[d + 1].get());
   if (kick_ > 0) {
     const int z0 = rho_[d], z1 = rho_[d + 1];
     for (int a = 0; a < 2; ++a) {
       ZL_[a][d + 1].reset(ctx_, (size_t)R(a, d + 1) * z1 * r1);
-      interface_left(ctx_, view(a, d), ZL_[a][d].get(), Z_[d].get(), X_[d].get(), z0, z1, r0, r1,
-                     ZL_[a][d + 1].get());
+      ileft(a, d, ZL_[a][d].get(), Z_[d].get(), X_[d].get(), z0, z1, r0, r1, ZL_[a][d + 1].get());
     }
     ZYL_[d + 1].reset(ctx_, (size_t)R(0, d + 1) * z1 * ry_[d + 1]);
-    interface_left(ctx_, view(0, d), ZYL_[d].get(), Z_[d].get(), Ycore(d), z0, z1, ry_[d], ry_[d + 1],
-                   ZYL_[d + 1].get());
+    ileft(0, d, ZYL_[d].get(), Z_[d].get(), Ycore(d), z0, z1, ry_[d], ry_[d + 1], ZYL_[d + 1].get());
   }
   t_if_.end(id);
 }
@@ -460,7 +476,7 @@ void Amen::rhs_local(int d, Frame left, Frame right, double* out) {
   const long e = (long)a_out * n_[d] * b_out;
   const double* PL = left == FX ? YL_[d].get() : ZYL_[d].get();
   const double* PR = right == FX ? YR_[d].get() : ZYR_[d].get();
-  local_apply(ctx_, view(0, d), PL, PR, a_out, ry_[d], b_out, ry_[d + 1], 1, Ycore(d), 0, out, 0, 1.0, 0.0);
+  apply_one_mc(ctx_, viewr(0, d), blocks_of(0, d), PL, PR, a_out, ry_[d], ry_[d + 1], b_out, Ycore(d), out, iw_);
   const std::vector<double>& cb = kkt_->cb;
   for (int o = nb_ - 1; o >= 1; --o) {
     if (cb[o] == 0.0) k::fill(st_, e, 0.0, out + o * e);
@@ -1231,6 +1247,14 @@ int Amen::run(const iga_btt* x0, iga_btt** sol, iga_amen_stats* stats) {
       if (!fwd && d > 0) move_left(d);
     }
     last_max = max_res_;
+    if (half < IGA_MAX_HISTORY) {
+      hist_res_[half] = max_res_;
+      hist_r_[half][0] = r_[1];
+      hist_r_[half][1] = r_[2];
+      long long st = 0;
+      for (int d = 0; d < 3; ++d) st += (long long)(d == ell_ ? nb_ : 1) * core_size(d);
+      hist_st_[half] = st;
+    }
     if (o_.verbose >= 2) {
       std::fprintf(stderr, "[amen] half-sweep %d ranks %d %d ell %d\n", half + 1, r_[1], r_[2], ell_);
       // exact global residual of the current iterate (diagnostics only)
@@ -1292,6 +1316,12 @@ int Amen::run(const iga_btt* x0, iga_btt** sol, iga_amen_stats* stats) {
     stats->local_matvec_flops_fp32 = flops32_;
     stats->t_local_matvec_fp32 = t_mv32_.total();
     stats->refinements = n_refine_;
+    for (int h = 0; h < std::min(half, (int)IGA_MAX_HISTORY); ++h) {
+      stats->history_max_local_residual[h] = hist_res_[h];
+      stats->history_ranks[h][0] = hist_r_[h][0];
+      stats->history_ranks[h][1] = hist_r_[h][1];
+      stats->history_storage[h] = hist_st_[h];
+    }
     const auto t2 = std::chrono::steady_clock::now();
     stats->residual = kkt_residual_impl(ctx_, kkt_, Y_, out.get());
     stats->t_residual = std::chrono::duration<double>(std::chrono::steady_clock::now() - t2).count();

@@ -123,30 +123,36 @@ static void upload(iga_ctx* ctx, double* dst, const double* src, size_t n) {
 
 namespace iga {
 // ||A f - b|| / ||b|| with the block structure of the KKT handle (b_o = cb[o] M yhat): f and
-// yhat are expanded and the TT-matrices applied to the full tensors mode by mode, all in FP64.
+// yhat are expanded, M and K applied to each component once (mode by mode on the matrix cores,
+// all in FP64), and the block rows combined.
 double kkt_residual_impl(iga_ctx* ctx, const iga_kkt* kkt, const iga_tt* yhat, const iga_btt* f) {
   require(f->nblk == kkt->nblk, IGA_EINVAL, "kkt_residual: block count differs from the KKT system");
+  hipStream_t st = ctx->stream;
   const long N = (long)f->n[0] * f->n[1] * f->n[2];
   const int nb = kkt->nblk;
-  DBuf full(ctx, (size_t)nb * N), yh(ctx, N), Myh(ctx, N), r(ctx, N);
+  DBuf full(ctx, (size_t)nb * N), yh(ctx, N), Myh(ctx, N), r(ctx, (size_t)nb * N), Af(ctx, N);
+  FullWork w;
   btt_expand(ctx, f, full.get());
   tt_expand(ctx, yhat->n, yhat->r, yhat->core, yh.get());
-  full_apply(ctx, kkt->M, yh.get(), Myh.get(), 1.0, 0.0);
-  double nb2 = 0, nr2 = 0;
-  const double nm = norm2_host(ctx, N, Myh.get());
-  for (int o = 0; o < nb; ++o) {
-    const double cb = kkt->cb[o];
-    nb2 += cb * cb * nm;
-    // r_o = sum_l cM[o][l] M f_l + cK[o][l] K f_l - cb[o] M yhat
-    k::fill(ctx->stream, N, 0.0, r.get());
-    for (int l = 0; l < nb; ++l) {
-      const double cm = kkt->cM[(size_t)o * nb + l], ck = kkt->cK[(size_t)o * nb + l];
-      if (cm != 0.0) full_apply(ctx, kkt->M, full.get() + l * N, r.get(), cm, 1.0);
-      if (ck != 0.0) full_apply(ctx, kkt->K, full.get() + l * N, r.get(), ck, 1.0);
+  full_apply_mc(ctx, kkt->M, yh.get(), Myh.get(), 1.0, 0.0, w);
+  // r_o = sum_l cM[o][l] M f_l + cK[o][l] K f_l - cb[o] M yhat
+  for (int o = 0; o < nb; ++o) k::axpby(st, N, -kkt->cb[o], Myh.get(), 0.0, r.get() + o * N);
+  for (int l = 0; l < nb; ++l)
+    for (int op = 0; op < 2; ++op) {
+      const std::vector<double>& c = op == 0 ? kkt->cM : kkt->cK;
+      bool used = false;
+      for (int o = 0; o < nb; ++o) used = used || c[(size_t)o * nb + l] != 0.0;
+      if (!used) continue;
+      full_apply_mc(ctx, op == 0 ? kkt->M : kkt->K, full.get() + l * N, Af.get(), 1.0, 0.0, w);
+      for (int o = 0; o < nb; ++o) {
+        const double co = c[(size_t)o * nb + l];
+        if (co != 0.0) k::axpby(st, N, co, Af.get(), 1.0, r.get() + o * N);
+      }
     }
-    if (cb != 0.0) k::axpby(ctx->stream, N, -cb, Myh.get(), 1.0, r.get());
-    nr2 += norm2_host(ctx, N, r.get());
-  }
+  const double nm = norm2_host(ctx, N, Myh.get());
+  double nb2 = 0;
+  for (int o = 0; o < nb; ++o) nb2 += kkt->cb[o] * kkt->cb[o] * nm;
+  const double nr2 = norm2_host(ctx, (long)nb * N, r.get());
   return nb2 > 0 ? std::sqrt(nr2 / nb2) : std::sqrt(nr2);
 }
 

@@ -83,91 +83,361 @@ template <> struct Prec<float> {
 // Stage 1 writes t1[j + p][d][c][a'][b] (p zero slices on both ends of j), so that the
 // banded stage is, for every row i, one dense GEMM over (o, d) whose B operand is the
 // contiguous window of slices j = i-p .. i+p; one GEMM per nonzero rank block.
+// Element counts of the intermediates of op_apply: t1 (with its p zero end slices), t2, and
+// the split-K partials of stage 3.
+static long op_t1_len(int n, int p, int R0, int r0o, int r1, int ncol) {
+  return (long)(n + 2 * p) * R0 * ncol * r0o * r1;
+}
+static long op_t2_len(int n, int R1, int r0o, int r1, int ncol) { return (long)n * R1 * ncol * r0o * r1; }
+static long op_split_len(int n, int r0o, int r1o, int ncol) { return 16L * ncol * r0o * n * r1o; }
+
+// An operator core as the banded stage contracts it: element (d, i, o, g) -- input rank d,
+// row i, band offset o (column j = i + o - p), output rank g -- at d s_in + g s_out + i s_row +
+// o s_off of core. The usual orientation (input = left rank, output = right rank) has s_in =
+// n b R1, s_out = 1, s_row = b R1, s_off = R1; the transposed one (used by the right interface
+// update) swaps s_in and s_out. relaid is the core re-laid as [n][b][Rin][Rout] in this
+// orientation (or null); blocks are its nonzero rank blocks (a0, na over input ranks, b0, nb
+// over output ranks).
 template <class T>
-static void op_apply(iga_ctx* ctx, const OpView& A, const T* core, const T* relaid, const std::vector<RankBlock>& blocks,
-                     const T* PhiL, const T* PhiR, int r0o, int r0, int r1, int r1o, int ncol, const T* x,
-                     long xcs, T* z, long zcs, DevBuf<T>& t1, DevBuf<T>& t2, DevBuf<T>& wk,
-                     LocalWork::PadKey& pad, int op_id, bool bf16 = false) {
+struct BandCore {
+  int n = 0, p = 0, Rin = 0, Rout = 0;
+  const T* core = nullptr;
+  long s_in = 0, s_out = 0, s_row = 0, s_off = 0;
+  const T* relaid = nullptr;
+  const std::vector<RankBlock>* blocks = nullptr;
+};
+
+template <class T>
+static BandCore<T> band_core(const OpView& A, const T* core, const T* relaid, const std::vector<RankBlock>& blocks) {
+  BandCore<T> c;
+  const int b = 2 * A.p + 1;
+  c.n = A.n; c.p = A.p; c.Rin = A.R0; c.Rout = A.R1;
+  c.core = core;
+  c.s_in = (long)A.n * b * A.R1; c.s_out = 1; c.s_row = (long)b * A.R1; c.s_off = A.R1;
+  c.relaid = relaid;
+  c.blocks = &blocks;
+  return c;
+}
+
+// The banded stage on a padded input: out[i][g][c] = sum_{o, d} A(d, i, o, g) in[i + o][d][c] for
+// c < S1, with in[j][d][c] at j SJ + d S1 + c (p zero slices at both ends of j) and out[i][g][c]
+// at (i Rout + g) S1 + c.
+template <class T>
+static void band_stage(hipStream_t st, const BandCore<T>& A, const T* t1, long SJ, long S1, T* t2, bool bf16) {
   using G = typename Prec<T>::G;
-  hipStream_t st = ctx->stream;
-  const int n = A.n, p = A.p, b = 2 * p + 1, R0 = A.R0, R1 = A.R1;
-  const long S2 = (long)r0o * r1;         // one (c) slab of (a', b)
-  const long S1 = (long)ncol * S2;        // one (d) slab
-  const long SJ = (long)R0 * S1;          // one j slice of t1
-  t1.ensure(ctx, (size_t)(n + 2 * p) * SJ);
-  t2.ensure(ctx, (size_t)n * R1 * S1);
-  // the p zero slices at both ends of j are never written by stage 1: fill them once per layout
-  if (p > 0 && (pad.gen != t1.gen() || pad.sj != SJ || pad.n != n || pad.p != p)) {
-    Prec<T>::zero(st, p * SJ, t1.get());
-    Prec<T>::zero(st, p * SJ, t1.get() + (long)(n + p) * SJ);
-    pad.gen = t1.gen(); pad.sj = SJ; pad.n = n; pad.p = p;
-  }
-  // stage 1: one GEMM per column c with rows (d, a'): t1[j+p][d][c][a'][b] = sum_a PhiL[d][a'][a] x[c][a][j][b]
-  G g1;
-  g1.M = R0 * r0o; g1.N = n * r1; g1.N2 = r1; g1.K = r0;
-  g1.A = PhiL; g1.sAm1 = (long)r0o * r0; g1.sAm2 = r0; g1.sAk2 = 1;
-  g1.B = x; g1.sBk2 = (long)n * r1; g1.sBn1 = r1; g1.sBn2 = 1;
-  g1.C = t1.get() + p * SJ; g1.M2 = r0o; g1.sCm1 = S1; g1.sCm2 = r1; g1.sCn1 = SJ; g1.sCn2 = 1;
-  g1.nb1 = ncol; g1.sBb1 = xcs; g1.sCb1 = S2;
-  Prec<T>::gemm(st, g1, nullptr, 0, bf16);
-  // stage 2: per rank block, batched over rows i
-  hipEvent_t pa = nullptr, pb = nullptr;
-  if (ctx->prof_on) {
-    pa = prof_event(ctx);
-    pb = prof_event(ctx);
-    IGA_HIP(hipEventRecord(pa, st));
-  }
+  const int n = A.n, p = A.p, b = 2 * p + 1, R0 = A.Rin, R1 = A.Rout;
+  const std::vector<RankBlock>& blocks = *A.blocks;
   const bool dense = blocks.size() == 1 && blocks[0].na == R0 && blocks[0].nb == R1;
   // a re-laid core: dense, or block-structured with few rank pairs (zeros included)
+  const T* relaid = A.relaid;
   const bool whole = relaid && (dense || (long)R0 * R1 <= kDenseRankPairs);
   if (whole && R0 == 1 && R1 == 1 && !bf16) {
     // a rank-1 core (the mass operator of a separable weight): a one-row GEMM would use one
     // sixteenth of a matrix-core tile, so the band combination of t1's slices runs as a
     // memory-bound stencil; the relaid core is [i][o]
-    Prec<T>::band1(st, n, b, S1, relaid, t1.get(), SJ, t2.get());
+    Prec<T>::band1(st, n, b, S1, relaid, t1, SJ, t2);
   } else if (whole && R1 <= kSmallR1 && !bf16) {
-    // few right ranks: a 16-row matrix-core tile would be mostly padding and its launch
+    // few output ranks: a 16-row matrix-core tile would be mostly padding and its launch
     // overheads dominate, so the band sums run on the vector units
-    Prec<T>::bandsm(st, n, b, R0, R1, S1, relaid, t1.get(), SJ, S1, t2.get());
+    Prec<T>::bandsm(st, n, b, R0, R1, S1, relaid, t1, SJ, S1, t2);
   } else if (whole) {
     // core [i][o][d][g]: for row i the contraction index k = o R0 + d has constant strides
     // (R1 in the core, S1 in t1, whose slice i + o starts at (i + o) SJ = i SJ + o R0 S1)
     G g2;
     g2.M = R1; g2.N = (int)S1; g2.K = R0 * b;
     g2.A = relaid; g2.sAm2 = 1; g2.sAk2 = R1;
-    g2.B = t1.get(); g2.sBk2 = S1; g2.sBn2 = 1;
-    g2.C = t2.get(); g2.sCm2 = S1; g2.sCn2 = 1;
+    g2.B = t1; g2.sBk2 = S1; g2.sBn2 = 1;
+    g2.C = t2; g2.sCm2 = S1; g2.sCn2 = 1;
     g2.nb1 = n; g2.sAb1 = (long)b * R0 * R1; g2.sBb1 = SJ; g2.sCb1 = (long)R1 * S1;
     Prec<T>::gemm(st, g2, nullptr, 0, bf16);
   } else {
+    // one product per nonzero rank block, K = (o, d) two-level; the blocks partition the
+    // output ranks (a dense core, or the block-diagonal middle core of K), so every row of t2
+    // is written once
     for (const RankBlock& rb : blocks) {
       G g2;
       g2.M = rb.nb; g2.N = (int)S1; g2.K = rb.na * b; g2.K2 = rb.na;
-      g2.A = core + (long)rb.a0 * n * b * R1 + rb.b0;
-      g2.sAm2 = 1; g2.sAk1 = R1; g2.sAk2 = (long)n * b * R1;
-      g2.B = t1.get() + rb.a0 * S1; g2.sBk1 = SJ; g2.sBk2 = S1; g2.sBn2 = 1;
-      g2.C = t2.get() + rb.b0 * S1; g2.sCm2 = S1; g2.sCn2 = 1;
-      g2.nb1 = n; g2.sAb1 = (long)b * R1; g2.sBb1 = SJ; g2.sCb1 = (long)R1 * S1;
+      g2.A = A.core + rb.a0 * A.s_in + rb.b0 * A.s_out;
+      g2.sAm2 = A.s_out; g2.sAk1 = A.s_off; g2.sAk2 = A.s_in;
+      g2.B = t1 + rb.a0 * S1; g2.sBk1 = SJ; g2.sBk2 = S1; g2.sBn2 = 1;
+      g2.C = t2 + rb.b0 * S1; g2.sCm2 = S1; g2.sCn2 = 1;
+      g2.nb1 = n; g2.sAb1 = A.s_row; g2.sBb1 = SJ; g2.sCb1 = (long)R1 * S1;
       Prec<T>::gemm(st, g2, nullptr, 0, bf16);
     }
   }
-  if (ctx->prof_on) {
+}
+
+// Stages 1 and 2 on caller-provided intermediates t1 and t2 (see op_apply):
+//   t1[j+p][d][c][a'][b] = sum_a PhiL[d][a'][a] x[c][a][j][b]
+//   t2[i][g][c][a'][b]   = sum_{o,d} A(d, i, o, g) t1[i+o][d][c][a'][b]
+// zero_pads fills t1's p zero end slices first (the caller knows whether they are in place);
+// prof allows the event timing of the banded stage.
+template <class T>
+static void op_stage12(iga_ctx* ctx, const BandCore<T>& A, const T* PhiL, int r0o, int r0, int r1, int ncol,
+                       const T* x, long xcs, T* t1, T* t2, bool zero_pads, int op_id, bool bf16, bool prof) {
+  using G = typename Prec<T>::G;
+  hipStream_t st = ctx->stream;
+  const int n = A.n, p = A.p, b = 2 * p + 1, R0 = A.Rin, R1 = A.Rout;
+  const std::vector<RankBlock>& blocks = *A.blocks;
+  const long S2 = (long)r0o * r1;         // one (c) slab of (a', b)
+  const long S1 = (long)ncol * S2;        // one (d) slab
+  const long SJ = (long)R0 * S1;          // one j slice of t1
+  // the p zero slices at both ends of j are never written by stage 1
+  if (p > 0 && zero_pads) {
+    Prec<T>::zero(st, p * SJ, t1);
+    Prec<T>::zero(st, p * SJ, t1 + (long)(n + p) * SJ);
+  }
+  // stage 1: one GEMM per column c with rows (d, a'): t1[j+p][d][c][a'][b] = sum_a PhiL[d][a'][a] x[c][a][j][b]
+  G g1;
+  g1.M = R0 * r0o; g1.N = n * r1; g1.N2 = r1; g1.K = r0;
+  g1.A = PhiL; g1.sAm1 = (long)r0o * r0; g1.sAm2 = r0; g1.sAk2 = 1;
+  g1.B = x; g1.sBk2 = (long)n * r1; g1.sBn1 = r1; g1.sBn2 = 1;
+  g1.C = t1 + p * SJ; g1.M2 = r0o; g1.sCm1 = S1; g1.sCm2 = r1; g1.sCn1 = SJ; g1.sCn2 = 1;
+  g1.nb1 = ncol; g1.sBb1 = xcs; g1.sCb1 = S2;
+  Prec<T>::gemm(st, g1, nullptr, 0, bf16);
+  // stage 2: per rank block, batched over rows i
+  hipEvent_t pa = nullptr, pb = nullptr;
+  prof = prof && ctx->prof_on;
+  if (prof) {
+    pa = prof_event(ctx);
+    pb = prof_event(ctx);
+    IGA_HIP(hipEventRecord(pa, st));
+  }
+  band_stage<T>(st, A, t1, SJ, S1, t2, bf16);
+  if (prof) {
     IGA_HIP(hipEventRecord(pb, st));
     double nz = 0;
     for (const RankBlock& rb : blocks) nz += (double)rb.na * rb.nb;
     ctx->prof.push_back({pa, pb, Prec<T>::prof_base + (bf16 ? 2 : 0) + op_id, (int)blocks.size(),
                          2.0 * r0o * r1 * ncol * nz * band_nnz(n, p)});
   }
+}
+
+// The contraction itself, on caller-provided intermediates t1, t2 and wk (wlen elements).
+template <class T>
+static void op_apply_raw(iga_ctx* ctx, const OpView& A, const T* core, const T* relaid,
+                         const std::vector<RankBlock>& blocks, const T* PhiL, const T* PhiR, int r0o, int r0, int r1,
+                         int r1o, int ncol, const T* x, long xcs, T* z, long zcs, T* t1, T* t2, T* wk, size_t wlen,
+                         bool zero_pads, int op_id, bool bf16, bool prof) {
+  using G = typename Prec<T>::G;
+  const int n = A.n, R1 = A.R1;
+  const long S2 = (long)r0o * r1, S1 = (long)ncol * S2;
+  op_stage12<T>(ctx, band_core<T>(A, core, relaid, blocks), PhiL, r0o, r0, r1, ncol, x, xcs, t1, t2, zero_pads,
+                op_id, bf16, prof);
   // stage 3: z[c][(a' i)][b'] = sum_{(g, b)} t2[i][g][c][a'][b] PhiR[g][b'][b]
   G g3;
   g3.M = r0o * n; g3.M2 = n; g3.N = r1o; g3.K = R1 * r1; g3.K2 = r1;
-  g3.A = t2.get(); g3.sAm1 = r1; g3.sAm2 = (long)R1 * S1; g3.sAk1 = S1; g3.sAk2 = 1;
+  g3.A = t2; g3.sAm1 = r1; g3.sAm2 = (long)R1 * S1; g3.sAk1 = S1; g3.sAk2 = 1;
   g3.B = PhiR; g3.sBk1 = (long)r1o * r1; g3.sBk2 = 1; g3.sBn2 = r1;
   g3.C = z; g3.sCm1 = (long)n * r1o; g3.sCm2 = r1o; g3.sCn2 = 1;
   g3.nb1 = ncol; g3.sAb1 = S2; g3.sCb1 = zcs;
-  const size_t wlen = (size_t)16 * ncol * r0o * n * r1o;
+  Prec<T>::gemm(ctx->stream, g3, wk, wlen, bf16);
+}
+
+// op_apply_raw on intermediates from the context pool (grown on demand); t1's zero end
+// slices are filled once per layout.
+template <class T>
+static void op_apply(iga_ctx* ctx, const OpView& A, const T* core, const T* relaid, const std::vector<RankBlock>& blocks,
+                     const T* PhiL, const T* PhiR, int r0o, int r0, int r1, int r1o, int ncol, const T* x,
+                     long xcs, T* z, long zcs, DevBuf<T>& t1, DevBuf<T>& t2, DevBuf<T>& wk,
+                     LocalWork::PadKey& pad, int op_id, bool bf16 = false) {
+  const int n = A.n, p = A.p;
+  const long SJ = (long)A.R0 * ncol * r0o * r1;
+  t1.ensure(ctx, (size_t)op_t1_len(n, p, A.R0, r0o, r1, ncol));
+  t2.ensure(ctx, (size_t)op_t2_len(n, A.R1, r0o, r1, ncol));
+  const size_t wlen = (size_t)op_split_len(n, r0o, r1o, ncol);
   wk.ensure(ctx, wlen);
-  Prec<T>::gemm(st, g3, wk.get(), wlen, bf16);
+  const bool zero_pads = p > 0 && (pad.gen != t1.gen() || pad.sj != SJ || pad.n != n || pad.p != p);
+  if (zero_pads) {
+    pad.gen = t1.gen(); pad.sj = SJ; pad.n = n; pad.p = p;
+  }
+  op_apply_raw<T>(ctx, A, core, relaid, blocks, PhiL, PhiR, r0o, r0, r1, r1o, ncol, x, xcs, z, zcs, t1.get(),
+                  t2.get(), wk.get(), wlen, zero_pads, op_id, bf16, true);
+}
+
+// ---- interface updates and one-column projections on the matrix cores ----
+
+static std::vector<RankBlock> transposed_blocks(const std::vector<RankBlock>& blocks) {
+  std::vector<RankBlock> t;
+  t.reserve(blocks.size());
+  for (const RankBlock& rb : blocks) t.push_back(RankBlock{rb.b0, rb.nb, rb.a0, rb.na});
+  return t;
+}
+
+// Grows the workspace for stages 1-2 of one column and reports whether t1's zero end slices
+// must be filled (a new buffer or another layout).
+static bool iface_ensure(iga_ctx* ctx, IfaceWork& w, int n, int p, int Rin, int Rout, int r0o, int r1) {
+  w.t1.ensure(ctx, (size_t)op_t1_len(n, p, Rin, r0o, r1, 1));
+  w.t2.ensure(ctx, (size_t)op_t2_len(n, Rout, r0o, r1, 1));
+  const long SJ = (long)Rin * r0o * r1;
+  const bool zero = p > 0 && (w.pad.gen != w.t1.gen() || w.pad.sj != SJ || w.pad.n != n || w.pad.p != p);
+  if (zero) {
+    w.pad.gen = w.t1.gen(); w.pad.sj = SJ; w.pad.n = n; w.pad.p = p;
+  }
+  return zero;
+}
+
+void interface_left_mc(iga_ctx* ctx, const OpView& A, const std::vector<RankBlock>& blocks, const double* Phi,
+                       const double* U, const double* V, int ru0, int ru1, int rv0, int rv1, double* out,
+                       IfaceWork& w) {
+  const int n = A.n;
+  const bool zero = iface_ensure(ctx, w, n, A.p, A.R0, A.R1, ru0, rv1);
+  // t2[i][g][a'][b] = sum_{o, d} A(d, i, o, g) sum_a Phi[d][a'][a] V[a][i+o-p][b]
+  op_stage12<double>(ctx, band_core<double>(A, A.A, A.Ar, blocks), Phi, ru0, rv0, rv1, 1, V, 0, w.t1.get(),
+                     w.t2.get(), zero, 0, false, false);
+  // out[g][b'][b] = sum_{(a', i)} U[a'][i][b'] t2[i][g][a'][b]: one product per output rank g,
+  // K = (a', i) two-level
+  const long S1 = (long)ru0 * rv1;
+  k::Gemm2 g;
+  g.M = ru1; g.N = rv1; g.K = ru0 * n; g.K2 = n;
+  g.A = U; g.sAm2 = 1; g.sAk1 = (long)n * ru1; g.sAk2 = ru1;
+  g.B = w.t2.get(); g.sBk1 = rv1; g.sBk2 = (long)A.R1 * S1; g.sBn2 = 1;
+  g.C = out; g.sCm2 = rv1; g.sCn2 = 1;
+  g.nb1 = A.R1; g.sBb1 = S1; g.sCb1 = (long)ru1 * rv1;
+  const size_t wlen = (size_t)16 * A.R1 * ru1 * rv1;
+  w.split.ensure(ctx, wlen);
+  k::gemm2(ctx->stream, g, w.split.get(), wlen);
+}
+
+void interface_right_mc(iga_ctx* ctx, const OpView& A, const double* relaidT, const std::vector<RankBlock>& blocks,
+                        const double* Phi, const double* U, const double* V, int ru0, int ru1, int rv0, int rv1,
+                        double* out, IfaceWork& w) {
+  const int n = A.n, b = 2 * A.p + 1;
+  // the core with its rank roles swapped: input rank g (right), output rank d (left)
+  BandCore<double> c;
+  c.n = n; c.p = A.p; c.Rin = A.R1; c.Rout = A.R0;
+  c.core = A.A;
+  c.s_in = 1; c.s_out = (long)n * b * A.R1; c.s_row = (long)b * A.R1; c.s_off = A.R1;
+  c.relaid = relaidT;
+  const std::vector<RankBlock> tb = transposed_blocks(blocks);
+  c.blocks = &tb;
+  // V^T[b][j][a] = V[a][j][b], so that stage 1 contracts Phi[g][b'][b] with it over b
+  w.vt.ensure(ctx, (size_t)rv0 * n * rv1);
+  {
+    const int dims[4] = {1, rv0, n, rv1}, perm[4] = {0, 3, 2, 1};
+    k::permute4(ctx->stream, V, dims, perm, w.vt.get());
+  }
+  const bool zero = iface_ensure(ctx, w, n, A.p, A.R1, A.R0, ru1, rv0);
+  // t2[i][d][b'][a] = sum_{o, g} A(d, i, o, g) sum_b Phi[g][b'][b] V[a][i+o-p][b]
+  op_stage12<double>(ctx, c, Phi, ru1, rv1, rv0, 1, w.vt.get(), 0, w.t1.get(), w.t2.get(), zero, 0, false, false);
+  // out[d][a'][a] = sum_{(i, b')} U[a'][i][b'] t2[i][d][b'][a]: one product per output rank d,
+  // K = (i, b') two-level, so that U is read along its unit-stride index b'
+  const long S1 = (long)ru1 * rv0;
+  k::Gemm2 g;
+  g.M = ru0; g.N = rv0; g.K = n * ru1; g.K2 = ru1;
+  g.A = U; g.sAm2 = (long)n * ru1; g.sAk1 = ru1; g.sAk2 = 1;
+  g.B = w.t2.get(); g.sBk1 = (long)A.R0 * S1; g.sBk2 = rv0; g.sBn2 = 1;
+  g.C = out; g.sCm2 = rv0; g.sCn2 = 1;
+  g.nb1 = A.R0; g.sBb1 = S1; g.sCb1 = (long)ru0 * rv0;
+  const size_t wlen = (size_t)16 * A.R0 * ru0 * rv0;
+  w.split.ensure(ctx, wlen);
+  k::gemm2(ctx->stream, g, w.split.get(), wlen);
+}
+
+void apply_one_mc(iga_ctx* ctx, const OpView& A, const std::vector<RankBlock>& blocks, const double* PhiL,
+                  const double* PhiR, int r0o, int r0, int r1, int r1o, const double* x, double* z, IfaceWork& w) {
+  const bool zero = iface_ensure(ctx, w, A.n, A.p, A.R0, A.R1, r0o, r1);
+  const size_t wlen = (size_t)op_split_len(A.n, r0o, r1o, 1);
+  w.split.ensure(ctx, wlen);
+  op_apply_raw<double>(ctx, A, A.A, A.Ar, blocks, PhiL, PhiR, r0o, r0, r1, r1o, 1, x, 0, z, 0, w.t1.get(),
+                       w.t2.get(), w.split.get(), wlen, zero, 0, false, false);
+}
+
+// ---- a TT-matrix applied to a full tensor, mode by mode on the matrix cores ----
+
+// y = alpha A x + beta y, x and y full tensors [n0][n1][n2] (C order), A a TT-matrix with banded
+// cores (eqs. M_kron, K_kron). A is the sum of the terms of its middle core's rank blocks (one
+// for a dense middle core, the nine (k, l) terms of the stiffness operator); each term applies
+// its three factor cores one mode at a time, with the mode being contracted moved outermost and
+// padded with p zero slices, so that every mode product is the banded stage of the local matvec:
+//   mode 0: Y0[i0][g1][(j1 j2)] = sum A0(0, i0, o, g1) x[i0+o-p][(j1 j2)]
+//   mode 1: Y1[i1][g2][(i0 j2)] = sum A1(g1, i1, o, g2) Y0[i0][g1][i1+o-p][j2]
+//   mode 2: Y2[i2][(i1 i0)]     = sum A2(g2, i2, o, 0)  Y1[i1][g2][i0][i2+o-p]
+// and y[i0][i1][i2] += alpha Y2[i2][i1][i0].
+void full_apply_mc(iga_ctx* ctx, const iga_ttop* A, const double* x, double* y, double alpha, double beta,
+                   FullWork& w) {
+  hipStream_t st = ctx->stream;
+  const int n0 = A->n[0], n1 = A->n[1], n2 = A->n[2], p = A->p, b = 2 * p + 1;
+  const long N = (long)n0 * n1 * n2;
+  const OpCore& c0 = A->core[0];
+  const OpCore& c1 = A->core[1];
+  const OpCore& c2 = A->core[2];
+  require(c0.R0 == 1 && c2.R1 == 1 && c0.blocks.size() == 1 && c2.blocks.size() == 1, IGA_EINVAL,
+          "full_apply: outer cores must be single dense blocks");
+  const std::vector<RankBlock>& terms = c1.blocks;
+  int rmax = 1;
+  for (const RankBlock& t : terms) rmax = std::max(rmax, std::max(t.na, t.nb));
+  const int nmax = std::max(n0, std::max(n1, n2));
+  const size_t big = (size_t)(nmax + 2 * p) * rmax * (N / std::min(n0, std::min(n1, n2)));
+  w.p0.ensure(ctx, (size_t)(n0 + 2 * p) * n1 * n2);
+  w.a.ensure(ctx, big);
+  w.b.ensure(ctx, big);
+  w.r2.ensure(ctx, (size_t)rmax * n2 * b);
+  // x padded along mode 0
+  const long C0 = (long)n1 * n2;
+  k::fill(st, p * C0, 0.0, w.p0.get());
+  k::fill(st, p * C0, 0.0, w.p0.get() + (long)(n0 + p) * C0);
+  IGA_HIP(hipMemcpyAsync(w.p0.get() + p * C0, x, N * sizeof(double), hipMemcpyDeviceToDevice, st));
+  for (size_t t = 0; t < terms.size(); ++t) {
+    const RankBlock& tb = terms[t];
+    const int na = tb.na, nb = tb.nb;
+    // mode 0: core 0 restricted to columns [a0, a0 + na)
+    {
+      BandCore<double> c;
+      const std::vector<RankBlock> one = {RankBlock{0, 1, 0, na}};
+      c.n = n0; c.p = p; c.Rin = 1; c.Rout = na;
+      c.core = c0.data.get() + tb.a0;
+      c.s_in = (long)n0 * b * c0.R1; c.s_out = 1; c.s_row = (long)b * c0.R1; c.s_off = c0.R1;
+      c.blocks = &one;
+      band_stage<double>(st, c, w.p0.get(), C0, C0, w.a.get(), false);
+    }
+    // Y0 [i0][g1][j1][j2] -> P1 [j1 + p][g1][i0][j2]
+    const long C1 = (long)n0 * n2, SJ1 = (long)na * C1;
+    {
+      const int dims[4] = {n0, na, n1, n2}, perm[4] = {2, 1, 0, 3};
+      k::fill(st, p * SJ1, 0.0, w.b.get());
+      k::fill(st, p * SJ1, 0.0, w.b.get() + (long)(n1 + p) * SJ1);
+      k::permute4(st, w.a.get(), dims, perm, w.b.get() + p * SJ1);
+    }
+    // mode 1: the term's block of the middle core
+    {
+      BandCore<double> c;
+      const std::vector<RankBlock> one = {RankBlock{0, na, 0, nb}};
+      c.n = n1; c.p = p; c.Rin = na; c.Rout = nb;
+      c.core = c1.data.get() + (long)tb.a0 * n1 * b * c1.R1 + tb.b0;
+      c.s_in = (long)n1 * b * c1.R1; c.s_out = 1; c.s_row = (long)b * c1.R1; c.s_off = c1.R1;
+      c.blocks = &one;
+      band_stage<double>(st, c, w.b.get(), SJ1, C1, w.a.get(), false);
+    }
+    // Y1 [i1][g2][i0][j2] -> P2 [j2 + p][g2][i1][i0]
+    const long C2 = (long)n1 * n0, SJ2 = (long)nb * C2;
+    {
+      const int dims[4] = {n1, nb, n0, n2}, perm[4] = {3, 1, 0, 2};
+      k::fill(st, p * SJ2, 0.0, w.b.get());
+      k::fill(st, p * SJ2, 0.0, w.b.get() + (long)(n2 + p) * SJ2);
+      k::permute4(st, w.a.get(), dims, perm, w.b.get() + p * SJ2);
+    }
+    // mode 2: core 2 restricted to rows [b0, b0 + nb), re-laid as [n2][b][nb][1] (the rows are
+    // contiguous), one output rank: the vector-unit banded stage
+    {
+      const int dims[4] = {nb, n2, b, 1}, perm[4] = {1, 2, 0, 3};
+      k::permute4(st, c2.data.get() + (long)tb.b0 * n2 * b, dims, perm, w.r2.get());
+      BandCore<double> c;
+      const std::vector<RankBlock> one = {RankBlock{0, nb, 0, 1}};
+      c.n = n2; c.p = p; c.Rin = nb; c.Rout = 1;
+      c.core = c2.data.get() + (long)tb.b0 * n2 * b;
+      c.s_in = (long)n2 * b; c.s_out = 1; c.s_row = b; c.s_off = 1;
+      c.relaid = w.r2.get();
+      c.blocks = &one;
+      band_stage<double>(st, c, w.b.get(), SJ2, C2, w.a.get(), false);
+    }
+    // Y2 [i2][i1][i0] -> [i0][i1][i2], accumulated into y
+    {
+      const int dims[4] = {1, n2, n1, n0}, perm[4] = {0, 3, 2, 1};
+      k::permute4(st, w.a.get(), dims, perm, w.b.get());
+      k::axpby(st, N, alpha, w.b.get(), t == 0 ? beta : 1.0, y);
+    }
+  }
 }
 
 void local_matvec(iga_ctx* ctx, const LocalOp& L, const double* x, double* y, LocalWork& w) {

@@ -57,6 +57,39 @@ struct LocalWork {
   FBuf ftM, ftK, ftM2, ftK2, fz, fsplit, fx, fy;  // FP32 counterparts
 };
 
+// Workspace of the matrix-core interface updates and one-column projections.
+struct IfaceWork {
+  DBuf t1, t2, split, vt;
+  LocalWork::PadKey pad;
+};
+// Left interface of core d + 1 from core d (Section 5, eqs. frame and ttlin):
+//   out[g][b'][b] = sum U[a'][i][b'] Phi[d][a'][a] A[d][i][i+o-p][g] V[a][i+o-p][b],
+// U: [ru0][n][ru1], V: [rv0][n][rv1], Phi: [R0][ru0][rv0], out: [R1][ru1][rv1]. A.Ar (the core
+// re-laid as [n][2p+1][R0][R1]) may be null; blocks are the core's nonzero rank blocks.
+void interface_left_mc(iga_ctx* ctx, const OpView& A, const std::vector<RankBlock>& blocks, const double* Phi,
+                       const double* U, const double* V, int ru0, int ru1, int rv0, int rv1, double* out,
+                       IfaceWork& w);
+// Right interface of core d - 1 from core d:
+//   out[d][a'][a] = sum U[a'][i][b'] Phi[g][b'][b] A[d][i][i+o-p][g] V[a][i+o-p][b],
+// Phi: [R1][ru1][rv1], out: [R0][ru0][rv0]; relaidT (may be null) is the core re-laid as
+// [n][2p+1][R1][R0].
+void interface_right_mc(iga_ctx* ctx, const OpView& A, const double* relaidT, const std::vector<RankBlock>& blocks,
+                        const double* Phi, const double* U, const double* V, int ru0, int ru1, int rv0, int rv1,
+                        double* out, IfaceWork& w);
+// One column of the projected operator: z[a'][i][b'] = sum PhiL[d][a'][a] A[d][i][i+o-p][g]
+// x[a][i+o-p][b] PhiR[g][b'][b], x: [r0][n][r1], z: [r0o][n][r1o].
+void apply_one_mc(iga_ctx* ctx, const OpView& A, const std::vector<RankBlock>& blocks, const double* PhiL,
+                  const double* PhiR, int r0o, int r0, int r1, int r1o, const double* x, double* z, IfaceWork& w);
+
+// Workspace of full_apply_mc.
+struct FullWork {
+  DBuf p0, a, b, r2;
+};
+// y = alpha A x + beta y for a TT-matrix A (banded cores) and full tensors x, y [n0][n1][n2],
+// one mode at a time on the matrix cores.
+void full_apply_mc(iga_ctx* ctx, const iga_ttop* A, const double* x, double* y, double alpha, double beta,
+                   FullWork& w);
+
 // y = A_loc x (FP64); x: [3][r0][n][r1], y: [3][r0o][n][r1o]
 void local_matvec(iga_ctx* ctx, const LocalOp& L, const double* x, double* y, LocalWork& w);
 // Same product on FP32 operands (x, y FP32; needs the f* fields and Af views), every

@@ -22,6 +22,7 @@ lib = C.CDLL(LIB_PATH)
 
 OK, EINVAL, ENOMEM, EHIP, EGEOM, ENOCONV, ERANK, ENUM = 0, -1, -2, -3, -4, -5, -6, -7
 FP64, FP32, BF16 = 0, 1, 2
+MAX_HISTORY = 64  # IGA_MAX_HISTORY
 _NAMES = {EINVAL: "IGA_EINVAL", ENOMEM: "IGA_ENOMEM", EHIP: "IGA_EHIP", EGEOM: "IGA_EGEOM",
           ENOCONV: "IGA_ENOCONV", ERANK: "IGA_ERANK", ENUM: "IGA_ENUM"}
 
@@ -67,13 +68,23 @@ class AmenStats(C.Structure):
                 ("t_precond", C.c_double), ("t_krylov_other", C.c_double), ("t_interfaces", C.c_double),
                 ("t_svd", C.c_double), ("t_residual", C.c_double), ("local_matvecs_fp32", C.c_longlong),
                 ("local_matvec_flops_fp32", C.c_double), ("t_local_matvec_fp32", C.c_double),
-                ("refinements", C.c_longlong)]
+                ("refinements", C.c_longlong),
+                ("history_max_local_residual", C.c_double * MAX_HISTORY),
+                ("history_ranks", (C.c_int * 2) * MAX_HISTORY),
+                ("history_storage", C.c_longlong * MAX_HISTORY)]
 
     def as_dict(self):
         out = {}
+        h = min(self.half_sweeps, MAX_HISTORY)
         for name, _ in self._fields_:
             v = getattr(self, name)
-            out[name] = list(v) if name == "ranks" else v
+            if name == "ranks":
+                v = list(v)
+            elif name == "history_ranks":
+                v = [list(v[i]) for i in range(h)]
+            elif name.startswith("history_"):
+                v = list(v)[:h]
+            out[name] = v
         return out
 
 

@@ -21,3 +21,12 @@ def ttop_dense(iga, ctx, op):
 def kkt_rows(Mf, Kf, beta):
     """KKT block rows from (M f_l, K f_l) lists: [M f0 + K f2, beta M f1 - M f2, K f0 - M f1]."""
     return [Mf[0] + Kf[2], beta * Mf[1] - Mf[2], Kf[0] - Mf[1]]
+
+
+def elem_err(a, b):
+    """Largest elementwise difference relative to the largest entry of b: max|a - b| / max|b|
+    (the element-by-element counterpart of rel_err)."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    mb = np.abs(b).max() if b.size else 0.0
+    return (np.abs(a - b).max() if a.size else 0.0) / (mb if mb > 0 else 1.0)

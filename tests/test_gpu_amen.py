@@ -11,8 +11,8 @@ import numpy as np
 import pytest
 
 import synth
-from oracle import assembly, kkt as okkt, tt
-from tests.gpu_util import kkt_rows, rel_err
+from oracle import assembly, geometry, kkt as okkt, tt
+from tests.gpu_util import elem_err, kkt_rows, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -60,6 +60,26 @@ def _box_backward_errors(geo, n, p, beta, f, yh, boxes, Wint):
               np.linalg.norm(oM[3]), "backward error %.3e" % (rbox / scale), flush=True)
         out.append(rbox / scale)
     return out
+
+
+def _oracle_truncated_weights(geo, n, p, ranks):
+    """The interpolated weights (omega, q_11 .. q_33) with the library's truncation: the values at
+    the interpolation points (Greville points of the degree-(2p+1) space) compressed by TT-SVD to
+    the given ranks, then the collocation solve applied core by core. Returns (W, space) in the
+    form of oracle.assembly.interpolate_weights."""
+    sp = assembly.Space(n, p)
+    it = assembly.InterpSpace(sp)
+    F = geometry.weight_fields(geo, it.x, it.x, it.x)
+    Binv = np.linalg.inv(it.colloc)
+    W = []
+    for w, (r1, r2) in zip(F, ranks):
+        if r1 == 0:
+            W.append(np.zeros_like(w))
+            continue
+        cores = tt.tt_svd_ranks(w, (int(r1), int(r2)))
+        cores = [np.einsum("ai,rib->rab", Binv, core) for core in cores]
+        W.append(tt.tt_full(cores))
+    return np.stack(W), it
 
 
 def test_tiny_full_rank_equals_direct_solve(gpu_ctx):
@@ -304,9 +324,11 @@ def test_state_error_against_oracle_n32(gpu_ctx, prec):
     yc = synth.yhat_fourier(n, p, seed=int(g["seed_yhat"]))
     f, st, rc, res, r = _solve(gpu_ctx, geo, p, n, beta, yc, 1e-7, weight_tol=0.0, precision=getattr(iga, prec))
     err = rel_err(f[0].ravel(), g["y"])
-    print(prec, "state error vs oracle %.3e residual %.3e" % (err, res), "stats", st, flush=True)
+    eerr = elem_err(f[0].ravel(), g["y"])
+    print(prec, "state error vs oracle %.3e (elementwise %.3e) residual %.3e" % (err, eerr, res), "stats", st,
+          flush=True)
     assert rc == 0 and res < 1e-6
-    assert err < 1e-5
+    assert err < 1e-5 and eerr < 1e-5
 
 
 def test_perturbed_cube_n128_three_forms(gpu_ctx):
@@ -333,10 +355,15 @@ def test_perturbed_cube_n128_three_forms(gpu_ctx):
         assert d < 1e-5
     f = out["FP64"]
     yh = tt.tt_full(yc)
-    Wint = assembly.interpolate_weights(geo, assembly.Space(n, p))
+    # The library's operators come from weights truncated at 1e-6. The oracle rebuilds the same
+    # truncation: TT-SVD of each weight's values at the interpolation points, kept to the ranks
+    # the library reports, then the collocation solve per mode (Section 3). In those operators
+    # the box backward errors measure the solve alone. (In untruncated operators they would
+    # carry the truncation too, which is large against the small terms near the corners.)
+    M, K, wranks = iga.assemble_factors(gpu_ctx, geo, p, n, weight_tol=c["weight_tol"])
+    iga.ttop_destroy(M)
+    iga.ttop_destroy(K)
+    Wint = _oracle_truncated_weights(geo, n, p, np.asarray(wranks))
     boxes = [((0, 3), (0, 3), (0, 3)), ((62, 65), (30, 33), (90, 93)), ((125, 128), (125, 128), (0, 3))]
-    # the library's operators come from weights truncated at 1e-6, the oracle's from untruncated
-    # ones: each term in a box carries a relative difference of about 1e-6, on top of the solve's
-    # residual 1e-6, so the bar is 1e-5
     for e in _box_backward_errors(geo, n, p, beta, f, yh, boxes, Wint):
-        assert e <= 1e-5
+        assert e <= 1e-6

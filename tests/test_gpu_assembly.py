@@ -9,7 +9,7 @@ import pytest
 
 import synth
 from oracle import assembly, geometry, kkt as okkt, tt
-from tests.gpu_util import kkt_rows, rel_err, ttop_dense
+from tests.gpu_util import elem_err, kkt_rows, rel_err, ttop_dense
 
 pytestmark = pytest.mark.gpu
 
@@ -124,6 +124,7 @@ def test_kkt_apply_matches_oracle(gpu_ctx, ell):
         f = tt.btt_full(cores, ell).reshape(3, -1)
         ref = okkt.kkt_apply(Mo, Ko, beta, f).reshape(3, -1)
         assert rel_err(yf, ref) < TOL
+        assert elem_err(yf, ref) < TOL
         # the round trip of the input through the library is exact
         xf = iga.btt_to_full(gpu_ctx, x).cpu().numpy().reshape(3, -1)
         assert rel_err(xf, f) < 1e-15
@@ -156,6 +157,7 @@ def test_kkt_apply_full_size_sampled_boxes(gpu_ctx):
             ref = np.stack(kkt_rows(oM, oK, beta))
             sl = (slice(None),) + tuple(slice(a, b) for a, b in box)
             assert rel_err(yf[sl], ref) < TOL, box
+            assert elem_err(yf[sl], ref) < TOL, box
     finally:
         for h in (y, x):
             iga.btt_destroy(h)

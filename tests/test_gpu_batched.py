@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 import synth
-from tests.gpu_util import rel_err
+from tests.gpu_util import elem_err, rel_err
 from tests.test_gpu_localmatvec import FP32_TOL, _reference
 
 pytestmark = pytest.mark.gpu
@@ -37,6 +37,7 @@ def test_batched_fp64_matches_oracle_and_single_calls(gpu_ctx):
     ys = [q["y"].cpu().numpy() for q in probs]
     for q, y, ref in zip(probs, ys, refs):
         assert rel_err(y, ref) < 1e-13
+        assert elem_err(y, ref) < 1e-13
         single = torch.zeros_like(q["y"])
         iga.local_matvec(gpu_ctx, q["r0"], q["n"], q["r1"], q["degree"], q["RM0"], q["RM1"], q["RK0"], q["RK1"],
                          q["PhiL_M"], q["PhiR_M"], q["PhiL_K"], q["PhiR_K"], q["Mcore"], q["Kcore"], q["beta"],

@@ -5,7 +5,7 @@ import pytest
 
 import synth
 from oracle import tt
-from tests.gpu_util import kkt_rows, rel_err
+from tests.gpu_util import elem_err, kkt_rows, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -44,7 +44,9 @@ def test_local_matvec_matches_oracle(gpu_ctx, r, RM, RK, n, p, rr):
     prob = synth.random_local_problem(r, RM, RK, n, p, seed=r + n, r_right=rr)
     beta = 1e-3
     y = _run(gpu_ctx, prob, r, n, p, RM, RK, beta, iga.FP64, rr)
-    assert rel_err(y, _reference(prob, p, beta)) < 1e-13
+    ref = _reference(prob, p, beta)
+    assert rel_err(y, ref) < 1e-13
+    assert elem_err(y, ref) < 1e-13
 
 
 # FP32 form: inputs rounded to FP32 (relative 6e-8) and FP32 accumulation over the three
@@ -76,6 +78,7 @@ def test_local_matvec_benchmark_shape(gpu_ctx):
     y = _run(gpu_ctx, prob, r, n, p, RM, RK, 1e-6, iga.FP64)
     ref = _reference(prob, p, 1e-6)
     assert rel_err(y, ref) < 1e-13
+    assert elem_err(y, ref) < 1e-13
     yf = _run(gpu_ctx, prob, r, n, p, RM, RK, 1e-6, iga.FP32)
     assert rel_err(yf, ref) < FP32_TOL
 

@@ -52,3 +52,28 @@ def test_no_unresolved_library_symbols():
         pytest.skip("nm unavailable")
     strong = [l for l in out.stdout.splitlines() if " U " in l and "iga" in l]
     assert not strong, strong
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes mirrors of the option and statistics structs have the C layout of iga.h
+    (compiled here with the host C compiler: sizes and the offsets of the last fields)."""
+    import ctypes
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    from paper_1811_06797_amd import iga
+    src = tmp_path / "layout.c"
+    src.write_text(
+        '#include <stddef.h>\n#include <stdio.h>\n#include "iga.h"\n'
+        "int main(void) {\n"
+        '  printf("%zu %zu %zu %zu %zu\\n", sizeof(iga_amen_stats), offsetof(iga_amen_stats, history_storage),\n'
+        "         sizeof(iga_amen_opts), sizeof(iga_profile), sizeof(iga_local_problem));\n"
+        "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    want = [ctypes.sizeof(iga.AmenStats), iga.AmenStats.history_storage.offset, ctypes.sizeof(iga.AmenOpts),
+            ctypes.sizeof(iga.Profile), ctypes.sizeof(iga.LocalProblem)]
+    assert got == want

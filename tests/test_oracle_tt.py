@@ -112,3 +112,21 @@ def test_btt_full_of_rank_one_cores_is_an_outer_product_per_component():
     full = tt.btt_full(cores, 1)
     for l in range(3):
         assert np.allclose(full[l], np.einsum("i,j,k->ijk", a, b3[l], c), atol=1e-15)
+
+
+def test_tt_svd_with_the_ranks_it_chose_gives_the_same_tensor():
+    """tt_svd_ranks at the ranks tt_svd picked for a tolerance reproduces tt_svd's tensor; at
+    full ranks it reproduces the input exactly; ranks one lower give a larger error."""
+    rng = np.random.default_rng(3)
+    x = np.linspace(0, 1, 9)
+    A = np.einsum("i,j,k->ijk", np.sin(x), np.cos(2 * x), np.exp(x)) + 1e-3 * rng.standard_normal((9, 9, 9))
+    for eps in (1e-1, 1e-2):
+        ref = tt.tt_svd(A, eps)
+        ranks = [ref[0].shape[2], ref[1].shape[2]]
+        got = tt.tt_svd_ranks(A, ranks)
+        assert np.allclose(tt.tt_full(got), tt.tt_full(ref), atol=1e-13 * np.abs(A).max())
+    full = tt.tt_svd_ranks(A, [9, 9])
+    assert np.allclose(tt.tt_full(full), A, atol=1e-13 * np.abs(A).max())
+    e_hi = np.linalg.norm(tt.tt_full(tt.tt_svd_ranks(A, [3, 3])) - A)
+    e_lo = np.linalg.norm(tt.tt_full(tt.tt_svd_ranks(A, [2, 2])) - A)
+    assert e_lo > e_hi
