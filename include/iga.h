@@ -281,6 +281,24 @@ int iga_local_matvec(iga_ctx* ctx, int r0, int n, int r1, int degree, int RM0, i
                      const double* PhiR_K, const double* Mcore, const double* Kcore, double beta,
                      const double* x, double* y, int precision);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): iga_local_matvec in FP64 with no
+ * allocation. Same arguments, layouts and result as iga_local_matvec with precision
+ * IGA_FP64, the same kernels in the same order. Every intermediate (re-laid cores, the
+ * three contraction stages, split-K partials) lives in one fixed device array of
+ * IGA_NOALLOC_SCRATCH_BYTES per GPU, reserved when the library's code is loaded on that GPU
+ * and held until the process ends; its address is looked up by iga_ctx_create. A shape whose
+ * workspace exceeds the array returns IGA_EINVAL (the message gives the bytes needed). The
+ * call makes no device allocation or free. All calls on one GPU share that GPU's array and
+ * it keeps what the last call left: calls that overlap on one GPU (other streams or host
+ * threads) race, so a caller must order them. Enqueued on the context stream; returns
+ * immediately. */
+#define IGA_NOALLOC_SCRATCH_BYTES (64L << 20)
+int iga_local_matvec_noalloc(iga_ctx* ctx, int r0, int n, int r1, int degree, int RM0, int RM1, int RK0,
+                             int RK1, const double* PhiL_M, const double* PhiR_M, const double* PhiL_K,
+                             const double* PhiR_K, const double* Mcore, const double* Kcore, double beta,
+                             const double* x, double* y);
+
 /* Reduced cost of the control problem at a solution f = (y, u, lambda) of the KKT
  * system (Section 4, eq. optimization1 with time removed):
  *   J = 1/2 (y - yhat)^T M (y - yhat) + beta/2 u^T M u, in FP64 on expanded vectors. */

@@ -96,6 +96,11 @@ void local_matvec_impl(iga_ctx* ctx, int r0, int n, int r1, int p, int RM0, int 
                        const double* PhiR_K, const double* Mcore, const double* Kcore, double beta,
                        const double* x, double* y, int precision);
 double local_matvec_flops(int r0, int n, int r1, int p, int RM0, int RM1, int RK0, int RK1);
+void noalloc_scratch_init(int device);
+void local_matvec_noalloc_entry(iga_ctx* ctx, int r0, int n, int r1, int degree, int RM0, int RM1, int RK0,
+                                int RK1, const double* PhiL_M, const double* PhiR_M, const double* PhiL_K,
+                                const double* PhiR_K, const double* Mcore, const double* Kcore, double beta,
+                                const double* x, double* y);
 
 template <class F>
 int guarded(F&& f) {
@@ -217,6 +222,8 @@ int iga_ctx_create(int device, void* hip_stream, iga_ctx** out) {
     IGA_HIP(hipGetDeviceCount(&ndev));
     require(device >= 0 && device < ndev, IGA_EINVAL, "ctx_create: no such device");
     IGA_HIP(hipSetDevice(device));
+    // device address of this GPU's copy of the fixed scratch of iga_local_matvec_noalloc
+    noalloc_scratch_init(device);
     std::unique_ptr<iga_ctx> c(new iga_ctx());
     c->device = device;
     c->stream = static_cast<hipStream_t>(hip_stream);
@@ -628,6 +635,22 @@ int iga_local_matvec(iga_ctx* ctx, int r0, int n, int r1, int degree, int RM0, i
     use_device(ctx);
     local_matvec_impl(ctx, r0, n, r1, degree, RM0, RM1, RK0, RK1, PhiL_M, PhiR_M, PhiL_K, PhiR_K, Mcore,
                       Kcore, beta, x, y, precision);
+    return IGA_OK;
+  });
+}
+
+int iga_local_matvec_noalloc(iga_ctx* ctx, int r0, int n, int r1, int degree, int RM0, int RM1, int RK0,
+                             int RK1, const double* PhiL_M, const double* PhiR_M, const double* PhiL_K,
+                             const double* PhiR_K, const double* Mcore, const double* Kcore, double beta,
+                             const double* x, double* y) {
+  return guarded([&] {
+    require(ctx && PhiL_M && PhiR_M && PhiL_K && PhiR_K && Mcore && Kcore && x && y, IGA_EINVAL,
+            "local_matvec_noalloc: NULL argument");
+    require(r0 >= 1 && r1 >= 1 && n >= 1 && degree >= 0 && RM0 >= 1 && RM1 >= 1 && RK0 >= 1 && RK1 >= 1,
+            IGA_EINVAL, "local_matvec_noalloc: sizes must be positive");
+    use_device(ctx);
+    local_matvec_noalloc_entry(ctx, r0, n, r1, degree, RM0, RM1, RK0, RK1, PhiL_M, PhiR_M, PhiL_K, PhiR_K, Mcore,
+                               Kcore, beta, x, y);
     return IGA_OK;
   });
 }

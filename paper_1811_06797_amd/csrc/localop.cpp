@@ -588,6 +588,63 @@ void local_matvec_impl(iga_ctx* ctx, int r0, int n, int r1, int p, int RM0, int 
   k::to_f64(st, xz, C.fy.get(), y);
 }
 
+// Workspace of local_matvec_noalloc_impl in doubles, each part rounded up to 32 doubles (256
+// bytes): the two re-laid cores, t1 and t2 of each operator, the five output columns and the
+// split-K partials.
+static long round32(long v) { return (v + 31) / 32 * 32; }
+long local_matvec_noalloc_len(int r0, int n, int r1, int p, int RM0, int RM1, int RK0, int RK1) {
+  const int b = 2 * p + 1;
+  return round32((long)RM0 * n * b * RM1) + round32((long)RK0 * n * b * RK1) +
+         round32(op_t1_len(n, p, RM0, r0, r1, 3)) + round32(op_t2_len(n, RM1, r0, r1, 3)) +
+         round32(op_t1_len(n, p, RK0, r0, r1, 2)) + round32(op_t2_len(n, RK1, r0, r1, 2)) +
+         round32(5L * r0 * n * r1) + round32(op_split_len(n, r0, r1, 3));
+}
+
+// local_matvec_impl in FP64 with every intermediate carved from ws (ws_len doubles, 256-byte
+// aligned): the same kernels in the same order, no allocation, no event timing. The caller
+// has checked ws_len >= local_matvec_noalloc_len.
+void local_matvec_noalloc_impl(iga_ctx* ctx, int r0, int n, int r1, int p, int RM0, int RM1, int RK0, int RK1,
+                               const double* PhiL_M, const double* PhiR_M, const double* PhiL_K,
+                               const double* PhiR_K, const double* Mcore, const double* Kcore, double beta,
+                               const double* x, double* y, double* ws, long ws_len) {
+  require(local_matvec_noalloc_len(r0, n, r1, p, RM0, RM1, RK0, RK1) <= ws_len, IGA_EINVAL,
+          "local_matvec_noalloc: workspace too small");
+  hipStream_t st = ctx->stream;
+  const int b = 2 * p + 1;
+  double* cur = ws;
+  auto take = [&](long len) {
+    double* q = cur;
+    cur += round32(len);
+    return q;
+  };
+  double* rM = take((long)RM0 * n * b * RM1);
+  double* rK = take((long)RK0 * n * b * RK1);
+  double* tM = take(op_t1_len(n, p, RM0, r0, r1, 3));
+  double* tM2 = take(op_t2_len(n, RM1, r0, r1, 3));
+  double* tK = take(op_t1_len(n, p, RK0, r0, r1, 2));
+  double* tK2 = take(op_t2_len(n, RK1, r0, r1, 2));
+  double* z = take(5L * r0 * n * r1);
+  const size_t wlen = (size_t)op_split_len(n, r0, r1, 3);
+  double* split = take((long)wlen);
+  LocalOp L;
+  L.r0 = r0; L.n = n; L.r1 = r1;
+  L.coef.m11 = beta;
+  L.M.R0 = RM0; L.M.R1 = RM1; L.M.n = n; L.M.p = p; L.M.A = Mcore;
+  L.K.R0 = RK0; L.K.R1 = RK1; L.K.n = n; L.K.p = p; L.K.A = Kcore;
+  const std::vector<RankBlock> Mb = {RankBlock{0, RM0, 0, RM1}}, Kb = {RankBlock{0, RK0, 0, RK1}};
+  const int dimsM[4] = {RM0, n, b, RM1}, dimsK[4] = {RK0, n, b, RK1}, perm[4] = {1, 2, 0, 3};
+  k::permute4(st, Mcore, dimsM, perm, rM);
+  k::permute4(st, Kcore, dimsK, perm, rK);
+  const long colsz = (long)r0 * n * r1;
+  // the scratch keeps what the last call left in it: the zero end slices of t1 are filled on
+  // every call
+  op_apply_raw<double>(ctx, L.M, Mcore, rM, Mb, PhiL_M, PhiR_M, r0, r0, r1, r1, 3, x, colsz, z, colsz, tM, tM2,
+                       split, wlen, true, 0, false, false);
+  op_apply_raw<double>(ctx, L.K, Kcore, rK, Kb, PhiL_K, PhiR_K, r0, r0, r1, r1, 2, x, 2 * colsz, z + 3 * colsz,
+                       colsz, tK, tK2, split, (size_t)op_split_len(n, r0, r1, 2), true, 1, false, false);
+  k::kkt_combine(st, colsz, L.coef, z, z + 3 * colsz, y);
+}
+
 }  // namespace iga
 
 // ---- batched local operators: many independent problems, one grouped launch per stage ----

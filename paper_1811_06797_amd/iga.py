@@ -32,7 +32,7 @@ EXPORTED = [
     "iga_btt_create", "iga_btt_info", "iga_btt_blocks", "iga_btt_get_core", "iga_btt_to_full", "iga_btt_destroy",
     "iga_kkt_create", "iga_kkt_create_parabolic", "iga_kkt_blocks", "iga_kkt_destroy", "iga_kkt_apply", "iga_kkt_residual", "iga_amen_solve",
     "iga_amen_solve_many",
-    "iga_local_matvec", "iga_local_matvec_batched", "iga_local_matvec_flops", "iga_profile_start", "iga_profile_stop",
+    "iga_local_matvec", "iga_local_matvec_noalloc", "iga_local_matvec_batched", "iga_local_matvec_flops", "iga_profile_start", "iga_profile_stop",
     "iga_measure_peaks", "iga_objective",
     "iga_grad_yhat", "iga_grad_geometry", "iga_last_error",
 ]
@@ -144,6 +144,8 @@ lib.iga_amen_solve.argtypes = [P, P, P, C.c_double, C.POINTER(AmenOpts), P, C.PO
                                C.POINTER(AmenStats)]
 lib.iga_local_matvec.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                                  C.c_int, P, P, P, P, P, P, C.c_double, P, P, C.c_int]
+lib.iga_local_matvec_noalloc.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                         C.c_int, P, P, P, P, P, P, C.c_double, P, P]
 lib.iga_local_matvec_batched.argtypes = [P, C.c_int, C.POINTER(LocalProblem), C.c_int, C.c_int]
 lib.iga_local_matvec_flops.argtypes = [C.c_int] * 8
 lib.iga_local_matvec_flops.restype = C.c_double
@@ -388,6 +390,20 @@ def local_matvec(ctx, r0, n, r1, degree, RM0, RM1, RK0, RK1, PhiL_M, PhiR_M, Phi
     _check(lib.iga_local_matvec(ctx, r0, n, r1, degree, RM0, RM1, RK0, RK1, ptr(PhiL_M), ptr(PhiR_M),
                                 ptr(PhiL_K), ptr(PhiR_K), ptr(Mcore), ptr(Kcore), float(beta), ptr(x), ptr(y),
                                 int(precision)))
+
+
+def local_matvec_noalloc(ctx, r0, n, r1, degree, RM0, RM1, RK0, RK1, PhiL_M, PhiR_M, PhiL_K, PhiR_K, Mcore, Kcore,
+                         beta, x, y):
+    """iga_local_matvec_noalloc: the FP64 local matvec with its intermediates in the library's
+    fixed per-GPU scratch array. Array arguments are device pointers (ints) or CUDA tensors."""
+    def ptr(t):
+        return P(t.data_ptr() if hasattr(t, "data_ptr") else int(t))
+    _check(lib.iga_local_matvec_noalloc(ctx, r0, n, r1, degree, RM0, RM1, RK0, RK1, ptr(PhiL_M), ptr(PhiR_M),
+                                        ptr(PhiL_K), ptr(PhiR_K), ptr(Mcore), ptr(Kcore), float(beta), ptr(x),
+                                        ptr(y)))
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20  # IGA_NOALLOC_SCRATCH_BYTES
 
 
 def local_matvec_flops(r0, n, r1, degree, RM0, RM1, RK0, RK1) -> float:

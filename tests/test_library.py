@@ -54,6 +54,12 @@ def test_no_unresolved_library_symbols():
     assert not strong, strong
 
 
+def test_noalloc_scratch_size_matches_header():
+    from paper_1811_06797_amd import iga
+    m = re.search(r"#define IGA_NOALLOC_SCRATCH_BYTES \((\d+)L << (\d+)\)", open(HDR).read())
+    assert m and int(m.group(1)) << int(m.group(2)) == iga.NOALLOC_SCRATCH_BYTES
+
+
 def test_struct_layouts_match_the_header(tmp_path):
     """The ctypes mirrors of the option and statistics structs have the C layout of iga.h
     (compiled here with the host C compiler: sizes and the offsets of the last fields)."""
