@@ -78,6 +78,8 @@ def parse():
                     help="workload of --solve-only (perturbed_cube_n128, annulus_n64, annulus_n256, cube_n16)")
     ap.add_argument("--precision", default="FP64", choices=["FP64", "FP32", "BF16"],
                     help="precision form of --solve-only")
+    ap.add_argument("--micro-only", action="store_true",
+                    help="only the local TT-matvec microbenchmark and the reference copy (for counter runs)")
     return ap.parse_args()
 
 
@@ -319,7 +321,8 @@ def micro_bench(iga, ctx, torch, iters):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / iters
     flops = iga.local_matvec_flops(s["r"], s["n"], s["r"], s["p"], s["RM"], s["RM"], s["RK"], s["RK"])
-    out = {"shape": dict(s), "ms": ms, "gflops": flops / ms / 1e6, "flops": flops, "profile": prof}
+    out = {"shape": dict(s), "ms": ms, "gflops": flops / ms / 1e6, "flops": flops, "profile": prof,
+           "stages": stage_rates(prof, (0, 1))}
     # the same product in the mixed forms (operands converted to FP32 inside each call; BF16
     # rounds them once more as the products stage them)
     for name, prec, slot, peak in (("fp32", iga.FP32, 3, PEAK_FP32_TFLOPS), ("bf16", iga.BF16, 5, PEAK_BF16_TFLOPS)):
@@ -412,6 +415,18 @@ def cpu_baseline(prob, budget_s=15.0, max_calls=400):
                       "os.cpu_count() = %s" % (calls, s["r"], s["RM"], s["RK"], s["n"], s["p"], dt, os.cpu_count())}
 
 
+def stage_rates(prof, ops):
+    """TF/s and summed ms of the three local-matvec stages (left interface, banded operator core,
+    right interface) over the given operator indices of a library event profile."""
+    out = {}
+    for name, ms_key, fl_key in (("left_interface", "s1_ms", "s1_flops"), ("band", "ms", "flops"),
+                                 ("right_interface", "s3_ms", "s3_flops")):
+        ms = sum(prof[ms_key][i] for i in ops)
+        fl = sum(prof[fl_key][i] for i in ops)
+        out[name] = {"ms": ms, "tflops": fl / (ms * 1e-3) / 1e12 if ms else None}
+    return out
+
+
 def run_step(iga, ctx, torch, geo, c, Y, precision=None):
     """One step: assembly, KKT operator and block-AMEn solve of one workload; statistics of the
     solve with the wall times of both parts and the solve's status."""
@@ -457,6 +472,15 @@ def main():
     torch.cuda.init()
     stream = torch.cuda.current_stream()
     ctx = iga.ctx_create(0, stream.cuda_stream)
+
+    if a.micro_only:
+        micro, _ = micro_bench(iga, ctx, torch, a.micro_iters)
+        prof = micro["profile"]
+        print(json.dumps({"shape": micro["shape"], "ms": micro["ms"], "gflops": micro["gflops"],
+                          "band_K_ms_per_launch": prof["ms"][1] / max(prof["launches"][1], 1),
+                          "band_K_flops_per_launch": prof["flops"][1] / max(prof["launches"][1], 1)}), flush=True)
+        iga.ctx_destroy(ctx)
+        return
 
     if a.solve_only:
         geo, yc, c = synth.config(a.workload)
@@ -543,6 +567,7 @@ def main():
         "kkt_residual": max(s["residual"] for s in stats),
         "solve": {k: last[k] for k in STAT_KEYS},
         "weight_ranks": last["weight_ranks"],
+        "in_solve_stages": stage_rates(band, (0, 1)),
         "in_solve_band_stage": {"stages": band["stages"][0] + band["stages"][1],
                                 "launches": band["launches"][0] + band["launches"][1],
                                 "ms": band_ms, "flops": band_flops,
@@ -554,7 +579,7 @@ def main():
         "annulus_n64": secondary,
         "batching": batching,
         "time_dependent": timedep,
-        "microbench_local_matvec": {k: micro[k] for k in ("shape", "ms", "gflops", "flops", "fp32", "bf16")},
+        "microbench_local_matvec": {k: micro[k] for k in ("shape", "ms", "gflops", "flops", "stages", "fp32", "bf16")},
         "microbench_shapes": shapes,
         "measured_peaks": peaks,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",

@@ -349,11 +349,11 @@ int iga_local_matvec_batched(iga_ctx* ctx, int nprob, const iga_local_problem* p
 /* Algorithmic flops of one iga_local_matvec call with these sizes. */
 double iga_local_matvec_flops(int r0, int n, int r1, int degree, int RM0, int RM1, int RK0, int RK1);
 
-/* Event timing of the banded (middle) stage of the projected local TT-matvec, the
- * contraction of the operator core with the band of t1 = PhiL x (eq. KKT_red), for
- * measurement. Between iga_profile_start and iga_profile_stop every local matvec on the
- * context (inside iga_amen_solve or iga_local_matvec) records a HIP event pair on the
- * context stream around that stage, per operator and precision (index 0: M FP64, 1: K FP64,
+/* Event timing of the three stages of the projected local TT-matvec (eq. KKT_red), chiefly
+ * the banded (middle) stage, the contraction of the operator core with the band of
+ * t1 = PhiL x, for measurement. Between iga_profile_start and iga_profile_stop every local
+ * matvec on the context (inside iga_amen_solve or iga_local_matvec) records HIP event pairs on
+ * the context stream around each stage, per operator and precision (index 0: M FP64, 1: K FP64,
  * 2: M FP32, 3: K FP32, 4: M BF16, 5: K BF16). stop synchronises the stream and returns:
  * stages (banded stages
  * timed), launches (kernel launches inside them: one per nonzero rank block of the core),
@@ -364,6 +364,12 @@ typedef struct {
   long launches[6];
   double ms[6];
   double flops[6];
+  /* the same operators' other two stages: the left-interface product t1 = PhiL x and the
+   * right-interface product with PhiR (summed event time and algorithmic flops) */
+  double s1_ms[6];
+  double s1_flops[6];
+  double s3_ms[6];
+  double s3_flops[6];
 } iga_profile;
 int iga_profile_start(iga_ctx* ctx);
 int iga_profile_stop(iga_ctx* ctx, iga_profile* out);

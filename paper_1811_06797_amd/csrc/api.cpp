@@ -728,10 +728,18 @@ int iga_profile_stop(iga_ctx* ctx, iga_profile* out) {
     for (const auto& p : ctx->prof) {
       float ms = 0.0f;
       IGA_HIP(hipEventElapsedTime(&ms, p.a, p.b));
-      r.launches[p.op] += p.launches;
-      r.stages[p.op] += 1;
-      r.ms[p.op] += ms;
-      r.flops[p.op] += p.flops;
+      if (p.stage == 1) {
+        r.s1_ms[p.op] += ms;
+        r.s1_flops[p.op] += p.flops;
+      } else if (p.stage == 3) {
+        r.s3_ms[p.op] += ms;
+        r.s3_flops[p.op] += p.flops;
+      } else {
+        r.launches[p.op] += p.launches;
+        r.stages[p.op] += 1;
+        r.ms[p.op] += ms;
+        r.flops[p.op] += p.flops;
+      }
     }
     ctx->prof.clear();
     ctx->prof_next = 0;

@@ -138,22 +138,20 @@ void tt_svd3(iga_ctx* ctx, const double* F, const int nt[3], double delta, int r
 }
 
 void setup_blocks(iga_ctx* ctx, OpCore& c, const std::vector<RankBlock>& blocks) {
-  c.blocks = blocks;
-  std::vector<int> lo1(c.R1, 0), hi1(c.R1, 0), lo0(c.R0, 0), hi0(c.R0, 0);
+  (void)ctx;
+  // the banded stage writes each output rank of a block once, in either orientation of the
+  // core (the right interface update swaps the rank roles): the blocks must partition both the
+  // left and the right ranks
+  std::vector<int> cov1(c.R1, 0), cov0(c.R0, 0);
   for (const auto& b : blocks) {
-    for (int g = b.b0; g < b.b0 + b.nb; ++g) { lo1[g] = b.a0; hi1[g] = b.a0 + b.na; }
-    for (int g = b.a0; g < b.a0 + b.na; ++g) { lo0[g] = b.b0; hi0[g] = b.b0 + b.nb; }
+    require(b.a0 >= 0 && b.na >= 1 && b.a0 + b.na <= c.R0 && b.b0 >= 0 && b.nb >= 1 && b.b0 + b.nb <= c.R1,
+            IGA_EINVAL, "operator core: rank block out of range");
+    for (int g = b.b0; g < b.b0 + b.nb; ++g) ++cov1[g];
+    for (int g = b.a0; g < b.a0 + b.na; ++g) ++cov0[g];
   }
-  c.lo_of_R1.reset(ctx, std::max(c.R1, 1));
-  c.hi_of_R1.reset(ctx, std::max(c.R1, 1));
-  c.lo_of_R0.reset(ctx, std::max(c.R0, 1));
-  c.hi_of_R0.reset(ctx, std::max(c.R0, 1));
-  hipStream_t st = ctx->stream;
-  IGA_HIP(hipMemcpyAsync(c.lo_of_R1.get(), lo1.data(), c.R1 * sizeof(int), hipMemcpyHostToDevice, st));
-  IGA_HIP(hipMemcpyAsync(c.hi_of_R1.get(), hi1.data(), c.R1 * sizeof(int), hipMemcpyHostToDevice, st));
-  IGA_HIP(hipMemcpyAsync(c.lo_of_R0.get(), lo0.data(), c.R0 * sizeof(int), hipMemcpyHostToDevice, st));
-  IGA_HIP(hipMemcpyAsync(c.hi_of_R0.get(), hi0.data(), c.R0 * sizeof(int), hipMemcpyHostToDevice, st));
-  IGA_HIP(hipStreamSynchronize(st));
+  for (int v : cov1) require(v == 1, IGA_EINVAL, "operator core: rank blocks must partition the right ranks");
+  for (int v : cov0) require(v == 1, IGA_EINVAL, "operator core: rank blocks must partition the left ranks");
+  c.blocks = blocks;
 }
 
 }  // namespace

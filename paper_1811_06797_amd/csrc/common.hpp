@@ -66,6 +66,7 @@ struct iga_ctx {
     int op;  // 0: M, 1: K (FP64); 2, 3: FP32; 4, 5: BF16 products
     int launches;
     double flops;
+    int stage = 2;  // 1: left interface, 2: banded operator core, 3: right interface
   };
   bool prof_on = false;
   std::vector<ProfRec> prof;
@@ -136,8 +137,6 @@ struct OpCore {
   int R0 = 0, R1 = 0, n = 0;
   std::vector<RankBlock> blocks;
   DBuf data;
-  // per right rank index: range of contributing left ranks, and the converse
-  IBuf lo_of_R1, hi_of_R1, lo_of_R0, hi_of_R0;
 };
 
 }  // namespace iga

@@ -120,57 +120,6 @@ void launch_gemm(hipStream_t s, const G& d) {
   IGA_HIP(hipGetLastError());
 }
 
-template <typename T>
-struct BandArgs {
-  int n, p, b, R0, R1, rev, m, c, G;
-  const T* A;
-  const int* lo;
-  const int* hi;
-  const T* in;
-  T* out;
-  T alpha, beta;
-};
-
-template <typename T>
-__global__ __launch_bounds__(256) void band_kernel(BandArgs<T> a) {
-  const long total = (long)a.G * a.m * a.n * a.c;
-  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total;
-       idx += (long)gridDim.x * blockDim.x) {
-    long t = idx;
-    const int cc = t % a.c; t /= a.c;
-    const int i = t % a.n; t /= a.n;
-    const int mm = t % a.m;
-    const int g = t / a.m;
-    const int d0 = a.lo[g], d1 = a.hi[g];
-    T acc = T(0);
-    const int olo = max(0, a.p - i), ohi = min(a.b, a.n - i + a.p);
-    for (int d = d0; d < d1; ++d) {
-      const T* inrow = a.in + (((long)d * a.m + mm) * a.n) * a.c + cc;
-      for (int o = olo; o < ohi; ++o) {
-        const int j = i + o - a.p;
-        const T coef = a.rev ? a.A[(((long)g * a.n + i) * a.b + o) * a.R1 + d]
-                             : a.A[(((long)d * a.n + i) * a.b + o) * a.R1 + g];
-        acc = fma(coef, inrow[(long)j * a.c], acc);
-      }
-    }
-    T v = a.alpha * acc;
-    if (a.beta != T(0)) v += a.beta * a.out[idx];
-    a.out[idx] = v;
-  }
-}
-
-template <typename T, typename D>
-void launch_band(hipStream_t s, const D& d, T alpha, T beta) {
-  const int G = d.rev ? d.R0 : d.R1;
-  BandArgs<T> a{d.n, d.p, 2 * d.p + 1, d.R0, d.R1, d.rev ? 1 : 0, d.m, d.c, G,
-                d.A, d.lo, d.hi, d.in, d.out, alpha, beta};
-  const long total = (long)G * d.m * d.n * d.c;
-  if (total <= 0) return;
-  const long blocks = std::min<long>((total + 255) / 256, 1L << 20);
-  band_kernel<T><<<(unsigned)blocks, 256, 0, s>>>(a);
-  IGA_HIP(hipGetLastError());
-}
-
 __global__ void axpby_kernel(long n, double a, const double* x, double b, double* y) {
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
     y[i] = (b == 0.0) ? a * x[i] : a * x[i] + b * y[i];
@@ -737,7 +686,6 @@ void gemm(hipStream_t s, const Gemm& g, double* work, size_t work_len) {
   }
   gemm2(s, d, work, work_len);
 }
-void gemm_f32(hipStream_t s, const GemmF& g) { launch_gemm<float>(s, g); }
 
 void gemm_rm(hipStream_t s, int M, int N, int K, const double* A, long lda, bool tA,
              const double* B, long ldb, bool tB, double* C, long ldc, double alpha, double beta,
@@ -750,9 +698,6 @@ void gemm_rm(hipStream_t s, int M, int N, int K, const double* A, long lda, bool
   g.alpha = alpha; g.beta = beta;
   gemm(s, g, work, work_len);
 }
-
-void band(hipStream_t s, const Band& b) { launch_band<double>(s, b, b.alpha, b.beta); }
-void band_f32(hipStream_t s, const BandF& b) { launch_band<float>(s, b, 1.0f, 0.0f); }
 
 void axpby(hipStream_t s, long n, double a, const double* x, double b, double* y) {
   if (n <= 0) return;

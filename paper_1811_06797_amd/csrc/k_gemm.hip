@@ -76,7 +76,25 @@ struct G2Args {
   double alpha, beta;
   int ksplit, kchunk;   // split-K: chunk length (multiple of the K tile); ksplit == 1: direct store
   double* work;         // [ksplit][nbatch][M][N] partial products when ksplit > 1
+  int batch_inner;      // tile order within an XCD's range: batch index fastest (see tile_coords)
 };
+
+// (n-tile, m-tile, batch) of the XCD-ordered tile number: n-tile fastest by default; batch
+// fastest when the batch index is the row of a banded product, so that the rows that share
+// band slices of the B operand run together on one XCD while those slices are in its L2.
+__device__ __forceinline__ void tile_coords(int tile, int gx, int gy, int gz, int batch_inner, int& bx, int& by,
+                                            int& bz) {
+  if (batch_inner) {
+    bz = tile % gz;
+    const int r = tile / gz;
+    bx = r % gx;
+    by = r / gx;
+  } else {
+    bx = tile % gx;
+    by = (tile / gx) % gy;
+    bz = tile / (gx * gy);
+  }
+}
 
 __device__ __forceinline__ long off2(int idx, int inner, long s_outer, long s_inner) {
   const int o = idx / inner;
@@ -302,7 +320,9 @@ __global__ __launch_bounds__(NTHR) void gemm2_kernel(G2Args g) {
   const int lin = (blockIdx.z * gy + blockIdx.y) * gx + blockIdx.x;
   const int xcd = lin % 8, q = lin / 8, base = total / 8, rem = total % 8;
   const int tile = (xcd < rem ? xcd * (base + 1) : rem * (base + 1) + (xcd - rem) * base) + q;
-  gemm2_tile<WM, WN, WAVES_M, WAVES_N, BK, NBUF, PF, K1>(g, tile % gx, (tile / gx) % gy, tile / (gx * gy), L);
+  int bx, by, bz;
+  tile_coords(tile, gx, gy, gridDim.z, g.batch_inner, bx, by, bz);
+  gemm2_tile<WM, WN, WAVES_M, WAVES_N, BK, NBUF, PF, K1>(g, bx, by, bz, L);
 }
 
 // ---- Wide tile with LDS-direct operand loads ----
@@ -328,7 +348,8 @@ __global__ __launch_bounds__(NTHR) void gemm2_dma_kernel(G2Args g) {
   const int lin = (blockIdx.z * gy + blockIdx.y) * gx + blockIdx.x;
   const int xcd = lin % 8, q = lin / 8, base = total / 8, rem = total % 8;
   const int tile = (xcd < rem ? xcd * (base + 1) : rem * (base + 1) + (xcd - rem) * base) + q;
-  const int bx = tile % gx, by = (tile / gx) % gy, bz = tile / (gx * gy);
+  int bx, by, bz;
+  tile_coords(tile, gx, gy, gridDim.z, g.batch_inner, bx, by, bz);
   const int split = bz / g.nbatch, bb = bz - split * g.nbatch;
   const int b1 = bb / g.nb2, b2 = bb - b1 * g.nb2;
   const double* A = g.A + b1 * g.sAb1 + b2 * g.sAb2;
@@ -540,7 +561,8 @@ static G2Args make_args(const Gemm2& d) {
   require(nb <= 65535, IGA_EINVAL, "gemm2: batch too large");
   return G2Args{d.M, d.N, std::max(d.K, 0), d.M2, d.N2, d.K2, d.A, d.sAm1, d.sAm2, d.sAk1, d.sAk2, d.B, d.sBk1,
                 d.sBk2, d.sBn1, d.sBn2, d.C, d.sCm1, d.sCm2, d.sCn1, d.sCn2, d.nb2, (int)nb, d.sAb1, d.sAb2,
-                d.sBb1, d.sBb2, d.sCb1, d.sCb2, d.alpha, d.beta, 1, std::max(d.K, 0), nullptr};
+                d.sBb1, d.sBb2, d.sCb1, d.sCb2, d.alpha, d.beta, 1, std::max(d.K, 0), nullptr,
+                d.batch_inner ? 1 : 0};
 }
 
 // Output tile of each variant: 0: 64 x 64, 1: 32 x 128, 2: 16 x 256, 3: 128 x 32, 4: 64 x (32 WIDE_WN),
@@ -625,9 +647,17 @@ void gemm2(hipStream_t s, const Gemm2& d, double* work, size_t work_len) {
   const long tiles = (long)((d.M + BM - 1) / BM) * ((d.N + BN - 1) / BN) * nb;
   // split K when the tiles cannot fill the chip (about four workgroups per CU) and the
   // contraction is long
+  // long contraction (K >= 4096) whose tiles give fewer than ~16 workgroups per CU: split
+  // into about 2048 workgroups and chunks of at most 8192, so that no workgroup runs one long
+  // serial K loop while the chip idles
   constexpr int KALIGN = 48;  // split-K chunks are whole K tiles of every variant (12 or 16 deep)
-  if (work && tiles < 512 && d.K >= 4 * KALIGN) {
-    int ks = (int)std::min<long>((1024 + tiles - 1) / tiles, d.K / (2 * KALIGN));
+  int want = 1;
+  if (tiles < 512 && d.K >= 4 * KALIGN)
+    want = (int)((1024 + tiles - 1) / tiles);
+  else if (tiles < 4096 && d.K >= 4096)
+    want = (int)std::max<long>((2048 + tiles - 1) / tiles, (d.K + 8191) / 8192);
+  if (work && want > 1) {
+    int ks = (int)std::min<long>(want, d.K / (2 * KALIGN));
     while (ks > 1 && (size_t)ks * nb * d.M * d.N > work_len) --ks;
     if (ks > 1) {
       a.ksplit = ks;

@@ -48,7 +48,22 @@ struct G2FArgs {
   float alpha, beta;
   int ksplit, kchunk;
   float* work;
+  int batch_inner;  // tile order within an XCD's range: batch fastest (band rows; see gemm2)
 };
+
+__device__ __forceinline__ void tile_coords_f(int tile, int gx, int gy, int gz, int batch_inner, int& bx, int& by,
+                                              int& bz) {
+  if (batch_inner) {
+    bz = tile % gz;
+    const int r = tile / gz;
+    bx = r % gx;
+    by = r / gx;
+  } else {
+    bx = tile % gx;
+    by = (tile / gx) % gy;
+    bz = tile / (gx * gy);
+  }
+}
 
 __device__ __forceinline__ long off2f(int idx, int inner, long s_outer, long s_inner) {
   const int o = idx / inner;
@@ -256,7 +271,9 @@ __global__ __launch_bounds__(NT) void gemm2f_kernel(G2FArgs g) {
   const int lin = (blockIdx.z * gy + blockIdx.y) * gx + blockIdx.x;
   const int xcd = lin % 8, q8 = lin / 8, base = total / 8, rem = total % 8;
   const int tile = (xcd < rem ? xcd * (base + 1) : rem * (base + 1) + (xcd - rem) * base) + q8;
-  gemm2f_tile<WM, WN, WAVES_M, WAVES_N, BF>(g, tile % gx, (tile / gx) % gy, tile / (gx * gy), L);
+  int bx, by, bz;
+  tile_coords_f(tile, gx, gy, gridDim.z, g.batch_inner, bx, by, bz);
+  gemm2f_tile<WM, WN, WAVES_M, WAVES_N, BF>(g, bx, by, bz, L);
 }
 
 // FP32 wide tile (64 x 128, four waves of 32 x 64, K tile 16) with LDS-direct operand loads:
@@ -279,7 +296,8 @@ __global__ __launch_bounds__(NT) void gemm2f_dma_kernel(G2FArgs g) {
   const int lin = (blockIdx.z * gy + blockIdx.y) * gx + blockIdx.x;
   const int xcd = lin % 8, q8 = lin / 8, base = total / 8, rem = total % 8;
   const int tile = (xcd < rem ? xcd * (base + 1) : rem * (base + 1) + (xcd - rem) * base) + q8;
-  const int bx = tile % gx, by = (tile / gx) % gy, bz = tile / (gx * gy);
+  int bx, by, bz;
+  tile_coords_f(tile, gx, gy, gridDim.z, g.batch_inner, bx, by, bz);
   const int split = bz / g.nbatch, bb = bz - split * g.nbatch;
   const int b1 = bb / g.nb2, b2 = bb - b1 * g.nb2;
   const float* A = g.A + b1 * g.sAb1 + b2 * g.sAb2;
@@ -435,7 +453,8 @@ __global__ __launch_bounds__(NT) void gemm2b_dma_kernel(G2FArgs g) {
   const int lin = (blockIdx.z * gy + blockIdx.y) * gx + blockIdx.x;
   const int xcd = lin % 8, q8 = lin / 8, base = total / 8, rem = total % 8;
   const int tile = (xcd < rem ? xcd * (base + 1) : rem * (base + 1) + (xcd - rem) * base) + q8;
-  const int bx = tile % gx, by = (tile / gx) % gy, bz = tile / (gx * gy);
+  int bx, by, bz;
+  tile_coords_f(tile, gx, gy, gridDim.z, g.batch_inner, bx, by, bz);
   const int split = bz / g.nbatch, bb = bz - split * g.nbatch;
   const int b1 = bb / g.nb2, b2 = bb - b1 * g.nb2;
   const float* A = g.A + b1 * g.sAb1 + b2 * g.sAb2;
@@ -650,7 +669,8 @@ static G2FArgs make_args_f(const Gemm2F& d) {
   require(nb <= 65535, IGA_EINVAL, "gemm2_f32: batch too large");
   return G2FArgs{d.M, d.N, std::max(d.K, 0), d.M2, d.N2, d.K2, d.A, d.sAm1, d.sAm2, d.sAk1, d.sAk2, d.B, d.sBk1,
                  d.sBk2, d.sBn1, d.sBn2, d.C, d.sCm1, d.sCm2, d.sCn1, d.sCn2, d.nb2, (int)nb, d.sAb1, d.sAb2,
-                 d.sBb1, d.sBb2, d.sCb1, d.sCb2, d.alpha, d.beta, 1, std::max(d.K, 0), nullptr};
+                 d.sBb1, d.sBb2, d.sCb1, d.sCb2, d.alpha, d.beta, 1, std::max(d.K, 0), nullptr,
+                 d.batch_inner ? 1 : 0};
 }
 
 static void variant_tile_f(int v, int& BM, int& BN) {
@@ -721,9 +741,16 @@ static void gemm2_fstore(hipStream_t s, const Gemm2F& d, float* work, size_t wor
   int BM, BN;
   variant_tile_f(variant, BM, BN);
   const long tiles = (long)((d.M + BM - 1) / BM) * ((d.N + BN - 1) / BN) * nb;
-  // split K when the tiles cannot fill the chip (about four workgroups per CU)
-  if (work && tiles < 512 && d.K >= 4 * 32) {
-    int ks = (int)std::min<long>((1024 + tiles - 1) / tiles, d.K / 64);
+  // split K when the tiles cannot fill the chip (about four workgroups per CU), or when a long
+  // contraction (K >= 4096) has fewer than ~16 workgroups per CU (about 2048 workgroups,
+  // chunks of at most 8192)
+  int want = 1;
+  if (tiles < 512 && d.K >= 4 * 32)
+    want = (int)((1024 + tiles - 1) / tiles);
+  else if (tiles < 4096 && d.K >= 4096)
+    want = (int)std::max<long>((2048 + tiles - 1) / tiles, (d.K + 8191) / 8192);
+  if (work && want > 1) {
+    int ks = (int)std::min<long>(want, d.K / 64);
     while (ks > 1 && (size_t)ks * nb * d.M * d.N > work_len) --ks;
     if (ks > 1) {
       const int bk = bf16 ? BKH : BKF;

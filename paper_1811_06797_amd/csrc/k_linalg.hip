@@ -360,9 +360,13 @@ __global__ __launch_bounds__(ORT) void osbj_rot_kernel(const double* Gsum, doubl
         const double app = G[p][p], aqq = G[q][q], apq = G[p][q];
         double np = app, nq = aqq;
         const bool negligible = app <= floor_col && aqq <= floor_col;
-        if (!negligible && fabs(apq) > tol * sqrt(fabs(app * aqq))) {
-          const double tau = (aqq - app) / (2.0 * apq);
-          const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+        // |apq| > tol sqrt(|app aqq|), squared (no square root on the path of every rotation)
+        if (!negligible && apq * apq > tol * tol * fabs(app * aqq)) {
+          // t = tan(theta) = sign(tau) / (|tau| + sqrt(1 + tau^2)) with tau = dd / ee, written
+          // as sign(tau) |ee| / (|dd| + sqrt(dd^2 + ee^2)): one division and one root fewer
+          const double dd = aqq - app, ee = 2.0 * apq;
+          const double sg = (dd == 0.0 || (dd > 0.0) == (ee > 0.0)) ? 1.0 : -1.0;
+          const double t = sg * fabs(ee) / (fabs(dd) + sqrt(dd * dd + ee * ee));
           c = 1.0 / sqrt(1.0 + t * t);
           sv = t * c;
           np = app - t * apq;

@@ -19,6 +19,9 @@ struct Gemm {
   int nb1 = 1, nb2 = 1;
   long sAb1 = 0, sAb2 = 0, sBb1 = 0, sBb2 = 0, sCb1 = 0, sCb2 = 0;
   double alpha = 1.0, beta = 0.0;
+  // tiles of consecutive batch entries run together (set when the batch index is the row of a
+  // banded product whose B operand windows overlap from row to row)
+  bool batch_inner = false;
 };
 // work (nullable, work_len doubles): split-K partials, so that a product with few output tiles
 // and a long contraction spreads over the chip
@@ -39,6 +42,9 @@ struct Gemm2 {
   int nb1 = 1, nb2 = 1;
   long sAb1 = 0, sAb2 = 0, sBb1 = 0, sBb2 = 0, sCb1 = 0, sCb2 = 0;
   double alpha = 1.0, beta = 0.0;
+  // tiles of consecutive batch entries run together (set when the batch index is the row of a
+  // banded product whose B operand windows overlap from row to row)
+  bool batch_inner = false;
 };
 void gemm2(hipStream_t s, const Gemm2& g);
 // Same, with a workspace of work_len doubles that lets short-output, long-K products be split
@@ -70,6 +76,7 @@ struct Gemm2F {
   int nb1 = 1, nb2 = 1;
   long sAb1 = 0, sAb2 = 0, sBb1 = 0, sBb2 = 0, sCb1 = 0, sCb2 = 0;
   float alpha = 1.0f, beta = 0.0f;
+  bool batch_inner = false;  // as in Gemm2
 };
 void gemm2_f32(hipStream_t s, const Gemm2F& g, float* work, size_t work_len);
 // same products with the operands rounded to bfloat16 and BF16 matrix-core products (FP32 accumulation)
@@ -85,48 +92,6 @@ void gemm_rm(hipStream_t s, int M, int N, int K, const double* A, long lda, bool
              const double* B, long ldb, bool tB, double* C, long ldc, double alpha = 1.0,
              double beta = 0.0, double* work = nullptr, size_t work_len = 0);
 
-// Banded rank contraction of a TT-matrix core with a 4-way tensor:
-//   out[g][m][i][c] = alpha * sum_{d in [lo[g],hi[g])} sum_o A(d,i,o,g) in[d][m][i+o-p][c] + beta*out
-// A banded [R0][n][2p+1][R1]; rev=false: d runs over R0 and g over R1; rev=true: the converse.
-struct Band {
-  int n = 0, p = 0, R0 = 0, R1 = 0;
-  bool rev = false;
-  int m = 0, c = 0;
-  const double* A = nullptr;
-  const int* lo = nullptr;
-  const int* hi = nullptr;
-  const double* in = nullptr;
-  double* out = nullptr;
-  double alpha = 1.0, beta = 0.0;
-};
-void band(hipStream_t s, const Band& b);
-
-// Same contraction in FP32 (mixed-precision form).
-struct BandF {
-  int n = 0, p = 0, R0 = 0, R1 = 0;
-  bool rev = false;
-  int m = 0, c = 0;
-  const float* A = nullptr;
-  const int* lo = nullptr;
-  const int* hi = nullptr;
-  const float* in = nullptr;
-  float* out = nullptr;
-};
-void band_f32(hipStream_t s, const BandF& b);
-
-struct GemmF {
-  int M = 0, N = 0, K = 0, Kout = 1;
-  const float* A = nullptr;
-  long sAm = 0, sAk = 0, sAko = 0;
-  const float* B = nullptr;
-  long sBk = 0, sBn = 0, sBko = 0;
-  float* C = nullptr;
-  long sCm = 0, sCn = 0;
-  int nb1 = 1, nb2 = 1;
-  long sAb1 = 0, sAb2 = 0, sBb1 = 0, sBb2 = 0, sCb1 = 0, sCb2 = 0;
-  float alpha = 1.0f, beta = 0.0f;
-};
-void gemm_f32(hipStream_t s, const GemmF& g);
 
 // y = a x + b y (n doubles)
 void axpby(hipStream_t s, long n, double a, const double* x, double b, double* y);

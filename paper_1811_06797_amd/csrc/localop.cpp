@@ -119,6 +119,16 @@ static BandCore<T> band_core(const OpView& A, const T* core, const T* relaid, co
   return c;
 }
 
+// Tile order of a banded-stage product (batch = row i). Neighbouring rows share 2p of their
+// 2p + 1 slices of t1, the B operand, while each row has its own slice of the core, the A
+// operand. Taking rows fastest keeps the shared t1 slices in L2 but re-reads the row's core
+// slice for every column tile; that pays only while the core slice is small (measured at
+// R = 80, b = 7, 358 KB per row: rows fastest doubled the fetched bytes, no faster).
+template <class T>
+static bool band_rows_inner(int b, int R0, int R1) {
+  return (long)b * R0 * R1 * (long)sizeof(T) <= 64 * 1024;
+}
+
 // The banded stage on a padded input: out[i][g][c] = sum_{o, d} A(d, i, o, g) in[i + o][d][c] for
 // c < S1, with in[j][d][c] at j SJ + d S1 + c (p zero slices at both ends of j) and out[i][g][c]
 // at (i Rout + g) S1 + c.
@@ -149,6 +159,7 @@ static void band_stage(hipStream_t st, const BandCore<T>& A, const T* t1, long S
     g2.B = t1; g2.sBk2 = S1; g2.sBn2 = 1;
     g2.C = t2; g2.sCm2 = S1; g2.sCn2 = 1;
     g2.nb1 = n; g2.sAb1 = (long)b * R0 * R1; g2.sBb1 = SJ; g2.sCb1 = (long)R1 * S1;
+    g2.batch_inner = band_rows_inner<T>(b, R0, R1);
     Prec<T>::gemm(st, g2, nullptr, 0, bf16);
   } else {
     // one product per nonzero rank block, K = (o, d) two-level; the blocks partition the
@@ -162,6 +173,7 @@ static void band_stage(hipStream_t st, const BandCore<T>& A, const T* t1, long S
       g2.B = t1 + rb.a0 * S1; g2.sBk1 = SJ; g2.sBk2 = S1; g2.sBn2 = 1;
       g2.C = t2 + rb.b0 * S1; g2.sCm2 = S1; g2.sCn2 = 1;
       g2.nb1 = n; g2.sAb1 = A.s_row; g2.sBb1 = SJ; g2.sCb1 = (long)R1 * S1;
+      g2.batch_inner = band_rows_inner<T>(b, rb.na, rb.nb);
       Prec<T>::gemm(st, g2, nullptr, 0, bf16);
     }
   }
@@ -194,10 +206,22 @@ static void op_stage12(iga_ctx* ctx, const BandCore<T>& A, const T* PhiL, int r0
   g1.B = x; g1.sBk2 = (long)n * r1; g1.sBn1 = r1; g1.sBn2 = 1;
   g1.C = t1 + p * SJ; g1.M2 = r0o; g1.sCm1 = S1; g1.sCm2 = r1; g1.sCn1 = SJ; g1.sCn2 = 1;
   g1.nb1 = ncol; g1.sBb1 = xcs; g1.sCb1 = S2;
-  Prec<T>::gemm(st, g1, nullptr, 0, bf16);
-  // stage 2: per rank block, batched over rows i
-  hipEvent_t pa = nullptr, pb = nullptr;
   prof = prof && ctx->prof_on;
+  hipEvent_t pa = nullptr, pb = nullptr;
+  if (prof) {
+    pa = prof_event(ctx);
+    pb = prof_event(ctx);
+    IGA_HIP(hipEventRecord(pa, st));
+  }
+  Prec<T>::gemm(st, g1, nullptr, 0, bf16);
+  if (prof) {
+    IGA_HIP(hipEventRecord(pb, st));
+    iga_ctx::ProfRec rec{pa, pb, Prec<T>::prof_base + (bf16 ? 2 : 0) + op_id, 1,
+                         2.0 * r0o * r0 * (double)R0 * n * r1 * ncol};
+    rec.stage = 1;
+    ctx->prof.push_back(rec);
+  }
+  // stage 2: per rank block, batched over rows i
   if (prof) {
     pa = prof_event(ctx);
     pb = prof_event(ctx);
@@ -231,7 +255,21 @@ static void op_apply_raw(iga_ctx* ctx, const OpView& A, const T* core, const T* 
   g3.B = PhiR; g3.sBk1 = (long)r1o * r1; g3.sBk2 = 1; g3.sBn2 = r1;
   g3.C = z; g3.sCm1 = (long)n * r1o; g3.sCm2 = r1o; g3.sCn2 = 1;
   g3.nb1 = ncol; g3.sAb1 = S2; g3.sCb1 = zcs;
+  prof = prof && ctx->prof_on;
+  hipEvent_t pa = nullptr, pb = nullptr;
+  if (prof) {
+    pa = prof_event(ctx);
+    pb = prof_event(ctx);
+    IGA_HIP(hipEventRecord(pa, ctx->stream));
+  }
   Prec<T>::gemm(ctx->stream, g3, wk, wlen, bf16);
+  if (prof) {
+    IGA_HIP(hipEventRecord(pb, ctx->stream));
+    iga_ctx::ProfRec rec{pa, pb, Prec<T>::prof_base + (bf16 ? 2 : 0) + op_id, 1,
+                         2.0 * r0o * n * (double)R1 * r1 * r1o * ncol};
+    rec.stage = 3;
+    ctx->prof.push_back(rec);
+  }
 }
 
 // op_apply_raw on intermediates from the context pool (grown on demand); t1's zero end
@@ -486,8 +524,6 @@ void local_matvec_f32(iga_ctx* ctx, const LocalOp& L, const float* x, float* y, 
 
 namespace {
 struct RawCache {
-  IBuf loM1, hiM1, loM0, hiM0, loK1, hiK1, loK0, hiK0;
-  int RM0 = -1, RM1 = -1, RK0 = -1, RK1 = -1;
   LocalWork w;
   FBuf fPhi[4], fM, fK, fx, fy;
   DBuf rM, rK;  // cores re-laid for the banded stage
@@ -498,15 +534,6 @@ RawCache& raw_cache(iga_ctx* ctx) {
   auto& p = g_raw[ctx];
   if (!p) p.reset(new RawCache());
   return *p;
-}
-void dense_ranges(iga_ctx* ctx, int R0, int R1, IBuf& lo1, IBuf& hi1, IBuf& lo0, IBuf& hi0) {
-  std::vector<int> z1(R1, 0), h1(R1, R0), z0(R0, 0), h0(R0, R1);
-  lo1.reset(ctx, R1); hi1.reset(ctx, R1); lo0.reset(ctx, R0); hi0.reset(ctx, R0);
-  IGA_HIP(hipMemcpyAsync(lo1.get(), z1.data(), R1 * 4, hipMemcpyHostToDevice, ctx->stream));
-  IGA_HIP(hipMemcpyAsync(hi1.get(), h1.data(), R1 * 4, hipMemcpyHostToDevice, ctx->stream));
-  IGA_HIP(hipMemcpyAsync(lo0.get(), z0.data(), R0 * 4, hipMemcpyHostToDevice, ctx->stream));
-  IGA_HIP(hipMemcpyAsync(hi0.get(), h0.data(), R0 * 4, hipMemcpyHostToDevice, ctx->stream));
-  IGA_HIP(hipStreamSynchronize(ctx->stream));
 }
 }  // namespace
 
@@ -525,21 +552,11 @@ void local_matvec_impl(iga_ctx* ctx, int r0, int n, int r1, int p, int RM0, int 
                        const double* PhiR_K, const double* Mcore, const double* Kcore, double beta,
                        const double* x, double* y, int precision) {
   RawCache& C = raw_cache(ctx);
-  if (C.RM0 != RM0 || C.RM1 != RM1) {
-    dense_ranges(ctx, RM0, RM1, C.loM1, C.hiM1, C.loM0, C.hiM0);
-    C.RM0 = RM0; C.RM1 = RM1;
-  }
-  if (C.RK0 != RK0 || C.RK1 != RK1) {
-    dense_ranges(ctx, RK0, RK1, C.loK1, C.hiK1, C.loK0, C.hiK0);
-    C.RK0 = RK0; C.RK1 = RK1;
-  }
   LocalOp L;
   L.r0 = r0; L.n = n; L.r1 = r1;
   L.coef.m11 = beta;
   L.M.R0 = RM0; L.M.R1 = RM1; L.M.n = n; L.M.p = p; L.M.A = Mcore;
-  L.M.lo_R1 = C.loM1.get(); L.M.hi_R1 = C.hiM1.get(); L.M.lo_R0 = C.loM0.get(); L.M.hi_R0 = C.hiM0.get();
   L.K.R0 = RK0; L.K.R1 = RK1; L.K.n = n; L.K.p = p; L.K.A = Kcore;
-  L.K.lo_R1 = C.loK1.get(); L.K.hi_R1 = C.hiK1.get(); L.K.lo_R0 = C.loK0.get(); L.K.hi_R0 = C.hiK0.get();
   L.PhiL_M = PhiL_M; L.PhiR_M = PhiR_M; L.PhiL_K = PhiL_K; L.PhiR_K = PhiR_K;
   L.Mblocks = {RankBlock{0, RM0, 0, RM1}};
   L.Kblocks = {RankBlock{0, RK0, 0, RK1}};

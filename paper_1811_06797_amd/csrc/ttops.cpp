@@ -34,112 +34,10 @@ OpView view_of(const iga_ttop* op, int d) {
   const OpCore& c = op->core[d];
   v.R0 = c.R0; v.R1 = c.R1; v.n = c.n; v.p = op->p;
   v.A = c.data.get();
-  v.lo_R1 = c.lo_of_R1.get(); v.hi_R1 = c.hi_of_R1.get();
-  v.lo_R0 = c.lo_of_R0.get(); v.hi_R0 = c.hi_of_R0.get();
   long nz = 0;
   for (const auto& b : c.blocks) nz += (long)b.na * b.nb;
   v.flops_dense_factor = (c.R0 && c.R1) ? double(nz) / (double(c.R0) * c.R1) : 0.0;
   return v;
-}
-
-void local_stage12(iga_ctx* ctx, const OpView& A, const double* PhiL, int ra_out, int ra_in,
-                   int rb_in, int ncol, const double* x, long xcs, double* t2) {
-  Scratch& S = scratch_of(ctx);
-  const int n = A.n;
-  const long colsz = (long)ra_out * n * rb_in;
-  S.t1.ensure(ctx, (size_t)A.R0 * ncol * colsz);
-  // stage 1: t1[al][c][a'][j][b] = sum_a PhiL[al][a'][a] x[c][a][j][b]
-  k::Gemm g;
-  g.M = ra_out; g.N = n * rb_in; g.K = ra_in;
-  g.A = PhiL; g.sAm = ra_in; g.sAk = 1;
-  g.B = x; g.sBk = (long)n * rb_in; g.sBn = 1;
-  g.C = S.t1.get(); g.sCm = (long)n * rb_in; g.sCn = 1;
-  g.nb1 = A.R0; g.nb2 = ncol;
-  g.sAb1 = (long)ra_out * ra_in; g.sAb2 = 0;
-  g.sBb1 = 0; g.sBb2 = xcs;
-  g.sCb1 = ncol * colsz; g.sCb2 = colsz;
-  k::gemm(ctx->stream, g);
-  // stage 2: t2[be][c][a'][i][b] = sum_{al, o} A[al][i][o][be] t1[al][c][a'][i+o-p][b]
-  k::Band b;
-  b.n = n; b.p = A.p; b.R0 = A.R0; b.R1 = A.R1; b.rev = false;
-  b.m = ncol * ra_out; b.c = rb_in;
-  b.A = A.A; b.lo = A.lo_R1; b.hi = A.hi_R1;
-  b.in = S.t1.get(); b.out = t2;
-  k::band(ctx->stream, b);
-}
-
-void local_stage3(iga_ctx* ctx, const OpView& A, const double* t2, int ncol, int c, const double* PhiR,
-                  int ra_out, int rb_out, int rb_in, double* y, double alpha, double beta) {
-  const int n = A.n;
-  const long colsz = (long)ra_out * n * rb_in;
-  // y[a'][i][b'] = sum_{be, b} t2[be][c][a'][i][b] PhiR[be][b'][b]
-  k::Gemm g;
-  g.M = ra_out * n; g.N = rb_out; g.K = rb_in; g.Kout = A.R1;
-  g.A = t2 + c * colsz; g.sAm = rb_in; g.sAk = 1; g.sAko = ncol * colsz;
-  g.B = PhiR; g.sBk = 1; g.sBn = rb_in; g.sBko = (long)rb_out * rb_in;
-  g.C = y; g.sCm = rb_out; g.sCn = 1;
-  g.alpha = alpha; g.beta = beta;
-  k::gemm(ctx->stream, g);
-}
-
-void local_apply(iga_ctx* ctx, const OpView& A, const double* PhiL, const double* PhiR, int ra_out,
-                 int ra_in, int rb_out, int rb_in, int ncol, const double* x, long xcs, double* y,
-                 long ycs, double alpha, double beta) {
-  Scratch& S = scratch_of(ctx);
-  const long colsz = (long)ra_out * A.n * rb_in;
-  S.t2.ensure(ctx, (size_t)A.R1 * ncol * colsz);
-  local_stage12(ctx, A, PhiL, ra_out, ra_in, rb_in, ncol, x, xcs, S.t2.get());
-  for (int c = 0; c < ncol; ++c)
-    local_stage3(ctx, A, S.t2.get(), ncol, c, PhiR, ra_out, rb_out, rb_in, y + c * ycs, alpha, beta);
-}
-
-void interface_left(iga_ctx* ctx, const OpView& A, const double* Phi, const double* U,
-                    const double* V, int ru0, int ru1, int rv0, int rv1, double* out) {
-  Scratch& S = scratch_of(ctx);
-  const int n = A.n;
-  const long sz = (long)ru0 * n * rv1;
-  S.t2.ensure(ctx, (size_t)A.R1 * sz);
-  local_stage12(ctx, A, Phi, ru0, rv0, rv1, 1, V, 0, S.t2.get());
-  // out[be][b'][b] = sum_{(a' i)} U[(a' i)][b'] t2[be][(a' i)][b]
-  k::Gemm g;
-  g.M = ru1; g.N = rv1; g.K = ru0 * n;
-  g.A = U; g.sAm = 1; g.sAk = ru1;
-  g.B = S.t2.get(); g.sBk = rv1; g.sBn = 1;
-  g.C = out; g.sCm = rv1; g.sCn = 1;
-  g.nb1 = A.R1; g.sBb1 = sz; g.sCb1 = (long)ru1 * rv1;
-  k::gemm(ctx->stream, g);
-}
-
-void interface_right(iga_ctx* ctx, const OpView& A, const double* Phi, const double* U,
-                     const double* V, int ru0, int ru1, int rv0, int rv1, double* out) {
-  Scratch& S = scratch_of(ctx);
-  const int n = A.n;
-  const long sz = (long)rv0 * n * ru1;
-  S.t1.ensure(ctx, (size_t)A.R1 * sz);
-  S.t2.ensure(ctx, (size_t)A.R0 * sz);
-  // s1[be][(a j)][b'] = sum_b V[(a j)][b] Phi[be][b'][b]
-  k::Gemm g;
-  g.M = rv0 * n; g.N = ru1; g.K = rv1;
-  g.A = V; g.sAm = rv1; g.sAk = 1;
-  g.B = Phi; g.sBk = 1; g.sBn = rv1;
-  g.C = S.t1.get(); g.sCm = ru1; g.sCn = 1;
-  g.nb1 = A.R1; g.sBb1 = (long)ru1 * rv1; g.sCb1 = sz;
-  k::gemm(ctx->stream, g);
-  // s2[al][a][i][b'] = sum_{be, o} A[al][i][o][be] s1[be][a][i+o-p][b']
-  k::Band b;
-  b.n = n; b.p = A.p; b.R0 = A.R0; b.R1 = A.R1; b.rev = true;
-  b.m = rv0; b.c = ru1;
-  b.A = A.A; b.lo = A.lo_R0; b.hi = A.hi_R0;
-  b.in = S.t1.get(); b.out = S.t2.get();
-  k::band(ctx->stream, b);
-  // out[al][a'][a] = sum_{(i b')} U[a'][(i b')] s2[al][a][(i b')]
-  k::Gemm h;
-  h.M = ru0; h.N = rv0; h.K = n * ru1;
-  h.A = U; h.sAm = (long)n * ru1; h.sAk = 1;
-  h.B = S.t2.get(); h.sBk = 1; h.sBn = (long)n * ru1;
-  h.C = out; h.sCm = rv0; h.sCn = 1;
-  h.nb1 = A.R0; h.sBb1 = sz; h.sCb1 = (long)ru0 * rv0;
-  k::gemm(ctx->stream, h);
 }
 
 void core_product(iga_ctx* ctx, const OpView& A, const double* X, int r0, int r1, double* Y,
@@ -168,32 +66,6 @@ void btt_expand(iga_ctx* ctx, const iga_btt* x, double* out) {
     }
     tt_expand(ctx, x->n, x->r, c, out + l * N);
   }
-}
-
-void full_apply(iga_ctx* ctx, const iga_ttop* A, const double* x, double* y, double alpha, double beta) {
-  Scratch& S = scratch_of(ctx);
-  g_phase = "full_apply";
-  const int n0 = A->n[0], n1 = A->n[1], n2 = A->n[2];
-  const long N = (long)n0 * n1 * n2;
-  S.t1.ensure(ctx, (size_t)A->R[1] * N);
-  S.t2.ensure(ctx, (size_t)A->R[2] * N);
-  // T1[al][i1][j2 j3] = sum_j1 A0[0][i1][j1][al] x[j1][j2 j3]
-  OpView v0 = view_of(A, 0), v1 = view_of(A, 1), v2 = view_of(A, 2);
-  k::Band b;
-  b.n = n0; b.p = A->p; b.R0 = 1; b.R1 = A->R[1]; b.rev = false; b.m = 1; b.c = n1 * n2;
-  b.A = v0.A; b.lo = v0.lo_R1; b.hi = v0.hi_R1; b.in = x; b.out = S.t1.get();
-  k::band(ctx->stream, b);
-  // T2[be][i1][i2][j3] = sum_{al, j2} A1[al][i2][j2][be] T1[al][i1][j2][j3]
-  k::Band c;
-  c.n = n1; c.p = A->p; c.R0 = A->R[1]; c.R1 = A->R[2]; c.rev = false; c.m = n0; c.c = n2;
-  c.A = v1.A; c.lo = v1.lo_R1; c.hi = v1.hi_R1; c.in = S.t1.get(); c.out = S.t2.get();
-  k::band(ctx->stream, c);
-  // y[i1 i2][i3] = sum_{be, j3} A2[be][i3][j3][0] T2[be][i1 i2][j3]
-  k::Band e;
-  e.n = n2; e.p = A->p; e.R0 = A->R[2]; e.R1 = 1; e.rev = false; e.m = n0 * n1; e.c = 1;
-  e.A = v2.A; e.lo = v2.lo_R1; e.hi = v2.hi_R1; e.in = S.t2.get(); e.out = y;
-  e.alpha = alpha; e.beta = beta;
-  k::band(ctx->stream, e);
 }
 
 iga_btt* kkt_apply_impl(iga_ctx* ctx, const iga_kkt* kkt, const iga_btt* x) {

@@ -97,7 +97,8 @@ class LocalProblem(C.Structure):
 
 class Profile(C.Structure):
     _fields_ = [("stages", C.c_long * 6), ("launches", C.c_long * 6), ("ms", C.c_double * 6),
-                ("flops", C.c_double * 6)]
+                ("flops", C.c_double * 6), ("s1_ms", C.c_double * 6), ("s1_flops", C.c_double * 6),
+                ("s3_ms", C.c_double * 6), ("s3_flops", C.c_double * 6)]
 
     def as_dict(self):
         return {name: list(getattr(self, name)) for name, _ in self._fields_}
