@@ -415,6 +415,41 @@ def cpu_baseline(prob, budget_s=15.0, max_calls=400):
                       "os.cpu_count() = %s" % (calls, s["r"], s["RM"], s["RK"], s["n"], s["p"], dt, os.cpu_count())}
 
 
+def oracle_legs():
+    """The oracle timed on the host cores on two more bounded samples: the identity-cube
+    workload (n = 16, degree 2) end to end, full 3-D assembly plus its reduced PCG solve (its
+    sparse-LU KKT solve takes about a minute and is not timed), and the matrix-free KKT
+    residual at n = 128 on the perturbed cube, one 3 x 3 x 3 box of rows (the element-by-element
+    product the tests sample) after the weight interpolation it needs."""
+    import numpy as np
+    import synth
+    from oracle import assembly, kkt, tt
+    out = {}
+    geo, yc, c = synth.config("cube_n16")
+    yh = tt.tt_full(yc).ravel()
+    t0 = time.perf_counter()
+    Mo, Ko = assembly.assemble(geo, c["n"], c["degree"], mode="exact")
+    t1 = time.perf_counter()
+    y, u, lam, its = kkt.solve_reduced(Mo, Ko, c["beta"], yh)
+    t2 = time.perf_counter()
+    out["identity_cube_n16"] = {"assembly_s": t1 - t0, "reduced_solve_s": t2 - t1, "pcg_iterations": int(its),
+                                "residual": float(kkt.residual(Mo, Ko, c["beta"], yh, np.concatenate([y, u, lam])))}
+    geo, yc, c = synth.config("perturbed_cube_n128")
+    n, p = c["n"], c["degree"]
+    t0 = time.perf_counter()
+    W = assembly.interpolate_weights(geo, assembly.Space(n, p))
+    t1 = time.perf_counter()
+    rng = np.random.default_rng(0)
+    fields = [rng.standard_normal((n,) * 3) for _ in range(4)]
+    box = ((62, 65), (30, 33), (90, 93))
+    assembly.apply_box(geo, n, p, fields, box, mode="interp", Wint=W)
+    t2 = time.perf_counter()
+    out["perturbed_cube_n128_box_residual"] = {
+        "weights_s": t1 - t0, "box_s": t2 - t1, "rows_per_box": 27,
+        "full_residual_s_extrapolated": (t2 - t1) * n ** 3 / 27}
+    return out
+
+
 def stage_rates(prof, ops):
     """TF/s and summed ms of the three local-matvec stages (left interface, banded operator core,
     right interface) over the given operator indices of a library event profile."""
@@ -524,6 +559,14 @@ def main():
                  "solve_time_s": s2["solve_wall_s"], "status": s2["rc"], "valid": s2["valid"],
                  "kkt_residual": s2["residual"], "ranks": s2["ranks"], "half_sweeps": s2["half_sweeps"],
                  "local_matvec_gflops": s2["local_matvec_flops"] / s2["t_local_matvec"] / 1e9}
+    geo1, yc1, c1 = synth.config("cube_n16")
+    Y1 = iga.tt_create(ctx, yc1)
+    run_step(iga, ctx, torch, geo1, c1, Y1)
+    s1 = run_step(iga, ctx, torch, geo1, c1, Y1)
+    iga.tt_destroy(Y1)
+    cube16 = {"config": c1["name"] + ", beta %g, tol %g, FP64" % (c1["beta"], c1["tol"]),
+              "assembly_time_s": s1["assembly_s"], "solve_time_s": s1["solve_wall_s"], "status": s1["rc"],
+              "kkt_residual": s1["residual"], "ranks": s1["ranks"]}
     n256 = n256_leg(iga, ctx, torch)
     batching = batching_bench(iga, ctx, torch)
     timedep = time_dependent_bench(iga, ctx, torch, geo2, c2, Y2)
@@ -577,6 +620,7 @@ def main():
         "mixed_vs_fp64": mixed,
         "annulus_n256": n256,
         "annulus_n64": secondary,
+        "identity_cube_n16": cube16,
         "batching": batching,
         "time_dependent": timedep,
         "microbench_local_matvec": {k: micro[k] for k in ("shape", "ms", "gflops", "flops", "stages", "fp32", "bf16")},
@@ -596,6 +640,7 @@ def main():
     }
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(prob)
+        line["cpu_baseline"]["oracle_legs"] = oracle_legs()
     iga.tt_destroy(Y)
     iga.ctx_destroy(ctx)
     print(json.dumps(line), flush=True)

@@ -193,6 +193,10 @@ int iga_tt_create(iga_ctx* ctx, const int n[3], const int r[4], const double* co
 int iga_tt_wrap(iga_ctx* ctx, const int n[3], const int r[4], double* const dev_cores[3],
                 iga_tt** out);
 void iga_tt_destroy(iga_tt* t);
+/* Sizes n[3] and ranks r[4] of a TT (r[0] = r[3] = 1). */
+int iga_tt_info(const iga_tt* t, int n[3], int r[4]);
+/* Copy core d, [r_d][n_d][r_{d+1}] (r_d n_d r_{d+1} doubles), to host memory. Synchronises. */
+int iga_tt_get_core(iga_ctx* ctx, const iga_tt* t, int d, double* host_out);
 
 /* Block-TT from host cores (layout above), component index at core ell_core. */
 int iga_btt_create(iga_ctx* ctx, const int n[3], const int r[4], int ell_core,

@@ -271,6 +271,10 @@ class Amen {
   long long n_solves_ = 0, n_iters_ = 0, n_mv_ = 0, n_mv32_ = 0, n_refine_ = 0;
   double flops_ = 0, flops32_ = 0;
   double max_res_ = 0;
+  // factor on the tolerance part of the truncation target: 1 while the half-sweeps make
+  // progress, cut tenfold (down to 1e-3) after each half-sweep whose largest local residual
+  // did not fall below the previous one's
+  double trunc_scale_ = 1.0;
   double hist_res_[IGA_MAX_HISTORY] = {};
   int hist_r_[IGA_MAX_HISTORY][2] = {};
   long long hist_st_[IGA_MAX_HISTORY] = {};
@@ -822,8 +826,8 @@ double Amen::local_res_of(int d, const double* xk) {
 }
 
 // Residual-based truncation: the smallest k in [kmin, kmax] such that the rank-k
-// approximation of the solved core has local residual <= max(tol / 2, 1.5 r_full),
-// r_full the residual of the untruncated core (the residual decreases with k; kmax if no
+// approximation of the solved core has local residual <= max(s tol / 2, 1.5 min(r_full, tol)),
+// r_full the residual of the untruncated core, s = trunc_scale_ (the residual decreases with k; kmax if no
 // k passes). Each test costs a local matvec, so the search starts from a prediction: one
 // probe at the rank where the singular-value tail t(k) = (sum_{j >= k} s_j^2)^(1/2) drops
 // below target * t(0) fits r(k)^2 = r_full^2 + (a t(k))^2, the model's smallest passing
@@ -835,7 +839,10 @@ int Amen::residual_rank(int d, int kmin, int kmax, const std::vector<double>& si
   xk_.ensure(ctx_, N);
   const double full = local_res_of(d, X_[d].get());
   require(std::isfinite(full), IGA_ENUM, "amen_solve: non-finite local residual in the truncation");
-  const double target = std::max(0.5 * tol_, 1.5 * full);
+  // a local solve that stopped short of the tolerance (full > tol) grants no slack: the
+  // truncation must then reach 1.5 tol, which keeps the rank where the solve was incomplete
+  // instead of truncating to the solve's own (large) residual
+  const double target = std::max(0.5 * trunc_scale_ * tol_, 1.5 * std::min(full, tol_));
   std::vector<signed char> known((size_t)kmax + 1, -1);
   double probe_res = 0.0;
   auto test = [&](int kk, double* resid) {
@@ -1246,6 +1253,10 @@ int Amen::run(const iga_btt* x0, iga_btt** sol, iga_amen_stats* stats) {
       if (fwd && d < 2) move_right(d);
       if (!fwd && d > 0) move_left(d);
     }
+    // no progress over the previous half-sweep: the truncations gave back what the solves
+    // gained (a rank cut that the neighbouring core's system does not tolerate), so later
+    // truncations keep more of the spectrum
+    if (half > 0 && max_res_ > tol_ && !(max_res_ < last_max)) trunc_scale_ = std::max(0.1 * trunc_scale_, 1e-3);
     last_max = max_res_;
     if (half < IGA_MAX_HISTORY) {
       hist_res_[half] = max_res_;

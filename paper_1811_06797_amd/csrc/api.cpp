@@ -347,6 +347,26 @@ int iga_tt_create(iga_ctx* ctx, const int n[3], const int r[4], const double* co
   });
 }
 
+int iga_tt_info(const iga_tt* t, int n[3], int r[4]) {
+  return guarded([&] {
+    require(t && n && r, IGA_EINVAL, "tt_info: NULL argument");
+    for (int d = 0; d < 3; ++d) n[d] = t->n[d];
+    for (int d = 0; d < 4; ++d) r[d] = t->r[d];
+    return IGA_OK;
+  });
+}
+
+int iga_tt_get_core(iga_ctx* ctx, const iga_tt* t, int d, double* host_out) {
+  return guarded([&] {
+    require(ctx && t && host_out && d >= 0 && d < 3, IGA_EINVAL, "tt_get_core: bad argument");
+    use_device(ctx);
+    const size_t sz = (size_t)t->r[d] * t->n[d] * t->r[d + 1];
+    IGA_HIP(hipMemcpyAsync(host_out, t->core[d], sz * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    IGA_HIP(hipStreamSynchronize(ctx->stream));
+    return IGA_OK;
+  });
+}
+
 int iga_tt_from_full(iga_ctx* ctx, const int n[3], const double* full, double rel_tol, iga_tt** out) {
   return guarded([&] {
     require(ctx && n && full && out, IGA_EINVAL, "tt_from_full: NULL argument");

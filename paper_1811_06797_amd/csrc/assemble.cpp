@@ -95,7 +95,7 @@ void tt_svd3(iga_ctx* ctx, const double* F, const int nt[3], double delta, int r
   hipStream_t st = ctx->stream;
   const int m1 = nt[1] * nt[2];
   Svd s1;
-  svd(ctx, F, m1, nt[0], m1, /*trans=*/true, s1);
+  svd_product(ctx, F, m1, nt[0], m1, /*trans=*/true, s1);
   const int R1 = trunc_rank(s1.sigma, delta, rmax);
   out.r[1] = R1;
   out.core[0].reset(ctx, (size_t)nt[0] * R1);
@@ -106,7 +106,7 @@ void tt_svd3(iga_ctx* ctx, const double* F, const int nt[3], double delta, int r
   Svd s2;
   std::vector<int> id;
   if (m2 >= k2) {
-    svd(ctx, Y.get(), m2, k2, k2, false, s2);
+    svd_product(ctx, Y.get(), m2, k2, k2, false, s2);
     const int R2 = trunc_rank(s2.sigma, delta, rmax);
     out.r[2] = R2;
     std::vector<double> inv(R2), sg(R2);
@@ -127,7 +127,7 @@ void tt_svd3(iga_ctx* ctx, const double* F, const int nt[3], double delta, int r
     k::copy2d(st, R2, k2, T.get(), 1, R2, out.core[2].get(), k2);
     IGA_HIP(hipStreamSynchronize(st));
   } else {
-    svd(ctx, Y.get(), k2, m2, k2, true, s2);
+    svd_product(ctx, Y.get(), k2, m2, k2, true, s2);
     const int R2 = trunc_rank(s2.sigma, delta, rmax);
     out.r[2] = R2;
     out.core[1].reset(ctx, (size_t)m2 * R2);

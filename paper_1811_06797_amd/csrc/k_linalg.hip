@@ -473,6 +473,186 @@ __global__ __launch_bounds__(OST) void osbj_apply_kernel(double* B, int m, long 
   }
 }
 
+// Cholesky factor of a jb x jb diagonal block (jb <= CHB) of a symmetric matrix whose earlier
+// columns have already been eliminated: reads the lower triangle of G, writes the lower factor
+// to L and its inverse to Linv (CHB x CHB, row-major, zero above the diagonal). Columns are
+// eliminated in order; a pivot that is not positive (a semidefinite or indefinite block, or a
+// NaN) gives a zero column of L and of Linv and adds one to *bad.
+constexpr int CHB = 32;
+__global__ __launch_bounds__(256) void chol_block_kernel(const double* G, long ldg, int jb, double* L, long ldl,
+                                                         double* Linv, int* bad) {
+  __shared__ double S[CHB][CHB + 1];
+  __shared__ double X[CHB][CHB + 1];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < CHB * CHB; e += 256) {
+    const int i = e / CHB, j = e % CHB;
+    S[i][j] = (i < jb && j <= i) ? G[(long)i * ldg + j] : 0.0;
+    X[i][j] = 0.0;
+  }
+  __syncthreads();
+  for (int c = 0; c < jb; ++c) {
+    if (tid == 0) {
+      const double d = S[c][c];
+      const bool ok = d > 0.0;
+      S[c][c] = ok ? sqrt(d) : 0.0;
+      if (!ok) atomicAdd(bad, 1);
+    }
+    __syncthreads();
+    const double piv = S[c][c];
+    for (int r = c + 1 + tid; r < jb; r += 256) S[r][c] = piv > 0.0 ? S[r][c] / piv : 0.0;
+    __syncthreads();
+    const int w = jb - c - 1;
+    for (int e = tid; e < w * w; e += 256) {
+      const int r = c + 1 + e / w, q = c + 1 + e % w;
+      if (q <= r) S[r][q] -= S[r][c] * S[q][c];
+    }
+    __syncthreads();
+  }
+  // Linv: forward substitution L x = e_j, one column per thread
+  if (tid < jb) {
+    const int j = tid;
+    const double djj = S[j][j];
+    X[j][j] = djj > 0.0 ? 1.0 / djj : 0.0;
+    for (int r = j + 1; r < jb; ++r) {
+      double a = 0.0;
+      for (int t = j; t < r; ++t) a += S[r][t] * X[t][j];
+      X[r][j] = S[r][r] > 0.0 ? -a / S[r][r] : 0.0;
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < CHB * CHB; e += 256) {
+    const int i = e / CHB, j = e % CHB;
+    if (i < jb && j <= i) L[(long)i * ldl + j] = S[i][j];
+    Linv[e] = X[i][j];
+  }
+}
+
+// Cholesky factorisation with diagonal pivoting of a symmetric positive semidefinite k x k
+// matrix G (row-major, full storage, destroyed), by one workgroup: at step j the largest
+// remaining diagonal entry of the Schur complement (the first one on ties) is swapped to
+// position j, rows and columns alike, the column of the factor is formed and the whole
+// trailing block is updated. The pivot order is the greedy order of column-pivoted QR of any
+// A with A^T A = G. On return the lower triangle of G holds L with P^T G P = L L^T (zeros
+// above the diagonal), perm[j] the original index of pivot j; a pivot that is not positive
+// gives a zero column and adds one to *bad. The trailing updates read and write G in global
+// memory (L2-resident at the sizes this serves, k <= PCHOL_MAX).
+constexpr int PCHOL_MAX = 1024;
+__global__ __launch_bounds__(256) void pchol_kernel(double* G, int k, int* perm, int* bad) {
+  __shared__ double dg[PCHOL_MAX];
+  __shared__ int pm[PCHOL_MAX];
+  __shared__ double rv[256];
+  __shared__ int ri[256];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < k; i += 256) {
+    dg[i] = G[(long)i * k + i];
+    pm[i] = i;
+  }
+  __syncthreads();
+  for (int j = 0; j < k; ++j) {
+    // argmax of dg[j..k), the smallest index among equal values
+    double bv = -1.0;
+    int bi = j;
+    for (int i = j + tid; i < k; i += 256)
+      if (dg[i] > bv) { bv = dg[i]; bi = i; }
+    rv[tid] = bv;
+    ri[tid] = bi;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (tid < w) {
+        const double ov = rv[tid + w];
+        const int oi = ri[tid + w];
+        if (ov > rv[tid] || (ov == rv[tid] && oi < ri[tid])) { rv[tid] = ov; ri[tid] = oi; }
+      }
+      __syncthreads();
+    }
+    const int p = ri[0];
+    if (p != j) {
+      // swap rows j and p, then columns j and p
+      for (int t = tid; t < k; t += 256) {
+        const double a = G[(long)j * k + t], b = G[(long)p * k + t];
+        G[(long)j * k + t] = b;
+        G[(long)p * k + t] = a;
+      }
+      __syncthreads();
+      for (int t = tid; t < k; t += 256) {
+        const double a = G[(long)t * k + j], b = G[(long)t * k + p];
+        G[(long)t * k + j] = b;
+        G[(long)t * k + p] = a;
+      }
+      if (tid == 0) {
+        const double dv = dg[j]; dg[j] = dg[p]; dg[p] = dv;
+        const int pv = pm[j]; pm[j] = pm[p]; pm[p] = pv;
+      }
+      __syncthreads();
+    }
+    const double d = G[(long)j * k + j];
+    const bool ok = d > 0.0;
+    const double ljj = ok ? sqrt(d) : 0.0;
+    __syncthreads();
+    if (tid == 0) {
+      G[(long)j * k + j] = ljj;
+      if (!ok) atomicAdd(bad, 1);
+    }
+    for (int i = j + 1 + tid; i < k; i += 256) G[(long)i * k + j] = ok ? G[(long)i * k + j] / ljj : 0.0;
+    __syncthreads();
+    // trailing update of the full block (both triangles stay symmetric for later swaps)
+    const int w = k - j - 1;
+    for (long e = tid; e < (long)w * w; e += 256) {
+      const int i = j + 1 + (int)(e / w), t = j + 1 + (int)(e % w);
+      G[(long)i * k + t] -= G[(long)i * k + j] * G[(long)t * k + j];
+    }
+    __syncthreads();
+    for (int i = j + 1 + tid; i < k; i += 256) dg[i] = G[(long)i * k + i];
+    __syncthreads();
+  }
+  // zero the upper triangle
+  for (long e = tid; e < (long)k * k; e += 256) {
+    const int i = (int)(e / k), t = (int)(e % k);
+    if (t > i) G[e] = 0.0;
+  }
+  for (int i = tid; i < k; i += 256) perm[i] = pm[i];
+}
+
+// Inverses of the CHB x CHB diagonal blocks of a lower-triangular L (k x k, ldl): block b into
+// Linv[b] (CHB x CHB, row-major, zero above the diagonal), by forward substitution, one
+// column per thread; a zero diagonal entry gives a zero row and column.
+__global__ __launch_bounds__(64) void trinv_blocks_kernel(const double* L, long ldl, int k, double* Linv) {
+  __shared__ double S[CHB][CHB + 1];
+  __shared__ double X[CHB][CHB + 1];
+  const int b = blockIdx.x, j0 = b * CHB, jb = min(CHB, k - j0), tid = threadIdx.x;
+  for (int e = tid; e < CHB * CHB; e += 64) {
+    const int i = e / CHB, j = e % CHB;
+    S[i][j] = (i < jb && j <= i) ? L[(long)(j0 + i) * ldl + j0 + j] : 0.0;
+    X[i][j] = 0.0;
+  }
+  __syncthreads();
+  if (tid < jb) {
+    const int j = tid;
+    X[j][j] = S[j][j] > 0.0 ? 1.0 / S[j][j] : 0.0;
+    for (int r = j + 1; r < jb; ++r) {
+      double a = 0.0;
+      for (int t = j; t < r; ++t) a += S[r][t] * X[t][j];
+      X[r][j] = S[r][r] > 0.0 ? -a / S[r][r] : 0.0;
+    }
+  }
+  __syncthreads();
+  double* out = Linv + (long)b * CHB * CHB;
+  for (int e = tid; e < CHB * CHB; e += 64) out[e] = X[e / CHB][e % CHB];
+}
+
+// out[i][:] = in[idx[i]][:], i < m, k columns
+__global__ void gather_rows_kernel(int m, int k, const double* in, long ldi, const int* idx, double* out, long ldo) {
+  const long total = (long)m * k;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const int i = (int)(e / k), j = (int)(e % k);
+    out[(long)i * ldo + j] = in[(long)idx[i] * ldi + j];
+  }
+}
+
+__global__ void add_diag_kernel(int k, double* A, long lda, double v) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) A[(long)i * lda + i] += v;
+}
+
 }  // namespace
 
 static int osbj_chunk(int m, int nb) {
@@ -549,6 +729,41 @@ void transpose_square(hipStream_t s, int nmat, int k, const double* in, long sin
 
 void invert(hipStream_t s, int k, const double* A, double* Ainv, double* work, int* singular) {
   gauss_jordan<<<1, 1024, 0, s>>>(k, A, Ainv, work, singular);
+  IGA_HIP(hipGetLastError());
+}
+
+int chol_block_size() { return CHB; }
+
+void chol_block(hipStream_t s, int jb, const double* G, long ldg, double* L, long ldl, double* Linv, int* bad) {
+  require(jb >= 1 && jb <= CHB, IGA_EINVAL, "chol_block: block size out of range");
+  chol_block_kernel<<<1, 256, 0, s>>>(G, ldg, jb, L, ldl, Linv, bad);
+  IGA_HIP(hipGetLastError());
+}
+
+int pchol_max() { return PCHOL_MAX; }
+
+void pivoted_cholesky(hipStream_t s, int k, double* G, int* perm, int* bad) {
+  require(k >= 1 && k <= PCHOL_MAX, IGA_EINVAL, "pivoted_cholesky: size out of range");
+  pchol_kernel<<<1, 256, 0, s>>>(G, k, perm, bad);
+  IGA_HIP(hipGetLastError());
+}
+
+void trinv_blocks(hipStream_t s, int k, const double* L, long ldl, double* Linv) {
+  if (k <= 0) return;
+  trinv_blocks_kernel<<<(k + CHB - 1) / CHB, 64, 0, s>>>(L, ldl, k, Linv);
+  IGA_HIP(hipGetLastError());
+}
+
+void gather_rows(hipStream_t s, int m, int k, const double* in, long ldi, const int* idx, double* out, long ldo) {
+  const long total = (long)m * k;
+  if (total <= 0) return;
+  gather_rows_kernel<<<(unsigned)std::min<long>((total + 255) / 256, 4096), 256, 0, s>>>(m, k, in, ldi, idx, out, ldo);
+  IGA_HIP(hipGetLastError());
+}
+
+void add_diag(hipStream_t s, int k, double* A, long lda, double v) {
+  if (k <= 0) return;
+  add_diag_kernel<<<(unsigned)std::min(1024, (k + 255) / 256), 256, 0, s>>>(k, A, lda, v);
   IGA_HIP(hipGetLastError());
 }
 

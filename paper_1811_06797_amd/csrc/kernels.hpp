@@ -216,6 +216,22 @@ int osbj_block();
 int jacobi_lds_max();
 void transpose_square(hipStream_t s, int nmat, int k, const double* in, long sin, double* out,
                       long sout);
+// Cholesky of one diagonal block (jb <= chol_block_size()) of a symmetric matrix whose earlier
+// columns are eliminated: lower factor into L (ldl), its inverse into Linv (chol_block_size()^2,
+// row-major); a non-positive pivot gives a zero column and adds one to *bad (device int).
+int chol_block_size();
+void chol_block(hipStream_t s, int jb, const double* G, long ldg, double* L, long ldl, double* Linv, int* bad);
+// Cholesky with diagonal pivoting of a symmetric PSD k x k G (k <= pchol_max(), row-major, full
+// storage, destroyed; one workgroup): lower L in G with P^T G P = L L^T, perm[j] = original
+// index of pivot j (device), a non-positive pivot gives a zero column and adds one to *bad.
+int pchol_max();
+void pivoted_cholesky(hipStream_t s, int k, double* G, int* perm, int* bad);
+// Inverses of the chol_block_size() diagonal blocks of a lower-triangular k x k L, into Linv.
+void trinv_blocks(hipStream_t s, int k, const double* L, long ldl, double* Linv);
+// out[i][:] = in[idx[i]][:], i < m, k columns
+void gather_rows(hipStream_t s, int m, int k, const double* in, long ldi, const int* idx, double* out, long ldo);
+// A[i][i] += v, i < k
+void add_diag(hipStream_t s, int k, double* A, long lda, double v);
 // out[i][j] = in[i][idx[j]] * (scale ? scale[j] : 1), i < m, j < kout
 void gather_cols(hipStream_t s, int m, int kin, int kout, const double* in, long ldi, const int* idx,
                  const double* scale, double* out, long ldo);

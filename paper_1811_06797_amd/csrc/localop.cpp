@@ -7,6 +7,7 @@
 #include <cstring>
 #include <array>
 #include <memory>
+#include <mutex>
 #include <unordered_map>
 #include <vector>
 
@@ -529,15 +530,22 @@ struct RawCache {
   DBuf rM, rK;  // cores re-laid for the banded stage
   FBuf frM, frK;  // their FP32 copies (mixed-precision forms)
 };
+// Per-context caches: the maps are shared by every host thread (each context is used by one
+// thread at a time), so lookups and erasures take the lock.
+std::mutex g_raw_mu;
 std::unordered_map<iga_ctx*, std::unique_ptr<RawCache>> g_raw;
 RawCache& raw_cache(iga_ctx* ctx) {
+  std::lock_guard<std::mutex> lk(g_raw_mu);
   auto& p = g_raw[ctx];
   if (!p) p.reset(new RawCache());
   return *p;
 }
 }  // namespace
 
-void release_raw_cache(iga_ctx* ctx) { g_raw.erase(ctx); }
+void release_raw_cache(iga_ctx* ctx) {
+  std::lock_guard<std::mutex> lk(g_raw_mu);
+  g_raw.erase(ctx);
+}
 
 double local_matvec_flops(int r0, int n, int r1, int p, int RM0, int RM1, int RK0, int RK1) {
   LocalOp L;
@@ -678,6 +686,7 @@ struct BatchCache {
   std::vector<char> host;
   std::map<long, int> tuned;  // (precision, stage, size bucket) -> fastest tile variant
 };
+std::mutex g_batch_mu;
 std::unordered_map<iga_ctx*, std::unique_ptr<BatchCache>> g_batch;
 
 int log2_bucket(long x) {
@@ -909,12 +918,20 @@ void batched_run(iga_ctx* ctx, const std::vector<BatchProblem>& P, const std::ve
 
 }  // namespace
 
-void release_batch_cache(iga_ctx* ctx) { g_batch.erase(ctx); }
+void release_batch_cache(iga_ctx* ctx) {
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  g_batch.erase(ctx);
+}
 
 void local_matvec_batched_impl(iga_ctx* ctx, const std::vector<BatchProblem>& P, int precision, bool autotune) {
-  auto& cp = g_batch[ctx];
-  if (!cp) cp.reset(new BatchCache());
-  BatchCache& C = *cp;
+  BatchCache* cache;
+  {
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    auto& cp = g_batch[ctx];
+    if (!cp) cp.reset(new BatchCache());
+    cache = cp.get();
+  }
+  BatchCache& C = *cache;
   for (const BatchProblem& q : P) {
     require(q.r0 >= 1 && q.r1 >= 1 && q.n >= 1 && q.p >= 0 && q.RM0 >= 1 && q.RM1 >= 1 && q.RK0 >= 1 &&
                 q.RK1 >= 1,

@@ -125,13 +125,217 @@ iga_btt* kkt_apply_impl(iga_ctx* ctx, const iga_kkt* kkt, const iga_btt* x) {
 
 // ---------------------------------------------------------------- SVD
 
+namespace {
+
+// Lower Cholesky factor L (k x k, zero above the diagonal) of the symmetric G (k x k,
+// row-major, destroyed), by blocks of b = chol_block_size() columns, left to right: factor
+// the diagonal block (which also gives its inverse, kept in Linv[block]), solve the panel
+// below it, L21 = G21 L11^-T, and update the trailing matrix, G22 -= L21 L21^T. Returns the
+// number of non-positive pivots (each leaves a zero column).
+int cholesky(iga_ctx* ctx, int k, double* G, double* L, double* Linv) {
+  hipStream_t st = ctx->stream;
+  const int cb = k::chol_block_size();
+  IBuf bad(ctx, 1);
+  const int zero = 0;
+  IGA_HIP(hipMemcpyAsync(bad.get(), &zero, sizeof(int), hipMemcpyHostToDevice, st));
+  k::fill(st, (long)k * k, 0.0, L);
+  for (int j0 = 0; j0 < k; j0 += cb) {
+    const int jb = std::min(cb, k - j0), nr = k - j0 - jb;
+    double* Lj = Linv + (long)(j0 / cb) * cb * cb;
+    k::chol_block(st, jb, G + (long)j0 * k + j0, k, L + (long)j0 * k + j0, k, Lj, bad.get());
+    if (nr > 0) {
+      double* L21 = L + (long)(j0 + jb) * k + j0;
+      k::gemm_rm(st, nr, jb, jb, G + (long)(j0 + jb) * k + j0, k, false, Lj, cb, true, L21, k);
+      k::gemm_rm(st, nr, nr, jb, L21, k, false, L21, k, true, G + (long)(j0 + jb) * k + j0 + jb, k, -1.0, 1.0);
+    }
+  }
+  int nbad = 0;
+  IGA_HIP(hipMemcpyAsync(&nbad, bad.get(), sizeof(int), hipMemcpyDeviceToHost, st));
+  IGA_HIP(hipStreamSynchronize(st));
+  return nbad;
+}
+
+// Q = X R^-1 for R = L^T (X, Q: m x k, row-major, distinct), block column by block column:
+// Q_j = X_j Ljj^-T - Q_{<j} (L_{j,<j}^T Ljj^-T), with the diagonal-block inverses from
+// cholesky(). Mj: k x chol_block_size() scratch; work: split-K partials.
+void solve_right_lt(iga_ctx* ctx, int m, int k, const double* X, long ldx, const double* L, const double* Linv,
+                    double* Q, long ldq, double* Mj, double* work, size_t wlen) {
+  hipStream_t st = ctx->stream;
+  const int cb = k::chol_block_size();
+  for (int j0 = 0; j0 < k; j0 += cb) {
+    const int jb = std::min(cb, k - j0);
+    const double* Lj = Linv + (long)(j0 / cb) * cb * cb;
+    k::gemm_rm(st, m, jb, jb, X + j0, ldx, false, Lj, cb, true, Q + j0, ldq);
+    if (j0 > 0) {
+      k::gemm_rm(st, j0, jb, jb, L + (long)j0 * k, k, true, Lj, cb, true, Mj, cb);
+      k::gemm_rm(st, m, jb, j0, Q, ldq, false, Mj, cb, false, Q + j0, ldq, -1.0, 1.0, work, wlen);
+    }
+  }
+}
+
+// R^T (k x k, lower) of the triangular factor of X P, X m x k (ldx; m >= k, k <= pchol_max()),
+// P the column order of column-pivoted QR, by shifted Cholesky QR in three passes (Fukaya,
+// Kannan, Nakatsukasa, Yamamoto, Yanagisawa, 2020). The first pass factors the Gram matrix
+// plus a shift of 11 (m k + k (k + 1)) u ||X||_F^2 with diagonal pivoting, whose pivot order
+// equals column-pivoted QR's, and orthogonalises X P against that factor; the second factors
+// the remainder's Gram matrix plus 11 (m k + k (k + 1)) u; the shifts keep Cholesky from
+// breaking down on a rank-deficient X. The third factors the nearly orthonormal remainder
+// without a shift. R = R3 R2 R1 is backward stable, ||X P - Q R|| = O(u ||X||), whatever the
+// rank of X (only R is formed; Q is not needed). perm[j] (device) receives the original column
+// of pivot j and XP (m x k) the permuted columns. Returns false if a shifted pass still breaks
+// down.
+bool cholesky_qr3_rt(iga_ctx* ctx, int m, int k, const double* X, long ldx, double fro2, double* RT, int* perm,
+                     double* XP) {
+  hipStream_t st = ctx->stream;
+  const int cb = k::chol_block_size();
+  const int nblk = (k + cb - 1) / cb;
+  DBuf G(ctx, (size_t)k * k), L1(ctx, (size_t)k * k), L2(ctx, (size_t)k * k), L3(ctx, (size_t)k * k);
+  DBuf Li(ctx, (size_t)nblk * cb * cb), Mj(ctx, (size_t)k * cb);
+  DBuf Q1(ctx, (size_t)m * k), Q2(ctx, (size_t)m * k);
+  const size_t wlen = std::max<size_t>((size_t)32 * k * k, (size_t)8 * m * cb);
+  DBuf work(ctx, wlen);
+  const double c = 11.0 * ((double)m * k + (double)k * (k + 1)) * std::ldexp(1.0, -53);
+  // pass 1: pivoted
+  {
+    IBuf bad(ctx, 1);
+    double shift = c * fro2;
+    bool ok = false;
+    for (int attempt = 0; attempt < 4 && !ok; ++attempt, shift *= 100.0) {
+      const int zero = 0;
+      IGA_HIP(hipMemcpyAsync(bad.get(), &zero, sizeof(int), hipMemcpyHostToDevice, st));
+      k::gemm_rm(st, k, k, m, X, ldx, true, X, ldx, false, L1.get(), k, 1.0, 0.0, work.get(), wlen);
+      k::add_diag(st, k, L1.get(), k, shift);
+      k::pivoted_cholesky(st, k, L1.get(), perm, bad.get());
+      int nbad = 0;
+      IGA_HIP(hipMemcpyAsync(&nbad, bad.get(), sizeof(int), hipMemcpyDeviceToHost, st));
+      IGA_HIP(hipStreamSynchronize(st));
+      ok = nbad == 0;
+    }
+    if (!ok) return false;
+  }
+  k::trinv_blocks(st, k, L1.get(), k, Li.get());
+  k::gather_cols(st, m, (int)ldx, k, X, ldx, perm, nullptr, XP, k);
+  solve_right_lt(ctx, m, k, XP, k, L1.get(), Li.get(), Q1.get(), k, Mj.get(), work.get(), wlen);
+  // passes 2 and 3: blocked Cholesky of the remainder's Gram matrix
+  auto factor = [&](const double* Y, double shift, double* Lout, bool retry) {
+    for (int attempt = 0; attempt < 4; ++attempt) {
+      k::gemm_rm(st, k, k, m, Y, k, true, Y, k, false, G.get(), k, 1.0, 0.0, work.get(), wlen);
+      if (shift > 0.0) k::add_diag(st, k, G.get(), k, shift);
+      if (cholesky(ctx, k, G.get(), Lout, Li.get()) == 0 || !retry) return true;
+      shift *= 100.0;
+    }
+    return false;
+  };
+  if (!factor(Q1.get(), c, L2.get(), true)) return false;
+  solve_right_lt(ctx, m, k, Q1.get(), k, L2.get(), Li.get(), Q2.get(), k, Mj.get(), work.get(), wlen);
+  factor(Q2.get(), 0.0, L3.get(), false);
+  // R^T = R1^T R2^T R3^T = L1 (L2 L3)
+  k::gemm_rm(st, k, k, k, L2.get(), k, false, L3.get(), k, false, G.get(), k);
+  k::gemm_rm(st, k, k, k, L1.get(), k, false, G.get(), k, false, RT, k);
+  return true;
+}
+
+}  // namespace
+
+// product_only: the Jacobi iteration may run on the pivoted Cholesky-QR factor (see
+// svd_preconditioned), whose left vectors are accurate only in the product U Sigma.
+static void svd_impl(iga_ctx* ctx, const double* A, int m, int k, long lda, bool trans, Svd& out, bool product_only);
+
+// Product form of the tall SVD (m >= k) of B (m x kp, zero-padded beyond column k): R of B P
+// from the column-pivoted shifted Cholesky QR, then one-sided block Jacobi on R^T (k x k),
+// which converges in far fewer sweeps than on B itself (Drmac and Veselic's preconditioning;
+// without the pivoting it barely helps on smooth data): R^T W = U_X Sigma gives
+// R = W Sigma U_X^T, so the right singular vectors of B P are U_X, the normalised columns of
+// R^T W, those of B are P U_X, and B V = (B P) U_X = U Sigma. Columns with sigma = 0 get zero
+// vectors. B V holds u_j only to an absolute accuracy of about u ||B|| / sigma_j: the product
+// B V^T is accurate, B / sigma is not orthonormal to working accuracy for small sigma.
+// Returns false (nothing written) if the Cholesky QR broke down.
+static bool svd_preconditioned(iga_ctx* ctx, const double* B, int m, int k, int kp, double fro2, Svd& out) {
+  hipStream_t st = ctx->stream;
+  DBuf RT(ctx, (size_t)k * k), BP(ctx, (size_t)m * k);
+  IBuf perm(ctx, k);
+  if (!cholesky_qr3_rt(ctx, m, k, B, kp, fro2, RT.get(), perm.get(), BP.get())) return false;
+  DBuf X(ctx, (size_t)k * kp);
+  k::fill(st, (long)k * kp, 0.0, X.get());
+  k::copy2d(st, k, k, RT.get(), k, 1, X.get(), kp);
+  const int nb = kp / k::osbj_block(), npair = nb / 2, nround = nb - 1;
+  const double floor_col = 1e-28 * fro2;
+  const double tol = 4e-16 * std::max(1.0, std::sqrt((double)k));
+  IBuf flags(ctx, (size_t)npair * nround);
+  const size_t wlen = k::osbj_work_len(k, 0, nb);
+  DBuf work(ctx, wlen);
+  std::vector<int> hf((size_t)npair * nround);
+  int sweeps = 0;
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    for (int rd = 0; rd < nround; ++rd)
+      k::osbj_round(st, X.get(), k, kp, nullptr, 0, kp, nb, rd, tol, floor_col, flags.get() + rd * npair,
+                   work.get(), wlen);
+    IGA_HIP(hipMemcpyAsync(hf.data(), flags.get(), hf.size() * sizeof(int), hipMemcpyDeviceToHost, st));
+    IGA_HIP(hipStreamSynchronize(st));
+    ++sweeps;
+    bool any = false;
+    for (int f : hf) any = any || f;
+    if (!any) break;
+  }
+  DBuf nrm(ctx, kp);
+  k::colnorms(st, k, kp, X.get(), kp, nrm.get());
+  std::vector<double> sig(kp);
+  IGA_HIP(hipMemcpyAsync(sig.data(), nrm.get(), kp * sizeof(double), hipMemcpyDeviceToHost, st));
+  IGA_HIP(hipStreamSynchronize(st));
+  std::vector<int> idx(kp);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return sig[a] > sig[b]; });
+  const int p = k;
+  std::vector<int> id(idx.begin(), idx.begin() + p);
+  std::vector<double> inv(p);
+  out.m = m; out.k = k; out.p = p;
+  out.sigma.resize(p);
+  for (int j = 0; j < p; ++j) {
+    out.sigma[j] = sig[id[j]];
+    inv[j] = out.sigma[j] > 0 ? 1.0 / out.sigma[j] : 0.0;
+  }
+  IBuf didx(ctx, p);
+  DBuf dinv(ctx, p);
+  IGA_HIP(hipMemcpyAsync(didx.get(), id.data(), p * sizeof(int), hipMemcpyHostToDevice, st));
+  IGA_HIP(hipMemcpyAsync(dinv.get(), inv.data(), p * sizeof(double), hipMemcpyHostToDevice, st));
+  out.V.reset(ctx, (size_t)k * p);
+  out.B.reset(ctx, (size_t)m * p);
+  k::gather_cols(st, k, kp, p, X.get(), kp, didx.get(), dinv.get(), out.V.get(), p);
+  // B V in the permuted columns the factor was taken of
+  k::gemm_rm(st, m, p, k, BP.get(), k, false, out.V.get(), p, false, out.B.get(), p);
+  {
+    // V of the permuted columns to V of A: row perm[i] of V_A is row i of V_{AP}
+    std::vector<int> hp(k), inv_perm(k);
+    IGA_HIP(hipMemcpyAsync(hp.data(), perm.get(), k * sizeof(int), hipMemcpyDeviceToHost, st));
+    IGA_HIP(hipStreamSynchronize(st));
+    for (int i = 0; i < k; ++i) inv_perm[hp[i]] = i;
+    IBuf dinvp(ctx, k);
+    IGA_HIP(hipMemcpyAsync(dinvp.get(), inv_perm.data(), k * sizeof(int), hipMemcpyHostToDevice, st));
+    DBuf VA(ctx, (size_t)k * p);
+    k::gather_rows(st, k, p, out.V.get(), p, dinvp.get(), VA.get(), p);
+    out.V = std::move(VA);
+  }
+  out.passes = sweeps;
+  IGA_HIP(hipStreamSynchronize(st));
+  return true;
+}
+
 void svd(iga_ctx* ctx, const double* A, int m, int k, long lda, bool trans, Svd& out) {
+  svd_impl(ctx, A, m, k, lda, trans, out, false);
+}
+
+void svd_product(iga_ctx* ctx, const double* A, int m, int k, long lda, bool trans, Svd& out) {
+  svd_impl(ctx, A, m, k, lda, trans, out, true);
+}
+
+static void svd_impl(iga_ctx* ctx, const double* A, int m, int k, long lda, bool trans, Svd& out, bool product_only) {
   require(m >= 1 && k >= 1, IGA_EINVAL, "svd: empty matrix");
   hipStream_t st = ctx->stream;
   if (m < k) {
-    // work on the tall transpose: A^T = U' S V'^T  =>  A = V' S U'^T
+    // work on the tall transpose: A^T = U' S V'^T  =>  A = V' S U'^T (A's left vectors are the
+    // transpose's right vectors)
     Svd t;
-    svd(ctx, A, k, m, lda, !trans, t);
+    svd_impl(ctx, A, k, m, lda, !trans, t, product_only);
     const int p = t.p;
     std::vector<double> sg(t.sigma.begin(), t.sigma.begin() + p), inv(p);
     for (int j = 0; j < p; ++j) inv[j] = sg[j] > 0 ? 1.0 / sg[j] : 0.0;
@@ -169,6 +373,9 @@ void svd(iga_ctx* ctx, const double* A, int m, int k, long lda, bool trans, Svd&
   const double fro2 = norm2_host(ctx, (long)m * kp, B.get());
   // NaN or Inf would also break the ordering of the singular values below
   require(std::isfinite(fro2), IGA_ENUM, "svd: the matrix holds a non-finite entry");
+  if (product_only && k > 2 * bs && k <= k::pchol_max() && fro2 > 0 &&
+      svd_preconditioned(ctx, B.get(), m, k, kp, fro2, out))
+    return;
   const double floor_col = 1e-28 * fro2;
   const double tol = 4e-16 * std::max(1.0, std::sqrt((double)m));
   const int npair = nb / 2, nround = nb - 1;

@@ -52,6 +52,12 @@ struct Svd {
   int passes = 0;  // Jacobi sweeps
 };
 void svd(iga_ctx* ctx, const double* A, int m, int k, long lda, bool trans, Svd& out);
+// The same outputs where only the product U Sigma V^T = B V^T matters (the TT-SVD of a tensor):
+// with more than 32 columns (at most 1024) the Jacobi iteration runs on R^T of a column-pivoted
+// Cholesky QR (the pivoting is what makes the iteration converge in few sweeps on smooth
+// data); the columns of B = A V carry the QR's absolute error u ||A||, so B / sigma is not
+// orthonormal to working accuracy for small sigma.
+void svd_product(iga_ctx* ctx, const double* A, int m, int k, long lda, bool trans, Svd& out);
 // Smallest r with ||sigma[r:]|| <= abs_tol, capped to [rmin, rmax] (rmax <= 0: no cap).
 int trunc_rank(const std::vector<double>& sigma, double abs_tol, int rmax, int rmin = 1);
 

@@ -29,6 +29,7 @@ _NAMES = {EINVAL: "IGA_EINVAL", ENOMEM: "IGA_ENOMEM", EHIP: "IGA_EHIP", EGEOM: "
 EXPORTED = [
     "iga_ctx_create", "iga_ctx_destroy", "iga_assemble_factors", "iga_ttop_create", "iga_ttop_info",
     "iga_ttop_get_core", "iga_ttop_destroy", "iga_tt_create", "iga_tt_wrap", "iga_tt_from_full", "iga_tt_destroy",
+    "iga_tt_info", "iga_tt_get_core",
     "iga_btt_create", "iga_btt_info", "iga_btt_blocks", "iga_btt_get_core", "iga_btt_to_full", "iga_btt_destroy",
     "iga_kkt_create", "iga_kkt_create_parabolic", "iga_kkt_blocks", "iga_kkt_destroy", "iga_kkt_apply", "iga_kkt_residual", "iga_amen_solve",
     "iga_amen_solve_many",
@@ -125,6 +126,8 @@ lib.iga_tt_wrap.argtypes = [P, I3, I4, PD * 3, C.POINTER(P)]
 lib.iga_tt_from_full.argtypes = [P, I3, P, C.c_double, C.POINTER(P)]
 lib.iga_tt_destroy.argtypes = [P]
 lib.iga_tt_destroy.restype = None
+lib.iga_tt_info.argtypes = [P, I3, I4]
+lib.iga_tt_get_core.argtypes = [P, P, C.c_int, PD]
 lib.iga_btt_create.argtypes = [P, I3, I4, C.c_int, PD * 3, C.POINTER(P)]
 lib.iga_btt_info.argtypes = [P, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
 lib.iga_btt_get_core.argtypes = [P, P, C.c_int, PD]
@@ -463,6 +466,24 @@ def grad_geometry(ctx, geo, degree: int, n, beta: float, yhat, f, p_interp: int 
     nn = I3(*[int(v) for v in (n if hasattr(n, "__len__") else (n, n, n))])
     out = np.zeros(ctrl.shape, dtype=np.float64)
     _check(lib.iga_grad_geometry(ctx, C.byref(g), int(degree), nn, C.byref(o), float(beta), yhat, f, _dptr(out)))
+    return out
+
+
+def tt_info(t):
+    """(n, r) of a TT handle."""
+    n, r = I3(), I4()
+    _check(lib.iga_tt_info(t, n, r))
+    return list(n), list(r)
+
+
+def tt_get_cores(ctx, t):
+    """The three cores of a TT handle as host arrays [r_d][n_d][r_{d+1}]."""
+    n, r = tt_info(t)
+    out = []
+    for d in range(3):
+        c = np.empty((r[d], n[d], r[d + 1]), dtype=np.float64)
+        _check(lib.iga_tt_get_core(ctx, t, d, _dptr(c)))
+        out.append(c)
     return out
 
 

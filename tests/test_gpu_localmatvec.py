@@ -38,7 +38,12 @@ def _run(gpu_ctx, prob, r, n, p, RM, RK, beta, precision, rr=None):
                                              # is 17 column tiles and a ragged one, M = 50 a partial tile,
                                              # K = 350 a partial K tile; odd R_K = 51 takes the
                                              # register-staged kernel instead
-                                             (33, 4, 50, 32, 3, None), (33, 4, 51, 32, 3, None)])
+                                             (33, 4, 50, 32, 3, None), (33, 4, 51, 32, 3, None),
+                                             # 64 x 128 tiles on tall products with more than 64
+                                             # columns: the right-interface stage (M = r n = 320
+                                             # and 720, N = r' = 72 and 90), and the left one
+                                             # (M = R_K r = 360, N = n r' = 2160)
+                                             (20, 2, 5, 16, 3, 72), (30, 3, 12, 24, 2, 90)])
 def test_local_matvec_matches_oracle(gpu_ctx, r, RM, RK, n, p, rr):
     from paper_1811_06797_amd import iga
     prob = synth.random_local_problem(r, RM, RK, n, p, seed=r + n, r_right=rr)
