@@ -42,6 +42,22 @@ static size_t size_class(size_t bytes) {
   return p * 2;
 }
 
+// Device memory a large allocation must leave free: the HIP runtime allocates device memory of
+// its own while kernels are launched (kernel arguments, signals, staging), so a library
+// allocation that would leave the device almost full is refused instead (several solves
+// running at once on one GPU could otherwise exhaust it together).
+static bool leaves_headroom(size_t bytes) {
+  constexpr size_t kLarge = 64ull << 20;
+  if (bytes < kLarge) return true;
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+    (void)hipGetLastError();
+    return true;
+  }
+  const size_t reserve = std::max<size_t>(2ull << 30, total_b / 64);
+  return free_b >= bytes && free_b - bytes >= reserve;
+}
+
 void* Pool::alloc(size_t bytes) {
   const size_t requested = bytes;
   bytes = size_class(bytes);
@@ -51,6 +67,13 @@ void* Pool::alloc(size_t bytes) {
     p = it->second;
     free_.erase(it);
   } else {
+    if (!leaves_headroom(bytes)) {
+      for (auto& kv : free_) (void)hipFree(kv.second);
+      free_.clear();
+      if (!leaves_headroom(bytes))
+        fail(IGA_ENOMEM, "device allocation of " + std::to_string(requested) +
+                             " bytes would leave the device without headroom (in " + std::string(g_phase) + ")");
+    }
     hipError_t e = hipMalloc(&p, bytes);
     if (e != hipSuccess) {
       // release cached blocks and retry once

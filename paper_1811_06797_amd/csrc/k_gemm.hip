@@ -587,6 +587,10 @@ int gemm2_pick(const Gemm2& d) {
   if (d.N <= 32) return 3;
   if (d.M <= 64 && (long)((d.N + 32 * IGA_WIDE_WN - 1) / (32 * IGA_WIDE_WN)) * nb >= 512) return 4;
   if (d.M > 64 && d.M <= 80) return 5;  // one 80-row tile instead of 64 + 16
+  // tall products with more than 64 columns (the interface stages of the local matvec, whose
+  // columns are output ranks or (row, rank) pairs): a 128-wide column tile reads each row tile
+  // of the long operand half as often as 64-wide tiles (measured 1.05-1.4x on those stages)
+  if (d.M > 256 && d.N > 64) return 4;
   return 0;
 }
 

@@ -327,6 +327,44 @@ __global__ __launch_bounds__(256) void osbj_sum_kernel(const double* P, int nchu
   Gsum[(long)pair * (OSP * OSP) + e] = a;
 }
 
+// Round-robin partner of the 32-player schedule (as circle_pair with nplayers = 32), with the
+// modulo 31 done by one conditional subtraction (pos - 1 + round <= 60).
+__device__ __forceinline__ void circle_pair32(int t, int round, int& a, int& b) {
+  auto player = [&](int pos) {
+    int x = pos - 1 + round;
+    x = x >= OSP - 1 ? x - (OSP - 1) : x;
+    return pos == 0 ? 0 : 1 + x;
+  };
+  a = player(t);
+  b = player(OSP - 1 - t);
+  if (a > b) { const int x = a; a = b; b = x; }
+}
+
+// Rotation of pair (p, q) of the cyclic Jacobi method on a symmetric matrix:
+// |apq| > tol sqrt(|app aqq|) (squared: no square root on the path of every rotation) unless
+// both columns are negligible; then t = tan(theta) = sign(tau) / (|tau| + sqrt(1 + tau^2)) with
+// tau = dd / ee, written as sign(tau) |ee| / (|dd| + sqrt(dd^2 + ee^2)) (one division and one
+// root fewer), c = 1 / sqrt(1 + t^2), s = t c, and the new diagonal app - t apq, aqq + t apq.
+struct Rot {
+  double c, s, np, nq;
+  bool on;
+};
+__device__ __forceinline__ Rot jacobi_rot(double app, double aqq, double apq, double tol, double floor_col) {
+  Rot r{1.0, 0.0, app, aqq, false};
+  const bool negligible = app <= floor_col && aqq <= floor_col;
+  if (!negligible && apq * apq > tol * tol * fabs(app * aqq)) {
+    const double dd = aqq - app, ee = 2.0 * apq;
+    const double sg = (dd == 0.0 || (dd > 0.0) == (ee > 0.0)) ? 1.0 : -1.0;
+    const double t = sg * fabs(ee) / (fabs(dd) + sqrt(dd * dd + ee * ee));
+    r.c = 1.0 / sqrt(1.0 + t * t);
+    r.s = t * r.c;
+    r.np = app - t * apq;
+    r.nq = aqq + t * apq;
+    r.on = true;
+  }
+  return r;
+}
+
 __global__ __launch_bounds__(ORT) void osbj_rot_kernel(const double* Gsum, double tol, double floor_col,
                                                        double* Wout, int* flags) {
   __shared__ double G[OSP][OSP + 1];
@@ -342,6 +380,18 @@ __global__ __launch_bounds__(ORT) void osbj_rot_kernel(const double* Gsum, doubl
   }
   if (tid == 0) rot_any = 0;
   __syncthreads();
+  {
+    // a pair with nothing above the threshold exits before the sweep
+    int need = 0;
+    for (int e = tid; e < OSP * OSP; e += ORT) {
+      const int i = e / OSP, jj = e % OSP;
+      if (i < jj) need |= jacobi_rot(G[i][i], G[jj][jj], G[i][jj], tol, floor_col).on ? 1 : 0;
+    }
+    if (!__syncthreads_or(need)) {
+      if (tid == 0) flags[pair] = 0;
+      return;
+    }
+  }
   // Each round: the 16 disjoint rotations (p_t, q_t) of the round-robin schedule are found by
   // threads 0..15; then thread (t1, t2) applies rows of rotation t1 and columns of rotation t2
   // to the 2 x 2 block {p_t1, q_t1} x {p_t2, q_t2} of G at once (the blocks are disjoint and
@@ -355,31 +405,16 @@ __global__ __launch_bounds__(ORT) void osbj_rot_kernel(const double* Gsum, doubl
     for (int r2 = 0; r2 < OSP - 1; ++r2) {
       if (tid < OSP / 2) {
         int p, q;
-        circle_pair(tid, r2, OSP, p, q);
-        double c = 1.0, sv = 0.0;
-        const double app = G[p][p], aqq = G[q][q], apq = G[p][q];
-        double np = app, nq = aqq;
-        const bool negligible = app <= floor_col && aqq <= floor_col;
-        // |apq| > tol sqrt(|app aqq|), squared (no square root on the path of every rotation)
-        if (!negligible && apq * apq > tol * tol * fabs(app * aqq)) {
-          // t = tan(theta) = sign(tau) / (|tau| + sqrt(1 + tau^2)) with tau = dd / ee, written
-          // as sign(tau) |ee| / (|dd| + sqrt(dd^2 + ee^2)): one division and one root fewer
-          const double dd = aqq - app, ee = 2.0 * apq;
-          const double sg = (dd == 0.0 || (dd > 0.0) == (ee > 0.0)) ? 1.0 : -1.0;
-          const double t = sg * fabs(ee) / (fabs(dd) + sqrt(dd * dd + ee * ee));
-          c = 1.0 / sqrt(1.0 + t * t);
-          sv = t * c;
-          np = app - t * apq;
-          nq = aqq + t * apq;
-          rot_sweep = 1;
-        }
-        cs[tid] = c; sn[tid] = sv; dp[tid] = np; dq[tid] = nq;
+        circle_pair32(tid, r2, p, q);
+        const Rot R = jacobi_rot(G[p][p], G[q][q], G[p][q], tol, floor_col);
+        if (R.on) rot_sweep = 1;
+        cs[tid] = R.c; sn[tid] = R.s; dp[tid] = R.np; dq[tid] = R.nq;
       }
       __syncthreads();
       {
         int p1, q1, p2, q2;
-        circle_pair(t1, r2, OSP, p1, q1);
-        circle_pair(t2, r2, OSP, p2, q2);
+        circle_pair32(t1, r2, p1, q1);
+        circle_pair32(t2, r2, p2, q2);
         const double c1 = cs[t1], s1 = sn[t1], c2 = cs[t2], s2 = sn[t2];
         if (s1 != 0.0 || s2 != 0.0) {
           if (t1 == t2) {
