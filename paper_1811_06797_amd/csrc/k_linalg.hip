@@ -572,12 +572,21 @@ __global__ __launch_bounds__(256) void chol_block_kernel(const double* G, long l
 // gives a zero column and adds one to *bad. The trailing updates read and write G in global
 // memory (L2-resident at the sizes this serves, k <= PCHOL_MAX).
 constexpr int PCHOL_MAX = 1024;
-__global__ __launch_bounds__(256) void pchol_kernel(double* G, int k, int* perm, int* bad) {
-  __shared__ double dg[PCHOL_MAX];
-  __shared__ int pm[PCHOL_MAX];
+constexpr int PCHOL_LDS_MAX = 140;  // G itself in LDS (k^2 doubles) up to this size
+template <bool InLds>
+__global__ __launch_bounds__(256) void pchol_kernel(double* Gg, int k, int* perm, int* bad) {
+  constexpr int KM = InLds ? PCHOL_LDS_MAX : PCHOL_MAX;
+  extern __shared__ double Gl[];
+  __shared__ double dg[KM];
+  __shared__ int pm[KM];
   __shared__ double rv[256];
   __shared__ int ri[256];
   const int tid = threadIdx.x;
+  double* G = InLds ? Gl : Gg;
+  if (InLds) {
+    for (int e = tid; e < k * k; e += 256) Gl[e] = Gg[e];
+    __syncthreads();
+  }
   for (int i = tid; i < k; i += 256) {
     dg[i] = G[(long)i * k + i];
     pm[i] = i;
@@ -640,10 +649,10 @@ __global__ __launch_bounds__(256) void pchol_kernel(double* G, int k, int* perm,
     for (int i = j + 1 + tid; i < k; i += 256) dg[i] = G[(long)i * k + i];
     __syncthreads();
   }
-  // zero the upper triangle
+  // the lower triangle, zeros above
   for (long e = tid; e < (long)k * k; e += 256) {
     const int i = (int)(e / k), t = (int)(e % k);
-    if (t > i) G[e] = 0.0;
+    Gg[e] = t > i ? 0.0 : G[e];
   }
   for (int i = tid; i < k; i += 256) perm[i] = pm[i];
 }
@@ -779,7 +788,16 @@ int pchol_max() { return PCHOL_MAX; }
 
 void pivoted_cholesky(hipStream_t s, int k, double* G, int* perm, int* bad) {
   require(k >= 1 && k <= PCHOL_MAX, IGA_EINVAL, "pivoted_cholesky: size out of range");
-  pchol_kernel<<<1, 256, 0, s>>>(G, k, perm, bad);
+  if (k <= PCHOL_LDS_MAX) {
+    static std::once_flag attr_once;
+    std::call_once(attr_once, [] {
+      IGA_HIP(hipFuncSetAttribute((const void*)pchol_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  PCHOL_LDS_MAX * PCHOL_LDS_MAX * (int)sizeof(double)));
+    });
+    pchol_kernel<true><<<1, 256, (size_t)k * k * sizeof(double), s>>>(G, k, perm, bad);
+  } else {
+    pchol_kernel<false><<<1, 256, 0, s>>>(G, k, perm, bad);
+  }
   IGA_HIP(hipGetLastError());
 }
 
