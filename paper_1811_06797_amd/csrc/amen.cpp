@@ -1360,8 +1360,6 @@ int amen_impl(iga_ctx* ctx, const iga_kkt* kkt, const iga_tt* yhat, double tol, 
   if (o.init_rank <= 0) o.init_rank = 2;
   require(o.precision == IGA_FP64 || o.precision == IGA_FP32 || o.precision == IGA_BF16, IGA_EINVAL,
           "amen_solve: bad precision");
-  require(kkt->nt == 0 || o.precision == IGA_FP64, IGA_EINVAL,
-          "amen_solve: the time-dependent system is solved in FP64 only");
   Amen a(ctx, kkt, yhat, tol, o);
   return a.run(x0, sol, stats);
 }

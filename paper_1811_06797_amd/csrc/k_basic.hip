@@ -308,13 +308,13 @@ __global__ __launch_bounds__(64 * BAND_WAVES) void band_small_kernel(int b, int 
 }
 
 // y[o] = sum of coef[t] z[src[t]] over the terms t of output block o (blockIdx.y = o).
-__global__ void combine_blocks_kernel(long e, const int* toff, const int* src, const double* coef,
-                                      const double* z, double* y) {
+template <typename T>
+__global__ void combine_blocks_kernel(long e, const int* toff, const int* src, const double* coef, const T* z, T* y) {
   const int o = blockIdx.y;
   const int t0 = toff[o], t1 = toff[o + 1];
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < e; i += (long)gridDim.x * blockDim.x) {
-    double a = 0.0;
-    for (int t = t0; t < t1; ++t) a += coef[t] * z[(long)src[t] * e + i];
+    T a = T(0);
+    for (int t = t0; t < t1; ++t) a += T(coef[t]) * z[(long)src[t] * e + i];
     y[(long)o * e + i] = a;
   }
 }
@@ -502,13 +502,24 @@ void kkt_combine(hipStream_t s, long e, const KktCoef& c, const double* zM, cons
   IGA_HIP(hipGetLastError());
 }
 
-void combine_blocks(hipStream_t s, long e, int nblk, const int* toff, const int* src, const double* coef,
-                    const double* z, double* y) {
+template <typename T>
+static void combine_blocks_launch(hipStream_t s, long e, int nblk, const int* toff, const int* src,
+                                  const double* coef, const T* z, T* y) {
   if (e <= 0 || nblk <= 0) return;
   require(nblk <= 65535, IGA_EINVAL, "combine_blocks: too many blocks");
   dim3 g((unsigned)std::min<long>((e + 255) / 256, 1024), nblk);
-  combine_blocks_kernel<<<g, 256, 0, s>>>(e, toff, src, coef, z, y);
+  combine_blocks_kernel<T><<<g, 256, 0, s>>>(e, toff, src, coef, z, y);
   IGA_HIP(hipGetLastError());
+}
+
+void combine_blocks(hipStream_t s, long e, int nblk, const int* toff, const int* src, const double* coef,
+                    const double* z, double* y) {
+  combine_blocks_launch<double>(s, e, nblk, toff, src, coef, z, y);
+}
+
+void combine_blocks_f32(hipStream_t s, long e, int nblk, const int* toff, const int* src, const double* coef,
+                        const float* z, float* y) {
+  combine_blocks_launch<float>(s, e, nblk, toff, src, coef, z, y);
 }
 
 void fd_solve_time(hipStream_t s, int r0, int n, int r1, int nt, const double* lamL, const double* lamN,

@@ -138,6 +138,8 @@ void band_small_f32(hipStream_t s, int n, int b, int R0, int R1, long ncols, con
 // for o < nblk, blocks of e elements (device tables).
 void combine_blocks(hipStream_t s, long e, int nblk, const int* toff, const int* src, const double* coef,
                     const double* z, double* y);
+void combine_blocks_f32(hipStream_t s, long e, int nblk, const int* toff, const int* src, const double* coef,
+                        const float* z, float* y);
 // Per-mode solve of the time-dependent reference KKT system (nt steps of length tau) in
 // place on v [3][nt][r0 n r1]; work: nt r0 n r1 doubles.
 void fd_solve_time(hipStream_t s, int r0, int n, int r1, int nt, const double* lamL, const double* lamN,

@@ -509,10 +509,25 @@ void local_matvec(iga_ctx* ctx, const LocalOp& L, const double* x, double* y, Lo
 void local_matvec_f32(iga_ctx* ctx, const LocalOp& L, const float* x, float* y, LocalWork& w, bool bf16) {
   require(L.M.Af && L.K.Af && L.fPhiL_M && L.fPhiR_M && L.fPhiL_K && L.fPhiR_K, IGA_EINVAL,
           "local_matvec_f32: FP32 operands missing");
-  require(L.toff == nullptr, IGA_EINVAL, "local_matvec_f32: the time-dependent system is FP64 only");
   const long colsz = (long)L.r0 * L.n * L.r1;
   const int r0o = L.out0(), r1o = L.out1();
   const long osz = (long)r0o * L.n * r1o;
+  if (L.toff) {
+    // general block structure (the time-dependent system), as in local_matvec
+    const int nz = L.nblk + L.kcols();
+    w.fz.ensure(ctx, (size_t)nz * osz);
+    op_apply<float>(ctx, L.M, L.M.Af, L.M.Arf, L.Mblocks, L.fPhiL_M, L.fPhiR_M, r0o, L.r0, L.r1, r1o, L.nblk, x,
+                    colsz, w.fz.get(), osz, w.ftM, w.ftM2, w.fsplit, w.fpadM, 0, bf16);
+    int pos = L.nblk;
+    for (int j = 0; j < L.nkr; ++j) {
+      op_apply<float>(ctx, L.K, L.K.Af, L.K.Arf, L.Kblocks, L.fPhiL_K, L.fPhiR_K, r0o, L.r0, L.r1, r1o, L.kn[j],
+                      x + L.kb[j] * colsz, colsz, w.fz.get() + pos * osz, osz, w.ftK, w.ftK2, w.fsplit, w.fpadK, 1,
+                      bf16);
+      pos += L.kn[j];
+    }
+    k::combine_blocks_f32(ctx->stream, osz, L.nblk, L.toff, L.src, L.tcoef, w.fz.get(), y);
+    return;
+  }
   w.fz.ensure(ctx, (size_t)5 * osz);
   op_apply<float>(ctx, L.M, L.M.Af, L.M.Arf, L.Mblocks, L.fPhiL_M, L.fPhiR_M, r0o, L.r0, L.r1, r1o, 3, x, colsz,
                   w.fz.get(), osz, w.ftM, w.ftM2, w.fsplit, w.fpadM, 0, bf16);
