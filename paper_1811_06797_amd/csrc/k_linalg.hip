@@ -305,10 +305,12 @@ __global__ __launch_bounds__(OST) void osbj_gram_kernel(const double* B, int m, 
 
 constexpr int ORT = 256;  // threads per pair in osbj_rot: one per 2 x 2 block of the 32 x 32 Gram matrix
 static_assert(ORT == (OSP / 2) * (OSP / 2), "one thread per 2 x 2 block");
-// Inner Jacobi sweeps per pair and round. The pair's rotation need not diagonalise its Gram
-// matrix fully: the outer iteration revisits every pair each sweep and stops only when no
-// pair needs a rotation at the outer threshold.
-constexpr int OSBJ_INNER_SWEEPS = 1;
+// Inner Jacobi sweeps per pair and round (at most `inner`; a sweep that rotates nothing ends
+// them). The pair's rotation need not diagonalise its Gram matrix fully: the outer iteration
+// revisits every pair each sweep and stops only when no pair needs a rotation at the outer
+// threshold. On the triangular factor of a pivoted QR, whose columns are graded, solving the
+// pair's problem to convergence about halves the outer sweeps; the inner sweeps run in LDS,
+// so they cost little beside the Gram and update passes over the rows.
 
 // Gsum[pair] = sum over chunks of P[pair][chunk] (chunk order), 256 elements per workgroup,
 // eight chunks of loads in flight per thread.
@@ -345,17 +347,23 @@ __device__ __forceinline__ void circle_pair32(int t, int round, int& a, int& b) 
 // both columns are negligible; then t = tan(theta) = sign(tau) / (|tau| + sqrt(1 + tau^2)) with
 // tau = dd / ee, written as sign(tau) |ee| / (|dd| + sqrt(dd^2 + ee^2)) (one division and one
 // root fewer), c = 1 / sqrt(1 + t^2), s = t c, and the new diagonal app - t apq, aqq + t apq.
+// abs2 > 0 also skips a rotation that would move the larger column by at most sqrt(abs2) in
+// norm (t^2 max(app, aqq) <= abs2): on graded columns the block updates leave the small ones
+// with rounding noise of the size of u times the large ones, which the relative test alone
+// keeps chasing.
 struct Rot {
   double c, s, np, nq;
   bool on;
 };
-__device__ __forceinline__ Rot jacobi_rot(double app, double aqq, double apq, double tol, double floor_col) {
+__device__ __forceinline__ Rot jacobi_rot(double app, double aqq, double apq, double tol, double floor_col,
+                                          double abs2) {
   Rot r{1.0, 0.0, app, aqq, false};
   const bool negligible = app <= floor_col && aqq <= floor_col;
   if (!negligible && apq * apq > tol * tol * fabs(app * aqq)) {
     const double dd = aqq - app, ee = 2.0 * apq;
     const double sg = (dd == 0.0 || (dd > 0.0) == (ee > 0.0)) ? 1.0 : -1.0;
     const double t = sg * fabs(ee) / (fabs(dd) + sqrt(dd * dd + ee * ee));
+    if (t * t * fmax(app, aqq) <= abs2) return r;
     r.c = 1.0 / sqrt(1.0 + t * t);
     r.s = t * r.c;
     r.np = app - t * apq;
@@ -366,7 +374,7 @@ __device__ __forceinline__ Rot jacobi_rot(double app, double aqq, double apq, do
 }
 
 __global__ __launch_bounds__(ORT) void osbj_rot_kernel(const double* Gsum, double tol, double floor_col,
-                                                       double* Wout, int* flags) {
+                                                       double abs2, int inner, double* Wout, int* flags) {
   __shared__ double G[OSP][OSP + 1];
   __shared__ double W[OSP][OSP + 1];
   __shared__ double cs[OSP / 2], sn[OSP / 2], dp[OSP / 2], dq[OSP / 2];
@@ -385,7 +393,7 @@ __global__ __launch_bounds__(ORT) void osbj_rot_kernel(const double* Gsum, doubl
     int need = 0;
     for (int e = tid; e < OSP * OSP; e += ORT) {
       const int i = e / OSP, jj = e % OSP;
-      if (i < jj) need |= jacobi_rot(G[i][i], G[jj][jj], G[i][jj], tol, floor_col).on ? 1 : 0;
+      if (i < jj) need |= jacobi_rot(G[i][i], G[jj][jj], G[i][jj], tol, floor_col, abs2).on ? 1 : 0;
     }
     if (!__syncthreads_or(need)) {
       if (tid == 0) flags[pair] = 0;
@@ -399,14 +407,14 @@ __global__ __launch_bounds__(ORT) void osbj_rot_kernel(const double* Gsum, doubl
   // of rotated pairs are stored exactly (zero off-diagonal, closed-form diagonal), so rounding
   // noise in g_pq cannot trigger further rotations.
   const int t1 = tid / (OSP / 2), t2 = tid % (OSP / 2);
-  for (int sweep = 0; sweep < OSBJ_INNER_SWEEPS; ++sweep) {
+  for (int sweep = 0; sweep < inner; ++sweep) {
     if (tid == 0) rot_sweep = 0;
     __syncthreads();
     for (int r2 = 0; r2 < OSP - 1; ++r2) {
       if (tid < OSP / 2) {
         int p, q;
         circle_pair32(tid, r2, p, q);
-        const Rot R = jacobi_rot(G[p][p], G[q][q], G[p][q], tol, floor_col);
+        const Rot R = jacobi_rot(G[p][p], G[q][q], G[p][q], tol, floor_col, abs2);
         if (R.on) rot_sweep = 1;
         cs[tid] = R.c; sn[tid] = R.s; dp[tid] = R.np; dq[tid] = R.nq;
       }
@@ -716,7 +724,8 @@ size_t osbj_work_len(int m, int kv, int nb) {
 }
 
 void osbj_round(hipStream_t s, double* B, int m, long ldb, double* V, int kv, long ldv, int nb, int round,
-                double tol, double floor_col, int* flags, double* work, size_t work_len) {
+                double tol, double floor_col, int* flags, double* work, size_t work_len, int inner,
+                double abs2) {
   require(nb >= 2 && nb % 2 == 0, IGA_EINVAL, "osbj_round: block count must be even");
   require(m >= 1 && kv >= 0, IGA_EINVAL, "osbj_round: bad sizes");
   require(work_len >= osbj_work_len(m, kv, nb), IGA_EINVAL, "osbj_round: workspace too small");
@@ -729,7 +738,7 @@ void osbj_round(hipStream_t s, double* B, int m, long ldb, double* V, int kv, lo
   IGA_HIP(hipGetLastError());
   osbj_sum_kernel<<<dim3(npair, OSP * OSP / 256), 256, 0, s>>>(P, nchunkB, Gs);
   IGA_HIP(hipGetLastError());
-  osbj_rot_kernel<<<npair, ORT, 0, s>>>(Gs, tol, floor_col, Wg, flags);
+  osbj_rot_kernel<<<npair, ORT, 0, s>>>(Gs, tol, floor_col, abs2, std::max(1, inner), Wg, flags);
   IGA_HIP(hipGetLastError());
   osbj_apply_kernel<<<dim3(npair, nchunkB + nchunkV), OST, 0, s>>>(B, m, ldb, V, kv, ldv, nb, round, chunk,
                                                                    nchunkB, Wg, flags);

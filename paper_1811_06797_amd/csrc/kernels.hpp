@@ -209,9 +209,12 @@ void jacobi_eig(hipStream_t s, int nmat, int k, double* H, long strideH, double*
                 double tol, int max_sweeps, int* sweeps_out);
 // One round of the one-sided block Jacobi SVD on B (m x kp, kp = nb * osbj_block(), nb even)
 // with V (kv x kp) accumulated; flags[nb/2] receive 1 for pairs that rotated.
-// work holds osbj_work_len(m, kv, nb) doubles (partial Gram matrices and pair rotations).
+// work holds osbj_work_len(m, kv, nb) doubles (partial Gram matrices and pair rotations);
+// inner: cyclic sweeps on each pair's Gram matrix per round (ended early once converged);
+// abs2 > 0: rotations that would move the larger column by at most sqrt(abs2) are skipped.
 void osbj_round(hipStream_t s, double* B, int m, long ldb, double* V, int kv, long ldv, int nb, int round,
-                double tol, double floor_col, int* flags, double* work, size_t work_len);
+                double tol, double floor_col, int* flags, double* work, size_t work_len, int inner = 1,
+                double abs2 = 0.0);
 size_t osbj_work_len(int m, int kv, int nb);
 int osbj_block();
 // largest k for which jacobi_eig keeps the matrix in LDS
@@ -228,6 +231,17 @@ void chol_block(hipStream_t s, int jb, const double* G, long ldg, double* L, lon
 // index of pivot j (device), a non-positive pivot gives a zero column and adds one to *bad.
 int pchol_max();
 void pivoted_cholesky(hipStream_t s, int k, double* G, int* perm, int* bad);
+// Column-pivoted QR by modified Gram-Schmidt with one reorthogonalisation (k_qrcp.hip).
+// W: column c at W + c * ldw (m entries, overwritten by its remaining part); nrm2[k]: squared
+// remaining norms, -1 once chosen (qrcp_init sets them); Q: rmax x m (direction t in row t);
+// R: rmax x k over the original column indices, zero on entry; s: rmax, qraw: m,
+// part: qrcp_form_blocks(m) doubles; pivots: rmax ints; ctrl: 3 ints, zero on entry. Step j
+// (launched for j = 0, 1, ... < rmax in order) stops the factorisation (ctrl[0] = 1,
+// ctrl[2] = j) when the remaining squared Frobenius norm is <= thr2; later steps do nothing.
+int qrcp_form_blocks(int m);
+void qrcp_init(hipStream_t s, int m, int k, const double* W, long ldw, double* nrm2);
+void qrcp_step(hipStream_t s, int m, int k, int j, double* W, long ldw, double* nrm2, double* Q, double* R,
+               double* sv, double* qraw, double* part, int* pivots, int* ctrl, double thr2);
 // Inverses of the chol_block_size() diagonal blocks of a lower-triangular k x k L, into Linv.
 void trinv_blocks(hipStream_t s, int k, const double* L, long ldl, double* Linv);
 // out[i][:] = in[idx[i]][:], i < m, k columns

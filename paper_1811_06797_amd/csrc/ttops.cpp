@@ -237,9 +237,15 @@ bool cholesky_qr3_rt(iga_ctx* ctx, int m, int k, const double* X, long ldx, doub
 
 }  // namespace
 
-// product_only: the Jacobi iteration may run on the pivoted Cholesky-QR factor (see
-// svd_preconditioned), whose left vectors are accurate only in the product U Sigma.
-static void svd_impl(iga_ctx* ctx, const double* A, int m, int k, long lda, bool trans, Svd& out, bool product_only);
+// How the tall problem is solved: one-sided Jacobi on A itself (PLAIN), on the pivoted
+// Cholesky-QR factor with left vectors accurate only in the product U Sigma (PRODUCT, see
+// svd_preconditioned), or on the factor of the rank-revealing QR step (QR, see svd_qrcp).
+enum SvdMode { SVD_PLAIN, SVD_PRODUCT, SVD_QR };
+// Inner Jacobi sweeps per block pair and round on a triangular factor (graded columns), and
+// the size, relative to ||A||_F, below which a rotation's change of its columns is left out.
+constexpr int QR_INNER_SWEEPS = 1;
+constexpr double QR_ROT_FLOOR = 1e-15;
+static void svd_impl(iga_ctx* ctx, const double* A, int m, int k, long lda, bool trans, Svd& out, SvdMode mode);
 
 // Product form of the tall SVD (m >= k) of B (m x kp, zero-padded beyond column k): R of B P
 // from the column-pivoted shifted Cholesky QR, then one-sided block Jacobi on R^T (k x k),
@@ -269,7 +275,7 @@ static bool svd_preconditioned(iga_ctx* ctx, const double* B, int m, int k, int 
   for (int sweep = 0; sweep < 30; ++sweep) {
     for (int rd = 0; rd < nround; ++rd)
       k::osbj_round(st, X.get(), k, kp, nullptr, 0, kp, nb, rd, tol, floor_col, flags.get() + rd * npair,
-                   work.get(), wlen);
+                   work.get(), wlen, QR_INNER_SWEEPS);
     IGA_HIP(hipMemcpyAsync(hf.data(), flags.get(), hf.size() * sizeof(int), hipMemcpyDeviceToHost, st));
     IGA_HIP(hipStreamSynchronize(st));
     ++sweeps;
@@ -320,22 +326,150 @@ static bool svd_preconditioned(iga_ctx* ctx, const double* B, int m, int k, int 
   return true;
 }
 
+// Tall SVD (m >= k) of B (m x kp row-major, zero-padded beyond column k) through a rank-revealing
+// QR step (Sec. 5, eqs. svd1-svd2: QR of the unfolding, then the SVD of the triangular factor):
+// column-pivoted QR, B P = Q R, stopped at the first r_c with ||R(r_c:, r_c:)||_F <= eta ||B||_F
+// (eta = 1e-14, below every truncation threshold the sweep uses), so that B P = Q_top R_top + E
+// with ||E||_F <= eta ||B||_F; then the one-sided Jacobi iteration on R_top^T (k x r_c) with the
+// rotations accumulated: R_top^T W = Y Sigma gives B P ~ (Q_top W) Sigma Y^T, so U = Q_top W
+// (orthonormal to working accuracy, as a product of an orthonormal Q and a rotation) and
+// V = P Y. The pivoting also preconditions the Jacobi iteration (R_top's rows are graded), and
+// the iteration runs on r_c columns of length k instead of k columns of length m. Singular
+// values past r_c are returned as zero.
+static void svd_qrcp(iga_ctx* ctx, const double* B, int m, int k, int kp, double fro2, Svd& out) {
+  hipStream_t st = ctx->stream;
+  const int rmax = k;
+  DBuf W(ctx, (size_t)k * m), Q(ctx, (size_t)rmax * m), R(ctx, (size_t)rmax * k), sv(ctx, rmax), qraw(ctx, m),
+      part(ctx, k::qrcp_form_blocks(m)), nrm2(ctx, k);
+  IBuf pivots(ctx, rmax), ctrl(ctx, 3);
+  k::copy2d(st, k, m, B, 1, kp, W.get(), m);
+  k::fill(st, (long)rmax * k, 0.0, R.get());
+  const int zeros[3] = {0, 0, 0};
+  IGA_HIP(hipMemcpyAsync(ctrl.get(), zeros, sizeof zeros, hipMemcpyHostToDevice, st));
+  k::qrcp_init(st, m, k, W.get(), m, nrm2.get());
+  const double eta = 1e-14;
+  const double thr2 = eta * eta * fro2;
+  int rc = rmax, j = 0;
+  for (int chunk = 8; j < rmax;) {
+    const int je = std::min(rmax, j + chunk);
+    for (; j < je; ++j)
+      k::qrcp_step(st, m, k, j, W.get(), m, nrm2.get(), Q.get(), R.get(), sv.get(), qraw.get(), part.get(),
+                   pivots.get(), ctrl.get(), thr2);
+    int hc[3];
+    IGA_HIP(hipMemcpyAsync(hc, ctrl.get(), sizeof hc, hipMemcpyDeviceToHost, st));
+    IGA_HIP(hipStreamSynchronize(st));
+    if (hc[0]) {
+      rc = hc[2];
+      break;
+    }
+    chunk = std::min(2 * chunk, 64);
+  }
+  if (rc < 1) rc = 1;  // fro2 > 0: the first step always chooses a column
+  // pivot order: the chosen columns, then the others in their original order
+  std::vector<int> order(k), inv_order(k), hp(rc);
+  IGA_HIP(hipMemcpyAsync(hp.data(), pivots.get(), rc * sizeof(int), hipMemcpyDeviceToHost, st));
+  IGA_HIP(hipStreamSynchronize(st));
+  {
+    std::vector<char> chosen(k, 0);
+    int pos = 0;
+    for (int t = 0; t < rc; ++t) {
+      order[pos++] = hp[t];
+      chosen[hp[t]] = 1;
+    }
+    for (int c = 0; c < k; ++c)
+      if (!chosen[c]) order[pos++] = c;
+    for (int c = 0; c < k; ++c) inv_order[order[c]] = c;
+  }
+  IBuf dorder(ctx, k), dinvo(ctx, k);
+  IGA_HIP(hipMemcpyAsync(dorder.get(), order.data(), k * sizeof(int), hipMemcpyHostToDevice, st));
+  IGA_HIP(hipMemcpyAsync(dinvo.get(), inv_order.data(), k * sizeof(int), hipMemcpyHostToDevice, st));
+  // X = R_top^T in pivot order: k x rcp, zero-padded
+  const int bs = k::osbj_block();
+  const int rcp = ((rc + 2 * bs - 1) / (2 * bs)) * (2 * bs);
+  const int nb = rcp / bs, npair = nb / 2, nround = nb - 1;
+  DBuf RP(ctx, (size_t)rc * k), X(ctx, (size_t)k * rcp), Wr(ctx, (size_t)rcp * rcp);
+  k::gather_cols(st, rc, k, k, R.get(), k, dorder.get(), nullptr, RP.get(), k);
+  k::fill(st, (long)k * rcp, 0.0, X.get());
+  k::copy2d(st, k, rc, RP.get(), 1, k, X.get(), rcp);
+  {
+    std::vector<double> eye((size_t)rcp * rcp, 0.0);
+    for (int i = 0; i < rcp; ++i) eye[(size_t)i * rcp + i] = 1.0;
+    IGA_HIP(hipMemcpyAsync(Wr.get(), eye.data(), eye.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    IGA_HIP(hipStreamSynchronize(st));
+  }
+  const double floor_col = 1e-28 * fro2;
+  const double tol = 4e-16 * std::max(1.0, std::sqrt((double)k));
+  IBuf flags(ctx, (size_t)npair * nround);
+  const size_t wlen = k::osbj_work_len(k, rcp, nb);
+  DBuf work(ctx, wlen);
+  std::vector<int> hf((size_t)npair * nround);
+  int sweeps = 0;
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    for (int rd = 0; rd < nround; ++rd)
+      k::osbj_round(st, X.get(), k, rcp, Wr.get(), rcp, rcp, nb, rd, tol, floor_col, flags.get() + rd * npair,
+                   work.get(), wlen, QR_INNER_SWEEPS, QR_ROT_FLOOR * QR_ROT_FLOOR * fro2);
+    IGA_HIP(hipMemcpyAsync(hf.data(), flags.get(), hf.size() * sizeof(int), hipMemcpyDeviceToHost, st));
+    IGA_HIP(hipStreamSynchronize(st));
+    ++sweeps;
+    bool any = false;
+    for (int f : hf) any = any || f;
+    if (!any) break;
+  }
+  DBuf nrm(ctx, rcp);
+  k::colnorms(st, k, rcp, X.get(), rcp, nrm.get());
+  std::vector<double> sig(rcp);
+  IGA_HIP(hipMemcpyAsync(sig.data(), nrm.get(), rcp * sizeof(double), hipMemcpyDeviceToHost, st));
+  IGA_HIP(hipStreamSynchronize(st));
+  std::vector<int> idx(rcp);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return sig[a] > sig[b]; });
+  const int p = k;
+  out.m = m; out.k = k; out.p = p;
+  out.sigma.assign(p, 0.0);
+  std::vector<int> id(idx.begin(), idx.begin() + rc);
+  std::vector<double> sg(rc), inv(rc);
+  for (int t = 0; t < rc; ++t) {
+    sg[t] = out.sigma[t] = sig[id[t]];
+    inv[t] = sg[t] > 0 ? 1.0 / sg[t] : 0.0;
+  }
+  IBuf didx(ctx, rc);
+  DBuf dsg(ctx, rc), dinv(ctx, rc);
+  IGA_HIP(hipMemcpyAsync(didx.get(), id.data(), rc * sizeof(int), hipMemcpyHostToDevice, st));
+  IGA_HIP(hipMemcpyAsync(dsg.get(), sg.data(), rc * sizeof(double), hipMemcpyHostToDevice, st));
+  IGA_HIP(hipMemcpyAsync(dinv.get(), inv.data(), rc * sizeof(double), hipMemcpyHostToDevice, st));
+  // U Sigma = Q_top^T-as-columns times (W Sigma) in the sorted order
+  DBuf WS(ctx, (size_t)rc * rc), Y(ctx, (size_t)k * rc);
+  k::gather_cols(st, rc, rcp, rc, Wr.get(), rcp, didx.get(), dsg.get(), WS.get(), rc);
+  out.B.reset(ctx, (size_t)m * p);
+  out.V.reset(ctx, (size_t)k * p);
+  if (rc < p) {
+    k::fill(st, (long)m * p, 0.0, out.B.get());
+    k::fill(st, (long)k * p, 0.0, out.V.get());
+  }
+  k::gemm_rm(st, m, rc, rc, Q.get(), m, true, WS.get(), rc, false, out.B.get(), p);
+  // V = P Y: row order[c] of V is row c of Y
+  k::gather_cols(st, k, rcp, rc, X.get(), rcp, didx.get(), dinv.get(), Y.get(), rc);
+  k::gather_rows(st, k, rc, Y.get(), rc, dinvo.get(), out.V.get(), p);
+  out.passes = sweeps;
+  IGA_HIP(hipStreamSynchronize(st));
+}
+
 void svd(iga_ctx* ctx, const double* A, int m, int k, long lda, bool trans, Svd& out) {
-  svd_impl(ctx, A, m, k, lda, trans, out, false);
+  svd_impl(ctx, A, m, k, lda, trans, out, SVD_QR);
 }
 
 void svd_product(iga_ctx* ctx, const double* A, int m, int k, long lda, bool trans, Svd& out) {
-  svd_impl(ctx, A, m, k, lda, trans, out, true);
+  svd_impl(ctx, A, m, k, lda, trans, out, SVD_PRODUCT);
 }
 
-static void svd_impl(iga_ctx* ctx, const double* A, int m, int k, long lda, bool trans, Svd& out, bool product_only) {
+static void svd_impl(iga_ctx* ctx, const double* A, int m, int k, long lda, bool trans, Svd& out, SvdMode mode) {
   require(m >= 1 && k >= 1, IGA_EINVAL, "svd: empty matrix");
   hipStream_t st = ctx->stream;
   if (m < k) {
     // work on the tall transpose: A^T = U' S V'^T  =>  A = V' S U'^T (A's left vectors are the
     // transpose's right vectors)
     Svd t;
-    svd_impl(ctx, A, k, m, lda, !trans, t, product_only);
+    svd_impl(ctx, A, k, m, lda, !trans, t, mode);
     const int p = t.p;
     std::vector<double> sg(t.sigma.begin(), t.sigma.begin() + p), inv(p);
     for (int j = 0; j < p; ++j) inv[j] = sg[j] > 0 ? 1.0 / sg[j] : 0.0;
@@ -373,9 +507,13 @@ static void svd_impl(iga_ctx* ctx, const double* A, int m, int k, long lda, bool
   const double fro2 = norm2_host(ctx, (long)m * kp, B.get());
   // NaN or Inf would also break the ordering of the singular values below
   require(std::isfinite(fro2), IGA_ENUM, "svd: the matrix holds a non-finite entry");
-  if (product_only && k > 2 * bs && k <= k::pchol_max() && fro2 > 0 &&
+  if (mode == SVD_PRODUCT && k > 2 * bs && k <= k::pchol_max() && fro2 > 0 &&
       svd_preconditioned(ctx, B.get(), m, k, kp, fro2, out))
     return;
+  if (mode == SVD_QR && k > 2 * bs && fro2 > 0) {
+    svd_qrcp(ctx, B.get(), m, k, kp, fro2, out);
+    return;
+  }
   const double floor_col = 1e-28 * fro2;
   const double tol = 4e-16 * std::max(1.0, std::sqrt((double)m));
   const int npair = nb / 2, nround = nb - 1;
@@ -446,8 +584,9 @@ static void eig_sym(iga_ctx* ctx, int k, const double* X, double* Vc, double* la
     k::transpose_square(st, 1, k, WT.get(), 0, Vc, 0);
     return;
   }
+  // a symmetric positive definite matrix of full rank: the QR step would not shorten anything
   Svd s;
-  svd(ctx, X, k, k, k, false, s);
+  svd_impl(ctx, X, k, k, k, false, s, SVD_PLAIN);
   IGA_HIP(hipMemcpyAsync(Vc, s.V.get(), (size_t)k * k * sizeof(double), hipMemcpyDeviceToDevice, st));
   k::coldots(st, k, k, s.V.get(), k, s.B.get(), k, lam);
 }
