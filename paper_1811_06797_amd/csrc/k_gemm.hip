@@ -566,7 +566,7 @@ static G2Args make_args(const Gemm2& d) {
 }
 
 // Output tile of each variant: 0: 64 x 64, 1: 32 x 128, 2: 16 x 256, 3: 128 x 32, 4: 64 x (32 WIDE_WN),
-// 5: 80 x 64.
+// 5: 80 x 64, 6: 64 x 96, 7: 96 x 64.
 static void variant_tile(int v, int& BM, int& BN) {
   switch (v) {
     case 1: BM = 32; BN = 128; break;
@@ -574,11 +574,15 @@ static void variant_tile(int v, int& BM, int& BN) {
     case 3: BM = 128; BN = 32; break;
     case 4: BM = 64; BN = 32 * IGA_WIDE_WN; break;
     case 5: BM = 80; BN = 64; break;
+    case 6: BM = 64; BN = 96; break;
+    case 7: BM = 96; BN = 64; break;
     default: BM = 64; BN = 64; break;
   }
 }
 
-int gemm2_variants() { return 6; }
+int gemm2_variants() { return 8; }
+
+static bool dma_eligible(const Gemm2& d);
 
 int gemm2_pick(const Gemm2& d) {
   const long nb = (long)d.nb1 * d.nb2;
@@ -590,7 +594,13 @@ int gemm2_pick(const Gemm2& d) {
   // tall products with more than 64 columns (the interface stages of the local matvec, whose
   // columns are output ranks or (row, rank) pairs): a 128-wide column tile reads each row tile
   // of the long operand half as often as 64-wide tiles (measured 1.05-1.4x on those stages)
-  if (d.M > 256 && d.N > 64) return 4;
+  // Without the LDS-direct loads a 96-wide tile runs about as fast per flop, so it is taken
+  // where it pads the columns less (output ranks such as 74, 90 or 163: measured 1.04x on the
+  // right-interface stage)
+  if (d.M > 256 && d.N > 64) {
+    const long w96 = (d.N + 95) / 96 * 96L, w128 = (d.N + 127) / 128 * 128L;
+    return (w96 < w128 && !dma_eligible(d)) ? 6 : 4;
+  }
   return 0;
 }
 
@@ -625,6 +635,8 @@ void gemm2_grouped(hipStream_t s, int variant, const void* dev_desc, const int* 
                                                                                          ngemm, total);
       break;
     case 5: launch_grouped<10, 2, 2, 2, 16, 2, IGA_PREFETCH>(s, dev_desc, dev_prefix, ngemm, total); break;
+    case 6: launch_grouped<8, 3, 2, 2, 16, 2, IGA_PREFETCH>(s, dev_desc, dev_prefix, ngemm, total); break;
+    case 7: launch_grouped<12, 2, 2, 2, 16, 2, IGA_PREFETCH>(s, dev_desc, dev_prefix, ngemm, total); break;
     default: launch_grouped<8, 2, 2, 2, 16, 2, IGA_PREFETCH>(s, dev_desc, dev_prefix, ngemm, total); break;
   }
   IGA_HIP(hipGetLastError());
@@ -645,7 +657,7 @@ void gemm2(hipStream_t s, const Gemm2& d, double* work, size_t work_len) {
   G2Args a = make_args(d);
   const long nb = a.nbatch;
   // tile shape by output shape
-  const int variant = gemm2_pick(d);
+  const int variant = d.variant >= 0 ? d.variant : gemm2_pick(d);
   int BM, BN;
   variant_tile(variant, BM, BN);
   const long tiles = (long)((d.M + BM - 1) / BM) * ((d.N + BN - 1) / BN) * nb;
@@ -682,6 +694,8 @@ void gemm2(hipStream_t s, const Gemm2& d, double* work, size_t work_len) {
     case 3: launch<8, 2, 4, 1, 16, 2, IGA_PREFETCH>(s, a, (int)nb); break;
     case 4: launch<8, IGA_WIDE_WN, 2, 2, IGA_WIDE_BK, IGA_WIDE_NBUF, IGA_WIDE_PREFETCH>(s, a, (int)nb); break;
     case 5: launch<10, 2, 2, 2, 16, 2, IGA_PREFETCH>(s, a, (int)nb); break;
+    case 6: launch<8, 3, 2, 2, 16, 2, IGA_PREFETCH>(s, a, (int)nb); break;
+    case 7: launch<12, 2, 2, 2, 16, 2, IGA_PREFETCH>(s, a, (int)nb); break;
     default: launch<8, 2, 2, 2, 16, 2, IGA_PREFETCH>(s, a, (int)nb); break;
   }
   }

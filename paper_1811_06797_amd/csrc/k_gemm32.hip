@@ -740,7 +740,7 @@ static void gemm2_fstore(hipStream_t s, const Gemm2F& d, float* work, size_t wor
   if (d.M <= 0 || d.N <= 0 || d.nb1 <= 0 || d.nb2 <= 0) return;
   G2FArgs a = make_args_f(d);
   const long nb = a.nbatch;
-  const int variant = gemm2f_pick(d);
+  const int variant = d.variant >= 0 ? d.variant : gemm2f_pick(d);
   int BM, BN;
   variant_tile_f(variant, BM, BN);
   const long tiles = (long)((d.M + BM - 1) / BM) * ((d.N + BN - 1) / BN) * nb;

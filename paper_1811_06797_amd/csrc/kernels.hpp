@@ -45,6 +45,8 @@ struct Gemm2 {
   // tiles of consecutive batch entries run together (set when the batch index is the row of a
   // banded product whose B operand windows overlap from row to row)
   bool batch_inner = false;
+  // tile variant (see gemm2_pick); -1: chosen from the shape
+  int variant = -1;
 };
 void gemm2(hipStream_t s, const Gemm2& g);
 // Same, with a workspace of work_len doubles that lets short-output, long-K products be split
@@ -77,6 +79,7 @@ struct Gemm2F {
   long sAb1 = 0, sAb2 = 0, sBb1 = 0, sBb2 = 0, sCb1 = 0, sCb2 = 0;
   float alpha = 1.0f, beta = 0.0f;
   bool batch_inner = false;  // as in Gemm2
+  int variant = -1;          // tile variant (see gemm2f_pick); -1: chosen from the shape
 };
 void gemm2_f32(hipStream_t s, const Gemm2F& g, float* work, size_t work_len);
 // same products with the operands rounded to bfloat16 and BF16 matrix-core products (FP32 accumulation)
