@@ -1,22 +1,22 @@
-// Column-pivoted QR of a tall m x k matrix by modified Gram-Schmidt with one
-// reorthogonalisation of each new direction, stopped once the columns not yet chosen have a
-// Frobenius norm at or below a threshold: the QR step in front of the truncation SVD (the
-// unfolding is factored, then only the small triangular factor goes to the SVD; Sec. 5,
-// eqs. svd1-svd2). Greedy pivoting (the column with the largest remaining norm) makes the
-// factor rank revealing: the part left out is exactly the remaining columns.
+// Column-pivoted Householder QR of a tall m x k matrix, stopped once the columns not yet chosen
+// have a Frobenius norm (of their rows below the factored ones) at or below a threshold: the
+// QR step in front of the truncation SVD (the unfolding is factored, then only the small
+// triangular factor goes to the SVD; Sec. 5, eqs. svd1-svd2). Greedy pivoting (the column with
+// the largest remaining norm) makes the factor rank revealing: the part left out is exactly
+// the remaining block.
 //
-// Layout: the working copy W holds column c contiguously at W + c * ldw (m entries); Q holds
-// direction t as row t (m entries); R is rmax x k row-major over the original column indices;
-// nrm2[c] is the squared norm of column c's remaining part, -1 once c is chosen.
+// Layout: the working copy W holds column c contiguously at W + c * ldw (m entries, reflected in
+// place); V holds reflector t in row t (entries t..m-1); R is rmax x k row-major over the
+// original column indices, zero on entry; the squared remaining norms are recomputed exactly at
+// every step, -1 once a column is chosen.
 //
-// One step j is three launches: pivot (every workgroup finds the same argmax and the same
-// remaining norm, in a fixed reduction order; the dots of the chosen column with the earlier
-// directions), form (the column minus its components along the earlier directions, with
-// per-workgroup partial norms) and update (normalise, project every remaining column, store
-// its coefficient in R and recompute its remaining norm). The step index is a launch argument,
-// so no workgroup ever reads a counter that another one writes in the same launch. (A chunk of
-// steps in one cooperative launch, the phases separated by grid-wide barriers, measured five
-// times slower per step than the three launches.)
+// One step is one launch with one workgroup per column: every workgroup finds the same argmax
+// and the same remaining norm (fixed reduction order), builds the reflector from the pivot
+// column, which no workgroup writes in that step, and reflects its own column. The norms are
+// double-buffered (read one array, write the other), so no workgroup reads a value another one
+// writes in the same launch. (Modified Gram-Schmidt with reorthogonalisation needs three
+// dependent launches per step, and a chunk of steps in one cooperative launch with grid-wide
+// barriers measured five times slower per step than those launches.)
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -26,7 +26,6 @@ namespace {
 
 constexpr int QT = 256;       // threads per workgroup of the pivot and update kernels
 constexpr int QWAVES = QT / 64;
-constexpr int FT = 64;        // threads per workgroup of the form kernel (one element each)
 
 __device__ inline double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -85,15 +84,22 @@ __global__ __launch_bounds__(QT) void qrcp_init_kernel(int m, const double* W, l
   if (threadIdx.x == 0) nrm2[blockIdx.x] = acc;
 }
 
-// ctrl[0]: done flag, ctrl[1]: pivot of the current step, ctrl[2]: number of columns chosen.
-// Workgroup t (t < j) forms s_t = q_t . a_p; launched with max(j, 1) workgroups.
-__global__ __launch_bounds__(QT) void qrcp_pivot_kernel(int m, int k, int j, const double* W, long ldw,
-                                                        const double* nrm2, const double* Q, double* s,
-                                                        int* ctrl, double thr2) {
+// Step j: one workgroup per column c. ctrl[0]: done flag, ctrl[2]: number of columns chosen.
+// nin[c] = ||W[c][j:m)||^2 (-1 once chosen) is only read and nout only written, so the argmax
+// that every workgroup takes first sees the same values in all of them. The reflector
+// H = I - beta v v^T maps the pivot column's rows j..m-1 to alpha e_j, alpha = -sign(x_j) ||x||;
+// v = x - alpha e_j is built by every workgroup from the pivot column, which nobody writes in
+// this step. Column c's rows j..m-1 are reflected in place; row j becomes R[j][c] and the new
+// squared norm of rows j+1..m-1 goes to nout[c]. With RC > 0 (m <= QT RC) the column stays in
+// registers between the dot product and the update.
+template <int RC>
+__global__ __launch_bounds__(QT) void qrhh_step_kernel(int m, int k, int j, double* W, long ldw, const double* nin,
+                                                       double* nout, double* V, double* beta, double* R,
+                                                       int* pivots, int* ctrl, double thr2) {
   if (ctrl[0]) return;
   int p;
   double tail;
-  pivot_of(k, nrm2, p, tail);
+  pivot_of(k, nin, p, tail);
   if (p < 0 || !(tail > thr2)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       ctrl[0] = 1;
@@ -101,107 +107,143 @@ __global__ __launch_bounds__(QT) void qrcp_pivot_kernel(int m, int k, int j, con
     }
     return;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) ctrl[1] = p;
-  const int t = blockIdx.x;
-  if (t >= j) return;
   const double* a = W + (long)p * ldw;
-  const double* q = Q + (long)t * m;
-  double acc = 0.0;
-  for (int x = threadIdx.x; x < m; x += QT) acc = fma(q[x], a[x], acc);
-  acc = block_total(acc);
-  if (threadIdx.x == 0) s[t] = acc;
-}
-
-// qraw = a_p - sum_{t<j} s_t q_t; part[block] = its partial squared norm
-__global__ __launch_bounds__(FT) void qrcp_form_kernel(int m, int j, const double* W, long ldw, const double* Q,
-                                                       const double* s, const int* ctrl, double* qraw,
-                                                       double* part) {
-  if (ctrl[0]) return;
-  const int p = ctrl[1];
-  const int x = blockIdx.x * FT + threadIdx.x;
-  double v = 0.0;
-  if (x < m) {
-    // four independent partial sums keep several loads in flight
-    double a0 = W[(long)p * ldw + x], a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int t = 0;
-    for (; t + 4 <= j; t += 4) {
-      a0 = fma(-s[t], Q[(long)t * m + x], a0);
-      a1 = fma(-s[t + 1], Q[(long)(t + 1) * m + x], a1);
-      a2 = fma(-s[t + 2], Q[(long)(t + 2) * m + x], a2);
-      a3 = fma(-s[t + 3], Q[(long)(t + 3) * m + x], a3);
-    }
-    for (; t < j; ++t) a0 = fma(-s[t], Q[(long)t * m + x], a0);
-    v = (a0 + a1) + (a2 + a3);
-    qraw[x] = v;
-  }
-  const double tot = wave_sum(v * v);
-  if (threadIdx.x == 0) part[blockIdx.x] = tot;
-}
-
-// one workgroup per column: normalise the new direction (every workgroup its slice of rows),
-// project the column, store its coefficient and its new remaining norm
-__global__ __launch_bounds__(QT) void qrcp_update_kernel(int m, int k, int j, double* W, long ldw, double* Q,
-                                                         const double* s, const double* qraw,
-                                                         const double* part, int nparts, double* R,
-                                                         double* nrm2, int* pivots, const int* ctrl) {
-  if (ctrl[0]) return;
-  const int p = ctrl[1];
-  // every workgroup sums the partial norms in the same order
-  double a = 0.0;
-  for (int b = threadIdx.x; b < nparts; b += QT) a += part[b];
-  // block_total's order is fixed, so all workgroups get the same rjj
-  const double rjj = sqrt(block_total(a));
-  const double inv = rjj > 0.0 ? 1.0 / rjj : 0.0;
-  {
-    const int per = (m + gridDim.x - 1) / gridDim.x;
-    const int x0 = blockIdx.x * per, x1 = min(m, x0 + per);
-    for (int x = x0 + threadIdx.x; x < x1; x += QT) Q[(long)j * m + x] = qraw[x] * inv;
-  }
-  if (blockIdx.x == 0) {
-    for (int t = threadIdx.x; t < j; t += QT) R[(long)t * k + p] += s[t];
-    if (threadIdx.x == 0) {
-      R[(long)j * k + p] = rjj;
-      nrm2[p] = -1.0;
-      pivots[j] = p;
-    }
-  }
+  const double x0 = a[j], xn = sqrt(nin[p]);
+  const double alpha = x0 >= 0.0 ? -xn : xn;
+  const double v0 = x0 - alpha;
+  const double vn2 = 2.0 * xn * (xn + fabs(x0));  // ||v||^2 without cancellation
+  const double bt = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
   const int c = blockIdx.x;
-  if (c == p || nrm2[c] < 0.0) return;
+  if (c == p) {
+    for (int x = j + threadIdx.x; x < m; x += QT) V[(long)j * m + x] = x == j ? v0 : a[x];
+    if (threadIdx.x == 0) {
+      R[(long)j * k + p] = alpha;
+      beta[j] = bt;
+      pivots[j] = p;
+      nout[p] = -1.0;
+    }
+    return;
+  }
+  if (nin[c] < 0.0) {
+    if (threadIdx.x == 0) nout[c] = -1.0;
+    return;
+  }
   double* w = W + (long)c * ldw;
-  double acc = 0.0;
-  for (int x = threadIdx.x; x < m; x += QT) acc = fma(qraw[x], w[x], acc);
-  const double r = block_total(acc) * inv;
-  const double g = r * inv;
-  double n2 = 0.0;
-  for (int x = threadIdx.x; x < m; x += QT) {
-    const double v = fma(-g, qraw[x], w[x]);
-    w[x] = v;
-    n2 = fma(v, v, n2);
+  auto vat = [&](int x) { return x == j ? v0 : a[x]; };
+  double acc = 0.0, n2 = 0.0;
+  if constexpr (RC > 0) {
+    double wr[RC];
+#pragma unroll
+    for (int u = 0; u < RC; ++u) {
+      const int x = threadIdx.x + u * QT;
+      const bool in = x >= j && x < m;
+      wr[u] = in ? w[x] : 0.0;
+      acc = fma(in ? vat(x) : 0.0, wr[u], acc);
+    }
+    const double g = bt * block_total(acc);
+#pragma unroll
+    for (int u = 0; u < RC; ++u) {
+      const int x = threadIdx.x + u * QT;
+      if (x >= j && x < m) {
+        const double v = fma(-g, vat(x), wr[u]);
+        w[x] = v;
+        if (x == j)
+          R[(long)j * k + c] = v;
+        else
+          n2 = fma(v, v, n2);
+      }
+    }
+  } else {
+    for (int x = j + threadIdx.x; x < m; x += QT) acc = fma(vat(x), w[x], acc);
+    const double g = bt * block_total(acc);
+    for (int x = j + threadIdx.x; x < m; x += QT) {
+      const double v = fma(-g, vat(x), w[x]);
+      w[x] = v;
+      if (x == j)
+        R[(long)j * k + c] = v;
+      else
+        n2 = fma(v, v, n2);
+    }
   }
   n2 = block_total(n2);
-  if (threadIdx.x == 0) {
-    R[(long)j * k + c] = r;
-    nrm2[c] = n2;
+  if (threadIdx.x == 0) nout[c] = n2;
+}
+
+// Y <- H_0 H_1 ... H_{rc-1} Y for the columns of Y (column col at Y + col * m, m entries), one
+// workgroup per column: the reflectors applied from the last to the first.
+template <int RC>
+__global__ __launch_bounds__(QT) void qrhh_apply_kernel(int m, int rc, const double* V, const double* beta,
+                                                        double* Y) {
+  double* y = Y + (long)blockIdx.x * m;
+  if constexpr (RC > 0) {
+    double yr[RC];
+#pragma unroll
+    for (int u = 0; u < RC; ++u) {
+      const int x = threadIdx.x + u * QT;
+      yr[u] = x < m ? y[x] : 0.0;
+    }
+    for (int t = rc - 1; t >= 0; --t) {
+      const double* v = V + (long)t * m;
+      double acc = 0.0;
+#pragma unroll
+      for (int u = 0; u < RC; ++u) {
+        const int x = threadIdx.x + u * QT;
+        if (x >= t && x < m) acc = fma(v[x], yr[u], acc);
+      }
+      const double g = beta[t] * block_total(acc);
+#pragma unroll
+      for (int u = 0; u < RC; ++u) {
+        const int x = threadIdx.x + u * QT;
+        if (x >= t && x < m) yr[u] = fma(-g, v[x], yr[u]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < RC; ++u) {
+      const int x = threadIdx.x + u * QT;
+      if (x < m) y[x] = yr[u];
+    }
+  } else {
+    for (int t = rc - 1; t >= 0; --t) {
+      const double* v = V + (long)t * m;
+      double acc = 0.0;
+      for (int x = t + threadIdx.x; x < m; x += QT) acc = fma(v[x], y[x], acc);
+      const double g = beta[t] * block_total(acc);
+      for (int x = t + threadIdx.x; x < m; x += QT) y[x] = fma(-g, v[x], y[x]);
+      __syncthreads();
+    }
   }
 }
 
 }  // namespace
-
-int qrcp_form_blocks(int m) { return (m + FT - 1) / FT; }
 
 void qrcp_init(hipStream_t st, int m, int k, const double* W, long ldw, double* nrm2) {
   qrcp_init_kernel<<<k, QT, 0, st>>>(m, W, ldw, nrm2);
   IGA_HIP(hipGetLastError());
 }
 
-void qrcp_step(hipStream_t st, int m, int k, int j, double* W, long ldw, double* nrm2, double* Q, double* R,
-               double* s, double* qraw, double* part, int* pivots, int* ctrl, double thr2) {
-  const int nparts = qrcp_form_blocks(m);
-  qrcp_pivot_kernel<<<std::max(j, 1), QT, 0, st>>>(m, k, j, W, ldw, nrm2, Q, s, ctrl, thr2);
+void qrhh_step(hipStream_t st, int m, int k, int j, double* W, long ldw, const double* nin, double* nout,
+               double* V, double* beta, double* R, int* pivots, int* ctrl, double thr2) {
+  if (m <= 8 * QT)
+    qrhh_step_kernel<8><<<k, QT, 0, st>>>(m, k, j, W, ldw, nin, nout, V, beta, R, pivots, ctrl, thr2);
+  else if (m <= 16 * QT)
+    qrhh_step_kernel<16><<<k, QT, 0, st>>>(m, k, j, W, ldw, nin, nout, V, beta, R, pivots, ctrl, thr2);
+  else if (m <= 48 * QT)
+    qrhh_step_kernel<48><<<k, QT, 0, st>>>(m, k, j, W, ldw, nin, nout, V, beta, R, pivots, ctrl, thr2);
+  else
+    qrhh_step_kernel<0><<<k, QT, 0, st>>>(m, k, j, W, ldw, nin, nout, V, beta, R, pivots, ctrl, thr2);
   IGA_HIP(hipGetLastError());
-  qrcp_form_kernel<<<nparts, FT, 0, st>>>(m, j, W, ldw, Q, s, ctrl, qraw, part);
-  IGA_HIP(hipGetLastError());
-  qrcp_update_kernel<<<k, QT, 0, st>>>(m, k, j, W, ldw, Q, s, qraw, part, nparts, R, nrm2, pivots, ctrl);
+}
+
+void qrhh_apply(hipStream_t st, int m, int rc, const double* V, const double* beta, int ncol, double* Y) {
+  if (ncol <= 0 || rc <= 0) return;
+  if (m <= 8 * QT)
+    qrhh_apply_kernel<8><<<ncol, QT, 0, st>>>(m, rc, V, beta, Y);
+  else if (m <= 16 * QT)
+    qrhh_apply_kernel<16><<<ncol, QT, 0, st>>>(m, rc, V, beta, Y);
+  else if (m <= 48 * QT)
+    qrhh_apply_kernel<48><<<ncol, QT, 0, st>>>(m, rc, V, beta, Y);
+  else
+    qrhh_apply_kernel<0><<<ncol, QT, 0, st>>>(m, rc, V, beta, Y);
   IGA_HIP(hipGetLastError());
 }
 

@@ -234,17 +234,19 @@ void chol_block(hipStream_t s, int jb, const double* G, long ldg, double* L, lon
 // index of pivot j (device), a non-positive pivot gives a zero column and adds one to *bad.
 int pchol_max();
 void pivoted_cholesky(hipStream_t s, int k, double* G, int* perm, int* bad);
-// Column-pivoted QR by modified Gram-Schmidt with one reorthogonalisation (k_qrcp.hip).
-// W: column c at W + c * ldw (m entries, overwritten by its remaining part); nrm2[k]: squared
-// remaining norms, -1 once chosen (qrcp_init sets them); Q: rmax x m (direction t in row t);
-// R: rmax x k over the original column indices, zero on entry; s: rmax, qraw: m,
-// part: qrcp_form_blocks(m) doubles; pivots: rmax ints; ctrl: 3 ints, zero on entry. Step j
-// (launched for j = 0, 1, ... < rmax in order) stops the factorisation (ctrl[0] = 1,
-// ctrl[2] = j) when the remaining squared Frobenius norm is <= thr2; later steps do nothing.
-int qrcp_form_blocks(int m);
+// Column-pivoted Householder QR (k_qrcp.hip). W: column c at W + c * ldw (m entries, reflected
+// in place); qrcp_init sets nrm2[k] to the squared column norms. Step j (launched for
+// j = 0, 1, ... < rmax in order) reads the squared remaining norms from nin and writes them to
+// nout (swap the two arrays between steps; -1 marks a chosen column), writes reflector j into
+// row j of V (rmax x m) and beta[j], row j of R (rmax x k, original column indices, zero on
+// entry) and pivots[j]; when the remaining squared Frobenius norm is <= thr2 it stops the
+// factorisation instead (ctrl[0] = 1, ctrl[2] = j; ctrl: 3 ints, zero on entry) and later
+// steps do nothing. qrhh_apply: Y <- H_0 ... H_{rc-1} Y for ncol columns (column c at
+// Y + c * m).
 void qrcp_init(hipStream_t s, int m, int k, const double* W, long ldw, double* nrm2);
-void qrcp_step(hipStream_t s, int m, int k, int j, double* W, long ldw, double* nrm2, double* Q, double* R,
-               double* sv, double* qraw, double* part, int* pivots, int* ctrl, double thr2);
+void qrhh_step(hipStream_t s, int m, int k, int j, double* W, long ldw, const double* nin, double* nout,
+               double* V, double* beta, double* R, int* pivots, int* ctrl, double thr2);
+void qrhh_apply(hipStream_t s, int m, int rc, const double* V, const double* beta, int ncol, double* Y);
 // Inverses of the chol_block_size() diagonal blocks of a lower-triangular k x k L, into Linv.
 void trinv_blocks(hipStream_t s, int k, const double* L, long ldl, double* Linv);
 // out[i][:] = in[idx[i]][:], i < m, k columns

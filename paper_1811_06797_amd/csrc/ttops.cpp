@@ -328,33 +328,37 @@ static bool svd_preconditioned(iga_ctx* ctx, const double* B, int m, int k, int 
 
 // Tall SVD (m >= k) of B (m x kp row-major, zero-padded beyond column k) through a rank-revealing
 // QR step (Sec. 5, eqs. svd1-svd2: QR of the unfolding, then the SVD of the triangular factor):
-// column-pivoted QR, B P = Q R, stopped at the first r_c with ||R(r_c:, r_c:)||_F <= eta ||B||_F
-// (eta = 1e-14, below every truncation threshold the sweep uses), so that B P = Q_top R_top + E
-// with ||E||_F <= eta ||B||_F; then the one-sided Jacobi iteration on R_top^T (k x r_c) with the
-// rotations accumulated: R_top^T W = Y Sigma gives B P ~ (Q_top W) Sigma Y^T, so U = Q_top W
-// (orthonormal to working accuracy, as a product of an orthonormal Q and a rotation) and
-// V = P Y. The pivoting also preconditions the Jacobi iteration (R_top's rows are graded), and
+// column-pivoted Householder QR, B P = Q R, stopped at the first r_c with
+// ||R(r_c:, r_c:)||_F <= eta ||B||_F (eta = 1e-14, below every truncation threshold the sweep
+// uses), so that B P = Q_top R_top + E with ||E||_F <= eta ||B||_F; then the one-sided Jacobi
+// iteration on R_top^T (k x r_c) with the rotations accumulated: R_top^T W = Y Sigma gives
+// B P ~ (Q_top W) Sigma Y^T, so U = Q_top W (orthonormal to working accuracy: the reflectors
+// applied to the columns of a rotation) and V = P Y. The pivoting also preconditions the Jacobi iteration (R_top's rows are graded), and
 // the iteration runs on r_c columns of length k instead of k columns of length m. Singular
 // values past r_c are returned as zero.
 static void svd_qrcp(iga_ctx* ctx, const double* B, int m, int k, int kp, double fro2, Svd& out) {
   hipStream_t st = ctx->stream;
   const int rmax = k;
-  DBuf W(ctx, (size_t)k * m), Q(ctx, (size_t)rmax * m), R(ctx, (size_t)rmax * k), sv(ctx, rmax), qraw(ctx, m),
-      part(ctx, k::qrcp_form_blocks(m)), nrm2(ctx, k);
+  DBuf W(ctx, (size_t)k * m), V(ctx, (size_t)rmax * m), R(ctx, (size_t)rmax * k), beta(ctx, rmax),
+      rnorm(ctx, 2 * (size_t)k);
   IBuf pivots(ctx, rmax), ctrl(ctx, 3);
   k::copy2d(st, k, m, B, 1, kp, W.get(), m);
   k::fill(st, (long)rmax * k, 0.0, R.get());
   const int zeros[3] = {0, 0, 0};
   IGA_HIP(hipMemcpyAsync(ctrl.get(), zeros, sizeof zeros, hipMemcpyHostToDevice, st));
-  k::qrcp_init(st, m, k, W.get(), m, nrm2.get());
+  k::qrcp_init(st, m, k, W.get(), m, rnorm.get());
   const double eta = 1e-14;
   const double thr2 = eta * eta * fro2;
   int rc = rmax, j = 0;
   for (int chunk = 8; j < rmax;) {
     const int je = std::min(rmax, j + chunk);
-    for (; j < je; ++j)
-      k::qrcp_step(st, m, k, j, W.get(), m, nrm2.get(), Q.get(), R.get(), sv.get(), qraw.get(), part.get(),
-                   pivots.get(), ctrl.get(), thr2);
+    for (; j < je; ++j) {
+      // step j reads the norms written by step j - 1 (the two halves of rnorm alternate)
+      const double* nin = rnorm.get() + (j % 2) * (size_t)k;
+      double* nout = rnorm.get() + ((j + 1) % 2) * (size_t)k;
+      k::qrhh_step(st, m, k, j, W.get(), m, nin, nout, V.get(), beta.get(), R.get(), pivots.get(), ctrl.get(),
+                   thr2);
+    }
     int hc[3];
     IGA_HIP(hipMemcpyAsync(hc, ctrl.get(), sizeof hc, hipMemcpyDeviceToHost, st));
     IGA_HIP(hipStreamSynchronize(st));
@@ -437,16 +441,20 @@ static void svd_qrcp(iga_ctx* ctx, const double* B, int m, int k, int kp, double
   IGA_HIP(hipMemcpyAsync(didx.get(), id.data(), rc * sizeof(int), hipMemcpyHostToDevice, st));
   IGA_HIP(hipMemcpyAsync(dsg.get(), sg.data(), rc * sizeof(double), hipMemcpyHostToDevice, st));
   IGA_HIP(hipMemcpyAsync(dinv.get(), inv.data(), rc * sizeof(double), hipMemcpyHostToDevice, st));
-  // U Sigma = Q_top^T-as-columns times (W Sigma) in the sorted order
-  DBuf WS(ctx, (size_t)rc * rc), Y(ctx, (size_t)k * rc);
+  // U Sigma = Q_top (W Sigma) in the sorted order: the columns of W Sigma, padded with zero rows
+  // to length m, reflected by H_{rc-1} .. H_0
+  DBuf WS(ctx, (size_t)rc * rc), Yc(ctx, (size_t)rc * m), Y(ctx, (size_t)k * rc);
   k::gather_cols(st, rc, rcp, rc, Wr.get(), rcp, didx.get(), dsg.get(), WS.get(), rc);
+  k::fill(st, (long)rc * m, 0.0, Yc.get());
+  k::copy2d(st, rc, rc, WS.get(), 1, rc, Yc.get(), m);  // Yc[col][x] = WS[x][col]
+  k::qrhh_apply(st, m, rc, V.get(), beta.get(), rc, Yc.get());
   out.B.reset(ctx, (size_t)m * p);
   out.V.reset(ctx, (size_t)k * p);
   if (rc < p) {
     k::fill(st, (long)m * p, 0.0, out.B.get());
     k::fill(st, (long)k * p, 0.0, out.V.get());
   }
-  k::gemm_rm(st, m, rc, rc, Q.get(), m, true, WS.get(), rc, false, out.B.get(), p);
+  k::copy2d(st, m, rc, Yc.get(), 1, m, out.B.get(), p);  // B[x][col] = Yc[col][x]
   // V = P Y: row order[c] of V is row c of Y
   k::gather_cols(st, k, rcp, rc, X.get(), rcp, didx.get(), dinv.get(), Y.get(), rc);
   k::gather_rows(st, k, rc, Y.get(), rc, dinvo.get(), out.V.get(), p);
