@@ -26,8 +26,9 @@ Printed JSON line:
              control-point gradient at the uncapped solution (differentiation form);
   batching   64 uneven local TT-matvecs, one call per problem versus one batched call;
   time_dependent  the time-dependent KKT system on the annulus geometry and desired state
-             with 10 implicit Euler steps (3 x 10 x 64^3 = 7.9 M unknowns), FP64 AMEn to
-             1e-6: solve time, residual, ranks, time parts;
+             with 10 implicit Euler steps (3 x 10 x 64^3 = 7.9 M unknowns), AMEn to 1e-6:
+             FP64 solve time, residual, ranks, time parts; the FP32 and BF16 forms' solve
+             times, residuals and state differences against FP64;
   in_solve_band_stage  the banded middle stage of the local matvecs inside the timed solves
              (HIP events recorded by the library on its stream around every such stage);
   roofline   the dominant kernel of the local TT-matvec at the workload's microbenchmark
@@ -267,22 +268,38 @@ def batching_bench(iga, ctx, torch, nprob=64, seed=100, iters=3):
 
 def time_dependent_bench(iga, ctx, torch, geo, c, Y, nt=10):
     """The time-dependent system (implicit Euler, nt steps, tau = 1 / nt) on the workload's
-    geometry and desired state, FP64, AMEn tolerance 1e-6: one warm-up solve, one timed."""
+    geometry and desired state, AMEn tolerance 1e-6: FP64 (one warm-up solve, one timed), then
+    the FP32 and BF16 forms (one timed solve each) with their state's distance to FP64's."""
     n, p, beta = c["n"], c["degree"], c["beta"]
     M, K, _ = iga.assemble_factors(ctx, geo, p, n, weight_tol=c["weight_tol"])
     kk = iga.kkt_create_parabolic(ctx, M, K, beta, nt, 1.0 / nt)
     out = {"time_steps": nt, "unknowns": 3 * nt * n ** 3}
-    for i in range(2):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        sol, st, rc = iga.amen_solve(ctx, kk, Y, 1e-6)
-        t1 = time.perf_counter()
+    ref = None
+    for name, prec, runs in (("fp64", iga.FP64, 2), ("fp32", iga.FP32, 1), ("bf16", iga.BF16, 1)):
+        for i in range(runs):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sol, st, rc = iga.amen_solve(ctx, kk, Y, 1e-6, precision=prec)
+            t1 = time.perf_counter()
+            if i + 1 < runs:
+                iga.btt_destroy(sol)
+        full = iga.btt_to_full(ctx, sol)
         iga.btt_destroy(sol)
-    out.update({"solve_time_s": t1 - t0, "status": rc, "valid": solve_ok(rc, st), "kkt_residual": st["residual"],
-                "half_sweeps": st["half_sweeps"], "ranks": st["ranks"], "local_iterations": st["local_iterations"],
-                "t_local_matvec": st["t_local_matvec"], "t_svd": st["t_svd"], "t_precond": st["t_precond"],
-                "local_matvec_gflops": st["local_matvec_flops"] / st["t_local_matvec"] / 1e9
-                if st["t_local_matvec"] else None})
+        rec = {"solve_time_s": t1 - t0, "status": rc, "valid": solve_ok(rc, st), "kkt_residual": st["residual"],
+               "half_sweeps": st["half_sweeps"], "ranks": st["ranks"], "t_svd": st["t_svd"]}
+        if name == "fp64":
+            ref = full
+            rec.update({"local_iterations": st["local_iterations"], "t_local_matvec": st["t_local_matvec"],
+                        "t_precond": st["t_precond"],
+                        "local_matvec_gflops": st["local_matvec_flops"] / st["t_local_matvec"] / 1e9
+                        if st["t_local_matvec"] else None})
+            out.update(rec)
+        else:
+            rec["state_rel_diff_vs_fp64"] = float((full - ref).norm() / ref.norm())
+            rec["speedup_vs_fp64"] = out["solve_time_s"] / rec["solve_time_s"]
+            out[name] = rec
+        del full
+    del ref
     iga.kkt_destroy(kk)
     iga.ttop_destroy(M)
     iga.ttop_destroy(K)
