@@ -186,6 +186,14 @@ void iga_ttop_destroy(iga_ttop* op);
  * (iga_tt_destroy). Synchronises. */
 int iga_tt_from_full(iga_ctx* ctx, const int n[3], const double* full, double rel_tol, iga_tt** out);
 
+/* TT rounding (Section 5, eq. tt: the truncation applied to a TT vector): right-to-left
+ * orthogonalisation, then left-to-right truncated SVDs of the unfoldings with the absolute
+ * tolerance rel_tol ||in|| / sqrt(2) each, so that ||*out - in|| <= rel_tol ||in|| up to rounding
+ * (rel_tol = 0 only removes exact rank deficiencies). The SVDs are those of the solver's
+ * truncations. in is not modified; *out is new (iga_tt_destroy). IGA_EINVAL for a tolerance
+ * outside [0, 1) or a TT of another context. Synchronises. */
+int iga_tt_round(iga_ctx* ctx, const iga_tt* in, double rel_tol, iga_tt** out);
+
 /* TT vectors. iga_tt_create copies host cores; iga_tt_wrap wraps caller-owned
  * device cores without copying (they must outlive the handle). r[0]=r[3]=1. */
 int iga_tt_create(iga_ctx* ctx, const int n[3], const int r[4], const double* const host_cores[3],

@@ -108,6 +108,7 @@ int amen_many_impl(iga_ctx* ctx, int nprob, const iga_kkt* const* kkts, const ig
                    iga_amen_stats* stats, int* status);
 int objective_impl(iga_ctx* ctx, const iga_kkt* kkt, const iga_tt* Y, const iga_btt* f, double* J, double* grad);
 iga_tt* tt_from_full_impl(iga_ctx* ctx, const int n[3], const double* full, double rel_tol);
+iga_tt* tt_round_impl(iga_ctx* ctx, const iga_tt* in, double rel_tol);
 int grad_geometry_impl(iga_ctx* ctx, const iga_geometry* geo, int p, const int n[3], const iga_assembly_opts* opts,
                        double beta, const iga_tt* Y, const iga_btt* f, double* grad);
 int assemble_impl(iga_ctx* ctx, const iga_geometry* geo, int p, const int n[3],
@@ -396,6 +397,17 @@ int iga_tt_from_full(iga_ctx* ctx, const int n[3], const double* full, double re
     *out = nullptr;
     use_device(ctx);
     *out = tt_from_full_impl(ctx, n, full, rel_tol);
+    return IGA_OK;
+  });
+}
+
+int iga_tt_round(iga_ctx* ctx, const iga_tt* in, double rel_tol, iga_tt** out) {
+  return guarded([&] {
+    require(ctx && in && out, IGA_EINVAL, "tt_round: NULL argument");
+    *out = nullptr;
+    require(in->ctx == ctx, IGA_EINVAL, "tt_round: the TT belongs to another context");
+    use_device(ctx);
+    *out = tt_round_impl(ctx, in, rel_tol);
     return IGA_OK;
   });
 }

@@ -183,6 +183,87 @@ iga_tt* tt_from_full_impl(iga_ctx* ctx, const int n[3], const double* full, doub
   return t.release();
 }
 
+// Left factor and remainder of a truncated SVD: for the r leading singular triplets of s,
+// U = B / sigma (m x r, orthonormal columns) and C = Sigma V^T (r x k), both row-major.
+static void split_svd(iga_ctx* ctx, const Svd& s, int m, int k, int r, DBuf& U, DBuf& C) {
+  hipStream_t st = ctx->stream;
+  std::vector<int> id(r);
+  std::vector<double> inv(r), sg(r);
+  for (int j = 0; j < r; ++j) {
+    id[j] = j;
+    sg[j] = s.sigma[j];
+    inv[j] = s.sigma[j] > 0 ? 1.0 / s.sigma[j] : 0.0;
+  }
+  IBuf did(ctx, r);
+  IGA_HIP(hipMemcpyAsync(did.get(), id.data(), r * sizeof(int), hipMemcpyHostToDevice, st));
+  DBuf dinv = upload(ctx, inv.data(), r), dsg = upload(ctx, sg.data(), r), CT(ctx, (size_t)k * r);
+  U.reset(ctx, (size_t)m * r);
+  C.reset(ctx, (size_t)r * k);
+  k::gather_cols(st, m, s.p, r, s.B.get(), s.p, did.get(), dinv.get(), U.get(), r);
+  k::gather_cols(st, k, s.p, r, s.V.get(), s.p, did.get(), dsg.get(), CT.get(), r);
+  k::copy2d(st, r, k, CT.get(), 1, r, C.get(), k);
+  IGA_HIP(hipStreamSynchronize(st));
+}
+
+// TT rounding of a three-core TT (the truncation of Sec. 5, eq. tt, applied to a TT vector):
+// right-to-left orthogonalisation (cores 2 and 1 get orthonormal rows, their factors move left),
+// then left-to-right truncated SVDs of the unfoldings with the absolute tolerance
+// rel_tol ||x|| / sqrt(2) each, so that ||round(x) - x|| <= rel_tol ||x|| up to rounding. The
+// SVDs are those of the sweep's truncations (pivoted QR, then Jacobi on the small factor).
+iga_tt* tt_round_impl(iga_ctx* ctx, const iga_tt* in, double rel_tol) {
+  require(rel_tol >= 0.0 && rel_tol < 1.0, IGA_EINVAL, "tt_round: tolerance must be in [0, 1)");
+  hipStream_t st = ctx->stream;
+  const int* n = in->n;
+  int r[4] = {1, in->r[1], in->r[2], 1};
+  DBuf G[3];
+  for (int d = 0; d < 3; ++d) {
+    const size_t len = (size_t)r[d] * n[d] * r[d + 1];
+    G[d].reset(ctx, len);
+    IGA_HIP(hipMemcpyAsync(G[d].get(), in->core[d], len * sizeof(double), hipMemcpyDeviceToDevice, st));
+  }
+  // right-to-left: G_d^T = U Sigma V^T, G_d <- U^T, G_{d-1} <- G_{d-1} V Sigma
+  for (int d = 2; d >= 1; --d) {
+    const int m = n[d] * r[d + 1], k = r[d];
+    Svd s;
+    svd(ctx, G[d].get(), m, k, m, /*trans=*/true, s);
+    const int q = std::max(1, trunc_rank(s.sigma, 0.0, 0));
+    DBuf U, C;
+    split_svd(ctx, s, m, k, q, U, C);
+    DBuf Gd(ctx, (size_t)q * m), Gp(ctx, (size_t)r[d - 1] * n[d - 1] * q);
+    k::copy2d(st, q, m, U.get(), 1, q, Gd.get(), m);
+    k::gemm_rm(st, r[d - 1] * n[d - 1], q, k, G[d - 1].get(), k, false, C.get(), k, true, Gp.get(), q);
+    G[d] = std::move(Gd);
+    G[d - 1] = std::move(Gp);
+    r[d] = q;
+  }
+  const double fro = std::sqrt(norm2_host(ctx, (long)n[0] * r[1], G[0].get()));
+  const double delta = rel_tol / std::sqrt(2.0) * fro;
+  // left-to-right: G_d = U Sigma V^T, truncated; G_d <- U_r, G_{d+1} <- Sigma_r V_r^T G_{d+1}
+  for (int d = 0; d <= 1; ++d) {
+    const int m = r[d] * n[d], k = r[d + 1], rest = n[d + 1] * r[d + 2];
+    Svd s;
+    svd(ctx, G[d].get(), m, k, k, /*trans=*/false, s);
+    const int rt = std::max(1, trunc_rank(s.sigma, delta, 0));
+    DBuf U, C;
+    split_svd(ctx, s, m, k, rt, U, C);
+    DBuf Gn(ctx, (size_t)rt * rest);
+    k::gemm_rm(st, rt, rest, k, C.get(), k, false, G[d + 1].get(), rest, false, Gn.get(), rest);
+    G[d] = std::move(U);
+    G[d + 1] = std::move(Gn);
+    r[d + 1] = rt;
+  }
+  std::unique_ptr<iga_tt> t(new iga_tt());
+  t->ctx = ctx;
+  for (int d = 0; d < 3; ++d) t->n[d] = n[d];
+  for (int d = 0; d < 4; ++d) t->r[d] = r[d];
+  for (int d = 0; d < 3; ++d) {
+    t->own[d] = std::move(G[d]);
+    t->core[d] = t->own[d].get();
+  }
+  IGA_HIP(hipStreamSynchronize(st));
+  return t.release();
+}
+
 void setup_spaces(iga_ctx* ctx, int p, const int n[3], int pt, int nq, SpaceDir dir[3]) {
   hipStream_t st = ctx->stream;
   std::vector<double> gx, gw;

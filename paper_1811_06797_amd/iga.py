@@ -28,7 +28,7 @@ _NAMES = {EINVAL: "IGA_EINVAL", ENOMEM: "IGA_ENOMEM", EHIP: "IGA_EHIP", EGEOM: "
 
 EXPORTED = [
     "iga_ctx_create", "iga_ctx_destroy", "iga_assemble_factors", "iga_ttop_create", "iga_ttop_info",
-    "iga_ttop_get_core", "iga_ttop_destroy", "iga_tt_create", "iga_tt_wrap", "iga_tt_from_full", "iga_tt_destroy",
+    "iga_ttop_get_core", "iga_ttop_destroy", "iga_tt_create", "iga_tt_wrap", "iga_tt_from_full", "iga_tt_round", "iga_tt_destroy",
     "iga_tt_info", "iga_tt_get_core",
     "iga_btt_create", "iga_btt_info", "iga_btt_blocks", "iga_btt_get_core", "iga_btt_to_full", "iga_btt_destroy",
     "iga_kkt_create", "iga_kkt_create_parabolic", "iga_kkt_blocks", "iga_kkt_destroy", "iga_kkt_apply", "iga_kkt_residual", "iga_amen_solve",
@@ -124,6 +124,7 @@ lib.iga_ttop_destroy.restype = None
 lib.iga_tt_create.argtypes = [P, I3, I4, PD * 3, C.POINTER(P)]
 lib.iga_tt_wrap.argtypes = [P, I3, I4, PD * 3, C.POINTER(P)]
 lib.iga_tt_from_full.argtypes = [P, I3, P, C.c_double, C.POINTER(P)]
+lib.iga_tt_round.argtypes = [P, P, C.c_double, C.POINTER(P)]
 lib.iga_tt_destroy.argtypes = [P]
 lib.iga_tt_destroy.restype = None
 lib.iga_tt_info.argtypes = [P, I3, I4]
@@ -492,6 +493,13 @@ def tt_from_full(ctx, full, rel_tol: float = 0.0):
     assert full.is_cuda and full.dtype.is_floating_point and full.dim() == 3 and full.is_contiguous()
     out = P()
     _check(lib.iga_tt_from_full(ctx, I3(*full.shape), C.c_void_p(full.data_ptr()), float(rel_tol), C.byref(out)))
+    return out
+
+
+def tt_round(ctx, t, rel_tol: float = 0.0):
+    """New TT handle: the rounding of t to the relative Frobenius tolerance rel_tol."""
+    out = P()
+    _check(lib.iga_tt_round(ctx, t, float(rel_tol), C.byref(out)))
     return out
 
 
