@@ -118,9 +118,13 @@ template <int WM, int WN, int WAVES_M, int WAVES_N, int BK, int NBUF, int PF, bo
 __device__ __forceinline__ void gemm2_tile(const G2Args& g, int bx, int by, int bz,
                                            TileLds<4 * WM * WAVES_M, 16 * WN * WAVES_N, BK, NBUF>& L) {
   constexpr int BM = 4 * WM * WAVES_M, BN = 16 * WN * WAVES_N;
-  constexpr int LA = BM * BK / NTHR, LB = BN * BK / NTHR;
+  // loads per thread and K tile; where the A tile is not a whole number of rounds of the
+  // workgroup (the 24-row tile), the last round's extra threads load a duplicate of an element
+  // of the tile and do not store it
+  constexpr int LA = (BM * BK + NTHR - 1) / NTHR, LB = BN * BK / NTHR;
+  constexpr bool PA = LA * NTHR != BM * BK;
   static_assert(WAVES_M * WAVES_N == 4, "four waves");
-  static_assert(LA >= 1 && LB >= 1, "tile too small");
+  static_assert(LA >= 1 && LB >= 1 && LB * NTHR == BN * BK, "tile too small");
   auto& As = L.As;
   auto& Bs = L.Bs;
   const int split = bz / g.nbatch, bb = bz - split * g.nbatch;
@@ -143,11 +147,13 @@ __device__ __forceinline__ void gemm2_tile(const G2Args& g, int bx, int by, int 
   const int dA = kq * (int)g.sAk1 + krem * (int)g.sAk2, dAw = dA + (int)g.sAk1 - g.K2 * (int)g.sAk2;
   const int dB = kq * (int)g.sBk1 + krem * (int)g.sBk2, dBw = dB + (int)g.sBk1 - g.K2 * (int)g.sBk2;
   int a_mm[LA], a_kk[LA], b_nn[LB], b_kk[LB], ak2[LA], bk2[LB];
-  bool a_ok[LA], b_ok[LB];
+  bool a_ok[LA], b_ok[LB], a_st[LA];
   int oa[LA], ob[LB];  // element offsets from the batch's operand base (host checks they fit)
 #pragma unroll
   for (int s = 0; s < LA; ++s) {
-    const int e = tid + NTHR * s;
+    int e = tid + NTHR * s;
+    a_st[s] = !PA || e < BM * BK;
+    if (PA && !a_st[s]) e %= BM * BK;
     if (a_kfast) { a_kk[s] = e % BK; a_mm[s] = e / BK; } else { a_mm[s] = e % BM; a_kk[s] = e / BM; }
     const int m = m0 + a_mm[s];
     a_ok[s] = m < g.M;
@@ -206,7 +212,13 @@ __device__ __forceinline__ void gemm2_tile(const G2Args& g, int bx, int by, int 
   };
   auto store_tile = [&](int buf, const double (&ra)[LA], const double (&rb)[LB]) {
 #pragma unroll
-    for (int s = 0; s < LA; ++s) As[buf][a_kk[s]][a_mm[s]] = ra[s];
+    for (int s = 0; s < LA; ++s) {
+      if constexpr (PA) {
+        if (a_st[s]) As[buf][a_kk[s]][a_mm[s]] = ra[s];
+      } else {
+        As[buf][a_kk[s]][a_mm[s]] = ra[s];
+      }
+    }
 #pragma unroll
     for (int s = 0; s < LB; ++s) Bs[buf][b_kk[s]][b_nn[s]] = rb[s];
   };
@@ -566,7 +578,7 @@ static G2Args make_args(const Gemm2& d) {
 }
 
 // Output tile of each variant: 0: 64 x 64, 1: 32 x 128, 2: 16 x 256, 3: 128 x 32, 4: 64 x (32 WIDE_WN),
-// 5: 80 x 64, 6: 64 x 96, 7: 96 x 64.
+// 5: 80 x 64, 6: 64 x 96, 7: 96 x 64, 8: 24 x 128.
 static void variant_tile(int v, int& BM, int& BN) {
   switch (v) {
     case 1: BM = 32; BN = 128; break;
@@ -576,17 +588,21 @@ static void variant_tile(int v, int& BM, int& BN) {
     case 5: BM = 80; BN = 64; break;
     case 6: BM = 64; BN = 96; break;
     case 7: BM = 96; BN = 64; break;
+    case 8: BM = 24; BN = 128; break;
     default: BM = 64; BN = 64; break;
   }
 }
 
-int gemm2_variants() { return 8; }
+int gemm2_variants() { return 9; }
 
 static bool dma_eligible(const Gemm2& d);
 
 int gemm2_pick(const Gemm2& d) {
   const long nb = (long)d.nb1 * d.nb2;
   if (d.M <= 16) return 2;
+  // 17..24 rows (the blocks of the K core's middle factor, 18 to 25 ranks): a 24-row tile
+  // instead of 32 rows of which a quarter or more would be padding
+  if (d.M <= 24) return 8;
   if (d.M <= 32) return 1;
   if (d.N <= 32) return 3;
   if (d.M <= 64 && (long)((d.N + 32 * IGA_WIDE_WN - 1) / (32 * IGA_WIDE_WN)) * nb >= 512) return 4;
@@ -637,6 +653,7 @@ void gemm2_grouped(hipStream_t s, int variant, const void* dev_desc, const int* 
     case 5: launch_grouped<10, 2, 2, 2, 16, 2, IGA_PREFETCH>(s, dev_desc, dev_prefix, ngemm, total); break;
     case 6: launch_grouped<8, 3, 2, 2, 16, 2, IGA_PREFETCH>(s, dev_desc, dev_prefix, ngemm, total); break;
     case 7: launch_grouped<12, 2, 2, 2, 16, 2, IGA_PREFETCH>(s, dev_desc, dev_prefix, ngemm, total); break;
+    case 8: launch_grouped<6, 2, 1, 4, 16, 2, IGA_PREFETCH>(s, dev_desc, dev_prefix, ngemm, total); break;
     default: launch_grouped<8, 2, 2, 2, 16, 2, IGA_PREFETCH>(s, dev_desc, dev_prefix, ngemm, total); break;
   }
   IGA_HIP(hipGetLastError());
@@ -696,6 +713,7 @@ void gemm2(hipStream_t s, const Gemm2& d, double* work, size_t work_len) {
     case 5: launch<10, 2, 2, 2, 16, 2, IGA_PREFETCH>(s, a, (int)nb); break;
     case 6: launch<8, 3, 2, 2, 16, 2, IGA_PREFETCH>(s, a, (int)nb); break;
     case 7: launch<12, 2, 2, 2, 16, 2, IGA_PREFETCH>(s, a, (int)nb); break;
+    case 8: launch<6, 2, 1, 4, 16, 2, IGA_PREFETCH>(s, a, (int)nb); break;
     default: launch<8, 2, 2, 2, 16, 2, IGA_PREFETCH>(s, a, (int)nb); break;
   }
   }

@@ -45,11 +45,12 @@ def _run(gpu_ctx, prob, r, n, p, RM, RK, beta, precision, rr=None):
                                              # (M = R_K r = 360, N = n r' = 2160)
                                              (20, 2, 5, 16, 3, 72), (30, 3, 12, 24, 2, 90),
                                              # banded stages with 17..32 output ranks (the
-                                             # re-laid core's product on 32-row tiles): p = 3,
-                                             # a ragged p = 2 case, and p = 1 with both
-                                             # operators there (R_M = 17, R_K = 30)
+                                             # re-laid core's product on 24-row tiles up to 24
+                                             # ranks, 32-row ones above): p = 3, a ragged p = 2
+                                             # case, p = 1 with both operators there (R_M = 17,
+                                             # R_K = 30), and 21 and 23 ranks with n = 29
                                              (20, 3, 24, 18, 3, None), (12, 2, 19, 37, 2, 13),
-                                             (9, 17, 30, 20, 1, 7)])
+                                             (9, 17, 30, 20, 1, 7), (11, 21, 23, 29, 3, 5)])
 def test_local_matvec_matches_oracle(gpu_ctx, r, RM, RK, n, p, rr):
     from paper_1811_06797_amd import iga
     prob = synth.random_local_problem(r, RM, RK, n, p, seed=r + n, r_right=rr)
