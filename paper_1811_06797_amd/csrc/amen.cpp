@@ -190,7 +190,9 @@ class Amen {
   void setup_precond(int d);
   void apply_precond(const double* v, double* z);
   void matvec(const LocalOp& L, const double* x, double* y);
-  int fgmres(const LocalOp& L, const double* b, double* x, double bnorm, double abstol);
+  // r0 (may be null): b - A x for the x on entry, already computed by the caller
+  int fgmres(const LocalOp& L, const double* b, double* x, double bnorm, double abstol,
+             const double* r0 = nullptr);
   void residual_proj(int d, Frame left, Frame right, double* out);  // rhs - A x in the given frames
   void move_right(int d);
   void move_left(int d);
@@ -279,6 +281,10 @@ class Amen {
   int hist_r_[IGA_MAX_HISTORY][2] = {};
   long long hist_st_[IGA_MAX_HISTORY] = {};
   double bnorm_ = 1.0;  // norm of the local right-hand side of the last solve
+  // the FP64 local residual of X_[solved_d_] as the last local solve left it, when that solve
+  // computed it (-1: not known); the truncation of that core starts from it
+  double solved_res_ = -1.0;
+  int solved_d_ = -1;
   DBuf xk_;
 };
 
@@ -549,7 +555,7 @@ int Amen::refine_solve(int d, const LocalOp& L, double bn, double ltol, double r
     const double inner = std::max(ltol / res, floor);
     k::fill(st_, N, 0.0, e.get());
     lp_inner_ = true;
-    its += fgmres(L, r.get(), e.get(), rn, inner * rn);
+    its += fgmres(L, r.get(), e.get(), rn, inner * rn, r.get());  // e = 0: its residual is r
     lp_inner_ = false;
     k::axpby(st_, N, 1.0, e.get(), 1.0, X_[d].get());
     matvec(L, X_[d].get(), r.get());
@@ -558,6 +564,7 @@ int Amen::refine_solve(int d, const LocalOp& L, double bn, double ltol, double r
     require(std::isfinite(res), IGA_ENUM, "amen_solve: non-finite residual in the mixed-precision refinement");
     ++n_refine_;
   }
+  solved_res_ = res;
   return its;
 }
 
@@ -667,7 +674,7 @@ void Amen::apply_precond(const double* v, double* z) {
 
 // Right-preconditioned restarted flexible GMRES with classical Gram-Schmidt applied twice.
 // Returns the number of iterations; x is updated in place.
-int Amen::fgmres(const LocalOp& L, const double* b, double* x, double bnorm, double abstol) {
+int Amen::fgmres(const LocalOp& L, const double* b, double* x, double bnorm, double abstol, const double* r0) {
   g_phase = "fgmres";
   const long N = L.size();
   const int m = std::max(2, std::min(o_.local_restart, 63));
@@ -687,10 +694,16 @@ int Amen::fgmres(const LocalOp& L, const double* b, double* x, double bnorm, dou
   double* h = h_.get();
   int it = 0;
   std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), hh(m + 2), y(m);
+  bool first = true;
   while (it < maxit) {
-    // r = b - A x
-    matvec(L, x, V);
-    k::axpby(st_, N, 1.0, b, -1.0, V);
+    // r = b - A x (given for the first cycle)
+    if (first && r0) {
+      IGA_HIP(hipMemcpyAsync(V, r0, N * sizeof(double), hipMemcpyDeviceToDevice, st_));
+    } else {
+      matvec(L, x, V);
+      k::axpby(st_, N, 1.0, b, -1.0, V);
+    }
+    first = false;
     const double beta0 = std::sqrt(norm2_host(ctx_, N, V));
     require(std::isfinite(beta0), IGA_ENUM, "amen_solve: non-finite residual norm in the local Krylov solve");
     if (beta0 <= abstol || !(beta0 > 0)) break;
@@ -777,13 +790,16 @@ double Amen::solve_local(int d) {
   require(std::isfinite(res), IGA_ENUM, "amen_solve: non-finite local residual (the iterate holds NaN or Inf)");
   ++n_solves_;
   const double ltol = o_.local_tol;
+  solved_d_ = d;
+  solved_res_ = res;  // kept if no solve is needed
   if (res > ltol) {
     setup_precond(d);
     if (lowp_) {
       lowp_operands(d, L);
-      n_iters_ += refine_solve(d, L, bn, ltol, res);
+      n_iters_ += refine_solve(d, L, bn, ltol, res);  // leaves solved_res_ at its final residual
     } else {
-      n_iters_ += fgmres(L, bl_.get(), X_[d].get(), bn, ltol * bn);
+      solved_res_ = -1.0;
+      n_iters_ += fgmres(L, bl_.get(), X_[d].get(), bn, ltol * bn, tmp_.get());
     }
   }
   return res;
@@ -837,7 +853,9 @@ template <class Recon>
 int Amen::residual_rank(int d, int kmin, int kmax, const std::vector<double>& sigma, Recon recon) {
   const long N = (long)nb_ * r_[d] * n_[d] * r_[d + 1];
   xk_.ensure(ctx_, N);
-  const double full = local_res_of(d, X_[d].get());
+  // the solve's own final FP64 residual where it computed one (same operations, same value)
+  const double full = solved_d_ == d && solved_res_ >= 0.0 ? solved_res_ : local_res_of(d, X_[d].get());
+  solved_d_ = -1;
   require(std::isfinite(full), IGA_ENUM, "amen_solve: non-finite local residual in the truncation");
   // a local solve that stopped short of the tolerance (full > tol) grants no slack: the
   // truncation must then reach 1.5 tol, which keeps the rank where the solve was incomplete
