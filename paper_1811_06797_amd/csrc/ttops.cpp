@@ -601,6 +601,29 @@ static void eig_sym(iga_ctx* ctx, int k, const double* X, double* Vc, double* la
 
 void gen_eig(iga_ctx* ctx, int k, const double* A, const double* B, double* V, double* lam) {
   hipStream_t st = ctx->stream;
+  {
+    // Cholesky reduction: B = L L^T, W = L^-T (W^T B W = I), C = W^T A W = Z diag(lam) Z^T,
+    // V = W Z; one symmetric eigenproblem instead of two (B's and C's). Falls through to the
+    // eigen-decomposition of B if B is not numerically positive definite.
+    const int cb = k::chol_block_size(), nblk = (k + cb - 1) / cb;
+    const size_t wlen = (size_t)32 * k * k + (size_t)8 * k * cb;
+    DBuf G(ctx, (size_t)k * k), L(ctx, (size_t)k * k), Li(ctx, (size_t)nblk * cb * cb), Mj(ctx, (size_t)k * cb),
+        E(ctx, (size_t)k * k), W(ctx, (size_t)k * k), T(ctx, (size_t)k * k), C(ctx, (size_t)k * k),
+        Z(ctx, (size_t)k * k), work(ctx, wlen);
+    IGA_HIP(hipMemcpyAsync(G.get(), B, (size_t)k * k * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if (cholesky(ctx, k, G.get(), L.get(), Li.get()) == 0) {
+      k::fill(st, (long)k * k, 0.0, E.get());
+      k::add_diag(st, k, E.get(), k, 1.0);
+      solve_right_lt(ctx, k, k, E.get(), k, L.get(), Li.get(), W.get(), k, Mj.get(), work.get(), wlen);
+      k::gemm_rm(st, k, k, k, A, k, false, W.get(), k, false, T.get(), k);
+      k::gemm_rm(st, k, k, k, W.get(), k, true, T.get(), k, false, C.get(), k);
+      k::symmetrize(st, 1, k, C.get(), 0);
+      eig_sym(ctx, k, C.get(), Z.get(), lam);
+      k::gemm_rm(st, k, k, k, W.get(), k, false, Z.get(), k, false, V, k);
+      IGA_HIP(hipStreamSynchronize(st));
+      return;
+    }
+  }
   DBuf U(ctx, (size_t)k * k), d(ctx, k), lb(ctx, k), Sm(ctx, (size_t)k * k), T(ctx, (size_t)k * k),
       C(ctx, (size_t)k * k), Z(ctx, (size_t)k * k);
   IBuf idx(ctx, k);
