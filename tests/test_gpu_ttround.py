@@ -47,13 +47,15 @@ def _round(gpu_ctx, cores, rel_tol):
     return r, out
 
 
-def test_round_low_rank_plus_small_matches_oracle(gpu_ctx):
-    """x = a + 1e-9 b, a of ranks (3, 4), b of ranks (6, 6): rounding to 1e-6 recovers ranks
-    (3, 4), and with singular-value gaps of about 1e9 at both cuts the library's result equals
-    the oracle's TT-SVD of full(x) elementwise."""
-    n = (20, 24, 18)
+@pytest.mark.parametrize("n, rb", [((20, 24, 18), (6, 6)), ((60, 64, 50), (40, 40))])
+def test_round_low_rank_plus_small_matches_oracle(gpu_ctx, n, rb):
+    """x = a + 1e-9 b, a of ranks (3, 4), b of ranks rb: rounding to 1e-6 recovers ranks (3, 4),
+    and with singular-value gaps of about 1e9 at both cuts the library's result equals the
+    oracle's TT-SVD of full(x) elementwise. With rb = (40, 40) every unfolding has more than 32
+    columns, so each truncation SVD runs behind the pivoted QR step."""
     a = _random_cores(n, (1, 3, 4, 1), seed=1)
-    b = _random_cores(n, (1, 6, 6, 1), seed=2, scale=1e-9)
+    b = _random_cores(n, (1,) + rb + (1,), seed=2)
+    b[0] *= 1e-9
     x = _tt_sum(a, b)
     X = tt.tt_full(x)
     r, out = _round(gpu_ctx, x, 1e-6)
@@ -99,6 +101,19 @@ def test_round_smooth_tensor_error_and_ranks(gpu_ctx, rel_tol):
     for d in (1, 2):
         assert abs(r[d] - ref[d - 1].shape[2]) <= 1, (r, [c.shape for c in ref])
     assert np.abs(Y - tt.tt_full(ref)).max() <= 2 * rel_tol * nx + 1e-13 * nx
+
+
+def test_round_zero_tensor(gpu_ctx):
+    """The zero tensor (ranks (2, 3)) rounds to ranks (1, 1), the smallest the format holds, with
+    every entry exactly zero and no NaN from the zero singular values."""
+    n = (7, 5, 6)
+    x = [np.zeros((1, 7, 2)), np.zeros((2, 5, 3)), np.zeros((3, 6, 1))]
+    r, out = _round(gpu_ctx, x, 1e-6)
+    assert r == [1, 1, 1, 1]
+    Y = tt.tt_full(out)
+    assert Y.shape == n
+    assert np.all(Y == 0.0)
+    assert all(np.all(np.isfinite(c)) for c in out)
 
 
 def test_round_refusals(gpu_ctx):
